@@ -1,0 +1,309 @@
+"""Seeded synthetic inputs: grid layout and initial data for the benchmark workloads.
+
+This module holds no arithmetic of the method itself: it lays out arrays and
+fills them with seeded analytic data (mode sums, piecewise-constant states,
+their vector potentials and the extrinsic curvature of a static metric).  The
+conserved variables are NOT computed here; each side (GPU library, CPU oracle)
+maps these primitives to conserved variables with its own code.
+
+Index space (shared by every array): padded extents ld[0] x ld[1] x ld[2],
+x fastest; index (i, j, k) with owned range 0..n-1 and ghosts down to -ng and
+up to n+ng is stored at [.., k+ng, j+ng, i+ng].  Positions: cell centre
+((i+1/2)dx, (j+1/2)dy, (k+1/2)dz); vertex (i dx, j dy, k dz); x-edge
+((i+1/2)dx, j dy, k dz), y-edge (i dx, (j+1/2)dy, k dz), z-edge (i dx, j dy,
+(k+1/2)dz).
+
+Workloads (one block, one GPU):
+  riemann32  -- 32^3 + 3 ghosts, flat metric, Gamma = 5/3, seeded Riemann
+                problem split at x = 1/2, MINMOD, HLLE, Noble c2p, RK2, CFL 0.25.
+  curved128  -- 128^3 periodic block in a static curved metric (low-k mode
+                sums), Gamma = 2, PPM or WENO-Z, RK4, CFL 0.25.
+Both are also available at other sizes for tests.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+NG_DEFAULT = 3
+
+
+@dataclass
+class Layout:
+    n: tuple
+    ng: int = NG_DEFAULT
+    dx: tuple = None
+    xpad: int = 8
+    ld: tuple = field(init=False)
+
+    def __post_init__(self):
+        self.n = tuple(int(v) for v in self.n)
+        if self.dx is None:
+            self.dx = tuple(1.0 / v for v in self.n)
+        self.dx = tuple(float(v) for v in self.dx)
+        ext = [v + 2 * self.ng + 1 for v in self.n]
+        ext[0] = -(-ext[0] // self.xpad) * self.xpad
+        self.ld = tuple(ext)
+
+    @property
+    def shape3(self):
+        return (self.ld[2], self.ld[1], self.ld[0])
+
+    @property
+    def npts(self):
+        return self.ld[0] * self.ld[1] * self.ld[2]
+
+    def zeros(self, nf):
+        return np.zeros((nf,) + self.shape3, dtype=np.float64)
+
+    def owned(self, a):
+        """View of the owned index range 0..n-1 of an array (..., ld2, ld1, ld0)."""
+        g = self.ng
+        return a[..., g:g + self.n[2], g:g + self.n[1], g:g + self.n[0]]
+
+    def coords(self, where):
+        """Coordinates (x, y, z) of every stored point, broadcastable to shape3.
+
+        where: 'centre', 'vertex', 'xedge', 'yedge', 'zedge'."""
+        g = self.ng
+        off = {"centre": (0.5, 0.5, 0.5), "vertex": (0.0, 0.0, 0.0), "xedge": (0.5, 0.0, 0.0),
+               "yedge": (0.0, 0.5, 0.0), "zedge": (0.0, 0.0, 0.5)}[where]
+        x = (np.arange(self.ld[0]) - g + off[0]) * self.dx[0]
+        y = (np.arange(self.ld[1]) - g + off[1]) * self.dx[1]
+        z = (np.arange(self.ld[2]) - g + off[2]) * self.dx[2]
+        return x[None, None, :], y[None, :, None], z[:, None, None]
+
+    def periodic_wrap(self, a):
+        """Fill every ghost point of a (..., ld2, ld1, ld0) array from its periodic image (in place)."""
+        g = self.ng
+        for ax, d in ((-1, 0), (-2, 1), (-3, 2)):
+            n = self.n[d]
+            L = a.shape[ax]
+            idx = (np.arange(L) - g) % n + g
+            a[...] = np.take(a, idx, axis=ax)
+        return a
+
+
+def default_params(**kw):
+    p = dict(gamma=5.0 / 3.0, rho_atm=1e-10, k_atm=1.0, xi=1.5, c2p_tol=1e-14, wmax=1e3, weno_eps=1e-40,
+             weno_q=1.0, c2p_maxit=50, brent_maxit=100, recon="minmod", gauge="lorenz", speeds="quartic",
+             c2p_method=0)
+    p.update(kw)
+    return p
+
+
+# ---- mode sums --------------------------------------------------------------------------------------------
+
+class ModeSum:
+    """f(x) = sum_m a_m sin(2 pi k_m . x + phi_m) / sum_m |a_m|, k_m in {-2..2}^3 minus 0.
+
+    |f| <= 1 and f is periodic on the unit cube."""
+
+    def __init__(self, seed, tag, nmodes=4):
+        rng = np.random.default_rng([int(seed), int(tag)])
+        ks = []
+        while len(ks) < nmodes:
+            k = rng.integers(-2, 3, size=3)
+            if np.any(k != 0):
+                ks.append(k)
+        self.k = np.array(ks, dtype=np.float64)
+        self.phi = rng.uniform(0.0, 2.0 * np.pi, size=nmodes)
+        self.a = rng.uniform(-1.0, 1.0, size=nmodes)
+        self.norm = np.sum(np.abs(self.a))
+
+    def __call__(self, x, y, z):
+        out = 0.0
+        for m in range(len(self.a)):
+            ph = 2.0 * np.pi * (self.k[m, 0] * x + self.k[m, 1] * y + self.k[m, 2] * z) + self.phi[m]
+            out = out + self.a[m] * np.sin(ph)
+        return out / self.norm
+
+    def grad(self, x, y, z):
+        g = [0.0, 0.0, 0.0]
+        for m in range(len(self.a)):
+            ph = 2.0 * np.pi * (self.k[m, 0] * x + self.k[m, 1] * y + self.k[m, 2] * z) + self.phi[m]
+            c = self.a[m] * np.cos(ph) * 2.0 * np.pi
+            for d in range(3):
+                g[d] = g[d] + c * self.k[m, d]
+        return [gd / self.norm for gd in g]
+
+
+# ---- the Riemann-problem block (flat metric) -------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    layout: Layout
+    params: dict
+    metric: np.ndarray   # [10] vertex: alpha, beta^x..z, gxx, gxy, gxz, gyy, gyz, gzz
+    curv: np.ndarray     # [6] vertex: Kxx, Kxy, Kxz, Kyy, Kyz, Kzz
+    prim: np.ndarray     # [5] centre: rho, p, v^x, v^y, v^z
+    A: np.ndarray        # [3] edges
+    psi: np.ndarray      # [1] vertex
+    dt: float
+    nsteps: int
+    rk: int
+    bc_cell: tuple
+    bc_A: tuple
+    info: dict = field(default_factory=dict)
+
+    def state(self, cons):
+        """9-field state array (Dt, St_x, St_y, St_z, taut, A_x, A_y, A_z, Psi) from conserved variables."""
+        s = self.layout.zeros(9)
+        s[0:5] = cons
+        s[5:8] = self.A
+        s[8] = self.psi[0]
+        return s
+
+
+def flat_metric(layout):
+    m = layout.zeros(10)
+    m[0] = 1.0
+    m[4] = 1.0
+    m[7] = 1.0
+    m[9] = 1.0
+    return m
+
+
+def riemann_block(seed=0, n=32, ng=NG_DEFAULT, recon="minmod", nsteps=10, rk=2, cfl=0.25, gamma=5.0 / 3.0,
+                  split=0.5):
+    """Seeded relativistic MHD Riemann problem on [0,1]^3, split on the vertex plane x = split.
+
+    Left/right: rho, p ~ U[0.1, 1], v = 0, B^x ~ U[-1, 1] shared, B^y, B^z ~ U[-1, 1] per side.
+    The edge potential A = (0, int_0^x B^z dx', B^x y - int_0^x B^y dx') reproduces the
+    piecewise-constant face field exactly under the discrete curl."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    L = Layout(nn, ng)
+    rng = np.random.default_rng(int(seed))
+    rhoL, rhoR = rng.uniform(0.1, 1.0, 2)
+    pL, pR = rng.uniform(0.1, 1.0, 2)
+    Bx = rng.uniform(-1.0, 1.0)
+    ByL, BzL, ByR, BzR = rng.uniform(-1.0, 1.0, 4)
+    metric = flat_metric(L)
+    curv = L.zeros(6)
+    prim = L.zeros(5)
+    xc, _, _ = L.coords("centre")
+    left = np.broadcast_to(xc < split, L.shape3)
+    prim[0] = np.where(left, rhoL, rhoR)
+    prim[1] = np.where(left, pL, pR)
+
+    def int_B(x, bl, br):
+        return np.where(x < split, bl * x, bl * split + br * (x - split))
+
+    A = L.zeros(3)
+    xy, yy, zy = L.coords("yedge")
+    A[1] = np.broadcast_to(int_B(xy, BzL, BzR) + 0.0 * yy + 0.0 * zy, L.shape3)
+    xz, yz, zz = L.coords("zedge")
+    A[2] = np.broadcast_to(Bx * yz - int_B(xz, ByL, ByR) + 0.0 * zz, L.shape3)
+    psi = L.zeros(1)
+    rho_max = max(rhoL, rhoR)
+    params = default_params(gamma=gamma, rho_atm=1e-7 * rho_max, recon=recon)
+    dt = cfl * min(L.dx)
+    info = dict(rhoL=rhoL, rhoR=rhoR, pL=pL, pR=pR, Bx=Bx, ByL=ByL, BzL=BzL, ByR=ByR, BzR=BzR, seed=seed)
+    return Workload("riemann%d" % nn[0], L, params, metric, curv, prim, A, psi, dt, nsteps, rk,
+                    ("copy",) * 3, ("linear",) * 3, info)
+
+
+# ---- the curved periodic block -----------------------------------------------------------------------------
+
+_TAGS = {name: t for t, name in enumerate(
+    ["alpha", "betax", "betay", "betaz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz", "rho", "p", "vx", "vy", "vz",
+     "Ax", "Ay", "Az"])}
+
+
+def curved_metric(layout, seed, alpha0=0.8, alpha_amp=0.15, beta_amp=0.05, gamma_amp=0.1, want_curv=True):
+    """Static curved 3+1 metric at every vertex (bitwise periodic) and, optionally, its extrinsic curvature.
+
+    gamma_ij = delta_ij + gamma_amp f_ij, alpha = alpha0 + alpha_amp f_alpha, beta^i = beta_amp f_beta^i.
+    With d_t gamma_ij = 0 the extrinsic curvature (K = -L_n gamma / 2) is
+    K_ij = (D_i beta_j + D_j beta_i) / (2 alpha), evaluated analytically from the modes."""
+    L = layout
+    x, y, z = L.coords("vertex")
+    names = ["alpha", "betax", "betay", "betaz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz"]
+    f = {nm: ModeSum(seed, _TAGS[nm]) for nm in names}
+    m = L.zeros(10)
+    m[0] = alpha0 + alpha_amp * np.broadcast_to(f["alpha"](x, y, z), L.shape3)
+    for c, nm in enumerate(["betax", "betay", "betaz"]):
+        m[1 + c] = beta_amp * np.broadcast_to(f[nm](x, y, z), L.shape3)
+    for c, nm in enumerate(["gxx", "gxy", "gxz", "gyy", "gyz", "gzz"]):
+        delta = 1.0 if nm in ("gxx", "gyy", "gzz") else 0.0
+        m[4 + c] = delta + gamma_amp * np.broadcast_to(f[nm](x, y, z), L.shape3)
+    L.periodic_wrap(m)
+    if not want_curv:
+        return m, None, f
+    # analytic derivatives at vertices
+    sym = [(0, 0, "gxx"), (0, 1, "gxy"), (0, 2, "gxz"), (1, 1, "gyy"), (1, 2, "gyz"), (2, 2, "gzz")]
+    shape = L.shape3
+    g = np.zeros((3, 3) + shape)
+    dg = np.zeros((3, 3, 3) + shape)  # dg[k, a, b] = d_k gamma_ab
+    for a, b, nm in sym:
+        val = (1.0 if a == b else 0.0) + gamma_amp * np.broadcast_to(f[nm](x, y, z), shape)
+        gr = f[nm].grad(x, y, z)
+        g[a, b] = g[b, a] = val
+        for k in range(3):
+            dg[k, a, b] = dg[k, b, a] = gamma_amp * np.broadcast_to(gr[k], shape)
+    alpha = alpha0 + alpha_amp * np.broadcast_to(f["alpha"](x, y, z), shape)
+    beta = np.zeros((3,) + shape)
+    dbeta = np.zeros((3, 3) + shape)  # dbeta[k, a] = d_k beta^a
+    for a, nm in enumerate(["betax", "betay", "betaz"]):
+        beta[a] = beta_amp * np.broadcast_to(f[nm](x, y, z), shape)
+        gr = f[nm].grad(x, y, z)
+        for k in range(3):
+            dbeta[k, a] = beta_amp * np.broadcast_to(gr[k], shape)
+    gmat = np.moveaxis(g, (0, 1), (-2, -1))
+    gi = np.moveaxis(np.linalg.inv(gmat), (-2, -1), (0, 1))
+    beta_l = np.einsum("ab...,b...->a...", g, beta)
+    # d_i beta_j = d_i gamma_jk beta^k + gamma_jk d_i beta^k
+    dbl = np.einsum("ijk...,k...->ij...", dg, beta) + np.einsum("jk...,ik...->ij...", g, dbeta)
+    # Christoffel of the first kind Gamma_lij = (d_i g_lj + d_j g_li - d_l g_ij)/2
+    G1 = 0.5 * (np.einsum("ilj...->lij...", dg) + np.einsum("jli...->lij...", dg) - dg)
+    Gam = np.einsum("kl...,lij...->kij...", gi, G1)
+    Db = dbl - np.einsum("kij...,k...->ij...", Gam, beta_l)
+    K = (Db + np.swapaxes(Db, 0, 1)) / (2.0 * alpha)
+    curv = L.zeros(6)
+    for c, (a, b, _) in enumerate(sym):
+        curv[c] = K[a, b]
+    L.periodic_wrap(curv)
+    return m, curv, f
+
+
+def curved_block(seed=0, n=128, ng=NG_DEFAULT, recon="ppm", nsteps=5, rk=4, cfl=0.25, gamma=2.0, vmax=0.45,
+                 rho_atm=1e-10):
+    """Periodic block in a static curved metric with seeded low-k fluid, velocity and vector-potential modes."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    L = Layout(nn, ng)
+    metric, curv, fm = curved_metric(L, seed)
+    xc, yc, zc = L.coords("centre")
+    f = {nm: ModeSum(seed, _TAGS[nm]) for nm in ["rho", "p", "vx", "vy", "vz", "Ax", "Ay", "Az"]}
+    prim = L.zeros(5)
+    prim[0] = 1.0 + 0.5 * np.broadcast_to(f["rho"](xc, yc, zc), L.shape3)
+    prim[1] = 0.55 + 0.45 * np.broadcast_to(f["p"](xc, yc, zc), L.shape3)
+    v = np.stack([np.broadcast_to(f[nm](xc, yc, zc), L.shape3) for nm in ("vx", "vy", "vz")])
+    # scale so that max sqrt(gamma_ij v^i v^j) = vmax, with gamma_ij of the analytic modes at the centres
+    gsym = {}
+    for nm, (a, b) in zip(["gxx", "gxy", "gxz", "gyy", "gyz", "gzz"], [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
+        val = (1.0 if a == b else 0.0) + 0.1 * np.broadcast_to(fm[nm](xc, yc, zc), L.shape3)
+        gsym[(a, b)] = gsym[(b, a)] = val
+    vn2 = sum(gsym[(a, b)] * v[a] * v[b] for a in range(3) for b in range(3))
+    scale = vmax / np.sqrt(np.max(L.owned(vn2)))
+    prim[2:5] = scale * v
+    L.periodic_wrap(prim)
+    A = L.zeros(3)
+    curl_max = 0.0
+    for c, (nm, where) in enumerate((("Ax", "xedge"), ("Ay", "yedge"), ("Az", "zedge"))):
+        x, y, z = L.coords(where)
+        A[c] = np.broadcast_to(f[nm](x, y, z), L.shape3)
+    # analytic curl magnitude at the centres sets the amplitude (max |B| = 1)
+    gx = f["Ax"].grad(xc, yc, zc)
+    gy = f["Ay"].grad(xc, yc, zc)
+    gz = f["Az"].grad(xc, yc, zc)
+    Bx = gz[1] - gy[2]
+    By = gx[2] - gz[0]
+    Bz = gy[0] - gx[1]
+    curl_max = float(np.max(np.sqrt(Bx ** 2 + By ** 2 + Bz ** 2)))
+    A *= 1.0 / curl_max
+    L.periodic_wrap(A)
+    psi = L.zeros(1)
+    params = default_params(gamma=gamma, rho_atm=rho_atm, recon=recon)
+    dt = cfl * min(L.dx)
+    return Workload("curved%d" % nn[0], L, params, metric, curv, prim, A, psi, dt, nsteps, rk,
+                    ("periodic",) * 3, ("periodic",) * 3, dict(seed=seed, vscale=scale, a_B=1.0 / curl_max))
