@@ -1,0 +1,146 @@
+/* asterx.h -- C ABI of the MI355X (gfx950) library for the Valencia GRMHD right-hand side
+ * of AsterX (arXiv 2406.11669) on one 3-D Cartesian block with a given 3+1 metric.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.  Every array argument is a DEVICE pointer owned by the caller unless it is
+ *   documented as host memory.  The library keeps no pointer after a call returns and
+ *   never allocates or frees memory in these calls.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *   calls are asynchronous on it; none synchronizes the device.
+ * Errors.  Return 0 on success.  A negative value means an argument error detected on the
+ *   host before anything was launched (ASTERX_EARG) or a launch failure (ASTERX_ELAUNCH);
+ *   asterx_last_error() then returns a message (thread-local, valid until the next call).
+ *   Physical failures of the primitive recovery are not errors: they are counted in the
+ *   device-side statistics and per-cell flags.
+ * Layout (paper Sec. 3.1, storage locations).  All fields of a block share one padded
+ *   index space of extents ld[0] x ld[1] x ld[2], x fastest; field f of a multi-field
+ *   array starts at f * ld[0]*ld[1]*ld[2].  Index (i,j,k), i in [-ng, n+ng], is stored at
+ *   ((k+ng)*ld[1] + (j+ng))*ld[0] + (i+ng) and names: the cell centre (i,j,k); the x-face
+ *   (i-1/2,j,k), y-face (i,j-1/2,k), z-face (i,j,k-1/2); the x-edge (i,j-1/2,k-1/2),
+ *   y-edge (i-1/2,j,k-1/2), z-edge (i-1/2,j-1/2,k); the vertex (i-1/2,j-1/2,k-1/2).
+ *   Owned indices are 0..n-1 per axis; all others are ghosts, filled by the caller (or
+ *   asterx_fill_ghosts) before they are read.
+ * Field orders.
+ *   metric [10] at vertices: alpha, beta^x, beta^y, beta^z, g_xx, g_xy, g_xz, g_yy, g_yz, g_zz
+ *   curv   [6]  at vertices: K_xx, K_xy, K_xz, K_yy, K_yz, K_zz (extrinsic curvature)
+ *   prim   [5]  at centres : rho, p, v^x, v^y, v^z (Eulerian 3-velocity, contravariant)
+ *   cons   [5]  at centres : sqrt(gamma) (D, S_x, S_y, S_z, tau) (densitized, Sec. 2.2)
+ *   A      [3]  at edges   : A_x, A_y, A_z (vector potential, Sec. 2.3)
+ *   psi    [1]  at vertices: Psi_mhd = sqrt(gamma) Phi (Sec. 3.4)
+ *   state / rhs [9]        : cons (5), A (3), psi (1) in that order
+ */
+#ifndef ASTERX_H
+#define ASTERX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASTERX_OK 0
+#define ASTERX_EARG (-1)
+#define ASTERX_ELAUNCH (-2)
+
+enum { ASTERX_RECON_MINMOD = 0, ASTERX_RECON_PPM = 1, ASTERX_RECON_WENOZ = 2 };
+enum { ASTERX_GAUGE_LORENZ = 0, ASTERX_GAUGE_ALGEBRAIC = 1 };
+enum { ASTERX_SPEEDS_QUARTIC = 0, ASTERX_SPEEDS_BOUND = 1 };
+enum { ASTERX_C2P_NOBLE_PALENZUELA = 0, ASTERX_C2P_NOBLE_ONLY = 1, ASTERX_C2P_PALENZUELA_ONLY = 2 };
+enum { ASTERX_BC_PERIODIC = 0, ASTERX_BC_COPY = 1, ASTERX_BC_LINEAR = 2 };
+
+/* per-cell c2p flag bits */
+enum {
+  ASTERX_FLAG_NOBLE_FAIL = 1, ASTERX_FLAG_FALLBACK = 2, ASTERX_FLAG_ATMOSPHERE = 4,
+  ASTERX_FLAG_HARD_FAIL = 8, ASTERX_FLAG_NAN_IN = 16
+};
+
+/* Block geometry.  n: owned cells per axis (>= 1); ng: ghost layers (>= 3 for
+ * asterx_rhs, whose face stencils span six cells; >= 2 elsewhere); ld: allocated extents
+ * (>= n + 2 ng + 1; ld[0]*ld[1]*ld[2] below 2^31); dx: spacing. */
+typedef struct {
+  int32_t n[3];
+  int32_t ng;
+  int32_t ld[3];
+  int32_t pad_;
+  double dx[3];
+} asterx_grid;
+
+/* Method parameters (paper Secs. 3.3-3.7). */
+typedef struct {
+  double gamma;     /* ideal-gas adiabatic index (Sec. 3.7), > 1 */
+  double rho_atm;   /* atmosphere density floor (Sec. 3.6), >= 0 */
+  double k_atm;     /* polytropic constant of the atmosphere pressure p = K rho^Gamma */
+  double xi;        /* generalized-Lorenz damping in units of 1/dt_max (Sec. 3.4: 1.5) */
+  double c2p_tol;   /* Noble Newton tolerance on max(|dz/z|, |dw|) */
+  double wmax;      /* Lorentz-factor safety cap of the c2p clamps (> 1) */
+  double weno_eps;  /* WENO-Z epsilon */
+  double weno_q;    /* WENO-Z exponent (1 or 2) */
+  int32_t c2p_maxit;   /* Noble iteration cap */
+  int32_t brent_maxit; /* Brent iteration cap */
+  int32_t recon;       /* ASTERX_RECON_* */
+  int32_t gauge;       /* ASTERX_GAUGE_* */
+  int32_t speeds;      /* ASTERX_SPEEDS_* */
+  int32_t c2p_method;  /* ASTERX_C2P_* */
+} asterx_params;
+
+/* Device-side counters, accumulated (never reset) by asterx_c2p. */
+typedef struct {
+  unsigned long long noble_fail, fallback_used, atmosphere, hard_fail, nan_in, iters_max;
+} asterx_c2p_stats;
+
+int asterx_version(void);
+const char* asterx_last_error(void);
+
+/* Bytes of device workspace asterx_rhs needs for this grid. */
+size_t asterx_rhs_workspace_size(const asterx_grid* g);
+
+/* Primitive -> conserved map on owned cells (Sec. 2.2, conserved-variable definitions;
+ * Sec. 3.12: analytic initialisation of the conserved variables).  Reads metric at
+ * vertices i-1..i+2 (4th-order interpolation to the centre, Sec. 3.2) and A around the
+ * cell (centre field = average of the two faces of the curl, Sec. 3.1).  Writes cons on
+ * owned cells only. */
+int asterx_prim2con(const asterx_grid* g, const asterx_params* p, const double* metric, const double* A,
+                    const double* prim, double* cons, void* stream);
+
+/* Conservative-to-primitive recovery on owned cells (Sec. 3.5): Noble et al. 2D Newton in
+ * (z = rho h W^2, w = v^2) warm-started from `prim`, Palenzuela et al. 1D Brent fallback in
+ * x = h W, atmosphere (Sec. 3.6) when D < sqrt(gamma) rho_atm, when rho < rho_atm after
+ * recovery, or when both solvers fail.  In/out: cons (reset to the atmosphere state where
+ * applied), prim (guess in, result out).  flags: u8 per point (may be NULL).  stats:
+ * device asterx_c2p_stats (may be NULL), accumulated. */
+int asterx_c2p(const asterx_grid* g, const asterx_params* p, const double* metric, const double* A,
+               double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats, void* stream);
+
+/* Ghost fill of nf consecutive fields of f, axis by axis (x, then y, then z) over the full
+ * extent of the other axes, so edges and corners are filled.  kinds: host int[3], one
+ * ASTERX_BC_* per axis.  PERIODIC: index s maps to s mod n; COPY: nearest owned index;
+ * LINEAR: linear extrapolation from the two nearest owned indices. */
+int asterx_fill_ghosts(const asterx_grid* g, double* f, int32_t nf, const int32_t* kinds, void* stream);
+
+/* Right-hand side of the 9 evolved fields on owned points (Sec. 2.2 eq. fluxconseqs and
+ * grmhdsrc; Sec. 3.3 reconstruction + HLLE; Sec. 3.4 FCT electric field, gauge terms and
+ * the Psi equation; Sec. 3.12 workflow).  Reads prim on ng ghost layers, A on ng layers,
+ * psi and metric/curv on 2 layers.  dt_max sets xi = p->xi / dt_max.  red: device
+ * double[2] updated with max(red, value): [0] max characteristic speed over the faces of
+ * owned cells, [1] max |div Btilde| over owned cells (may be NULL).  workspace: device
+ * buffer of at least asterx_rhs_workspace_size(g) bytes. */
+int asterx_rhs(const asterx_grid* g, const asterx_params* p, const double* metric, const double* curv,
+               const double* prim, const double* A, const double* psi, double dt_max, double* rhs, double* red,
+               void* workspace, size_t ws_bytes, void* stream);
+
+/* Runge-Kutta stage combine on owned points of the 9 state fields:
+ * out = sum_m a[m] u[m] + b_dt rhs.  a: host double[nterms]; u: host array of nterms
+ * device pointers (each a 9-field state); 1 <= nterms <= 4; out may alias any u[m]. */
+int asterx_rk_stage(const asterx_grid* g, int32_t nterms, const double* a, const double* const* u, double b_dt,
+                    const double* rhs, double* out, void* stream);
+
+/* Sets red[0..1] to 0 (device double[2]); a kernel, not a memset, so that it can be
+ * recorded in a captured graph. */
+int asterx_zero(double* buf, int64_t count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASTERX_H */

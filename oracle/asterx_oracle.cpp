@@ -951,7 +951,7 @@ template <class T> void fill_ghosts(const Grid& g, T* f, int nf, const int kinds
             for (int t = 0; t < 3; ++t) { src0[t] = id[t]; src1[t] = id[t]; }
             T val;
             if (kinds[d] == BC_PERIODIC) {
-              src0[d] = s < 0 ? s + n : s - n;
+              src0[d] = ((s % n) + n) % n;  // periodic image (also for blocks thinner than the ghost width)
               val = F[at(g, src0[0], src0[1], src0[2])];
             } else if (kinds[d] == BC_COPY) {
               src0[d] = s < 0 ? 0 : n - 1;

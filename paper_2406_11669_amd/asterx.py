@@ -1,0 +1,236 @@
+"""Python binding of libasterx.so (C ABI in include/asterx.h): argument marshalling only.
+
+Every step of the right-hand side runs in the HIP kernels of the library.  torch is used
+for device memory (float64 CUDA tensors of shape (nfields, ld[2], ld[1], ld[0])) and for
+the current HIP stream.  There is no CPU fallback: if the library is not built, loading
+fails with an error.
+"""
+import ctypes
+import os
+
+import torch
+
+from . import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libasterx.so")
+
+RECON = {"minmod": 0, "ppm": 1, "wenoz": 2}
+GAUGE = {"lorenz": 0, "algebraic": 1}
+SPEEDS = {"quartic": 0, "bound": 1}
+BC = {"periodic": 0, "copy": 1, "linear": 2}
+FLAG_NOBLE_FAIL, FLAG_FALLBACK, FLAG_ATMOSPHERE, FLAG_HARD_FAIL, FLAG_NAN_IN = 1, 2, 4, 8, 16
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("ng", ctypes.c_int32), ("ld", ctypes.c_int32 * 3),
+                ("pad_", ctypes.c_int32), ("dx", ctypes.c_double * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("rho_atm", ctypes.c_double), ("k_atm", ctypes.c_double),
+                ("xi", ctypes.c_double), ("c2p_tol", ctypes.c_double), ("wmax", ctypes.c_double),
+                ("weno_eps", ctypes.c_double), ("weno_q", ctypes.c_double),
+                ("c2p_maxit", ctypes.c_int32), ("brent_maxit", ctypes.c_int32), ("recon", ctypes.c_int32),
+                ("gauge", ctypes.c_int32), ("speeds", ctypes.c_int32), ("c2p_method", ctypes.c_int32)]
+
+
+_lib = None
+
+EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "asterx_prim2con", "asterx_c2p",
+           "asterx_fill_ghosts", "asterx_rhs", "asterx_rk_stage", "asterx_zero"]
+
+
+def lib():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError("libasterx.so is not built: run `python -m paper_2406_11669_amd.build` "
+                               "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(LIB)
+        L.asterx_last_error.restype = ctypes.c_char_p
+        L.asterx_rhs_workspace_size.restype = ctypes.c_size_t
+        L.asterx_rhs_workspace_size.argtypes = [ctypes.c_void_p]
+        vp = ctypes.c_void_p
+        L.asterx_prim2con.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.asterx_c2p.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.asterx_fill_ghosts.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
+        L.asterx_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
+        L.asterx_rk_stage.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
+        L.asterx_zero.argtypes = [vp, ctypes.c_int64, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError("asterx error %d: %s" % (rc, lib().asterx_last_error().decode()))
+
+
+def make_grid(layout):
+    g = Grid()
+    for d in range(3):
+        g.n[d] = int(layout.n[d])
+        g.ld[d] = int(layout.ld[d])
+        g.dx[d] = float(layout.dx[d])
+    g.ng = int(layout.ng)
+    return g
+
+
+def make_params(p):
+    P = Params()
+    for k in ("gamma", "rho_atm", "k_atm", "xi", "c2p_tol", "wmax", "weno_eps", "weno_q"):
+        setattr(P, k, float(p[k]))
+    P.c2p_maxit = int(p["c2p_maxit"])
+    P.brent_maxit = int(p["brent_maxit"])
+    P.recon = RECON[p["recon"]] if isinstance(p["recon"], str) else int(p["recon"])
+    P.gauge = GAUGE[p["gauge"]] if isinstance(p["gauge"], str) else int(p["gauge"])
+    P.speeds = SPEEDS[p["speeds"]] if isinstance(p["speeds"], str) else int(p["speeds"])
+    P.c2p_method = int(p.get("c2p_method", 0))
+    return P
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _f64(t):
+    assert t.dtype == torch.float64, t.dtype
+    return t
+
+
+# ---- thin wrappers of the C entry points ------------------------------------------------------------------
+
+def workspace_size(layout):
+    return lib().asterx_rhs_workspace_size(ctypes.byref(make_grid(layout)))
+
+
+def prim2con(layout, params, metric, A, prim, cons, stream=None):
+    _check(lib().asterx_prim2con(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                                 _ptr(_f64(metric)), _ptr(_f64(A)), _ptr(_f64(prim)), _ptr(_f64(cons)),
+                                 _stream(stream)))
+
+
+def c2p(layout, params, metric, A, cons, prim, flags=None, stats=None, stream=None):
+    _check(lib().asterx_c2p(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                            _ptr(_f64(metric)), _ptr(_f64(A)), _ptr(_f64(cons)), _ptr(_f64(prim)), _ptr(flags),
+                            _ptr(stats), _stream(stream)))
+
+
+def fill_ghosts(layout, f, kinds, stream=None):
+    karr = (ctypes.c_int32 * 3)(*[BC[k] if isinstance(k, str) else int(k) for k in kinds])
+    nf = f.shape[0] if f.dim() == 4 else 1
+    _check(lib().asterx_fill_ghosts(ctypes.byref(make_grid(layout)), _ptr(_f64(f)), nf, karr, _stream(stream)))
+
+
+def rhs(layout, params, metric, curv, prim, A, psi, dt_max, out, red, workspace, stream=None):
+    _check(lib().asterx_rhs(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                            _ptr(_f64(metric)), _ptr(_f64(curv)), _ptr(_f64(prim)), _ptr(_f64(A)),
+                            _ptr(_f64(psi)), float(dt_max), _ptr(_f64(out)), _ptr(red), _ptr(workspace),
+                            workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def rk_stage(layout, a, us, b_dt, rhs_t, out, stream=None):
+    n = len(a)
+    arr_a = (ctypes.c_double * n)(*[float(x) for x in a])
+    arr_u = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+    for u in us:
+        assert u.is_cuda and u.is_contiguous() and u.dtype == torch.float64
+    _check(lib().asterx_rk_stage(ctypes.byref(make_grid(layout)), n, arr_a, arr_u, float(b_dt), _ptr(_f64(rhs_t)),
+                                 _ptr(_f64(out)), _stream(stream)))
+
+
+def zero(buf, stream=None):
+    _check(lib().asterx_zero(_ptr(buf), buf.numel(), _stream(stream)))
+
+
+# ---- a block advanced by whole RK steps (Sec. 3.12 workflow) ------------------------------------------------
+
+class Block:
+    """Device state of one block and the RK driver over the C ABI.
+
+    Per stage: c2p (resets atmosphere cells of the stage input in place) -> ghost fill of
+    the primitives -> right-hand side -> RK combine -> ghost fill of the new state.
+    RK2 is Heun's method, RK4 the classical scheme (accumulator form)."""
+
+    def __init__(self, wl, device="cuda"):
+        self.wl = wl
+        self.L = wl.layout
+        self.params = wl.params
+        dev = torch.device(device)
+        t = lambda a: torch.from_numpy(a).to(dev)
+        self.metric = t(wl.metric)
+        self.curv = t(wl.curv)
+        self.prim = t(wl.prim.copy())
+        shape = (9,) + self.L.shape3
+        self.state = torch.zeros(shape, dtype=torch.float64, device=dev)
+        self.state[5:8] = t(wl.A)
+        self.state[8] = t(wl.psi[0])
+        self.tmp = torch.zeros_like(self.state)
+        self.acc = torch.zeros_like(self.state)
+        self.k = torch.zeros_like(self.state)
+        self.ws = torch.empty(workspace_size(self.L) // 8, dtype=torch.float64, device=dev)
+        self.red = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.stats = torch.zeros(6, dtype=torch.int64, device=dev)
+        self.flags = torch.zeros(self.L.shape3, dtype=torch.uint8, device=dev)
+        self.dt = wl.dt
+        prim2con(self.L, self.params, self.metric, self.state[5:8], self.prim, self.state[0:5])
+        fill_ghosts(self.L, self.state[0:5], wl.bc_cell)
+
+    def fill_state(self, U):
+        fill_ghosts(self.L, U[0:5], self.wl.bc_cell)
+        fill_ghosts(self.L, U[5:8], self.wl.bc_A)
+        fill_ghosts(self.L, U[8:9], self.wl.bc_cell)
+
+    def eval_rhs(self, U, out):
+        """c2p on U (in place for atmosphere cells), primitive ghosts, right-hand side into out."""
+        c2p(self.L, self.params, self.metric, U[5:8], U[0:5], self.prim, self.flags, self.stats)
+        fill_ghosts(self.L, self.prim, self.wl.bc_cell)
+        rhs(self.L, self.params, self.metric, self.curv, self.prim, U[5:8], U[8:9], self.dt, out, self.red,
+            self.ws)
+
+    def step(self):
+        dt = self.dt
+        U0, K = self.state, self.k
+        if self.wl.rk == 2:
+            U1 = self.tmp
+            self.eval_rhs(U0, K)
+            rk_stage(self.L, [1.0], [U0], dt, K, U1)
+            self.fill_state(U1)
+            self.eval_rhs(U1, K)
+            rk_stage(self.L, [0.5, 0.5], [U0, U1], 0.5 * dt, K, U0)
+            self.fill_state(U0)
+        else:
+            Ut, acc = self.tmp, self.acc
+            self.eval_rhs(U0, K)
+            rk_stage(self.L, [1.0], [U0], 0.5 * dt, K, Ut)
+            rk_stage(self.L, [1.0], [U0], dt / 6.0, K, acc)
+            self.fill_state(Ut)
+            self.eval_rhs(Ut, K)
+            rk_stage(self.L, [1.0], [acc], dt / 3.0, K, acc)
+            rk_stage(self.L, [1.0], [U0], 0.5 * dt, K, Ut)
+            self.fill_state(Ut)
+            self.eval_rhs(Ut, K)
+            rk_stage(self.L, [1.0], [acc], dt / 3.0, K, acc)
+            rk_stage(self.L, [1.0], [U0], dt, K, Ut)
+            self.fill_state(Ut)
+            self.eval_rhs(Ut, K)
+            rk_stage(self.L, [1.0], [acc], dt / 6.0, K, U0)
+            self.fill_state(U0)
+
+    def run(self, nsteps):
+        for _ in range(nsteps):
+            self.step()
+
+    @property
+    def stages_per_step(self):
+        return 2 if self.wl.rk == 2 else 4

@@ -1,0 +1,545 @@
+// grmhd_device.h -- device-side physics of the Valencia GRMHD right-hand side (gfx950, FP64).
+//
+// Pointwise building blocks used by the kernels in asterx.hip: 3+1 geometry, ideal-gas
+// EOS, prim -> cons, fluxes, characteristic speeds, HLLE, reconstruction and the
+// conservative-to-primitive recovery.  Every routine works on one point in registers.
+// Section/equation references are to AsterX, arXiv 2406.11669.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DEV __device__ __forceinline__
+
+namespace ax {
+
+// Symmetric 3x3 storage: xx, xy, xz, yy, yz, zz.
+struct Geo {
+  double alp, beta[3];
+  double g[6];   // gamma_ij
+  double gu[6];  // gamma^ij
+  double sqrtg;
+};
+
+DEV void geo_from(const double m[10], Geo& G) {
+  G.alp = m[0];
+  G.beta[0] = m[1];
+  G.beta[1] = m[2];
+  G.beta[2] = m[3];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) G.g[c] = m[4 + c];
+  const double* g = G.g;
+  double c00 = g[3] * g[5] - g[4] * g[4];
+  double c01 = g[2] * g[4] - g[1] * g[5];
+  double c02 = g[1] * g[4] - g[2] * g[3];
+  double c11 = g[0] * g[5] - g[2] * g[2];
+  double c12 = g[1] * g[2] - g[0] * g[4];
+  double c22 = g[0] * g[3] - g[1] * g[1];
+  double det = g[0] * c00 + g[1] * c01 + g[2] * c02;
+  double idet = 1.0 / det;
+  G.gu[0] = c00 * idet;
+  G.gu[1] = c01 * idet;
+  G.gu[2] = c02 * idet;
+  G.gu[3] = c11 * idet;
+  G.gu[4] = c12 * idet;
+  G.gu[5] = c22 * idet;
+  G.sqrtg = sqrt(det);
+}
+
+DEV void lower(const double* g, const double v[3], double vl[3]) {
+  vl[0] = g[0] * v[0] + g[1] * v[1] + g[2] * v[2];
+  vl[1] = g[1] * v[0] + g[3] * v[1] + g[4] * v[2];
+  vl[2] = g[2] * v[0] + g[4] * v[1] + g[5] * v[2];
+}
+
+// Component (d, e) of a symmetric 3x3 in the 6-slot storage.
+DEV int sym(int d, int e) {
+  int a = d < e ? d : e, b = d < e ? e : d;
+  return a == 0 ? b : (a == 1 ? 2 + b : 5);
+}
+
+// ---------------------------------------------------------------------------------------
+// A fluid state with its magnetic field (Sec. 2.2, comoving field from the Eulerian one).
+// All quantities needed by fluxes and speeds, expressed through
+// W^-2 = 1 - v^2, B.v and B^2 (b^2 = B^2/W^2 + (B.v)^2, alpha b^0 = W B.v).
+struct State {
+  double rho, p, v[3], vl[3], iW2, W, B[3], Bl[3], B2, Bv, bsq, rhoh;
+};
+
+DEV void state_make(const Geo& G, const double pr[5], const double Bt[3], double gam, State& S) {
+  S.rho = pr[0];
+  S.p = pr[1];
+  S.v[0] = pr[2];
+  S.v[1] = pr[3];
+  S.v[2] = pr[4];
+  lower(G.g, S.v, S.vl);
+  double v2 = S.v[0] * S.vl[0] + S.v[1] * S.vl[1] + S.v[2] * S.vl[2];
+  S.iW2 = 1.0 - v2;
+  S.W = 1.0 / sqrt(S.iW2);
+  double is = 1.0 / G.sqrtg;
+  S.B[0] = Bt[0] * is;
+  S.B[1] = Bt[1] * is;
+  S.B[2] = Bt[2] * is;
+  lower(G.g, S.B, S.Bl);
+  S.B2 = S.B[0] * S.Bl[0] + S.B[1] * S.Bl[1] + S.B[2] * S.Bl[2];
+  S.Bv = S.B[0] * S.vl[0] + S.B[1] * S.vl[1] + S.B[2] * S.vl[2];
+  S.bsq = S.B2 * S.iW2 + S.Bv * S.Bv;
+  S.rhoh = S.rho + gam / (gam - 1.0) * S.p;  // rho h = rho (1 + eps) + p (ideal gas, Sec. 3.7)
+}
+
+// Densitized conserved variables, written with z = rho h W^2 (Sec. 3.5 rewriting of the
+// definitions): S_j = (z + B^2) v_j - (B.v) B_j, tau = z + B^2 - p - B^2/(2W^2) - (B.v)^2/2 - D.
+DEV void cons_of(const Geo& G, const State& S, double U[5]) {
+  double z = S.rhoh * S.W * S.W;
+  double D = S.rho * S.W;
+  double zb = z + S.B2;
+  U[0] = G.sqrtg * D;
+  U[1] = G.sqrtg * (zb * S.vl[0] - S.Bv * S.Bl[0]);
+  U[2] = G.sqrtg * (zb * S.vl[1] - S.Bv * S.Bl[1]);
+  U[3] = G.sqrtg * (zb * S.vl[2] - S.Bv * S.Bl[2]);
+  U[4] = G.sqrtg * (zb - S.p - 0.5 * (S.B2 * S.iW2 + S.Bv * S.Bv) - D);
+}
+
+// Conserved vector and flux along D (eq. grmhdeqs times alpha sqrt(gamma)):
+// 5 hydro components and the two transverse densitized induction components
+// (t1 = (D+1)%3, t2 = (D+2)%3): Btilde^t vt^D - Btilde^D vt^t.
+template <int D>
+DEV void flux_of(const Geo& G, const State& S, double U[7], double F[7]) {
+  constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  cons_of(G, S, U);
+  double vt[3];
+  vt[0] = G.alp * S.v[0] - G.beta[0];
+  vt[1] = G.alp * S.v[1] - G.beta[1];
+  vt[2] = G.alp * S.v[2] - G.beta[2];
+  double ptot = S.p + 0.5 * S.bsq;
+  double as = G.alp * G.sqrtg;
+  // b_j B^D / W = B_j B^D / W^2 + (B.v) v_j B^D ;  alpha b^0 B^D / W = (B.v) B^D
+  double BD = S.B[D];
+  double m1 = BD * S.iW2, m2 = S.Bv * BD;
+  F[0] = U[0] * vt[D];
+  F[1] = U[1] * vt[D] - as * (S.Bl[0] * m1 + S.vl[0] * m2);
+  F[2] = U[2] * vt[D] - as * (S.Bl[1] * m1 + S.vl[1] * m2);
+  F[3] = U[3] * vt[D] - as * (S.Bl[2] * m1 + S.vl[2] * m2);
+  F[1 + D] += as * ptot;
+  F[4] = U[4] * vt[D] + as * (ptot * S.v[D] - m2);
+  double Bt1 = G.sqrtg * S.B[t1], Bt2 = G.sqrtg * S.B[t2], BtD = G.sqrtg * BD;
+  F[5] = Bt1 * vt[D] - BtD * vt[t1];
+  F[6] = Bt2 * vt[D] - BtD * vt[t2];
+  U[5] = Bt1;
+  U[6] = Bt2;
+}
+
+// ---------------------------------------------------------------------------------------
+// Characteristic speeds along D (Sec. 3.3).  The fast-magnetosonic dispersion relation for
+// a front with covector (-lambda, e_D):
+//   rho h (1 - cs^2) a^4 - (rho h cs^2 + b^2) a^2 G + cs^2 bb^2 G = 0,
+// a = -lambda u^0 + u^D, bb = -lambda b^0 + b^D, G = g^00 lambda^2 - 2 g^0D lambda + g^DD,
+// expanded into a quartic in lambda and solved by Newton from the outer roots of the
+// isotropic bound (1 - w2) a^2 - w2 G = 0, w2 = cs^2 + cA^2 - cs^2 cA^2, inward.
+DEV void qroots(double qa, double qb, double qc, double& rp, double& rm) {
+  double disc = fmax(qb * qb - 4.0 * qa * qc, 0.0);
+  double sd = sqrt(disc);
+  double q = -0.5 * (qb + copysign(sd, qb));
+  double r1 = q / qa, r2 = qc / q;
+  if (q == 0.0) r1 = r2 = 0.0;
+  rp = fmax(r1, r2);
+  rm = fmin(r1, r2);
+}
+
+DEV double newton_root(const double c[5], double x) {
+  for (int it = 0; it < 30; ++it) {
+    double q = (((c[4] * x + c[3]) * x + c[2]) * x + c[1]) * x + c[0];
+    double dq = ((4.0 * c[4] * x + 3.0 * c[3]) * x + 2.0 * c[2]) * x + c[1];
+    if (dq == 0.0) break;
+    double s = q / dq;
+    x -= s;
+    if (fabs(s) <= 8.881784197001252e-16 * fmax(1.0, fabs(x))) break;
+  }
+  return x;
+}
+
+template <int D>
+DEV void speeds_of(const Geo& G, const State& S, double gam, int kind, double& cm, double& cp) {
+  double ia = 1.0 / G.alp;
+  double bD = G.beta[D];
+  double uD = S.W * (S.v[D] - bD * ia);
+  double u0 = S.W * ia;
+  double b0 = S.W * S.Bv * ia;
+  double bDc = (S.B[D] + G.alp * b0 * uD) / S.W;
+  double cs2 = gam * S.p / S.rhoh;
+  double cA2 = S.bsq / (S.rhoh + S.bsq);
+  double w2 = cs2 + cA2 - cs2 * cA2;
+  double ia2 = ia * ia;
+  double G0 = G.gu[sym(D, D)] - bD * bD * ia2, G1 = -2.0 * bD * ia2, G2 = -ia2;
+  double a0 = uD, a1 = -u0;
+  double om = 1.0 - w2;
+  double lp, lm;
+  qroots(om * a1 * a1 - w2 * G2, 2.0 * om * a0 * a1 - w2 * G1, om * a0 * a0 - w2 * G0, lp, lm);
+  if (kind == 1) {
+    cp = lp;
+    cm = lm;
+    return;
+  }
+  double A4 = S.rhoh * (1.0 - cs2), Bq = S.rhoh * cs2 + S.bsq, Cq = cs2;
+  // a^2 and bb^2 as quadratics, products with G as quartics
+  double s0 = a0 * a0, s1 = 2.0 * a0 * a1, s2 = a1 * a1;
+  double t0 = bDc * bDc, t1 = -2.0 * bDc * b0, t2 = b0 * b0;
+  double c[5];
+  // A4 a^4
+  c[0] = A4 * s0 * s0;
+  c[1] = A4 * 2.0 * s0 * s1;
+  c[2] = A4 * (s1 * s1 + 2.0 * s0 * s2);
+  c[3] = A4 * 2.0 * s1 * s2;
+  c[4] = A4 * s2 * s2;
+  // (-Bq a^2 + Cq bb^2) G
+  double r0 = -Bq * s0 + Cq * t0, r1 = -Bq * s1 + Cq * t1, r2 = -Bq * s2 + Cq * t2;
+  c[0] += r0 * G0;
+  c[1] += r0 * G1 + r1 * G0;
+  c[2] += r0 * G2 + r1 * G1 + r2 * G0;
+  c[3] += r1 * G2 + r2 * G1;
+  c[4] += r2 * G2;
+  cp = newton_root(c, lp);
+  cm = newton_root(c, lm);
+}
+
+// HLLE (Sec. 3.3, eq. HLLEfluxes).
+DEV void hlle7(const double UL[7], const double FL[7], double cmL, double cpL, const double UR[7],
+               const double FR[7], double cmR, double cpR, double Fo[7], double& smax) {
+  double cmax = fmax(0.0, fmax(cpL, cpR));
+  double cmin = -fmin(0.0, fmin(cmL, cmR));
+  double den = cmax + cmin;
+  smax = fmax(cmax, cmin);
+  if (den > 0.0) {
+    double id = 1.0 / den, cc = cmax * cmin;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) Fo[c] = (cmin * FR[c] + cmax * FL[c] - cc * (UR[c] - UL[c])) * id;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) Fo[c] = 0.5 * (FL[c] + FR[c]);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Reconstruction (Sec. 3.3) at the face between cells i-1 and i from a[0..5] = a_{i-3..i+2}:
+// L = right-face value of cell i-1, R = left-face value of cell i.
+DEV double mm(double x, double y) {
+  return (x * y > 0.0) ? copysign(fmin(fabs(x), fabs(y)), x) : 0.0;
+}
+
+DEV void rec_minmod(const double a[6], double& L, double& R) {
+  L = a[2] + 0.5 * mm(a[2] - a[1], a[3] - a[2]);
+  R = a[3] - 0.5 * mm(a[3] - a[2], a[4] - a[3]);
+}
+
+// Monotonized-central slope of PPM (Colella-Woodward).
+DEV double mc_slope(double am, double a0, double ap) {
+  double dl = a0 - am, dr = ap - a0;
+  if (dl * dr > 0.0) {
+    double dc = 0.5 * (ap - am);
+    return copysign(fmin(fabs(dc), 2.0 * fmin(fabs(dl), fabs(dr))), dc);
+  }
+  return 0.0;
+}
+
+// PPM cell parabola limited per Colella-Woodward; returns (left, right) face values of
+// the cell with neighbour face values fl (c-1/2) and fr (c+1/2).
+DEV void ppm_limit(double ac, double& fl, double& fr) {
+  if ((fr - ac) * (ac - fl) <= 0.0) {
+    fl = ac;
+    fr = ac;
+    return;
+  }
+  double dd = fr - fl;
+  double a6 = dd * (ac - 0.5 * (fl + fr));
+  double d2 = dd * dd * (1.0 / 6.0);
+  if (a6 > d2)
+    fl = 3.0 * ac - 2.0 * fr;
+  else if (-d2 > a6)
+    fr = 3.0 * ac - 2.0 * fl;
+}
+
+DEV void rec_ppm(const double a[6], double& L, double& R) {
+  // slopes of cells i-2 .. i+1 (a[1..4])
+  double s1 = mc_slope(a[0], a[1], a[2]);
+  double s2 = mc_slope(a[1], a[2], a[3]);
+  double s3 = mc_slope(a[2], a[3], a[4]);
+  double s4 = mc_slope(a[3], a[4], a[5]);
+  const double sixth = 1.0 / 6.0;
+  // unlimited face values at i-3/2, i-1/2, i+1/2
+  double fm = 0.5 * (a[1] + a[2]) - (s2 - s1) * sixth;
+  double f0 = 0.5 * (a[2] + a[3]) - (s3 - s2) * sixth;
+  double fp = 0.5 * (a[3] + a[4]) - (s4 - s3) * sixth;
+  double l1 = fm, r1 = f0;  // cell i-1
+  ppm_limit(a[2], l1, r1);
+  double l2 = f0, r2 = fp;  // cell i
+  ppm_limit(a[3], l2, r2);
+  L = r1;
+  R = l2;
+}
+
+// WENO-Z (Borges et al. 2008) value at the right face of the middle cell of (m2..p2).
+DEV double wenoz_face(double m2, double m1, double c0, double p1, double p2, double eps, double q) {
+  const double t13 = 13.0 / 12.0;
+  double e0 = m2 - 2.0 * m1 + c0, f0 = m2 - 4.0 * m1 + 3.0 * c0;
+  double e1 = m1 - 2.0 * c0 + p1, f1 = m1 - p1;
+  double e2 = c0 - 2.0 * p1 + p2, f2 = 3.0 * c0 - 4.0 * p1 + p2;
+  double b0 = t13 * e0 * e0 + 0.25 * f0 * f0;
+  double b1 = t13 * e1 * e1 + 0.25 * f1 * f1;
+  double b2 = t13 * e2 * e2 + 0.25 * f2 * f2;
+  double tau = fabs(b0 - b2);
+  double r0 = tau / (b0 + eps), r1 = tau / (b1 + eps), r2 = tau / (b2 + eps);
+  if (q != 1.0) {
+    r0 = pow(r0, q);
+    r1 = pow(r1, q);
+    r2 = pow(r2, q);
+  }
+  double w0 = 0.1 * (1.0 + r0), w1 = 0.6 * (1.0 + r1), w2 = 0.3 * (1.0 + r2);
+  double q0 = (2.0 * m2 - 7.0 * m1 + 11.0 * c0), q1 = (-m1 + 5.0 * c0 + 2.0 * p1), q2 = (2.0 * c0 + 5.0 * p1 - p2);
+  return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0 * (w0 + w1 + w2));
+}
+
+DEV void rec_wenoz(const double a[6], double& L, double& R, double eps, double q) {
+  L = wenoz_face(a[0], a[1], a[2], a[3], a[4], eps, q);
+  R = wenoz_face(a[5], a[4], a[3], a[2], a[1], eps, q);
+}
+
+DEV void reconstruct(int kind, const double a[6], double& L, double& R, double eps, double q) {
+  if (kind == 0)
+    rec_minmod(a, L, R);
+  else if (kind == 1)
+    rec_ppm(a, L, R);
+  else
+    rec_wenoz(a, L, R, eps, q);
+}
+
+// ---------------------------------------------------------------------------------------
+// Conservative-to-primitive recovery (Sec. 3.5) and atmosphere (Sec. 3.6).
+struct C2PParams {
+  double gam, rho_atm, k_atm, tol, wmax;
+  int maxit, brent_maxit, method;
+};
+
+struct C2PIn {
+  double D, S[3], tau, B[3], S2, B2, BS;
+};
+
+// Noble residuals (eqs. Noble2D momentum, Noble2D energy) with p(z, w) of the ideal gas
+// and their Jacobian; solved by Newton with the 2x2 inverse.
+DEV bool noble(const Geo& G, const C2PIn& c, const C2PParams& P, double z, double w, double out[5], int& iters) {
+  const double gm = (P.gam - 1.0) / P.gam;
+  const double wcap = 1.0 - 1.0 / (P.wmax * P.wmax);
+  const double BS2 = c.BS * c.BS;
+  bool ok = false;
+  iters = 0;
+  for (int it = 1; it <= P.maxit; ++it) {
+    iters = it;
+    double sw = sqrt(1.0 - w);
+    double iz = 1.0 / z;
+    double iz2 = iz * iz;
+    double Bz = c.B2 + z;
+    double p = gm * (z * (1.0 - w) - c.D * sw);
+    double R1 = w * Bz * Bz - BS2 * (c.B2 + 2.0 * z) * iz2 - c.S2;
+    double R2 = c.tau + c.D - 0.5 * c.B2 * (1.0 + w) + 0.5 * BS2 * iz2 - z + p;
+    double J11 = 2.0 * Bz * (w + BS2 * iz2 * iz);
+    double J12 = Bz * Bz;
+    double J21 = -BS2 * iz2 * iz - 1.0 + gm * (1.0 - w);
+    double J22 = -0.5 * c.B2 + gm * (-z + 0.5 * c.D / sw);
+    double idet = 1.0 / (J11 * J22 - J12 * J21);
+    double dz = (J12 * R2 - J22 * R1) * idet;
+    double dw = (J21 * R1 - J11 * R2) * idet;
+    z += dz;
+    w = fmin(fmax(w + dw, 0.0), wcap);
+    if (!(z > 0.0) || !isfinite(z) || !isfinite(w)) return false;
+    if (fmax(fabs(dz) / z, fabs(dw)) < P.tol) {
+      ok = true;
+      break;
+    }
+  }
+  if (!ok) return false;
+  double W2 = 1.0 / (1.0 - w);
+  double W = sqrt(W2);
+  double rho = c.D / W;
+  double eps = (z / (rho * W2) - 1.0) / P.gam;
+  double p = (P.gam - 1.0) * rho * eps;
+  if (!(eps >= 0.0) || !isfinite(p)) return false;
+  double izb = 1.0 / (z + c.B2), fB = c.BS * izb / z;
+  out[0] = rho;
+  out[1] = p;
+  out[2] = (G.gu[0] * c.S[0] + G.gu[1] * c.S[1] + G.gu[2] * c.S[2]) * izb + fB * c.B[0];
+  out[3] = (G.gu[1] * c.S[0] + G.gu[3] * c.S[1] + G.gu[4] * c.S[2]) * izb + fB * c.B[1];
+  out[4] = (G.gu[2] * c.S[0] + G.gu[4] * c.S[1] + G.gu[5] * c.S[2]) * izb + fB * c.B[2];
+  return true;
+}
+
+// Palenzuela et al. master function in x = h W (eqs. Palenzuela qrst, Palenzuela Brent;
+// the eps expression with t^2/x^2, see the oracle and design notes).
+struct Palen {
+  double q, r, s, t2, D, gam, iw2min;
+};
+
+DEV double palen_f(const Palen& P, double x, double& W, double& rho, double& eps, double& p) {
+  double xs = x + P.s;
+  double v2 = (P.r * x * x + P.t2 * (2.0 * x + P.s)) / (x * x * xs * xs);
+  double iW2 = fmax(1.0 - v2, P.iw2min);
+  W = 1.0 / sqrt(iW2);
+  rho = P.D / W;
+  eps = -1.0 + (x / W) * (1.0 - W * W) + W * (1.0 + P.q - P.s + 0.5 * (P.t2 / (x * x) + P.s * iW2));
+  p = (P.gam - 1.0) * rho * eps;
+  return x - (1.0 + eps + p / rho) * W;
+}
+
+// Brent's method (1973): bracketing with inverse quadratic / secant steps and bisection.
+DEV bool palenzuela(const Geo& G, const C2PIn& c, const C2PParams& CP, double out[5]) {
+  Palen P;
+  P.D = c.D;
+  P.q = c.tau / c.D;
+  P.r = c.S2 / (c.D * c.D);
+  P.s = c.B2 / c.D;
+  P.t2 = c.BS * c.BS / (c.D * c.D * c.D);
+  P.gam = CP.gam;
+  P.iw2min = 1.0 / (CP.wmax * CP.wmax);
+  double lo = fmax(1.0 + P.q - P.s, 1.0), hi = 2.0 + 2.0 * P.q - P.s;
+  if (!(hi > lo)) return false;
+  double W, rho, eps, p;
+  double a = lo, b = hi;
+  double fa = palen_f(P, a, W, rho, eps, p);
+  double fb = palen_f(P, b, W, rho, eps, p);
+  if (!isfinite(fa) || !isfinite(fb)) return false;
+  if ((fa > 0.0 && fb > 0.0) || (fa < 0.0 && fb < 0.0)) return false;
+  double cc = a, fc = fa, d = b - a, e = d;
+  bool conv = false;
+  for (int it = 0; it < CP.brent_maxit; ++it) {
+    if ((fb > 0.0 && fc > 0.0) || (fb < 0.0 && fc < 0.0)) {
+      cc = a;
+      fc = fa;
+      d = e = b - a;
+    }
+    if (fabs(fc) < fabs(fb)) {
+      a = b; fa = fb;
+      b = cc; fb = fc;
+      cc = a; fc = fa;
+    }
+    double tol = 4.440892098500626e-16 * fabs(b);
+    double m = 0.5 * (cc - b);
+    if (fabs(m) <= tol || fb == 0.0) {
+      conv = true;
+      break;
+    }
+    if (fabs(e) >= tol && fabs(fa) > fabs(fb)) {
+      double s = fb / fa, pp, qq;
+      if (a == cc) {
+        pp = 2.0 * m * s;
+        qq = 1.0 - s;
+      } else {
+        double qa = fa / fc, r = fb / fc;
+        pp = s * (2.0 * m * qa * (qa - r) - (b - a) * (r - 1.0));
+        qq = (qa - 1.0) * (r - 1.0) * (s - 1.0);
+      }
+      if (pp > 0.0) qq = -qq; else pp = -pp;
+      if (2.0 * pp < fmin(3.0 * m * qq - fabs(tol * qq), fabs(e * qq))) {
+        e = d;
+        d = pp / qq;
+      } else {
+        d = m;
+        e = m;
+      }
+    } else {
+      d = m;
+      e = m;
+    }
+    a = b;
+    fa = fb;
+    b += (fabs(d) > tol) ? d : copysign(tol, m);
+    fb = palen_f(P, b, W, rho, eps, p);
+    if (!isfinite(fb)) return false;
+  }
+  if (!conv) return false;
+  palen_f(P, b, W, rho, eps, p);
+  if (!(eps >= 0.0) || !isfinite(p)) return false;
+  double z = c.D * b;
+  double izb = 1.0 / (z + c.B2), fB = c.BS * izb / z;
+  out[0] = rho;
+  out[1] = p;
+  out[2] = (G.gu[0] * c.S[0] + G.gu[1] * c.S[1] + G.gu[2] * c.S[2]) * izb + fB * c.B[0];
+  out[3] = (G.gu[1] * c.S[0] + G.gu[3] * c.S[1] + G.gu[4] * c.S[2]) * izb + fB * c.B[1];
+  out[4] = (G.gu[2] * c.S[0] + G.gu[4] * c.S[1] + G.gu[5] * c.S[2]) * izb + fB * c.B[2];
+  return true;
+}
+
+// Atmosphere state and its conserved variables (field kept).
+DEV void atmo(const Geo& G, const double Bt[3], const C2PParams& P, double pr[5], double U[5]) {
+  pr[0] = P.rho_atm;
+  pr[1] = P.k_atm * pow(P.rho_atm, P.gam);
+  pr[2] = pr[3] = pr[4] = 0.0;
+  State S;
+  state_make(G, pr, Bt, P.gam, S);
+  cons_of(G, S, U);
+}
+
+// Full recovery at a point.  U: densitized conserved (in/out), prev: warm start.
+DEV uint32_t c2p_point(const Geo& G, double U[5], const double Bt[3], const double prev[5], const C2PParams& P,
+                       double out[5], int& iters) {
+  uint32_t fl = 0;
+  iters = 0;
+  bool nan_in = !(isfinite(U[0]) && isfinite(U[1]) && isfinite(U[2]) && isfinite(U[3]) && isfinite(U[4]));
+  if (nan_in || !(U[0] >= G.sqrtg * P.rho_atm)) {
+    fl = 4u | (nan_in ? 16u : 0u);
+    atmo(G, Bt, P, out, U);
+    return fl;
+  }
+  double is = 1.0 / G.sqrtg;
+  C2PIn c;
+  c.D = U[0] * is;
+  c.S[0] = U[1] * is;
+  c.S[1] = U[2] * is;
+  c.S[2] = U[3] * is;
+  c.tau = U[4] * is;
+  c.B[0] = Bt[0] * is;
+  c.B[1] = Bt[1] * is;
+  c.B[2] = Bt[2] * is;
+  double Su[3];
+  Su[0] = G.gu[0] * c.S[0] + G.gu[1] * c.S[1] + G.gu[2] * c.S[2];
+  Su[1] = G.gu[1] * c.S[0] + G.gu[3] * c.S[1] + G.gu[4] * c.S[2];
+  Su[2] = G.gu[2] * c.S[0] + G.gu[4] * c.S[1] + G.gu[5] * c.S[2];
+  c.S2 = Su[0] * c.S[0] + Su[1] * c.S[1] + Su[2] * c.S[2];
+  double Bl[3];
+  lower(G.g, c.B, Bl);
+  c.B2 = c.B[0] * Bl[0] + c.B[1] * Bl[1] + c.B[2] * Bl[2];
+  c.BS = c.B[0] * c.S[0] + c.B[1] * c.S[1] + c.B[2] * c.S[2];
+  bool ok = false;
+  const double wcap = 1.0 - 1.0 / (P.wmax * P.wmax);
+  if (P.method != 2) {
+    // warm start from the previous primitives, cold start if they are unusable
+    double vl[3], v[3] = {prev[2], prev[3], prev[4]};
+    lower(G.g, v, vl);
+    double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
+    double z0, w0;
+    if (prev[0] > 0.0 && prev[1] >= 0.0 && v2 < wcap && isfinite(v2) && isfinite(prev[1])) {
+      double rhoh = prev[0] + P.gam / (P.gam - 1.0) * prev[1];
+      z0 = rhoh / (1.0 - v2);
+      w0 = v2;
+    } else {
+      z0 = c.tau + c.D;
+      double den = z0 + c.B2;
+      w0 = fmin(c.S2 / (den * den), wcap);
+    }
+    ok = noble(G, c, P, z0, w0, out, iters);
+    if (!ok) fl |= 1u;
+  }
+  if (!ok && P.method != 1) {
+    ok = palenzuela(G, c, P, out);
+    if (ok && P.method == 0) fl |= 2u;
+  }
+  if (!ok) {
+    fl |= 8u | 4u;
+    atmo(G, Bt, P, out, U);
+    return fl;
+  }
+  if (out[0] < P.rho_atm) {
+    fl |= 4u;
+    atmo(G, Bt, P, out, U);
+  }
+  return fl;
+}
+
+}  // namespace ax

@@ -1,0 +1,96 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry point declared in include/asterx.h,
+matches the header's struct layouts, and rejects bad arguments on the host before any launch."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "asterx.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|size_t|const char\*)\s+(asterx_[a-z0-9_]+)\s*\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2406_11669_amd import asterx
+    if not os.path.exists(asterx.LIB):
+        from paper_2406_11669_amd import build
+        build.build()
+    return asterx.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "asterx_rhs" in names and "asterx_c2p" in names and "asterx_rk_stage" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header(tmp_path):
+    from paper_2406_11669_amd import asterx
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "asterx.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(asterx_grid), '
+                   'offsetof(asterx_grid, dx), sizeof(asterx_params), offsetof(asterx_params, c2p_maxit), '
+                   'offsetof(asterx_params, c2p_method), sizeof(asterx_c2p_stats), '
+                   'offsetof(asterx_params, weno_q));return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert vals == [ctypes.sizeof(asterx.Grid), asterx.Grid.dx.offset, ctypes.sizeof(asterx.Params),
+                    asterx.Params.c2p_maxit.offset, asterx.Params.c2p_method.offset, 48,
+                    asterx.Params.weno_q.offset]
+
+
+def test_host_side_argument_validation(lib):
+    from paper_2406_11669_amd import asterx
+    from paper_2406_11669_amd.workloads import Layout, default_params
+    L = Layout((8, 8, 8), 3)
+    g = asterx.make_grid(L)
+    p = asterx.make_params(default_params(recon="ppm"))
+    dummy = ctypes.c_void_p(16)
+    # too few ghost layers for PPM
+    g2 = asterx.make_grid(Layout((8, 8, 8), 2))
+    rc = lib.asterx_rhs(ctypes.byref(g2), ctypes.byref(p), dummy, dummy, dummy, dummy, dummy, 0.01, dummy, None,
+                        dummy, 1 << 40, None)
+    assert rc == -1 and b"ghost" in lib.asterx_last_error()
+    # workspace too small
+    rc = lib.asterx_rhs(ctypes.byref(g), ctypes.byref(p), dummy, dummy, dummy, dummy, dummy, 0.01, dummy, None,
+                        dummy, 8, None)
+    assert rc == -1 and b"workspace" in lib.asterx_last_error()
+    # bad gamma
+    p.gamma = 1.0
+    rc = lib.asterx_c2p(ctypes.byref(g), ctypes.byref(p), dummy, dummy, dummy, dummy, None, None, None)
+    assert rc == -1 and b"gamma" in lib.asterx_last_error()
+    # ld too small
+    g.ld[1] = 10
+    rc = lib.asterx_fill_ghosts(ctypes.byref(g), dummy, 1, (ctypes.c_int32 * 3)(0, 0, 0), None)
+    assert rc == -1 and b"ld" in lib.asterx_last_error()
+    assert lib.asterx_rhs_workspace_size(ctypes.byref(asterx.make_grid(L))) == 28 * 8 * L.npts
+
+
+def test_oracle_ghost_fill_matches_definitions(orc):
+    import numpy as np
+    from paper_2406_11669_amd.workloads import Layout
+    L = Layout((2, 5, 4), 3)
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=(1,) + L.shape3)
+    ref = a.copy()
+    L.periodic_wrap(ref)
+    b = a.copy()
+    orc.fill_ghosts(L, b, ["periodic"] * 3)
+    ext = L.n[0] + 2 * L.ng + 1
+    assert np.array_equal(b[..., :ext], ref[..., :ext])
+    c = a.copy()
+    orc.fill_ghosts(L, c, ["linear"] * 3)
+    o = L.owned(c)[0]
+    g = L.ng
+    # linear extrapolation along z below the block, at an owned (i, j)
+    k0, k1 = c[0, g, g + 1, g + 1], c[0, g + 1, g + 1, g + 1]
+    assert np.isclose(c[0, g - 2, g + 1, g + 1], k0 - 2 * (k1 - k0), rtol=1e-14)

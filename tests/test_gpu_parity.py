@@ -1,0 +1,243 @@
+"""GPU parity: the HIP library (through its C ABI) against the serial CPU oracle on the same seeded inputs.
+
+Tolerances: 1e-12 relative per cell per stage (cancellation-aware scale, see tests/parity.py) and 1e-10 after
+several steps; integer outputs (flags, counters) and pure data movement (ghost fill) bit-exact."""
+import numpy as np
+import pytest
+
+from paper_2406_11669_amd import workloads as W
+from tests.parity import assert_fields_close
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+STATE_NAMES = ["D", "Sx", "Sy", "Sz", "tau", "Ax", "Ay", "Az", "Psi"]
+PRIM_NAMES = ["rho", "p", "vx", "vy", "vz"]
+
+
+@pytest.fixture(scope="module")
+def ax():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_11669_amd import asterx
+    asterx.lib()
+    return asterx
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def test_library_exports(ax):
+    assert ax.lib().asterx_version() == 1
+
+
+@pytest.mark.parametrize("shape", [(70, 9, 7), (13, 11, 9)])
+def test_prim2con_parity(ax, torch_mod, orc, shape):
+    w = W.curved_block(seed=11, n=shape, recon="ppm")
+    L = w.layout
+    print("case prim2con", shape, flush=True)
+    ref = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+    cons = torch_mod.zeros((5,) + L.shape3, dtype=torch_mod.float64, device="cuda")
+    ax.prim2con(L, w.params, _dev(torch_mod, w.metric), _dev(torch_mod, w.A), _dev(torch_mod, w.prim), cons)
+    torch_mod.cuda.synchronize()
+    assert_fields_close(_host(cons), ref, 1e-13, L.owned, PRIM_NAMES)
+
+
+def _c2p_case(orc, seed, shape, inject):
+    w = W.curved_block(seed=seed, n=shape, recon="ppm", rho_atm=1e-6)
+    L = w.layout
+    cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+    rng = np.random.default_rng(seed)
+    guess = w.prim * (1.0 + rng.uniform(-0.02, 0.02, w.prim.shape))
+    if inject:
+        o = L.owned
+        c = o(cons)
+        c[2, 1, 1, 1] = np.nan                      # NaN input
+        c[1:4, 2, 3, 4] *= 50.0                     # momentum beyond energy: no solution
+        c[0, 3, 2, 1] = 1e-9                        # below the density floor
+        c[4, 4, 4, 2] = -abs(c[4, 4, 4, 2])         # negative energy
+        o(guess)[:, 5, 5, 5] = 0.0                  # unusable warm start -> cold start
+    return w, L, cons, guess
+
+
+@pytest.mark.parametrize("inject", [False, True])
+def test_c2p_parity(ax, torch_mod, orc, inject):
+    torch = torch_mod
+    w, L, cons, guess = _c2p_case(orc, 12, (70, 9, 7), inject)
+    print("case c2p inject=%s" % inject, flush=True)
+    c_ref, p_ref = cons.copy(), guess.copy()
+    fl_ref, st_ref = orc.c2p(L, w.params, w.metric, w.A, c_ref, p_ref)
+    c_g, p_g = _dev(torch, cons), _dev(torch, guess)
+    flags = torch.zeros(L.shape3, dtype=torch.uint8, device="cuda")
+    stats = torch.zeros(6, dtype=torch.int64, device="cuda")
+    ax.c2p(L, w.params, _dev(torch, w.metric), _dev(torch, w.A), c_g, p_g, flags, stats)
+    torch.cuda.synchronize()
+    assert np.array_equal(L.owned(_host(flags)), L.owned(fl_ref))
+    st = _host(stats).astype(np.uint64)
+    assert np.array_equal(st[:5], st_ref[:5]), (st, st_ref)
+    assert_fields_close(_host(p_g), p_ref, 1e-12, L.owned, PRIM_NAMES)
+    assert_fields_close(_host(c_g), c_ref, 1e-13, L.owned, PRIM_NAMES)
+    if inject:
+        assert st_ref[2] >= 4 and st_ref[3] >= 1 and st_ref[4] == 1
+
+
+@pytest.mark.parametrize("kinds", [("periodic",) * 3, ("copy",) * 3, ("linear",) * 3, ("periodic", "copy", "linear")])
+def test_fill_ghosts_bitwise(ax, torch_mod, orc, kinds):
+    L = W.Layout((10, 7, 5))
+    rng = np.random.default_rng(13)
+    a = rng.normal(size=(3,) + L.shape3)
+    ref = a.copy()
+    orc.fill_ghosts(L, ref, kinds)
+    t = _dev(torch_mod, a)
+    ax.fill_ghosts(L, t, kinds)
+    torch_mod.cuda.synchronize()
+    g = _host(t)
+    ext = L.n[0] + 2 * L.ng + 1
+    assert np.array_equal(g[..., :ext], ref[..., :ext])
+
+
+def test_rk_stage_parity(ax, torch_mod, orc):
+    L = W.Layout((10, 7, 5))
+    rng = np.random.default_rng(14)
+    us = [rng.normal(size=(9,) + L.shape3) for _ in range(3)]
+    r = rng.normal(size=(9,) + L.shape3)
+    a = [0.25, 0.5, 0.25]
+    ref = np.zeros_like(r)
+    orc.rk_stage(L, a, us, 0.013, r, ref)
+    out = torch_mod.zeros((9,) + L.shape3, dtype=torch_mod.float64, device="cuda")
+    ax.rk_stage(L, a, [_dev(torch_mod, u) for u in us], 0.013, _dev(torch_mod, r), out)
+    torch_mod.cuda.synchronize()
+    assert_fields_close(_host(out), ref, 1e-15, L.owned)
+
+
+def _rhs_case(ax, torch, orc, w):
+    L = w.layout
+    cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+    ref, red_ref, _ = orc.rhs(L, w.params, w.metric, w.curv, w.prim, w.A, w.psi, w.dt)
+    out = torch.zeros((9,) + L.shape3, dtype=torch.float64, device="cuda")
+    red = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ws = torch.empty(ax.workspace_size(L) // 8, dtype=torch.float64, device="cuda")
+    ax.rhs(L, w.params, _dev(torch, w.metric), _dev(torch, w.curv), _dev(torch, w.prim), _dev(torch, w.A),
+           _dev(torch, w.psi), w.dt, out, red, ws)
+    torch.cuda.synchronize()
+    return _host(out), ref, _host(red), red_ref
+
+
+@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz"])
+@pytest.mark.parametrize("shape", [(70, 9, 7), (13, 11, 9)])
+def test_rhs_parity_curved(ax, torch_mod, orc, recon, shape):
+    w = W.curved_block(seed=15, n=shape, recon=recon)
+    w.psi = w.layout.zeros(1) + 0.01 * np.random.default_rng(3).normal(size=(1,) + w.layout.shape3)
+    print("case rhs", recon, shape, flush=True)
+    g, c, red, red_ref = _rhs_case(ax, torch_mod, orc, w)
+    assert_fields_close(g, c, 1e-12, w.layout.owned, STATE_NAMES)
+    assert abs(red[0] - red_ref[0]) <= 1e-12 * red_ref[0]
+    assert red[1] <= 1e-12 * 1e3 and red_ref[1] <= 1e-12 * 1e3
+
+
+def test_rhs_parity_riemann32(ax, torch_mod, orc):
+    w = W.riemann_block(seed=16, n=32)
+    print("case rhs riemann32", flush=True)
+    g, c, red, red_ref = _rhs_case(ax, torch_mod, orc, w)
+    assert_fields_close(g, c, 1e-12, w.layout.owned, STATE_NAMES)
+
+
+def _run_both(ax, torch, orc, w, nsteps):
+    L = w.layout
+    blk = ax.Block(w)
+    blk.run(nsteps)
+    torch.cuda.synchronize()
+    cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+    orc.fill_ghosts(L, cons, w.bc_cell)
+    state = w.state(cons)
+    prim = w.prim.copy()
+    flags, stats, red = orc.run(L, w.params, w.metric, w.curv, state, prim, w.dt, nsteps, w.rk, w.bc_cell, w.bc_A)
+    return blk, state, prim, stats, red
+
+
+def test_steps_parity_riemann32(ax, torch_mod, orc):
+    """The 32^3 Riemann-problem workload, 10 RK2 steps: state and primitives within 1e-10."""
+    w = W.riemann_block(seed=17, n=32, nsteps=10)
+    print("case steps riemann32", flush=True)
+    blk, state, prim, stats, red = _run_both(ax, torch_mod, orc, w, 10)
+    assert_fields_close(_host(blk.state), state, 1e-10, w.layout.owned, STATE_NAMES)
+    assert_fields_close(_host(blk.prim), prim, 1e-10, w.layout.owned, PRIM_NAMES)
+    st = _host(blk.stats)
+    assert st[3] == 0 and stats[3] == 0
+
+
+@pytest.mark.parametrize("recon", ["ppm", "wenoz"])
+def test_steps_parity_curved(ax, torch_mod, orc, recon):
+    w = W.curved_block(seed=18, n=(20, 13, 11), recon=recon, nsteps=2)
+    print("case steps curved", recon, flush=True)
+    blk, state, prim, stats, red = _run_both(ax, torch_mod, orc, w, 2)
+    assert_fields_close(_host(blk.state), state, 1e-10, w.layout.owned, STATE_NAMES)
+    assert_fields_close(_host(blk.prim), prim, 1e-10, w.layout.owned, PRIM_NAMES)
+
+
+@pytest.mark.parametrize("recon", ["ppm"])
+def test_full_size_curved128_first_stage(ax, torch_mod, orc, recon):
+    """The 128^3 curved workload at full size in the benchmark's launch configuration: c2p of the initial
+    state and one right-hand side, every owned cell against the oracle."""
+    torch = torch_mod
+    w = W.curved_block(seed=0, n=128, recon=recon)
+    L = w.layout
+    print("case full-size 128", recon, flush=True)
+    blk = ax.Block(w)
+    blk.eval_rhs(blk.state, blk.k)
+    torch.cuda.synchronize()
+    cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+    prim = w.prim.copy()
+    orc.c2p(L, w.params, w.metric, w.A, cons, prim)
+    orc.fill_ghosts(L, prim, w.bc_cell)
+    assert_fields_close(_host(blk.prim), prim, 1e-12, L.owned, PRIM_NAMES)
+    ref, red_ref, _ = orc.rhs(L, w.params, w.metric, w.curv, prim, w.A, w.psi, w.dt)
+    assert_fields_close(_host(blk.k), ref, 1e-12, L.owned, STATE_NAMES)
+
+
+# ---------------------------------------------------------------- invariants on the GPU path
+
+
+def test_gpu_uniform_state_hydro_rhs_bitwise_zero(ax, torch_mod, orc):
+    from tests.test_oracle_grid import _uniform_setup
+    L, m10, metric, prim, A, Bt = _uniform_setup(n=8)
+    for recon in ("minmod", "ppm", "wenoz"):
+        P = W.default_params(recon=recon)
+        torch = torch_mod
+        out = torch.zeros((9,) + L.shape3, dtype=torch.float64, device="cuda")
+        ws = torch.empty(ax.workspace_size(L) // 8, dtype=torch.float64, device="cuda")
+        red = torch.zeros(2, dtype=torch.float64, device="cuda")
+        ax.rhs(L, P, _dev(torch, metric), torch.zeros((6,) + L.shape3, dtype=torch.float64, device="cuda"),
+               _dev(torch, prim), _dev(torch, A), torch.zeros((1,) + L.shape3, dtype=torch.float64, device="cuda"),
+               0.01, out, red, ws)
+        torch.cuda.synchronize()
+        assert np.all(L.owned(_host(out)[0:5]) == 0.0)
+        assert _host(red)[1] == 0.0
+
+
+def test_gpu_determinism_and_conservation(ax, torch_mod):
+    import math
+    w = W.curved_block(seed=19, n=16, recon="ppm", nsteps=2)
+    L = w.layout
+    a = ax.Block(w)
+    b = ax.Block(w)
+    D0 = math.fsum(L.owned(_host(a.state)[0]).ravel())
+    a.run(2)
+    b.run(2)
+    torch_mod.cuda.synchronize()
+    sa, sb = _host(a.state), _host(b.state)
+    assert np.array_equal(sa, sb)
+    D1 = math.fsum(L.owned(sa[0]).ravel())
+    assert abs(D1 - D0) <= 1e-13 * abs(D0)
+    assert _host(a.red)[1] <= 1e-12 * 16 * 10
