@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Benchmark of the FP64 GRMHD right-hand side on one MI355X.
+
+Workload: the 128^3 periodic block in a static curved 3+1 metric (seeded low-k mode sums), Gamma = 2, PPM
+reconstruction, HLLE, quartic characteristic speeds, Noble c2p, RK4 at CFL 0.25.  A step is one whole RK4
+step (4 stages: c2p, primitive ghost fill, right-hand side, combine, state ghost fill), replayed from a
+captured HIP graph, with all inputs resident in HBM.
+
+Prints one JSON line: zone-updates/s per RK stage (interior cells x stages / wall time of the timed steps),
+the roofline of the dominant kernel (per-kernel HIP events recorded live on the launch stream), the
+whole-stage HBM roofline, and the serial CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "zone-updates/s per RK stage (FP64, 128^3) and % of HBM roofline"
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 128 FLOP/clk x 2.4 GHz)
+
+# Algorithmic FP64 operations per face of the face kernel (reconstruction of 7 variables on both sides,
+# 16-point face metric of 10 components, prim->cons, fluxes, quartic speeds, HLLE), counted by running the
+# plain serial implementation on an operation-counting scalar (+, -, *, /, sqrt, pow = 1 each) over the
+# faces of a 24^3 block of this workload (same seed and recipe).
+FACE_FLOPS = {"ppm": 2548.0, "wenoz": 3955.0, "minmod": 2020.0}
+# Algorithmic bytes per face: read 5 primitives + 2 centre fields + 10 face-metric components + 2 potential
+# components, write 7 face fluxes (each value once, stencil reuse served on chip).
+FACE_BYTES = 8.0 * (5 + 2 + 10 + 2 + 7)
+# Whole-stage algorithmic HBM bytes per zone-stage, RK4 averaged over its four stages: reads of the stage
+# state (9), metric and curvature (16), previous primitives (5), RK base state and accumulator (9 + 9 when
+# used); writes of primitives (5), next state (9) and accumulator (9 when used).
+STAGE_BYTES_RK4 = 514.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--recon", default="ppm", choices=["ppm", "wenoz", "minmod"])
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=56, help="edge of the block the CPU oracle times")
+    return ap.parse_args()
+
+
+def cpu_baseline(recon, n_cpu):
+    """The serial oracle, as it stands, on an n_cpu^3 block of the same workload: one RK4 step."""
+    from oracle import oracle as O
+    from paper_2406_11669_amd import workloads as W
+    O.build(force=False)
+    w = W.curved_block(seed=0, n=n_cpu, recon=recon, nsteps=1)
+    L = w.layout
+    cons = O.prim2con(L, w.params, w.metric, w.A, w.prim)
+    O.fill_ghosts(L, cons, w.bc_cell)
+    state = w.state(cons)
+    prim = w.prim.copy()
+    t0 = time.perf_counter()
+    O.run(L, w.params, w.metric, w.curv, state, prim, w.dt, 1, 4, w.bc_cell, w.bc_A)
+    dt = time.perf_counter() - t0
+    zs = n_cpu ** 3 * 4
+    return {"value": zs / dt, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "one RK4 step (4 stages) of the %d^3 block of the same workload recipe, serial FP64 oracle "
+                      "(g++ -O2 -ffp-contract=off), %.1f s" % (n_cpu, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one block on one GPU; runs on more than one GPU are not part of this build "
+              "(the multi-GPU design is a domain decomposition with halo exchange, not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2406_11669_amd import asterx
+    from paper_2406_11669_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n = args.n
+    w = W.curved_block(seed=0, n=n, recon=args.recon, nsteps=args.steps)
+    blk = asterx.Block(w)
+    torch.cuda.synchronize()
+    print("bench: %s n=%d recon=%s, block resident (%.2f GB device memory)" % (
+        w.name, n, args.recon, torch.cuda.memory_allocated() / 1e9), file=sys.stderr, flush=True)
+
+    step = blk.step
+    graph = None
+    if not args.no_graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            blk.step()  # first step eagerly on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            blk.step()
+        step = graph.replay
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    stages = blk.stages_per_step
+    zone_stages = n ** 3 * stages * args.steps
+    value = zone_stages / (ms * 1e-3)
+    print("bench: %d steps in %.3f ms" % (args.steps, ms), file=sys.stderr, flush=True)
+
+    # per-kernel durations, live, from HIP events bracketing each launch on its stream (one eager step)
+    asterx.timing_reset()
+    asterx.timing_enable(True)
+    blk.step()
+    torch.cuda.synchronize()
+    kt = asterx.timing_read()
+    asterx.timing_enable(False)
+    per_stage = {k: round(v[0] / stages, 4) for k, v in kt.items() if v[1] > 0}
+    face_ms = sum(kt[k][0] for k in ("face_x", "face_y", "face_z"))
+    face_launches = sum(kt[k][1] for k in ("face_x", "face_y", "face_z"))
+    dominant = max(((k, v[0]) for k, v in kt.items()), key=lambda kv: kv[1])[0]
+    faces_per_launch = (n + 1) ** 3
+    avg_face_s = face_ms * 1e-3 / face_launches
+    achieved = FACE_FLOPS[args.recon] * faces_per_launch / avg_face_s / 1e12
+    roofline = {"kernel": "face (x, y, z launches averaged)", "dominant_by_time": dominant,
+                "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_face_s * 1e3, 4),
+                "flops_per_face": FACE_FLOPS[args.recon], "faces_per_launch": faces_per_launch,
+                "algorithmic_GBs": round(FACE_BYTES * faces_per_launch / avg_face_s / 1e9, 1)}
+    stage_gbs = STAGE_BYTES_RK4 * value / 1e9
+    hbm = {"bytes_per_zone_stage": STAGE_BYTES_RK4, "achieved": round(stage_gbs, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(stage_gbs / HBM_PEAK_GBS, 4)}
+    out = {"metric": METRIC, "value": value, "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "curved%d-%s-rk4" % (n, args.recon), "n": n, "ng": w.layout.ng,
+                      "recon": args.recon, "rk": 4, "stages_per_step": stages, "cfl": 0.25, "gamma": 2.0,
+                      "speeds": "quartic", "graph": graph is not None},
+           "roofline": roofline, "hbm_roofline_stage": hbm, "kernel_ms_per_stage": per_stage,
+           "c2p_stats": [int(v) for v in blk.stats.cpu().tolist()]}
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a %d^3 sample" % args.cpu_n, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.recon, args.cpu_n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

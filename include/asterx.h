@@ -140,6 +140,16 @@ int asterx_rk_stage(const asterx_grid* g, int32_t nterms, const double* a, const
  * recorded in a captured graph. */
 int asterx_zero(double* buf, int64_t count, void* stream);
 
+/* Per-kernel timing (diagnostics).  When enabled, every launch of the library is bracketed
+ * by two HIP events on its stream; asterx_timing_read waits for the recorded events and
+ * returns, for each kernel class k < n, the accumulated milliseconds ms[k] and launch count
+ * counts[k] (either may be NULL); it returns the number of kernel classes.
+ * asterx_timing_name(k) names class k.  Do not enable while a stream is being captured. */
+int asterx_timing_enable(int32_t on);
+int asterx_timing_read(double* ms, long long* counts, int32_t n);
+int asterx_timing_reset(void);
+const char* asterx_timing_name(int32_t k);
+
 #ifdef __cplusplus
 }
 #endif

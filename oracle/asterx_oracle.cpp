@@ -83,6 +83,44 @@ template <class T> static inline T sq(const T& x) { return x * x; }
 template <class T> static inline bool is_finite(const T& x) { return std::isfinite(value_of(x)); }
 
 // ---------------------------------------------------------------------------
+// Operation-counting scalar: a double that counts its floating-point operations
+// (+, -, *, /, sqrt, pow each count one) so that the algorithmic FLOPs of a
+// kernel can be measured by running the plain implementation on it.
+struct Cnt {
+  double v;
+  static unsigned long long ops;
+  Cnt() : v(0.0) {}
+  Cnt(double x) : v(x) {}
+};
+unsigned long long Cnt::ops = 0;
+static inline double value_of(const Cnt& x) { return x.v; }
+static inline Cnt operator+(const Cnt& a, const Cnt& b) { ++Cnt::ops; return Cnt(a.v + b.v); }
+static inline Cnt operator-(const Cnt& a, const Cnt& b) { ++Cnt::ops; return Cnt(a.v - b.v); }
+static inline Cnt operator*(const Cnt& a, const Cnt& b) { ++Cnt::ops; return Cnt(a.v * b.v); }
+static inline Cnt operator/(const Cnt& a, const Cnt& b) { ++Cnt::ops; return Cnt(a.v / b.v); }
+static inline Cnt operator-(const Cnt& a) { return Cnt(-a.v); }
+static inline bool operator<(const Cnt& a, const Cnt& b) { return a.v < b.v; }
+static inline bool operator>(const Cnt& a, const Cnt& b) { return a.v > b.v; }
+static inline bool operator<=(const Cnt& a, const Cnt& b) { return a.v <= b.v; }
+static inline bool operator>=(const Cnt& a, const Cnt& b) { return a.v >= b.v; }
+static inline bool operator==(const Cnt& a, const Cnt& b) { return a.v == b.v; }
+static inline bool operator!=(const Cnt& a, const Cnt& b) { return a.v != b.v; }
+static inline Cnt sqrt(const Cnt& a) { ++Cnt::ops; return Cnt(std::sqrt(a.v)); }
+static inline Cnt fabs(const Cnt& a) { return Cnt(std::fabs(a.v)); }
+static inline Cnt pow(const Cnt& a, const Cnt& b) { ++Cnt::ops; return Cnt(std::pow(a.v, b.v)); }
+static inline Cnt pow(const Cnt& a, double b) { ++Cnt::ops; return Cnt(std::pow(a.v, b)); }
+
+// Phase marks: rhs_grid calls phase_mark(k) at the boundaries of its parts; for the
+// counting type the operations of each part are accumulated into g_phase_ops.
+static unsigned long long g_phase_ops[4];
+static unsigned long long g_phase_last = 0;
+template <class T> static inline void phase_mark(int) {}
+template <> inline void phase_mark<Cnt>(int k) {
+  if (k >= 0) g_phase_ops[k] += Cnt::ops - g_phase_last;
+  g_phase_last = Cnt::ops;
+}
+
+// ---------------------------------------------------------------------------
 // 3+1 geometry at a point (Sec. 2.1, line element): lapse alpha, shift beta^i,
 // spatial metric gamma_ij; derived inverse, determinant, sqrt(gamma).
 // Metric storage order: alpha, beta^x, beta^y, beta^z, gxx, gxy, gxz, gyy, gyz, gzz.
@@ -1018,6 +1056,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
                                  const T* prim, const T* A, const T* psi, double dt_max, T* rhs, double* red,
                                  long long* nfix_out) {
   size_t N = npts(g);
+  phase_mark<T>(-1);
   // centre field everywhere it can be formed
   std::vector<T> Bc(3 * N, T(0));
   for (int k = -g.ng; k < g.n[2] + g.ng; ++k)
@@ -1027,6 +1066,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
         centre_B(g, A, i, j, k, b);
         for (int c = 0; c < 3; ++c) Bc[c * N + at(g, i, j, k)] = b[c];
       }
+  phase_mark<T>(0);
   // face fluxes: 3 directions x 7 components
   std::vector<T> flux(21 * N, T(0));
   double vmax = 0.0;
@@ -1068,6 +1108,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
           }
         }
   }
+  phase_mark<T>(1);
   // hydro: flux divergence (eq. fluxconseqs) plus sources, owned cells
   const size_t CURV = 6;
   double divmax = 0.0;
@@ -1102,6 +1143,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
         double adb = std::fabs(value_of(dB));
         if (adb > divmax) divmax = adb;
       }
+  phase_mark<T>(2);
   // electric field on edges by flux-CT (Sec. 3.4, FCT): each component is the
   // average of the four induction fluxes on the faces that share the edge.
   // Induction flux slots: direction d stores (B^{(d+1)%3}, B^{(d+2)%3}) in
@@ -1161,6 +1203,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
           rhs[8 * N + id] = T(0);
         }
       }
+  phase_mark<T>(3);
   if (red) {
     red[0] = vmax;
     red[1] = divmax;
@@ -1285,6 +1328,33 @@ void orc_run(const Grid* g, const Params* P, const double* metric, const double*
 void orc_rk_stage(const Grid* g, int nterms, const double* a, const double* const* u, double b_dt, const double* rhs,
                   double* out) {
   rk_combine<double>(*g, nterms, a, u, b_dt, rhs, out);
+}
+
+// Algorithmic operation counts of one right-hand side and one c2p on this block,
+// measured with the counting scalar: out[0..3] = centre field, faces (all three
+// directions), cells (divergence + sources), constrained transport; out[4] = c2p.
+void orc_count_ops(const Grid* g, const Params* P, const double* metric, const double* curv, const double* prim,
+                   const double* A, const double* psi, double dt_max, unsigned long long* out) {
+  size_t N = npts(*g);
+  auto conv = [&](const double* a, size_t n) {
+    std::vector<Cnt> v(n);
+    for (size_t i = 0; i < n; ++i) v[i] = Cnt(a[i]);
+    return v;
+  };
+  std::vector<Cnt> m = conv(metric, 10 * N), k = conv(curv, 6 * N), pr = conv(prim, 5 * N), a = conv(A, 3 * N),
+                   ps = conv(psi, N), rhs(9 * N);
+  for (int q = 0; q < 4; ++q) g_phase_ops[q] = 0;
+  Cnt::ops = 0;
+  g_phase_last = 0;
+  rhs_grid<Cnt>(*g, *P, Cnt(P->gamma), m.data(), k.data(), pr.data(), a.data(), ps.data(), dt_max, rhs.data(),
+                nullptr, nullptr);
+  for (int q = 0; q < 4; ++q) out[q] = g_phase_ops[q];
+  // c2p from the conserved variables of these primitives, warm-started from them
+  std::vector<Cnt> cons(5 * N);
+  prim2con_grid<Cnt>(*g, *P, Cnt(P->gamma), m.data(), a.data(), pr.data(), cons.data());
+  Cnt::ops = 0;
+  c2p_grid<Cnt>(*g, *P, Cnt(P->gamma), m.data(), a.data(), cons.data(), pr.data(), nullptr, nullptr);
+  out[4] = Cnt::ops;
 }
 
 // Face B (densitized) of direction d for every index in [-ng+?]: fills all

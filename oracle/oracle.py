@@ -149,6 +149,15 @@ def run(layout, params, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A
     return flags, stats, redmax
 
 
+def count_ops(layout, params, metric, curv, prim, A, psi, dt_max):
+    """Algorithmic FP64 operation counts of one right-hand side and one c2p on this block:
+    dict(centre_B, faces, cells, ct, c2p) in operations (each +, -, *, /, sqrt, pow counts one)."""
+    out = np.zeros(5, dtype=np.uint64)
+    lib().orc_count_ops(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), _p(metric), _p(curv),
+                        _p(prim), _p(A), _p(psi), ctypes.c_double(dt_max), out.ctypes.data_as(ctypes.c_void_p))
+    return dict(zip(["centre_B", "faces", "cells", "ct", "c2p"], [int(v) for v in out]))
+
+
 def face_B(layout, A):
     out = np.zeros((3,) + layout.shape3, dtype=np.float64)
     lib().orc_face_B(ctypes.byref(make_grid(layout)), _p(A), _p(out))

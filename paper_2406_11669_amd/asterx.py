@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "asterx_prim2con", "asterx_c2p",
-           "asterx_fill_ghosts", "asterx_rhs", "asterx_rk_stage", "asterx_zero"]
+           "asterx_fill_ghosts", "asterx_rhs", "asterx_rk_stage", "asterx_zero", "asterx_timing_enable",
+           "asterx_timing_read", "asterx_timing_reset", "asterx_timing_name"]
 
 
 def lib():
@@ -59,6 +60,10 @@ def lib():
         L.asterx_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
         L.asterx_rk_stage.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
         L.asterx_zero.argtypes = [vp, ctypes.c_int64, vp]
+        L.asterx_timing_enable.argtypes = [ctypes.c_int32]
+        L.asterx_timing_read.argtypes = [vp, vp, ctypes.c_int32]
+        L.asterx_timing_name.restype = ctypes.c_char_p
+        L.asterx_timing_name.argtypes = [ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -151,6 +156,23 @@ def rk_stage(layout, a, us, b_dt, rhs_t, out, stream=None):
 
 def zero(buf, stream=None):
     _check(lib().asterx_zero(_ptr(buf), buf.numel(), _stream(stream)))
+
+
+def timing_enable(on=True):
+    lib().asterx_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    lib().asterx_timing_reset()
+
+
+def timing_read():
+    """{kernel name: (total ms, launches)} accumulated since the last reset (waits for the events)."""
+    n = lib().asterx_timing_read(None, None, 0)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_longlong * n)()
+    lib().asterx_timing_read(ms, cnt, n)
+    return {lib().asterx_timing_name(k).decode(): (ms[k], cnt[k]) for k in range(n)}
 
 
 # ---- a block advanced by whole RK steps (Sec. 3.12 workflow) ------------------------------------------------

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "asterx.h"
 #include "grmhd_device.h"
@@ -73,7 +74,7 @@ DEV unsigned xcd_block(unsigned bid, unsigned nblocks) {
 
 // Linear tile decomposition of a 3-D box of extents e[3] into blocks of TX x TY x 1.
 template <int TX, int TY>
-DEV bool box_index(const int e[3], int& a, int& b, int& c) {
+DEV bool box_index_t(const int e[3], unsigned tid, int& a, int& b, int& c) {
   unsigned nbx = (e[0] + TX - 1) / TX, nby = (e[1] + TY - 1) / TY;
   unsigned nblocks = nbx * nby * (unsigned)e[2];
   unsigned bid = xcd_block(blockIdx.x, nblocks);
@@ -81,9 +82,14 @@ DEV bool box_index(const int e[3], int& a, int& b, int& c) {
   unsigned t = bid / nbx;
   unsigned by = t % nby;
   c = (int)(t / nby);
-  a = (int)(bx * TX + threadIdx.x % TX);
-  b = (int)(by * TY + threadIdx.x / TX);
+  a = (int)(bx * TX + tid % TX);
+  b = (int)(by * TY + tid / TX);
   return a < e[0] && b < e[1] && c < e[2];
+}
+
+template <int TX, int TY>
+DEV bool box_index(const int e[3], int& a, int& b, int& c) {
+  return box_index_t<TX, TY>(e, threadIdx.x, a, b, c);
 }
 
 template <int TX, int TY>
@@ -132,29 +138,6 @@ DEV double centre_val(const double* __restrict__ p, int sy, int sz) {
   return lag(zz[0], zz[1], zz[2], zz[3]);
 }
 
-// Value and first derivatives (unscaled by 1/dx) at the centre.
-DEV void centre_val_der(const double* __restrict__ p, int sy, int sz, double& v, double& dx, double& dy, double& dz) {
-  double vz[4], dyz[4], dxz[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    double vx[4], ddx[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const double* r = p + b * sy + c * sz;
-      double r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-      vx[b] = lag(r0, r1, r2, r3);
-      ddx[b] = dlag(r0, r1, r2, r3);
-    }
-    vz[c] = lag(vx[0], vx[1], vx[2], vx[3]);
-    dyz[c] = dlag(vx[0], vx[1], vx[2], vx[3]);
-    dxz[c] = lag(ddx[0], ddx[1], ddx[2], ddx[3]);
-  }
-  v = lag(vz[0], vz[1], vz[2], vz[3]);
-  dz = dlag(vz[0], vz[1], vz[2], vz[3]);
-  dy = lag(dyz[0], dyz[1], dyz[2], dyz[3]);
-  dx = lag(dxz[0], dxz[1], dxz[2], dxz[3]);
-}
-
 DEV void centre_metric(const double* __restrict__ metric, size_t N, int base, int sy, int sz, double m[10]) {
 #pragma unroll
   for (int c = 0; c < 10; ++c) m[c] = centre_val(metric + c * N + base, sy, sz);
@@ -196,6 +179,101 @@ C2PParams make_c2p_params(const asterx_params* p) {
   return c;
 }
 
+// ---------------------------------------------------------------------------------------
+// Cell tiles of 16 x 4 x 4 with the spacetime data staged in LDS.  The vertex tile
+// (19 x 7 x 7) of one component is loaded once, then interpolated separably -- z, then y,
+// then x -- with each pass shared by all cells of the tile (Sec. 3.2 Lagrange weights).
+constexpr int CTX = 16, CTY = 4, CTZ = 4;
+constexpr int VX = CTX + 3, VY = CTY + 3, VZ = CTZ + 3;
+constexpr int NV = VX * VY * VZ;    // vertex tile
+constexpr int NZP = VX * VY * CTZ;  // after the z pass
+constexpr int NYP = VX * CTY * CTZ; // after the y pass
+
+struct TileLDS {
+  double v[NV];
+  double z[2 * NZP];
+  double y[3 * NYP];
+};
+
+struct TileCell {
+  int i0, j0, k0, cx, cy, cz;
+  bool valid;
+};
+
+DEV TileCell tile_cell(const GD& g) {
+  TileCell t;
+  int ntx = (g.n[0] + CTX - 1) / CTX, nty = (g.n[1] + CTY - 1) / CTY, ntz = (g.n[2] + CTZ - 1) / CTZ;
+  unsigned bid = xcd_block(blockIdx.x, (unsigned)(ntx * nty * ntz));
+  t.i0 = (int)(bid % ntx) * CTX;
+  t.j0 = (int)((bid / ntx) % nty) * CTY;
+  t.k0 = (int)(bid / (ntx * nty)) * CTZ;
+  t.cx = threadIdx.x % CTX;
+  t.cy = (threadIdx.x / CTX) % CTY;
+  t.cz = threadIdx.x / (CTX * CTY);
+  t.valid = t.i0 + t.cx < g.n[0] && t.j0 + t.cy < g.n[1] && t.k0 + t.cz < g.n[2];
+  return t;
+}
+
+unsigned tile_blocks(const GD& g) {
+  return (unsigned)(((g.n[0] + CTX - 1) / CTX) * ((g.n[1] + CTY - 1) / CTY) * ((g.n[2] + CTZ - 1) / CTZ));
+}
+
+// Stage vertices i0-1 .. i0+CTX+1 (etc.) of field f; vertices no owned cell needs (beyond
+// n+1, in a ragged last tile) are not read.
+DEV void stage_vertices(const GD& g, const double* __restrict__ f, const TileCell& t, double* sv) {
+  for (int q = threadIdx.x; q < NV; q += 256) {
+    int vx = q % VX, vy = (q / VX) % VY, vz = q / (VX * VY);
+    int i = t.i0 - 1 + vx, j = t.j0 - 1 + vy, k = t.k0 - 1 + vz;
+    sv[q] = (i <= g.n[0] + 1 && j <= g.n[1] + 1 && k <= g.n[2] + 1) ? f[at(g, i, j, k)] : 0.0;
+  }
+}
+
+// Centre value of the staged component (every thread of the block must call it).
+DEV double tile_value(TileLDS& S, const TileCell& t) {
+  __syncthreads();
+  for (int q = threadIdx.x; q < NZP; q += 256) {
+    int vx = q % VX, vy = (q / VX) % VY, z = q / (VX * VY);
+    const double* p = S.v + vx + VX * (vy + VY * z);
+    S.z[q] = lag(p[0], p[VX * VY], p[2 * VX * VY], p[3 * VX * VY]);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < NYP; q += 256) {
+    int vx = q % VX, y = (q / VX) % CTY, z = q / (VX * CTY);
+    const double* p = S.z + vx + VX * (y + VY * z);
+    S.y[q] = lag(p[0], p[VX], p[2 * VX], p[3 * VX]);
+  }
+  __syncthreads();
+  const double* p = S.y + t.cx + VX * (t.cy + CTY * t.cz);
+  return lag(p[0], p[1], p[2], p[3]);
+}
+
+// Centre derivatives (d/dx, d/dy, d/dz, scaled) of the staged component.
+DEV void tile_derivs(TileLDS& S, const TileCell& t, const GD& g, double d[3]) {
+  __syncthreads();
+  for (int q = threadIdx.x; q < NZP; q += 256) {
+    int vx = q % VX, vy = (q / VX) % VY, z = q / (VX * VY);
+    const double* p = S.v + vx + VX * (vy + VY * z);
+    double a = p[0], b = p[VX * VY], c = p[2 * VX * VY], e = p[3 * VX * VY];
+    S.z[q] = lag(a, b, c, e);
+    S.z[NZP + q] = dlag(a, b, c, e);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < NYP; q += 256) {
+    int vx = q % VX, y = (q / VX) % CTY, z = q / (VX * CTY);
+    const double* p = S.z + vx + VX * (y + VY * z);
+    const double* r = p + NZP;
+    double a = p[0], b = p[VX], c = p[2 * VX], e = p[3 * VX];
+    S.y[q] = lag(a, b, c, e);
+    S.y[NYP + q] = dlag(a, b, c, e);
+    S.y[2 * NYP + q] = lag(r[0], r[VX], r[2 * VX], r[3 * VX]);
+  }
+  __syncthreads();
+  const double* p = S.y + t.cx + VX * (t.cy + CTY * t.cz);
+  d[0] = dlag(p[0], p[1], p[2], p[3]) * g.idx[0];
+  d[1] = lag(p[NYP], p[NYP + 1], p[NYP + 2], p[NYP + 3]) * g.idx[1];
+  d[2] = lag(p[2 * NYP], p[2 * NYP + 1], p[2 * NYP + 2], p[2 * NYP + 3]) * g.idx[2];
+}
+
 // =======================================================================================
 // prim -> cons on owned cells.
 __global__ __launch_bounds__(256) void k_prim2con(GD g, double gam, const double* __restrict__ metric,
@@ -220,19 +298,25 @@ __global__ __launch_bounds__(256) void k_prim2con(GD g, double gam, const double
   for (int c = 0; c < 5; ++c) cons[c * g.N + id] = U[c];
 }
 
-// c2p on owned cells (Sec. 3.5, 3.6).
-__global__ __launch_bounds__(256) void k_c2p(GD g, C2PParams P, const double* __restrict__ metric,
-                                             const double* __restrict__ A, double* __restrict__ cons,
-                                             double* __restrict__ prim, uint8_t* __restrict__ flags,
-                                             unsigned long long* __restrict__ stats) {
-  int i, j, k;
-  bool valid = box_index<64, 4>(g.n, i, j, k);
+// c2p on owned cells, tiled: the ten metric components are interpolated to the centres
+// through LDS (Sec. 3.2), then each thread recovers its cell (Secs. 3.5, 3.6).
+__global__ __launch_bounds__(256) void k_c2p_t(GD g, C2PParams P, const double* __restrict__ metric,
+                                               const double* __restrict__ A, double* __restrict__ cons,
+                                               double* __restrict__ prim, uint8_t* __restrict__ flags,
+                                               unsigned long long* __restrict__ stats) {
+  __shared__ TileLDS S;
+  const TileCell t = tile_cell(g);
+  double m[10];
+#pragma unroll
+  for (int c = 0; c < 10; ++c) {
+    if (c > 0) __syncthreads();
+    stage_vertices(g, metric + c * g.N, t, S.v);
+    m[c] = tile_value(S, t);
+  }
   uint32_t fl = 0;
   int iters = 0;
-  if (valid) {
-    int id = at(g, i, j, k);
-    double m[10];
-    centre_metric(metric, g.N, id - 1 - g.sy - g.sz, g.sy, g.sz, m);
+  if (t.valid) {
+    const int id = at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz);
     Geo G;
     geo_from(m, G);
     double Bt[3], U[5], prev[5], out[5];
@@ -271,6 +355,9 @@ struct FillArgs {
 };
 
 __global__ __launch_bounds__(256) void k_fill(GD g, FillArgs a) {
+  // ghost values are a pure function of owned values: no contraction, so that linear
+  // extrapolation rounds exactly like its definition (one multiply, then one add)
+#pragma clang fp contract(off)
   const int d = a.d;
   int ext[3];
   for (int t = 0; t < 3; ++t) ext[t] = g.n[t] + 2 * g.ng + 1;
@@ -340,58 +427,87 @@ struct FaceArgs {
   int recon, speeds;
 };
 
+// Paired-lane variant: lanes 2f and 2f+1 of a wavefront handle the left and the right state
+// of face f.  Each lane reconstructs its own side (the right lane reads its stencil
+// mirrored, so both run the "right face of the middle cell" formula), interpolates half of
+// the face metric, and computes the conserved vector, flux and speeds of its side; the pair
+// exchanges metric halves and side results through lane shuffles and both evaluate HLLE,
+// the left lane storing components 0-3, the right lane 4-6.  Half the live state per lane
+// of a one-lane-per-face kernel, twice the lanes in flight.
+DEV double shfl1(double v) { return __shfl_xor(v, 1, 64); }
+
+DEV double recon_right_face(int kind, const double a[5], double eps, double q) {
+  if (kind == 0) return a[2] + 0.5 * mm(a[2] - a[1], a[3] - a[2]);
+  if (kind == 1) {
+    double s1 = mc_slope(a[0], a[1], a[2]);
+    double s2 = mc_slope(a[1], a[2], a[3]);
+    double s3 = mc_slope(a[2], a[3], a[4]);
+    const double sixth = 1.0 / 6.0;
+    double fl = 0.5 * (a[1] + a[2]) - (s2 - s1) * sixth;
+    double fr = 0.5 * (a[2] + a[3]) - (s3 - s2) * sixth;
+    ppm_limit(a[2], fl, fr);
+    return fr;
+  }
+  return wenoz_face(a[0], a[1], a[2], a[3], a[4], eps, q);
+}
+
 template <int D>
-__global__ __launch_bounds__(256) void k_face(GD g, FaceArgs fa) {
+__global__ __launch_bounds__(256) void k_face2(GD g, FaceArgs fa) {
   constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  const int side = threadIdx.x & 1;
   int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
   int a, b, c;
-  bool valid = box_index<64, 4>(e, a, b, c);
+  bool valid = box_index_t<32, 4>(e, threadIdx.x >> 1, a, b, c);
+  // keep both lanes of a pair valid or invalid together (they share the face)
   double smax = 0.0;
   if (valid) {
     int ijk[3] = {a - 1, b - 1, c - 1};
     ijk[D] += 1;
-    const int i = ijk[0], j = ijk[1], k = ijk[2];
-    const int id = at(g, i, j, k);
+    const int id = at(g, ijk[0], ijk[1], ijk[2]);
     const int st[3] = {1, g.sy, g.sz};
     const int sD = st[D], s1 = st[t1], s2 = st[t2];
-    // face metric: Lagrange weights in the two transverse directions
-    double m[10];
-    const int mb = id - s1 - s2;
-#pragma unroll
-    for (int cc = 0; cc < 10; ++cc) {
-      const double* p = fa.metric + cc * g.N + mb;
-      double rr[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double* r = p + q * s2;
-        rr[q] = lag(r[0], r[s1], r[2 * s1], r[3 * s1]);
-      }
-      m[cc] = lag(rr[0], rr[1], rr[2], rr[3]);
-    }
-    Geo G;
-    geo_from(m, G);
-    // reconstruction of rho, p, v^x..z and the two transverse centre fields
-    double L[7], R[7], cl[7], cr[7];
+    // reconstruction of this lane's side: left lane cells i-3..i+1, right lane i+2..i-2
+    double X[7], C[7];
+    const int o0 = side ? 2 : -3, os = side ? -1 : 1;
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
       const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
-      double s6[6];
+      double s5[5];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) s6[q] = f[id + (q - 3) * sD];
-      reconstruct(fa.recon, s6, L[v], R[v], fa.weno_eps, fa.weno_q);
-      cl[v] = s6[2];
-      cr[v] = s6[3];
+      for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
+      X[v] = recon_right_face(fa.recon, s5, fa.weno_eps, fa.weno_q);
+      C[v] = s5[2];
     }
-    // normal field on the face from the curl
+    // face metric: this lane interpolates components [5 side, 5 side + 5)
+    double mine[5];
+    const int mb = id - s1 - s2;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const double* p = fa.metric + (size_t)(5 * side + q) * g.N + mb;
+      double rr[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double* row = p + r * s2;
+        rr[r] = lag(row[0], row[s1], row[2 * s1], row[3 * s1]);
+      }
+      mine[q] = lag(rr[0], rr[1], rr[2], rr[3]);
+    }
+    double m[10];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      double other = shfl1(mine[q]);
+      m[q] = side ? other : mine[q];
+      m[5 + q] = side ? mine[q] : other;
+    }
+    Geo G;
+    geo_from(m, G);
     const double* Ax = fa.A;
     const double* Ay = fa.A + g.N;
     const double* Az = fa.A + 2 * g.N;
-    double Bn = D == 0 ? faceBx(Ay, Az, id, g.sy, g.sz, g) : (D == 1 ? faceBy(Ax, Az, id, g.sy, g.sz, g) : faceBz(Ax, Ay, id, g.sy, g.sz, g));
-    double UL[7], FL[7], UR[7], FR[7], cmL, cpL, cmR, cpR;
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      double* X = side == 0 ? L : R;
-      const double* C = side == 0 ? cl : cr;
+    double Bn = D == 0 ? faceBx(Ay, Az, id, g.sy, g.sz, g)
+                       : (D == 1 ? faceBy(Ax, Az, id, g.sy, g.sz, g) : faceBz(Ax, Ay, id, g.sy, g.sz, g));
+    // an unphysical reconstructed state falls back to the cell's own values
+    {
       double vl[3], v[3] = {X[2], X[3], X[4]};
       lower(G.g, v, vl);
       double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
@@ -399,25 +515,44 @@ __global__ __launch_bounds__(256) void k_face(GD g, FaceArgs fa) {
 #pragma unroll
         for (int q = 0; q < 7; ++q) X[q] = C[q];
       }
-      double Bt[3];
-      Bt[D] = Bn;
-      Bt[t1] = X[5];
-      Bt[t2] = X[6];
-      State S;
-      state_make(G, X, Bt, fa.gam, S);
-      if (side == 0) {
-        flux_of<D>(G, S, UL, FL);
-        speeds_of<D>(G, S, fa.gam, fa.speeds, cmL, cpL);
-      } else {
-        flux_of<D>(G, S, UR, FR);
-        speeds_of<D>(G, S, fa.gam, fa.speeds, cmR, cpR);
-      }
     }
-    double Fo[7], sm;
-    hlle7(UL, FL, cmL, cpL, UR, FR, cmR, cpR, Fo, sm);
+    double Bt[3];
+    Bt[D] = Bn;
+    Bt[t1] = X[5];
+    Bt[t2] = X[6];
+    State S;
+    state_make(G, X, Bt, fa.gam, S);
+    double U[7], F[7], cm, cp;
+    flux_of<D>(G, S, U, F);
+    speeds_of<D>(G, S, fa.gam, fa.speeds, cm, cp);
+    // exchange with the partner lane and combine (HLLE, eq. HLLEfluxes)
+    double Uo[7], Fo[7];
 #pragma unroll
-    for (int q = 0; q < 7; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = Fo[q];
-    if (ijk[t1] >= 0 && ijk[t2] >= 0) smax = sm;
+    for (int q = 0; q < 7; ++q) {
+      Uo[q] = shfl1(U[q]);
+      Fo[q] = shfl1(F[q]);
+    }
+    double cmo = shfl1(cm), cpo = shfl1(cp);
+    double cmax = fmax(0.0, fmax(cp, cpo));
+    double cmin = -fmin(0.0, fmin(cm, cmo));
+    double den = cmax + cmin;
+    double id_ = den > 0.0 ? 1.0 / den : 0.0;
+    double cc = cmax * cmin;
+    double out[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      double UL = side ? Uo[q] : U[q], UR = side ? U[q] : Uo[q];
+      double FL = side ? Fo[q] : F[q], FR = side ? F[q] : Fo[q];
+      out[q] = den > 0.0 ? (cmin * FR + cmax * FL - cc * (UR - UL)) * id_ : 0.5 * (FL + FR);
+    }
+    if (side == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = out[q];
+    } else {
+#pragma unroll
+      for (int q = 4; q < 7; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = out[q];
+    }
+    if (ijk[t1] >= 0 && ijk[t2] >= 0) smax = fmax(cmax, cmin);
   }
   if (fa.red) {
     double w = wave_max(smax);
@@ -439,38 +574,25 @@ struct CellArgs {
   double gam;
 };
 
-__global__ __launch_bounds__(256) void k_cell(GD g, CellArgs ca) {
-  int i, j, k;
-  bool valid = box_index<64, 4>(g.n, i, j, k);
-  double divb = 0.0;
-  if (valid) {
-    const int id = at(g, i, j, k);
-    const int st[3] = {1, g.sy, g.sz};
-    double rhs[5];
+// Tiled cell kernel.  Pass 1 interpolates the values of the 10 metric and 6 curvature
+// components through LDS; the stress tensor follows.  The momentum source
+// 1/2 T^{mu nu} d_j g_{mu nu} is linear in the derivatives of the stored components,
+// sum_c w_c d_j m_c with weights w_c built from T, beta and gamma, so pass 2 takes one
+// component's three derivatives at a time and accumulates them (few live registers).
+__global__ __launch_bounds__(256) void k_cell_t(GD g, CellArgs ca) {
+  __shared__ TileLDS S;
+  const TileCell t = tile_cell(g);
+  double m[10], K[6];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      double s = 0.0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double* F = ca.flux + (size_t)(d * 7 + c) * g.N;
-        s += (F[id + st[d]] - F[id]) * g.idx[d];
-      }
-      rhs[c] = -s;
-    }
-    // metric, derivatives and K at the centre
-    const int vb = id - 1 - g.sy - g.sz;
-    double m[10], dm[3][10];
-#pragma unroll
-    for (int c = 0; c < 10; ++c) {
-      double dx, dy, dz;
-      centre_val_der(ca.metric + c * g.N + vb, g.sy, g.sz, m[c], dx, dy, dz);
-      dm[0][c] = dx * g.idx[0];
-      dm[1][c] = dy * g.idx[1];
-      dm[2][c] = dz * g.idx[2];
-    }
-    double K[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) K[c] = centre_val(ca.curv + c * g.N + vb, g.sy, g.sz);
+  for (int c = 0; c < 16; ++c) {
+    if (c > 0) __syncthreads();
+    stage_vertices(g, c < 10 ? ca.metric + c * g.N : ca.curv + (c - 10) * g.N, t, S.v);
+    double v = tile_value(S, t);
+    if (c < 10) m[c] = v; else K[c - 10] = v;
+  }
+  const int id = t.valid ? at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz) : 0;
+  double w[10], wa[3], src[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, as = 0.0;
+  if (t.valid) {
     Geo G;
     geo_from(m, G);
     double pr[5], Bt[3];
@@ -479,17 +601,17 @@ __global__ __launch_bounds__(256) void k_cell(GD g, CellArgs ca) {
     Bt[0] = ca.bc[id];
     Bt[1] = ca.bc[g.N + id];
     Bt[2] = ca.bc[2 * g.N + id];
-    State S;
-    state_make(G, pr, Bt, ca.gam, S);
+    State St;
+    state_make(G, pr, Bt, ca.gam, St);
     // T^{mu nu} = (rho h + b^2) u u + (p + b^2/2) g^{mu nu} - b b   (eq. tmunu)
     double ia = 1.0 / G.alp, ia2 = ia * ia;
-    double u0 = S.W * ia, u[3], b0 = S.W * S.Bv * ia, bu[3];
+    double u0 = St.W * ia, u[3], b0 = St.W * St.Bv * ia, bu[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      u[a] = S.W * (S.v[a] - G.beta[a] * ia);
-      bu[a] = (S.B[a] + G.alp * b0 * u[a]) / S.W;
+      u[a] = St.W * (St.v[a] - G.beta[a] * ia);
+      bu[a] = (St.B[a] + G.alp * b0 * u[a]) / St.W;
     }
-    double e = S.rhoh + S.bsq, pt = S.p + 0.5 * S.bsq;
+    double e = St.rhoh + St.bsq, pt = St.p + 0.5 * St.bsq;
     double T00 = e * u0 * u0 - pt * ia2 - b0 * b0;
     double T0[3], Tk[6];
 #pragma unroll
@@ -497,53 +619,62 @@ __global__ __launch_bounds__(256) void k_cell(GD g, CellArgs ca) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int bb = a; bb < 3; ++bb)
-        Tk[sym(a, bb)] = e * u[a] * u[bb] + pt * (G.gu[sym(a, bb)] - G.beta[a] * G.beta[bb] * ia2) - bu[a] * bu[bb];
+      for (int b = a; b < 3; ++b)
+        Tk[sym(a, b)] = e * u[a] * u[b] + pt * (G.gu[sym(a, b)] - G.beta[a] * G.beta[b] * ia2) - bu[a] * bu[b];
     double bl[3];
     lower(G.g, G.beta, bl);
-    double as = G.alp * G.sqrtg;
-    // momentum sources: 1/2 T^{mu nu} d_j g_{mu nu}
+    as = G.alp * G.sqrtg;
+    // weights of d_j alpha, d_j beta^k, d_j gamma_ab in 1/2 T^{mu nu} d_j g_{mu nu}
+    w[0] = -T00 * G.alp;
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-      const double* dg = &dm[jj][4];
-      const double dal = dm[jj][0];
-      const double db[3] = {dm[jj][1], dm[jj][2], dm[jj][3]};
-      // beta^k beta^l d gamma_kl and T^kl d gamma_kl (symmetric sums)
-      double bbdg = 0.0, Tdg = 0.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int bb = 0; bb < 3; ++bb) {
-          bbdg += G.beta[a] * G.beta[bb] * dg[sym(a, bb)];
-          Tdg += Tk[sym(a, bb)] * dg[sym(a, bb)];
-        }
-      double d00 = -2.0 * G.alp * dal + bbdg + 2.0 * (bl[0] * db[0] + bl[1] * db[1] + bl[2] * db[2]);
-      double s0k = 0.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        double d0a = 0.0;
-#pragma unroll
-        for (int bb = 0; bb < 3; ++bb) d0a += G.beta[bb] * dg[sym(a, bb)] + G.g[sym(a, bb)] * db[bb];
-        s0k += T0[a] * d0a;
-      }
-      rhs[1 + jj] += as * (0.5 * T00 * d00 + s0k + 0.5 * Tdg);
-    }
-    // energy source: T^00 (beta beta K - beta.d alpha) + T^0k (2 beta^l K_kl - d_k alpha) + T^kl K_kl
-    double dal[3] = {dm[0][0], dm[1][0], dm[2][0]};
-    double bK[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) bK[a] = G.beta[0] * K[sym(a, 0)] + G.beta[1] * K[sym(a, 1)] + G.beta[2] * K[sym(a, 2)];
-    double se = T00 * (G.beta[0] * bK[0] + G.beta[1] * bK[1] + G.beta[2] * bK[2] -
-                       (G.beta[0] * dal[0] + G.beta[1] * dal[1] + G.beta[2] * dal[2]));
-#pragma unroll
-    for (int a = 0; a < 3; ++a) se += T0[a] * (2.0 * bK[a] - dal[a]);
+    for (int k = 0; k < 3; ++k)
+      w[1 + k] = T00 * bl[k] + T0[0] * G.g[sym(0, k)] + T0[1] * G.g[sym(1, k)] + T0[2] * G.g[sym(2, k)];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int bb = 0; bb < 3; ++bb) se += Tk[sym(a, bb)] * K[sym(a, bb)];
-    rhs[4] += as * se;
+      for (int b = a; b < 3; ++b) {
+        if (a == b)
+          w[4 + sym(a, b)] = 0.5 * T00 * G.beta[a] * G.beta[a] + T0[a] * G.beta[a] + 0.5 * Tk[sym(a, a)];
+        else
+          w[4 + sym(a, b)] = T00 * G.beta[a] * G.beta[b] + T0[a] * G.beta[b] + T0[b] * G.beta[a] + Tk[sym(a, b)];
+      }
+    // energy source: K terms now, the lapse-gradient terms with the derivatives of alpha
+    double se = 0.0;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) ca.rhs[c * g.N + id] = rhs[c];
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        se += (T00 * G.beta[a] * G.beta[b] + 2.0 * T0[a] * G.beta[b] + Tk[sym(a, b)]) * K[sym(a, b)];
+    src[4] = se;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) wa[a] = -(T00 * G.beta[a] + T0[a]);
+  }
+#pragma unroll
+  for (int c = 0; c < 10; ++c) {
+    __syncthreads();
+    stage_vertices(g, ca.metric + c * g.N, t, S.v);
+    double d[3];
+    tile_derivs(S, t, g, d);
+    if (t.valid) {
+      src[1] += w[c] * d[0];
+      src[2] += w[c] * d[1];
+      src[3] += w[c] * d[2];
+      if (c == 0) src[4] += wa[0] * d[0] + wa[1] * d[1] + wa[2] * d[2];
+    }
+  }
+  double divb = 0.0;
+  if (t.valid) {
+    const int st[3] = {1, g.sy, g.sz};
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      double sdiv = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double* F = ca.flux + (size_t)(d * 7 + c) * g.N;
+        sdiv += (F[id + st[d]] - F[id]) * g.idx[d];
+      }
+      ca.rhs[c * g.N + id] = as * src[c] - sdiv;
+    }
     if (ca.red) {
       const double* Ax = ca.A;
       const double* Ay = ca.A + g.N;
@@ -555,8 +686,8 @@ __global__ __launch_bounds__(256) void k_cell(GD g, CellArgs ca) {
     }
   }
   if (ca.red) {
-    double w = wave_max(divb);
-    if (__lane_id() == 0) atomic_max_pos(ca.red + 1, w);
+    double wm = wave_max(divb);
+    if (__lane_id() == 0) atomic_max_pos(ca.red + 1, wm);
   }
 }
 
@@ -700,10 +831,95 @@ int launched() {
   return 0;
 }
 
+// ---------------------------------------------------------------------------------------
+// Optional per-kernel timing: when enabled, every launch is bracketed by two HIP events on
+// its own stream; asterx_timing_read waits for them and accumulates elapsed times.  Not for
+// use while a stream is being captured into a graph.
+enum {
+  KT_PRIM2CON, KT_C2P, KT_FILL, KT_BCENT, KT_FACE_X, KT_FACE_Y, KT_FACE_Z, KT_CELL, KT_VERTEX, KT_EDGE, KT_RK,
+  KT_ZERO, KT_N
+};
+const char* const kt_names[KT_N] = {"prim2con", "c2p", "fill_ghosts", "centre_B", "face_x", "face_y",
+                                    "face_z", "cell", "vertex", "edge", "rk_stage", "zero"};
+struct Pending {
+  hipEvent_t a, b;
+  int kind;
+};
+bool g_timing = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_free_events;
+double g_ms[KT_N];
+long long g_count[KT_N];
+
+hipEvent_t take_event() {
+  if (!g_free_events.empty()) {
+    hipEvent_t e = g_free_events.back();
+    g_free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+template <class F>
+int timed(int kind, hipStream_t s, F&& launch) {
+  if (!g_timing) {
+    launch();
+    return launched();
+  }
+  hipEvent_t a = take_event(), b = take_event();
+  bool ok = a && b && hipEventRecord(a, s) == hipSuccess;
+  launch();
+  int rc = launched();
+  ok = ok && hipEventRecord(b, s) == hipSuccess;
+  if (ok) {
+    g_pending.push_back(Pending{a, b, kind});
+  } else {
+    if (a) g_free_events.push_back(a);
+    if (b) g_free_events.push_back(b);
+  }
+  return rc;
+}
+
 }  // namespace
 
 // =======================================================================================
 extern "C" {
+
+int asterx_timing_enable(int32_t on) {
+  g_timing = on != 0;
+  return 0;
+}
+
+int asterx_timing_read(double* ms, long long* counts, int32_t n) {
+  for (const Pending& p : g_pending) {
+    float t = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+      g_ms[p.kind] += t;
+      g_count[p.kind] += 1;
+    }
+    g_free_events.push_back(p.a);
+    g_free_events.push_back(p.b);
+  }
+  g_pending.clear();
+  for (int k = 0; k < n && k < KT_N; ++k) {
+    if (ms) ms[k] = g_ms[k];
+    if (counts) counts[k] = g_count[k];
+  }
+  return KT_N;
+}
+
+int asterx_timing_reset(void) {
+  asterx_timing_read(nullptr, nullptr, 0);
+  for (int k = 0; k < KT_N; ++k) {
+    g_ms[k] = 0.0;
+    g_count[k] = 0;
+  }
+  return 0;
+}
+
+const char* asterx_timing_name(int32_t k) { return (k >= 0 && k < KT_N) ? kt_names[k] : ""; }
 
 int asterx_version(void) { return 1; }
 
@@ -721,9 +937,11 @@ int asterx_prim2con(const asterx_grid* g, const asterx_params* p, const double* 
   if ((rc = check_grid(g, 2)) || (rc = check_params(p))) return rc;
   if (!metric || !A || !prim || !cons) return fail(ASTERX_EARG, "prim2con: NULL array");
   GD d = make_gd(g);
-  hipLaunchKernelGGL(k_prim2con, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, (hipStream_t)stream, d, p->gamma,
-                     metric, A, prim, cons);
-  return launched();
+  hipStream_t s = (hipStream_t)stream;
+  return timed(KT_PRIM2CON, s, [&] {
+    hipLaunchKernelGGL(k_prim2con, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, s, d, p->gamma, metric, A, prim,
+                       cons);
+  });
 }
 
 int asterx_c2p(const asterx_grid* g, const asterx_params* p, const double* metric, const double* A, double* cons,
@@ -732,9 +950,12 @@ int asterx_c2p(const asterx_grid* g, const asterx_params* p, const double* metri
   if ((rc = check_grid(g, 2)) || (rc = check_params(p))) return rc;
   if (!metric || !A || !prim || !cons) return fail(ASTERX_EARG, "c2p: NULL array");
   GD d = make_gd(g);
-  hipLaunchKernelGGL(k_c2p, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, (hipStream_t)stream, d, make_c2p_params(p),
-                     metric, A, cons, prim, flags, (unsigned long long*)stats);
-  return launched();
+  hipStream_t s = (hipStream_t)stream;
+  C2PParams cp = make_c2p_params(p);
+  return timed(KT_C2P, s, [&] {
+    hipLaunchKernelGGL(k_c2p_t, dim3(tile_blocks(d)), dim3(256), 0, s, d, cp, metric, A, cons, prim, flags,
+                       (unsigned long long*)stats);
+  });
 }
 
 int asterx_fill_ghosts(const asterx_grid* g, double* f, int32_t nf, const int32_t* kinds, void* stream) {
@@ -752,8 +973,8 @@ int asterx_fill_ghosts(const asterx_grid* g, double* f, int32_t nf, const int32_
       if (b != a) cnt *= (g->n[b] + 2 * g->ng + 1);
     FillArgs fa{f, nf, a, kinds[a]};
     unsigned nb = (unsigned)((cnt + 255) / 256);
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, (hipStream_t)stream, d, fa);
-    if ((rc = launched())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = timed(KT_FILL, s, [&] { hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, d, fa); }))) return rc;
   }
   return 0;
 }
@@ -777,26 +998,26 @@ int asterx_rhs(const asterx_grid* g, const asterx_params* p, const double* metri
   double* ga = ws + 24 * d.N;
   double* fp = ws + 25 * d.N;
   int ebc[3] = {d.n[0] + 2 * d.ng, d.n[1] + 2 * d.ng, d.n[2] + 2 * d.ng};
-  hipLaunchKernelGGL(k_bcent, dim3(box_blocks<64, 4>(ebc)), dim3(256), 0, s, d, A, bc);
-  if ((rc = launched())) return rc;
+  if ((rc = timed(KT_BCENT, s, [&] { hipLaunchKernelGGL(k_bcent, dim3(box_blocks<64, 4>(ebc)), dim3(256), 0, s, d, A, bc); })))
+    return rc;
   FaceArgs fa{metric, prim, A, bc, flux, red, p->gamma, p->weno_eps, p->weno_q, p->recon, p->speeds};
   int ef[3] = {d.n[0] + 1, d.n[1] + 1, d.n[2] + 1};
-  unsigned nbf = box_blocks<64, 4>(ef);
-  hipLaunchKernelGGL(k_face<0>, dim3(nbf), dim3(256), 0, s, d, fa);
-  hipLaunchKernelGGL(k_face<1>, dim3(nbf), dim3(256), 0, s, d, fa);
-  hipLaunchKernelGGL(k_face<2>, dim3(nbf), dim3(256), 0, s, d, fa);
-  if ((rc = launched())) return rc;
+  unsigned nbf = box_blocks<32, 4>(ef);
+  if ((rc = timed(KT_FACE_X, s, [&] { hipLaunchKernelGGL(k_face2<0>, dim3(nbf), dim3(256), 0, s, d, fa); }))) return rc;
+  if ((rc = timed(KT_FACE_Y, s, [&] { hipLaunchKernelGGL(k_face2<1>, dim3(nbf), dim3(256), 0, s, d, fa); }))) return rc;
+  if ((rc = timed(KT_FACE_Z, s, [&] { hipLaunchKernelGGL(k_face2<2>, dim3(nbf), dim3(256), 0, s, d, fa); }))) return rc;
   CellArgs ca{metric, curv, prim, A, bc, flux, rhs, red, p->gamma};
-  hipLaunchKernelGGL(k_cell, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, s, d, ca);
-  if ((rc = launched())) return rc;
+  if ((rc = timed(KT_CELL, s, [&] { hipLaunchKernelGGL(k_cell_t, dim3(tile_blocks(d)), dim3(256), 0, s, d, ca); })))
+    return rc;
   if (p->gauge == ASTERX_GAUGE_LORENZ) {
     int ev[3] = {d.n[0] + 2, d.n[1] + 2, d.n[2] + 2};
-    hipLaunchKernelGGL(k_vertex, dim3(box_blocks<64, 4>(ev)), dim3(256), 0, s, d, metric, A, psi, ga, fp);
-    if ((rc = launched())) return rc;
+    if ((rc = timed(KT_VERTEX, s, [&] {
+           hipLaunchKernelGGL(k_vertex, dim3(box_blocks<64, 4>(ev)), dim3(256), 0, s, d, metric, A, psi, ga, fp);
+         })))
+      return rc;
   }
   EdgeArgs ea{metric, psi, flux, ga, fp, rhs, p->xi / dt_max, p->gauge};
-  hipLaunchKernelGGL(k_edge, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, s, d, ea);
-  return launched();
+  return timed(KT_EDGE, s, [&] { hipLaunchKernelGGL(k_edge, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, s, d, ea); });
 }
 
 int asterx_rk_stage(const asterx_grid* g, int32_t nterms, const double* a, const double* const* u, double b_dt,
@@ -815,15 +1036,16 @@ int asterx_rk_stage(const asterx_grid* g, int32_t nterms, const double* a, const
   ra.rhs = rhs;
   ra.out = out;
   GD d = make_gd(g);
-  hipLaunchKernelGGL(k_rk, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, (hipStream_t)stream, d, ra);
-  return launched();
+  hipStream_t s = (hipStream_t)stream;
+  return timed(KT_RK, s, [&] { hipLaunchKernelGGL(k_rk, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, s, d, ra); });
 }
 
 int asterx_zero(double* buf, int64_t count, void* stream) {
   if (!buf || count < 1) return fail(ASTERX_EARG, "zero: bad arguments");
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, (hipStream_t)stream, buf,
-                     (long long)count);
-  return launched();
+  hipStream_t s = (hipStream_t)stream;
+  return timed(KT_ZERO, s, [&] {
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, buf, (long long)count);
+  });
 }
 
 }  // extern "C"
