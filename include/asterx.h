@@ -119,6 +119,12 @@ int asterx_c2p(const asterx_grid* g, const asterx_params* p, const double* metri
  * LINEAR: linear extrapolation from the two nearest owned indices. */
 int asterx_fill_ghosts(const asterx_grid* g, double* f, int32_t nf, const int32_t* kinds, void* stream);
 
+/* Periodic ghost fill of nf <= 3 fields with a constant added per period of wrap:
+ * f(s) = f(s mod n) + shift[q*3 + d] * floor(s / n) for field q along axis d.  This is the
+ * periodic image of a vector potential A = B_mean x r / 2 + (periodic part) of a field with
+ * a uniform mean.  shift: host double[nf*3]. */
+int asterx_fill_ghosts_shift(const asterx_grid* g, double* f, int32_t nf, const double* shift, void* stream);
+
 /* Right-hand side of the 9 evolved fields on owned points (Sec. 2.2 eq. fluxconseqs and
  * grmhdsrc; Sec. 3.3 reconstruction + HLLE; Sec. 3.4 FCT electric field, gauge terms and
  * the Psi equation; Sec. 3.12 workflow).  Reads prim on ng ghost layers, A on ng layers,
@@ -139,6 +145,72 @@ int asterx_rk_stage(const asterx_grid* g, int32_t nterms, const double* a, const
 /* Sets red[0..1] to 0 (device double[2]); a kernel, not a memset, so that it can be
  * recorded in a captured graph. */
 int asterx_zero(double* buf, int64_t count, void* stream);
+
+/* ---- Batches of patches ----------------------------------------------------------------
+ * Many blocks ("patches", e.g. the boxes of a mesh-refinement hierarchy, each with its own
+ * n, ld and dx) advanced together: every phase is one launch of a persistent grid whose
+ * workgroups walk a precomputed list of (patch, tile) work items, instead of one launch per
+ * patch.  Arrays of a batch are field-major pools: field f of patch p starts at
+ * f * asterx_batch_points(b) + asterx_batch_offset(b, p) and uses the patch's own padded
+ * index space from there (the single-block layout with the pool's field stride).  The
+ * batch calls have the single-block semantics on every patch. */
+typedef struct asterx_batch asterx_batch;
+
+/* Schedule of the persistent launches: workgroups per compute unit, and the order of the
+ * work list (0: patches as given; 1: largest patch first; 2: round robin over patches,
+ * largest first). */
+typedef struct {
+  int32_t blocks_per_cu;
+  int32_t order;
+} asterx_batch_tuning;
+
+/* Creates the work lists (host memory, plus small device tables it allocates and
+ * asterx_batch_destroy frees; the only allocating calls of the library).  grids: host
+ * array of npatches descriptors (ng >= 3 each); tuning may be NULL (4 per CU, order 1). */
+int asterx_batch_create(int32_t npatches, const asterx_grid* grids, const asterx_batch_tuning* tuning,
+                        asterx_batch** out);
+int asterx_batch_destroy(asterx_batch* b);
+int64_t asterx_batch_points(const asterx_batch* b);
+int64_t asterx_batch_offset(const asterx_batch* b, int32_t p);
+size_t asterx_batch_workspace_size(const asterx_batch* b);
+int asterx_batch_prim2con(const asterx_batch* b, const asterx_params* p, const double* metric, const double* A,
+                          const double* prim, double* cons, void* stream);
+int asterx_batch_c2p(const asterx_batch* b, const asterx_params* p, const double* metric, const double* A,
+                     double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats, void* stream);
+int asterx_batch_fill_ghosts(const asterx_batch* b, double* f, int32_t nf, const int32_t* kinds, void* stream);
+int asterx_batch_rhs(const asterx_batch* b, const asterx_params* p, const double* metric, const double* curv,
+                     const double* prim, const double* A, const double* psi, double dt_max, double* rhs, double* red,
+                     void* workspace, size_t ws_bytes, void* stream);
+int asterx_batch_rk_stage(const asterx_batch* b, int32_t nterms, const double* a, const double* const* u,
+                          double b_dt, const double* rhs, double* out, void* stream);
+
+/* ---- Adjoint (reverse mode) ---------------------------------------------------------------
+ * Vector-Jacobian products for differentiating whole RK steps with respect to the state and
+ * the adiabatic index.  Periodic blocks only (every axis; n > ng): the transposed ghost fill
+ * is the periodic one.  The forward maps are evaluated again inside these calls (c2p warm-
+ * started from prim_guess); inputs are not modified.  Cotangent outputs are ACCUMULATED
+ * (+=) on owned points; gamma_bar is a device double[1], accumulated.  Non-smooth points
+ * take the active branch (an exact tie of the two HLLE sides splits evenly); converged
+ * iterations are differentiated implicitly.  workspace: asterx_adjoint_workspace_size. */
+size_t asterx_adjoint_workspace_size(const asterx_grid* g);
+
+/* L(U) = rhs(fill(c2p(cons, A)), A, psi) (the right-hand side of asterx_rhs with the c2p that
+ * precedes it in a stage).  Given rhs_bar (9 fields, owned points), adds L^T rhs_bar to
+ * cons_bar (5), A_bar (3), psi_bar (1) and gamma_bar. */
+int asterx_rhs_adjoint(const asterx_grid* g, const asterx_params* p, const double* metric, const double* curv,
+                       const double* cons, const double* prim_guess, const double* A, const double* psi,
+                       double dt_max, const double* rhs_bar, double* cons_bar, double* A_bar, double* psi_bar,
+                       double* gamma_bar, void* workspace, size_t ws_bytes, void* stream);
+
+/* prim = c2p(cons, A): given prim_bar (5 fields, owned), adds to cons_bar, A_bar, gamma_bar. */
+int asterx_c2p_adjoint(const asterx_grid* g, const asterx_params* p, const double* metric, const double* cons,
+                       const double* prim_guess, const double* A, const double* prim_bar, double* cons_bar,
+                       double* A_bar, double* gamma_bar, void* workspace, size_t ws_bytes, void* stream);
+
+/* cons = prim2con(prim, A): given cons_bar (5 fields, owned), adds to prim_bar, A_bar, gamma_bar. */
+int asterx_prim2con_adjoint(const asterx_grid* g, const asterx_params* p, const double* metric, const double* A,
+                            const double* prim, const double* cons_bar, double* prim_bar, double* A_bar,
+                            double* gamma_bar, void* workspace, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing (diagnostics).  When enabled, every launch of the library is bracketed
  * by two HIP events on its stream; asterx_timing_read waits for the recorded events and

@@ -971,7 +971,7 @@ template <class T> void c2p_grid(const Grid& g, const Params& P, const T& gam, c
 
 // Ghost fill of nf fields, axis by axis over the full extent of the other
 // axes (so edges and corners are filled).  kind per axis.
-template <class T> void fill_ghosts(const Grid& g, T* f, int nf, const int kinds[3]) {
+template <class T> void fill_ghosts(const Grid& g, T* f, int nf, const int kinds[3], const double* shift = nullptr) {
   size_t N = npts(g);
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) { lo[d] = -g.ng; hi[d] = g.n[d] + g.ng; }
@@ -991,6 +991,8 @@ template <class T> void fill_ghosts(const Grid& g, T* f, int nf, const int kinds
             if (kinds[d] == BC_PERIODIC) {
               src0[d] = ((s % n) + n) % n;  // periodic image (also for blocks thinner than the ghost width)
               val = F[at(g, src0[0], src0[1], src0[2])];
+              // a potential of a field with a uniform mean changes by a constant per period
+              if (shift && q < 3) val = val + T(shift[q * 3 + d] * (double)((s - src0[d]) / n));
             } else if (kinds[d] == BC_COPY) {
               src0[d] = s < 0 ? 0 : n - 1;
               val = F[at(g, src0[0], src0[1], src0[2])];
@@ -1234,12 +1236,13 @@ template <class T> void rk_combine(const Grid& g, int nterms, const double* a, c
 // state: 9 fields (Dt, St_x, St_y, St_z, taut, A_x, A_y, A_z, Psi).
 template <class T> void run_steps(const Grid& g, const Params& P, const T& gam, const T* metric, const T* curv, T* state,
                                   T* prim, double dt, int nsteps, int rk, const int bc_cell[3], const int bc_A[3],
-                                  uint8_t* flags, unsigned long long* stats, double* redmax) {
+                                  uint8_t* flags, unsigned long long* stats, double* redmax,
+                                  const double* shiftA = nullptr) {
   size_t N = npts(g);
   std::vector<T> U0(9 * N), U1(9 * N), U2(9 * N), U3(9 * N), k1(9 * N), k2(9 * N), k3(9 * N), k4(9 * N);
   auto fill_state = [&](T* U) {
     fill_ghosts(g, U, 5, bc_cell);
-    fill_ghosts(g, U + 5 * N, 3, bc_A);
+    fill_ghosts(g, U + 5 * N, 3, bc_A, shiftA);
     fill_ghosts(g, U + 8 * N, 1, bc_cell);
   };
   auto stage = [&](T* U, T* k) {
@@ -1314,6 +1317,11 @@ void orc_c2p(const Grid* g, const Params* P, const double* metric, const double*
 
 void orc_fill_ghosts(const Grid* g, double* f, int nf, const int* kinds) { fill_ghosts<double>(*g, f, nf, kinds); }
 
+void orc_fill_ghosts_shift(const Grid* g, double* f, int nf, const double* shift) {
+  const int per[3] = {BC_PERIODIC, BC_PERIODIC, BC_PERIODIC};
+  fill_ghosts<double>(*g, f, nf, per, shift);
+}
+
 void orc_rhs(const Grid* g, const Params* P, const double* metric, const double* curv, const double* prim,
              const double* A, const double* psi, double dt_max, double* rhs, double* red, long long* nfix) {
   rhs_grid<double>(*g, *P, P->gamma, metric, curv, prim, A, psi, dt_max, rhs, red, nfix);
@@ -1321,8 +1329,9 @@ void orc_rhs(const Grid* g, const Params* P, const double* metric, const double*
 
 void orc_run(const Grid* g, const Params* P, const double* metric, const double* curv, double* state, double* prim,
              double dt, int nsteps, int rk, const int* bc_cell, const int* bc_A, uint8_t* flags,
-             unsigned long long* stats, double* redmax) {
-  run_steps<double>(*g, *P, P->gamma, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A, flags, stats, redmax);
+             unsigned long long* stats, double* redmax, const double* shiftA) {
+  run_steps<double>(*g, *P, P->gamma, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A, flags, stats, redmax,
+                    shiftA);
 }
 
 void orc_rk_stage(const Grid* g, int nterms, const double* a, const double* const* u, double b_dt, const double* rhs,

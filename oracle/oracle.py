@@ -112,6 +112,13 @@ def c2p(layout, params, metric, A, cons, prim):
     return flags, stats
 
 
+def fill_ghosts_shift(layout, f, shift):
+    """Periodic fill of f (nf <= 3 fields) with shift[q, d] added per period of wrap along axis d."""
+    nf = f.shape[0] if f.ndim == 4 else 1
+    sh = np.ascontiguousarray(np.asarray(shift, dtype=np.float64)[:nf])
+    lib().orc_fill_ghosts_shift(ctypes.byref(make_grid(layout)), _p(f), ctypes.c_int(nf), _p(sh))
+
+
 def fill_ghosts(layout, f, kinds):
     kinds = [BC[k] if isinstance(k, str) else k for k in kinds]
     karr = (ctypes.c_int * 3)(*kinds)
@@ -136,16 +143,19 @@ def rk_stage(layout, a, us, b_dt, rhs_arr, out):
                        _p(rhs_arr), _p(out))
 
 
-def run(layout, params, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A):
-    """Advance state (9 fields) and prim in place by nsteps.  Returns (flags, stats, redmax)."""
+def run(layout, params, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A, A_shift=None):
+    """Advance state (9 fields) and prim in place by nsteps.  Returns (flags, stats, redmax).
+    A_shift (3x3, optional): periodic fill of A with A_shift[q, d] added per period along axis d."""
     flags = np.zeros(layout.shape3, dtype=np.uint8)
     stats = np.zeros(6, dtype=np.uint64)
     redmax = np.zeros(2, dtype=np.float64)
     bcc = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_cell])
     bca = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_A])
+    sh = None if A_shift is None else np.ascontiguousarray(A_shift, dtype=np.float64)
     lib().orc_run(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), _p(metric), _p(curv),
                   _p(state), _p(prim), ctypes.c_double(dt), ctypes.c_int(nsteps), ctypes.c_int(rk), bcc, bca,
-                  flags.ctypes.data_as(ctypes.c_void_p), stats.ctypes.data_as(ctypes.c_void_p), _p(redmax))
+                  flags.ctypes.data_as(ctypes.c_void_p), stats.ctypes.data_as(ctypes.c_void_p), _p(redmax),
+                  None if sh is None else _p(sh))
     return flags, stats, redmax
 
 

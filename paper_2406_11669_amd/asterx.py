@@ -8,6 +8,7 @@ fails with an error.
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 from . import workloads as W
@@ -27,6 +28,10 @@ class Grid(ctypes.Structure):
                 ("pad_", ctypes.c_int32), ("dx", ctypes.c_double * 3)]
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("rho_atm", ctypes.c_double), ("k_atm", ctypes.c_double),
                 ("xi", ctypes.c_double), ("c2p_tol", ctypes.c_double), ("wmax", ctypes.c_double),
@@ -38,8 +43,11 @@ class Params(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "asterx_prim2con", "asterx_c2p",
-           "asterx_fill_ghosts", "asterx_rhs", "asterx_rk_stage", "asterx_zero", "asterx_timing_enable",
-           "asterx_timing_read", "asterx_timing_reset", "asterx_timing_name"]
+           "asterx_fill_ghosts", "asterx_fill_ghosts_shift", "asterx_rhs", "asterx_rk_stage", "asterx_zero", "asterx_timing_enable",
+           "asterx_timing_read", "asterx_timing_reset", "asterx_timing_name", "asterx_batch_create",
+           "asterx_batch_destroy", "asterx_batch_points", "asterx_batch_offset", "asterx_batch_workspace_size",
+           "asterx_batch_prim2con", "asterx_batch_c2p", "asterx_batch_fill_ghosts", "asterx_batch_rhs",
+           "asterx_batch_rk_stage"]
 
 
 def lib():
@@ -57,6 +65,7 @@ def lib():
         L.asterx_prim2con.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.asterx_c2p.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.asterx_fill_ghosts.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
+        L.asterx_fill_ghosts_shift.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
         L.asterx_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
         L.asterx_rk_stage.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
         L.asterx_zero.argtypes = [vp, ctypes.c_int64, vp]
@@ -64,6 +73,20 @@ def lib():
         L.asterx_timing_read.argtypes = [vp, vp, ctypes.c_int32]
         L.asterx_timing_name.restype = ctypes.c_char_p
         L.asterx_timing_name.argtypes = [ctypes.c_int32]
+        L.asterx_batch_create.argtypes = [ctypes.c_int32, vp, vp, vp]
+        L.asterx_batch_destroy.argtypes = [vp]
+        L.asterx_batch_points.restype = ctypes.c_int64
+        L.asterx_batch_points.argtypes = [vp]
+        L.asterx_batch_offset.restype = ctypes.c_int64
+        L.asterx_batch_offset.argtypes = [vp, ctypes.c_int32]
+        L.asterx_batch_workspace_size.restype = ctypes.c_size_t
+        L.asterx_batch_workspace_size.argtypes = [vp]
+        L.asterx_batch_prim2con.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.asterx_batch_c2p.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.asterx_batch_fill_ghosts.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
+        L.asterx_batch_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t,
+                                       vp]
+        L.asterx_batch_rk_stage.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -129,6 +152,13 @@ def c2p(layout, params, metric, A, cons, prim, flags=None, stats=None, stream=No
     _check(lib().asterx_c2p(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
                             _ptr(_f64(metric)), _ptr(_f64(A)), _ptr(_f64(cons)), _ptr(_f64(prim)), _ptr(flags),
                             _ptr(stats), _stream(stream)))
+
+
+def fill_ghosts_shift(layout, f, shift, stream=None):
+    """Periodic ghost fill of f (nf <= 3 fields) plus shift[q, d] per period of wrap along axis d."""
+    nf = f.shape[0] if f.dim() == 4 else 1
+    sh = (ctypes.c_double * (3 * nf))(*np.asarray(shift, dtype=np.float64)[:nf].ravel().tolist())
+    _check(lib().asterx_fill_ghosts_shift(ctypes.byref(make_grid(layout)), _ptr(_f64(f)), nf, sh, _stream(stream)))
 
 
 def fill_ghosts(layout, f, kinds, stream=None):
@@ -210,7 +240,10 @@ class Block:
 
     def fill_state(self, U):
         fill_ghosts(self.L, U[0:5], self.wl.bc_cell)
-        fill_ghosts(self.L, U[5:8], self.wl.bc_A)
+        if self.wl.A_shift is not None:
+            fill_ghosts_shift(self.L, U[5:8], self.wl.A_shift)
+        else:
+            fill_ghosts(self.L, U[5:8], self.wl.bc_A)
         fill_ghosts(self.L, U[8:9], self.wl.bc_cell)
 
     def eval_rhs(self, U, out):
@@ -256,3 +289,113 @@ class Block:
     @property
     def stages_per_step(self):
         return 2 if self.wl.rk == 2 else 4
+
+
+# ---- batches of patches (one persistent launch per phase for all patches) -----------------------------------
+
+class Batch:
+    """A set of patches advanced together through the asterx_batch_* entry points.
+
+    Arrays are field-major pools of shape (nfields, points) with points = sum of the patches' padded
+    sizes; patch p's field f is the slice [f, off[p] : off[p] + npts_p], laid out like a single block."""
+
+    def __init__(self, workloads, tuning=(4, 1), device="cuda"):
+        self.wls = list(workloads)
+        n = len(self.wls)
+        grids = (Grid * n)(*[make_grid(w.layout) for w in self.wls])
+        tun = BatchTuning(int(tuning[0]), int(tuning[1]))
+        h = ctypes.c_void_p()
+        _check(lib().asterx_batch_create(n, grids, ctypes.byref(tun), ctypes.byref(h)))
+        self.h = h
+        self.tuning = tuning
+        self.ntot = lib().asterx_batch_points(h)
+        self.off = [lib().asterx_batch_offset(h, p) for p in range(n)]
+        w0 = self.wls[0]
+        self.params = w0.params
+        self.bc_cell, self.bc_A = w0.bc_cell, w0.bc_A
+        self.dt = w0.dt
+        dev = torch.device(device)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.metric = self._pack([w.metric for w in self.wls], 10, dev)
+        self.curv = self._pack([w.curv for w in self.wls], 6, dev)
+        self.prim = self._pack([w.prim for w in self.wls], 5, dev)
+        self.state = torch.zeros((9, self.ntot), **f64)
+        self.state[5:8] = self._pack([w.A for w in self.wls], 3, dev)
+        self.state[8:9] = self._pack([w.psi for w in self.wls], 1, dev)
+        self.tmp = torch.zeros_like(self.state)
+        self.k = torch.zeros_like(self.state)
+        self.ws = torch.empty(lib().asterx_batch_workspace_size(h) // 8, **f64)
+        self.red = torch.zeros(2, **f64)
+        self.stats = torch.zeros(6, dtype=torch.int64, device=dev)
+        self.flags = torch.zeros(self.ntot, dtype=torch.uint8, device=dev)
+        self._call("asterx_batch_prim2con", self._P(), _ptr(self.metric), _ptr(self.state[5:8]), _ptr(self.prim),
+                   _ptr(self.state[0:5]), _stream(None))
+        self.fill(self.state[0:5], self.bc_cell)
+
+    def _pack(self, arrays, nf, dev):
+        import numpy as np
+        out = np.zeros((nf, self.ntot))
+        for a, o in zip(arrays, self.off):
+            out[:, o:o + a[0].size] = a.reshape(nf, -1)
+        return torch.from_numpy(out).to(dev)
+
+    def unpack(self, pool, p):
+        """Patch p's view of a pool as (nf, ld2, ld1, ld0)."""
+        L = self.wls[p].layout
+        o = self.off[p]
+        return pool[:, o:o + L.npts].reshape((pool.shape[0],) + L.shape3)
+
+    def _P(self):
+        return ctypes.byref(make_params(self.params))
+
+    def _call(self, name, *args):
+        _check(getattr(lib(), name)(self.h, *args))
+
+    def fill(self, f, kinds):
+        karr = (ctypes.c_int32 * 3)(*[BC[k] if isinstance(k, str) else int(k) for k in kinds])
+        self._call("asterx_batch_fill_ghosts", _ptr(f), f.shape[0], karr, _stream(None))
+
+    def fill_state(self, U):
+        self.fill(U[0:5], self.bc_cell)
+        self.fill(U[5:8], self.bc_A)
+        self.fill(U[8:9], self.bc_cell)
+
+    def rk(self, a, us, b_dt, rhs_t, out):
+        n = len(a)
+        arr_a = (ctypes.c_double * n)(*[float(x) for x in a])
+        arr_u = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+        self._call("asterx_batch_rk_stage", n, arr_a, arr_u, float(b_dt), _ptr(rhs_t), _ptr(out), _stream(None))
+
+    def eval_rhs(self, U, out):
+        self._call("asterx_batch_c2p", self._P(), _ptr(self.metric), _ptr(U[5:8]), _ptr(U[0:5]), _ptr(self.prim),
+                   _ptr(self.flags), _ptr(self.stats), _stream(None))
+        self.fill(self.prim, self.bc_cell)
+        self._call("asterx_batch_rhs", self._P(), _ptr(self.metric), _ptr(self.curv), _ptr(self.prim), _ptr(U[5:8]),
+                   _ptr(U[8:9]), float(self.dt), _ptr(out), _ptr(self.red), _ptr(self.ws),
+                   self.ws.numel() * 8, _stream(None))
+
+    def step(self):
+        """One Heun (RK2) step of every patch."""
+        U0, U1, K, dt = self.state, self.tmp, self.k, self.dt
+        self.eval_rhs(U0, K)
+        self.rk([1.0], [U0], dt, K, U1)
+        self.fill_state(U1)
+        self.eval_rhs(U1, K)
+        self.rk([0.5, 0.5], [U0, U1], 0.5 * dt, K, U0)
+        self.fill_state(U0)
+
+    def run(self, nsteps):
+        for _ in range(nsteps):
+            self.step()
+
+    @property
+    def interior_cells(self):
+        return sum(w.layout.n[0] * w.layout.n[1] * w.layout.n[2] for w in self.wls)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().asterx_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass

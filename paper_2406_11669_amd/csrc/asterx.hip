@@ -16,6 +16,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,9 @@ using namespace ax;
 namespace {
 
 thread_local std::string g_err;
+
+// rhs workspace: centre field (3) + face fluxes (3 directions x 7) + G_A (1) + F_Psi (3)
+constexpr int WS_FIELDS = 3 + 21 + 1 + 3;
 
 int fail(int code, const char* msg) {
   g_err = msg;
@@ -72,14 +76,13 @@ DEV unsigned xcd_block(unsigned bid, unsigned nblocks) {
   return start + r;
 }
 
-// Linear tile decomposition of a 3-D box of extents e[3] into blocks of TX x TY x 1.
+// Linear tile decomposition of a 3-D box of extents e[3] into tiles of TX x TY x 1; `tile`
+// is the logical tile index, `tid` the thread's index inside the tile.
 template <int TX, int TY>
-DEV bool box_index_t(const int e[3], unsigned tid, int& a, int& b, int& c) {
+DEV bool box_at(const int e[3], unsigned tile, unsigned tid, int& a, int& b, int& c) {
   unsigned nbx = (e[0] + TX - 1) / TX, nby = (e[1] + TY - 1) / TY;
-  unsigned nblocks = nbx * nby * (unsigned)e[2];
-  unsigned bid = xcd_block(blockIdx.x, nblocks);
-  unsigned bx = bid % nbx;
-  unsigned t = bid / nbx;
+  unsigned bx = tile % nbx;
+  unsigned t = tile / nbx;
   unsigned by = t % nby;
   c = (int)(t / nby);
   a = (int)(bx * TX + tid % TX);
@@ -87,10 +90,8 @@ DEV bool box_index_t(const int e[3], unsigned tid, int& a, int& b, int& c) {
   return a < e[0] && b < e[1] && c < e[2];
 }
 
-template <int TX, int TY>
-DEV bool box_index(const int e[3], int& a, int& b, int& c) {
-  return box_index_t<TX, TY>(e, threadIdx.x, a, b, c);
-}
+// Logical tile of a one-tile-per-workgroup launch.
+DEV unsigned my_tile() { return xcd_block(blockIdx.x, gridDim.x); }
 
 template <int TX, int TY>
 unsigned box_blocks(const int e[3]) {
@@ -200,10 +201,9 @@ struct TileCell {
   bool valid;
 };
 
-DEV TileCell tile_cell(const GD& g) {
+DEV TileCell tile_cell(const GD& g, unsigned bid) {
   TileCell t;
-  int ntx = (g.n[0] + CTX - 1) / CTX, nty = (g.n[1] + CTY - 1) / CTY, ntz = (g.n[2] + CTZ - 1) / CTZ;
-  unsigned bid = xcd_block(blockIdx.x, (unsigned)(ntx * nty * ntz));
+  int ntx = (g.n[0] + CTX - 1) / CTX, nty = (g.n[1] + CTY - 1) / CTY;
   t.i0 = (int)(bid % ntx) * CTX;
   t.j0 = (int)((bid / ntx) % nty) * CTY;
   t.k0 = (int)(bid / (ntx * nty)) * CTZ;
@@ -218,57 +218,104 @@ unsigned tile_blocks(const GD& g) {
   return (unsigned)(((g.n[0] + CTX - 1) / CTX) * ((g.n[1] + CTY - 1) / CTY) * ((g.n[2] + CTZ - 1) / CTZ));
 }
 
-// Stage vertices i0-1 .. i0+CTX+1 (etc.) of field f; vertices no owned cell needs (beyond
-// n+1, in a ragged last tile) are not read.
-DEV void stage_vertices(const GD& g, const double* __restrict__ f, const TileCell& t, double* sv) {
-  for (int q = threadIdx.x; q < NV; q += 256) {
+// The vertex tile of one component spans vertices i0-1 .. i0+CTX+1 (etc.).  Each thread
+// fetches its (at most four) points into registers first, so that the global loads of the
+// next component are in flight while the current one is interpolated; vertices no owned
+// cell needs (beyond n+1, in a ragged last tile) are not read.  All per-thread offsets of
+// the fetch and of the three passes are computed once per tile.
+constexpr int NFETCH = (NV + 255) / 256;
+constexpr int NZR = (NZP + 255) / 256;
+constexpr int NYR = (NYP + 255) / 256;
+
+struct TileIdx {
+  int fetch[NFETCH];  // point index of the fetched vertex, -1 if none
+  int zsrc[NZR];      // z pass: first source in S.v, -1 if no item
+  int ysrc[NYR];      // y pass: first source in S.z, -1 if no item
+  int xsrc;           // x pass: first source in S.y
+};
+
+DEV TileIdx tile_index(const GD& g, const TileCell& t) {
+  TileIdx x;
+#pragma unroll
+  for (int r = 0; r < NFETCH; ++r) {
+    int q = threadIdx.x + 256 * r;
     int vx = q % VX, vy = (q / VX) % VY, vz = q / (VX * VY);
     int i = t.i0 - 1 + vx, j = t.j0 - 1 + vy, k = t.k0 - 1 + vz;
-    sv[q] = (i <= g.n[0] + 1 && j <= g.n[1] + 1 && k <= g.n[2] + 1) ? f[at(g, i, j, k)] : 0.0;
+    bool in = q < NV && i <= g.n[0] + 1 && j <= g.n[1] + 1 && k <= g.n[2] + 1;
+    x.fetch[r] = in ? at(g, i, j, k) : (q < NV ? -2 : -1);
   }
+#pragma unroll
+  for (int r = 0; r < NZR; ++r) {
+    int q = threadIdx.x + 256 * r;
+    int vx = q % VX, vy = (q / VX) % VY, z = q / (VX * VY);
+    x.zsrc[r] = q < NZP ? vx + VX * (vy + VY * z) : -1;
+  }
+#pragma unroll
+  for (int r = 0; r < NYR; ++r) {
+    int q = threadIdx.x + 256 * r;
+    int vx = q % VX, y = (q / VX) % CTY, z = q / (VX * CTY);
+    x.ysrc[r] = q < NYP ? vx + VX * (y + VY * z) : -1;
+  }
+  x.xsrc = t.cx + VX * (t.cy + CTY * t.cz);
+  return x;
+}
+
+DEV void tile_fetch(const double* __restrict__ f, const TileIdx& x, double pre[NFETCH]) {
+#pragma unroll
+  for (int r = 0; r < NFETCH; ++r) pre[r] = x.fetch[r] >= 0 ? f[x.fetch[r]] : 0.0;
+}
+
+DEV void tile_store(const TileIdx& x, const double pre[NFETCH], double* sv) {
+#pragma unroll
+  for (int r = 0; r < NFETCH; ++r)
+    if (x.fetch[r] != -1) sv[threadIdx.x + 256 * r] = pre[r];
 }
 
 // Centre value of the staged component (every thread of the block must call it).
-DEV double tile_value(TileLDS& S, const TileCell& t) {
+DEV double tile_value(TileLDS& S, const TileIdx& x) {
   __syncthreads();
-  for (int q = threadIdx.x; q < NZP; q += 256) {
-    int vx = q % VX, vy = (q / VX) % VY, z = q / (VX * VY);
-    const double* p = S.v + vx + VX * (vy + VY * z);
-    S.z[q] = lag(p[0], p[VX * VY], p[2 * VX * VY], p[3 * VX * VY]);
-  }
+#pragma unroll
+  for (int r = 0; r < NZR; ++r)
+    if (x.zsrc[r] >= 0) {
+      const double* p = S.v + x.zsrc[r];
+      S.z[threadIdx.x + 256 * r] = lag(p[0], p[VX * VY], p[2 * VX * VY], p[3 * VX * VY]);
+    }
   __syncthreads();
-  for (int q = threadIdx.x; q < NYP; q += 256) {
-    int vx = q % VX, y = (q / VX) % CTY, z = q / (VX * CTY);
-    const double* p = S.z + vx + VX * (y + VY * z);
-    S.y[q] = lag(p[0], p[VX], p[2 * VX], p[3 * VX]);
-  }
+#pragma unroll
+  for (int r = 0; r < NYR; ++r)
+    if (x.ysrc[r] >= 0) {
+      const double* p = S.z + x.ysrc[r];
+      S.y[threadIdx.x + 256 * r] = lag(p[0], p[VX], p[2 * VX], p[3 * VX]);
+    }
   __syncthreads();
-  const double* p = S.y + t.cx + VX * (t.cy + CTY * t.cz);
+  const double* p = S.y + x.xsrc;
   return lag(p[0], p[1], p[2], p[3]);
 }
 
 // Centre derivatives (d/dx, d/dy, d/dz, scaled) of the staged component.
-DEV void tile_derivs(TileLDS& S, const TileCell& t, const GD& g, double d[3]) {
+DEV void tile_derivs(TileLDS& S, const TileIdx& x, const GD& g, double d[3]) {
   __syncthreads();
-  for (int q = threadIdx.x; q < NZP; q += 256) {
-    int vx = q % VX, vy = (q / VX) % VY, z = q / (VX * VY);
-    const double* p = S.v + vx + VX * (vy + VY * z);
-    double a = p[0], b = p[VX * VY], c = p[2 * VX * VY], e = p[3 * VX * VY];
-    S.z[q] = lag(a, b, c, e);
-    S.z[NZP + q] = dlag(a, b, c, e);
-  }
+#pragma unroll
+  for (int r = 0; r < NZR; ++r)
+    if (x.zsrc[r] >= 0) {
+      const double* p = S.v + x.zsrc[r];
+      double a = p[0], b = p[VX * VY], c = p[2 * VX * VY], e = p[3 * VX * VY];
+      S.z[threadIdx.x + 256 * r] = lag(a, b, c, e);
+      S.z[NZP + threadIdx.x + 256 * r] = dlag(a, b, c, e);
+    }
   __syncthreads();
-  for (int q = threadIdx.x; q < NYP; q += 256) {
-    int vx = q % VX, y = (q / VX) % CTY, z = q / (VX * CTY);
-    const double* p = S.z + vx + VX * (y + VY * z);
-    const double* r = p + NZP;
-    double a = p[0], b = p[VX], c = p[2 * VX], e = p[3 * VX];
-    S.y[q] = lag(a, b, c, e);
-    S.y[NYP + q] = dlag(a, b, c, e);
-    S.y[2 * NYP + q] = lag(r[0], r[VX], r[2 * VX], r[3 * VX]);
-  }
+#pragma unroll
+  for (int r = 0; r < NYR; ++r)
+    if (x.ysrc[r] >= 0) {
+      const double* p = S.z + x.ysrc[r];
+      const double* q = p + NZP;
+      double a = p[0], b = p[VX], c = p[2 * VX], e = p[3 * VX];
+      S.y[threadIdx.x + 256 * r] = lag(a, b, c, e);
+      S.y[NYP + threadIdx.x + 256 * r] = dlag(a, b, c, e);
+      S.y[2 * NYP + threadIdx.x + 256 * r] = lag(q[0], q[VX], q[2 * VX], q[3 * VX]);
+    }
   __syncthreads();
-  const double* p = S.y + t.cx + VX * (t.cy + CTY * t.cz);
+  const double* p = S.y + x.xsrc;
   d[0] = dlag(p[0], p[1], p[2], p[3]) * g.idx[0];
   d[1] = lag(p[NYP], p[NYP + 1], p[NYP + 2], p[NYP + 3]) * g.idx[1];
   d[2] = lag(p[2 * NYP], p[2 * NYP + 1], p[2 * NYP + 2], p[2 * NYP + 3]) * g.idx[2];
@@ -276,11 +323,10 @@ DEV void tile_derivs(TileLDS& S, const TileCell& t, const GD& g, double d[3]) {
 
 // =======================================================================================
 // prim -> cons on owned cells.
-__global__ __launch_bounds__(256) void k_prim2con(GD g, double gam, const double* __restrict__ metric,
-                                                  const double* __restrict__ A, const double* __restrict__ prim,
-                                                  double* __restrict__ cons) {
+DEV void prim2con_body(const GD& g, double gam, const double* __restrict__ metric, const double* __restrict__ A,
+                       const double* __restrict__ prim, double* __restrict__ cons, unsigned tile) {
   int i, j, k;
-  if (!box_index<64, 4>(g.n, i, j, k)) return;
+  if (!box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k)) return;
   int id = at(g, i, j, k);
   double m[10];
   centre_metric(metric, g.N, id - 1 - g.sy - g.sz, g.sy, g.sz, m);
@@ -300,18 +346,32 @@ __global__ __launch_bounds__(256) void k_prim2con(GD g, double gam, const double
 
 // c2p on owned cells, tiled: the ten metric components are interpolated to the centres
 // through LDS (Sec. 3.2), then each thread recovers its cell (Secs. 3.5, 3.6).
-__global__ __launch_bounds__(256) void k_c2p_t(GD g, C2PParams P, const double* __restrict__ metric,
-                                               const double* __restrict__ A, double* __restrict__ cons,
-                                               double* __restrict__ prim, uint8_t* __restrict__ flags,
-                                               unsigned long long* __restrict__ stats) {
-  __shared__ TileLDS S;
-  const TileCell t = tile_cell(g);
-  double m[10];
+struct C2PArgs {
+  const double* metric;
+  const double* A;
+  double* cons;
+  double* prim;
+  uint8_t* flags;
+  unsigned long long* stats;
+};
+
+DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S, unsigned tile) {
+  const double* __restrict__ metric = a.metric;
+  const double* __restrict__ A = a.A;
+  double* __restrict__ cons = a.cons;
+  double* __restrict__ prim = a.prim;
+  uint8_t* __restrict__ flags = a.flags;
+  unsigned long long* __restrict__ stats = a.stats;
+  const TileCell t = tile_cell(g, tile);
+  const TileIdx x = tile_index(g, t);
+  double m[10], pre[NFETCH];
+  tile_fetch(metric, x, pre);
 #pragma unroll
   for (int c = 0; c < 10; ++c) {
-    if (c > 0) __syncthreads();
-    stage_vertices(g, metric + c * g.N, t, S.v);
-    m[c] = tile_value(S, t);
+    // the previous component's passes no longer read S.v (three barriers ago)
+    tile_store(x, pre, S.v);
+    if (c < 9) tile_fetch(metric + (c + 1) * g.N, x, pre);
+    m[c] = tile_value(S, x);
   }
   uint32_t fl = 0;
   int iters = 0;
@@ -352,59 +412,66 @@ struct FillArgs {
   int nf;
   int d;
   int kind;
+  double shift[3];  // periodic kind: added per period of wrap, for fields 0..2 (else 0)
 };
 
-__global__ __launch_bounds__(256) void k_fill(GD g, FillArgs a) {
+// Ghost points along axis d: the ghost index set of axis d times the full extents of the
+// other two axes; one thread per point, looping over the nf fields.
+DEV long long fill_points(const GD& g, int d) {
+  long long cnt = 2 * g.ng + 1;
+  for (int t = 0; t < 3; ++t)
+    if (t != d) cnt *= (g.n[t] + 2 * g.ng + 1);
+  return cnt;
+}
+
+DEV void fill_body(const GD& g, const FillArgs& a, unsigned tile) {
   // ghost values are a pure function of owned values: no contraction, so that linear
   // extrapolation rounds exactly like its definition (one multiply, then one add)
 #pragma clang fp contract(off)
   const int d = a.d;
-  int ext[3];
-  for (int t = 0; t < 3; ++t) ext[t] = g.n[t] + 2 * g.ng + 1;
-  int nghost = 2 * g.ng + 1;
-  int cnt[3] = {ext[0], ext[1], ext[2]};
-  cnt[d] = nghost;
-  long long total = (long long)cnt[0] * cnt[1] * cnt[2] * a.nf;
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= total) return;
+  int cnt[3] = {g.n[0] + 2 * g.ng + 1, g.n[1] + 2 * g.ng + 1, g.n[2] + 2 * g.ng + 1};
+  cnt[d] = 2 * g.ng + 1;
+  long long tid = (long long)tile * 256 + threadIdx.x;
+  if (tid >= (long long)cnt[0] * cnt[1] * cnt[2]) return;
   int q0 = (int)(tid % cnt[0]);
   long long r = tid / cnt[0];
   int q1 = (int)(r % cnt[1]);
-  r /= cnt[1];
-  int q2 = (int)(r % cnt[2]);
-  int f = (int)(r / cnt[2]);
+  int q2 = (int)(r / cnt[1]);
   int idx[3] = {q0 - g.ng, q1 - g.ng, q2 - g.ng};
   int n = g.n[d];
-  int q = idx[d] + g.ng;  // 0 .. nghost-1
+  int q = idx[d] + g.ng;  // 0 .. 2 ng
   int s = q < g.ng ? q - g.ng : n + (q - g.ng);
   idx[d] = s;
-  double* F = a.f + (size_t)f * g.N;
   int dst = at(g, idx[0], idx[1], idx[2]);
   int stride = d == 0 ? 1 : (d == 1 ? g.sy : g.sz);
-  double val;
-  if (a.kind == ASTERX_BC_PERIODIC) {
-    int src = ((s % n) + n) % n;
-    val = F[dst + (src - s) * stride];
-  } else if (a.kind == ASTERX_BC_COPY) {
-    int src = s < 0 ? 0 : n - 1;
-    val = F[dst + (src - s) * stride];
-  } else {
-    if (s < 0) {
-      double f0 = F[dst - s * stride], f1 = F[dst + (1 - s) * stride];
-      val = f0 + (double)s * (f1 - f0);
+  for (int f = 0; f < a.nf; ++f) {
+    double* F = a.f + (size_t)f * g.N;
+    double val;
+    if (a.kind == ASTERX_BC_PERIODIC) {
+      int src = ((s % n) + n) % n;
+      val = F[dst + (src - s) * stride];
+      if (f < 3 && a.shift[f] != 0.0) val = val + (double)((s - src) / n) * a.shift[f];
+    } else if (a.kind == ASTERX_BC_COPY) {
+      int src = s < 0 ? 0 : n - 1;
+      val = F[dst + (src - s) * stride];
     } else {
-      double f0 = F[dst + (n - 1 - s) * stride], f1 = F[dst + (n - 2 - s) * stride];
-      val = f0 + (double)(s - n + 1) * (f0 - f1);
+      if (s < 0) {
+        double f0 = F[dst - s * stride], f1 = F[dst + (1 - s) * stride];
+        val = f0 + (double)s * (f1 - f0);
+      } else {
+        double f0 = F[dst + (n - 1 - s) * stride], f1 = F[dst + (n - 2 - s) * stride];
+        val = f0 + (double)(s - n + 1) * (f0 - f1);
+      }
     }
+    F[dst] = val;
   }
-  F[dst] = val;
 }
 
 // Centre field of every cell in [-ng, n+ng-1]^3 (read by the face stencils).
-__global__ __launch_bounds__(256) void k_bcent(GD g, const double* __restrict__ A, double* __restrict__ bc) {
+DEV void bcent_body(const GD& g, const double* __restrict__ A, double* __restrict__ bc, unsigned tile) {
   int e[3] = {g.n[0] + 2 * g.ng, g.n[1] + 2 * g.ng, g.n[2] + 2 * g.ng};
   int a, b, c;
-  if (!box_index<64, 4>(e, a, b, c)) return;
+  if (!box_at<64, 4>(e, tile, threadIdx.x, a, b, c)) return;
   int id = at(g, a - g.ng, b - g.ng, c - g.ng);
   double Bt[3];
   centre_B(A, g, id, Bt);
@@ -423,7 +490,7 @@ struct FaceArgs {
   const double* bc;
   double* flux;
   double* red;
-  double gam, weno_eps, weno_q;
+  double gam, weno_eps, weno_q, gfac;
   int recon, speeds;
 };
 
@@ -436,28 +503,29 @@ struct FaceArgs {
 // of a one-lane-per-face kernel, twice the lanes in flight.
 DEV double shfl1(double v) { return __shfl_xor(v, 1, 64); }
 
-DEV double recon_right_face(int kind, const double a[5], double eps, double q) {
-  if (kind == 0) return a[2] + 0.5 * mm(a[2] - a[1], a[3] - a[2]);
-  if (kind == 1) {
-    double s1 = mc_slope(a[0], a[1], a[2]);
-    double s2 = mc_slope(a[1], a[2], a[3]);
-    double s3 = mc_slope(a[2], a[3], a[4]);
+template <int kind, class T>
+DEV T recon_right_face(const T a[5], double eps, double q) {
+  if (kind == ASTERX_RECON_MINMOD) return a[2] + 0.5 * mm(a[2] - a[1], a[3] - a[2]);
+  if (kind == ASTERX_RECON_PPM) {
+    T s1 = mc_slope(a[0], a[1], a[2]);
+    T s2 = mc_slope(a[1], a[2], a[3]);
+    T s3 = mc_slope(a[2], a[3], a[4]);
     const double sixth = 1.0 / 6.0;
-    double fl = 0.5 * (a[1] + a[2]) - (s2 - s1) * sixth;
-    double fr = 0.5 * (a[2] + a[3]) - (s3 - s2) * sixth;
+    T fl = 0.5 * (a[1] + a[2]) - (s2 - s1) * sixth;
+    T fr = 0.5 * (a[2] + a[3]) - (s3 - s2) * sixth;
     ppm_limit(a[2], fl, fr);
     return fr;
   }
   return wenoz_face(a[0], a[1], a[2], a[3], a[4], eps, q);
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_face2(GD g, FaceArgs fa) {
+template <int D, int RECON>
+DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile) {
   constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
   const int side = threadIdx.x & 1;
   int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
   int a, b, c;
-  bool valid = box_index_t<32, 4>(e, threadIdx.x >> 1, a, b, c);
+  bool valid = box_at<32, 4>(e, tile, threadIdx.x >> 1, a, b, c);
   // keep both lanes of a pair valid or invalid together (they share the face)
   double smax = 0.0;
   if (valid) {
@@ -475,7 +543,7 @@ __global__ __launch_bounds__(256) void k_face2(GD g, FaceArgs fa) {
       double s5[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
-      X[v] = recon_right_face(fa.recon, s5, fa.weno_eps, fa.weno_q);
+      X[v] = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
       C[v] = s5[2];
     }
     // face metric: this lane interpolates components [5 side, 5 side + 5)
@@ -521,7 +589,7 @@ __global__ __launch_bounds__(256) void k_face2(GD g, FaceArgs fa) {
     Bt[t1] = X[5];
     Bt[t2] = X[6];
     State S;
-    state_make(G, X, Bt, fa.gam, S);
+    state_make(G, X, Bt, fa.gam, S, fa.gfac);
     double U[7], F[7], cm, cp;
     flux_of<D>(G, S, U, F);
     speeds_of<D>(G, S, fa.gam, fa.speeds, cm, cp);
@@ -536,15 +604,16 @@ __global__ __launch_bounds__(256) void k_face2(GD g, FaceArgs fa) {
     double cmax = fmax(0.0, fmax(cp, cpo));
     double cmin = -fmin(0.0, fmin(cm, cmo));
     double den = cmax + cmin;
+    // (cmin F_R + cmax F_L - cmax cmin (U_R - U_L)) / (cmax + cmin), written from this
+    // lane's point of view (own side, other side) so no per-component side selects
     double id_ = den > 0.0 ? 1.0 / den : 0.0;
     double cc = cmax * cmin;
+    double w_own = den > 0.0 ? (side ? cmin : cmax) * id_ : 0.5;
+    double w_oth = den > 0.0 ? (side ? cmax : cmin) * id_ : 0.5;
+    double w_u = den > 0.0 ? (side ? -cc : cc) * id_ : 0.0;
     double out[7];
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      double UL = side ? Uo[q] : U[q], UR = side ? U[q] : Uo[q];
-      double FL = side ? Fo[q] : F[q], FR = side ? F[q] : Fo[q];
-      out[q] = den > 0.0 ? (cmin * FR + cmax * FL - cc * (UR - UL)) * id_ : 0.5 * (FL + FR);
-    }
+    for (int q = 0; q < 7; ++q) out[q] = w_own * F[q] + w_oth * Fo[q] + w_u * (U[q] - Uo[q]);
     if (side == 0) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = out[q];
@@ -579,15 +648,19 @@ struct CellArgs {
 // 1/2 T^{mu nu} d_j g_{mu nu} is linear in the derivatives of the stored components,
 // sum_c w_c d_j m_c with weights w_c built from T, beta and gamma, so pass 2 takes one
 // component's three derivatives at a time and accumulates them (few live registers).
-__global__ __launch_bounds__(256) void k_cell_t(GD g, CellArgs ca) {
-  __shared__ TileLDS S;
-  const TileCell t = tile_cell(g);
-  double m[10], K[6];
+DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
+  const TileCell t = tile_cell(g, tile);
+  // 26 rounds: values of the 10 metric and 6 curvature components, then derivatives of
+  // the 10 metric components; round r+1's vertex tile is fetched during round r
+  auto comp = [&](int r) { return r < 10 ? ca.metric + r * g.N : (r < 16 ? ca.curv + (r - 10) * g.N : ca.metric + (r - 16) * g.N); };
+  const TileIdx x = tile_index(g, t);
+  double m[10], K[6], pre[NFETCH];
+  tile_fetch(comp(0), x, pre);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    if (c > 0) __syncthreads();
-    stage_vertices(g, c < 10 ? ca.metric + c * g.N : ca.curv + (c - 10) * g.N, t, S.v);
-    double v = tile_value(S, t);
+    tile_store(x, pre, S.v);
+    tile_fetch(comp(c + 1), x, pre);
+    double v = tile_value(S, x);
     if (c < 10) m[c] = v; else K[c - 10] = v;
   }
   const int id = t.valid ? at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz) : 0;
@@ -651,10 +724,10 @@ __global__ __launch_bounds__(256) void k_cell_t(GD g, CellArgs ca) {
   }
 #pragma unroll
   for (int c = 0; c < 10; ++c) {
-    __syncthreads();
-    stage_vertices(g, ca.metric + c * g.N, t, S.v);
+    tile_store(x, pre, S.v);
+    if (c < 9) tile_fetch(comp(17 + c), x, pre);
     double d[3];
-    tile_derivs(S, t, g, d);
+    tile_derivs(S, x, g, d);
     if (t.valid) {
       src[1] += w[c] * d[0];
       src[2] += w[c] * d[1];
@@ -695,12 +768,23 @@ __global__ __launch_bounds__(256) void k_cell_t(GD g, CellArgs ca) {
 // Vertices in [-1, n]^3: G_A = alpha Psi / sqrt(gamma) - beta^j A_j and
 // F_Psi^j = alpha sqrt(gamma) gamma^jk A_k - beta^j Psi, with A averaged to the vertex
 // along its own direction (Sec. 3.4).
-__global__ __launch_bounds__(256) void k_vertex(GD g, const double* __restrict__ metric, const double* __restrict__ A,
-                                                const double* __restrict__ psi, double* __restrict__ ga,
-                                                double* __restrict__ fp) {
+struct VertexArgs {
+  const double* metric;
+  const double* A;
+  const double* psi;
+  double* ga;
+  double* fp;
+};
+
+DEV void vertex_body(const GD& g, const VertexArgs& va, unsigned tile) {
+  const double* __restrict__ metric = va.metric;
+  const double* __restrict__ A = va.A;
+  const double* __restrict__ psi = va.psi;
+  double* __restrict__ ga = va.ga;
+  double* __restrict__ fp = va.fp;
   int e[3] = {g.n[0] + 2, g.n[1] + 2, g.n[2] + 2};
   int a, b, c;
-  if (!box_index<64, 4>(e, a, b, c)) return;
+  if (!box_at<64, 4>(e, tile, threadIdx.x, a, b, c)) return;
   const int id = at(g, a - 1, b - 1, c - 1);
   double m[10];
 #pragma unroll
@@ -732,9 +816,9 @@ struct EdgeArgs {
   int gauge;
 };
 
-__global__ __launch_bounds__(256) void k_edge(GD g, EdgeArgs ea) {
+DEV void edge_body(const GD& g, const EdgeArgs& ea, unsigned tile) {
   int i, j, k;
-  if (!box_index<64, 4>(g.n, i, j, k)) return;
+  if (!box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k)) return;
   const int id = at(g, i, j, k);
   const int sy = g.sy, sz = g.sz;
   const double* Fx_By = ea.flux + (size_t)(0 * 7 + 5) * g.N;
@@ -777,17 +861,877 @@ struct RKArgs {
   double* out;
 };
 
-__global__ __launch_bounds__(256) void k_rk(GD g, RKArgs ra) {
+DEV void rk_body(const GD& g, const RKArgs& ra, unsigned tile) {
   int i, j, k;
-  if (!box_index<64, 4>(g.n, i, j, k)) return;
+  if (!box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k)) return;
   const int id = at(g, i, j, k);
 #pragma unroll
   for (int f = 0; f < 9; ++f) {
     size_t o = (size_t)f * g.N + id;
     double s = ra.b_dt * ra.rhs[o];
-    for (int m = 0; m < ra.nterms; ++m) s += ra.a[m] * ra.u[m][o];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (m < ra.nterms) s += ra.a[m] * ra.u[m][o];
     ra.out[o] = s;
   }
+}
+
+// =======================================================================================
+// Kernels.  Single block: one workgroup per logical tile of the block.  Batched: a
+// persistent grid of workgroups walks a list of (patch, tile) items; every patch is a grid
+// descriptor plus a base offset into field-major pools whose field stride is the total
+// point count of all patches, so the same bodies run unchanged.
+struct PatchDesc {
+  GD g;
+  long long off;
+};
+struct Item {
+  int patch;
+  int tile;
+};
+
+template <class T>
+DEV T* shifted(T* p, long long off) {
+  return p ? p + off : p;
+}
+
+__global__ __launch_bounds__(256) void k_prim2con(GD g, double gam, const double* metric, const double* A,
+                                                  const double* prim, double* cons) {
+  prim2con_body(g, gam, metric, A, prim, cons, my_tile());
+}
+__global__ __launch_bounds__(256) void kb_prim2con(const PatchDesc* __restrict__ P, const Item* __restrict__ it,
+                                                   int nit, double gam, const double* metric, const double* A,
+                                                   const double* prim, double* cons) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    prim2con_body(d.g, gam, metric + d.off, A + d.off, prim + d.off, cons + d.off, (unsigned)m.tile);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_c2p(GD g, C2PParams cp, C2PArgs a) {
+  __shared__ TileLDS S;
+  c2p_body(g, cp, a, S, my_tile());
+}
+__global__ __launch_bounds__(256) void kb_c2p(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
+                                              C2PParams cp, C2PArgs a) {
+  __shared__ TileLDS S;
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    C2PArgs b = a;
+    b.metric = a.metric + d.off;
+    b.A = a.A + d.off;
+    b.cons = a.cons + d.off;
+    b.prim = a.prim + d.off;
+    b.flags = shifted(a.flags, d.off);
+    c2p_body(d.g, cp, b, S, (unsigned)m.tile);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill(GD g, FillArgs a) { fill_body(g, a, blockIdx.x); }
+__global__ __launch_bounds__(256) void kb_fill(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
+                                               FillArgs a) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    FillArgs b = a;
+    b.f = a.f + d.off;
+    fill_body(d.g, b, (unsigned)m.tile);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bcent(GD g, const double* A, double* bc) { bcent_body(g, A, bc, my_tile()); }
+__global__ __launch_bounds__(256) void kb_bcent(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
+                                                const double* A, double* bc) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    bcent_body(d.g, A + d.off, bc + d.off, (unsigned)m.tile);
+  }
+}
+
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_face(GD g, FaceArgs fa) {
+  face_body<D, R>(g, fa, my_tile());
+}
+template <int D, int R>
+__global__ __launch_bounds__(256) void kb_face(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
+                                               FaceArgs fa) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    FaceArgs b = fa;
+    b.metric = fa.metric + d.off;
+    b.prim = fa.prim + d.off;
+    b.A = fa.A + d.off;
+    b.bc = fa.bc + d.off;
+    b.flux = fa.flux + d.off;
+    face_body<D, R>(d.g, b, (unsigned)m.tile);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cell(GD g, CellArgs ca) {
+  __shared__ TileLDS S;
+  cell_body(g, ca, S, my_tile());
+}
+__global__ __launch_bounds__(256) void kb_cell(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
+                                               CellArgs ca) {
+  __shared__ TileLDS S;
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    CellArgs b = ca;
+    b.metric = ca.metric + d.off;
+    b.curv = ca.curv + d.off;
+    b.prim = ca.prim + d.off;
+    b.A = ca.A + d.off;
+    b.bc = ca.bc + d.off;
+    b.flux = ca.flux + d.off;
+    b.rhs = ca.rhs + d.off;
+    cell_body(d.g, b, S, (unsigned)m.tile);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_vertex(GD g, VertexArgs va) { vertex_body(g, va, my_tile()); }
+__global__ __launch_bounds__(256) void kb_vertex(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
+                                                 VertexArgs va) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    VertexArgs b{va.metric + d.off, va.A + d.off, va.psi + d.off, va.ga + d.off, va.fp + d.off};
+    vertex_body(d.g, b, (unsigned)m.tile);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_edge(GD g, EdgeArgs ea) { edge_body(g, ea, my_tile()); }
+__global__ __launch_bounds__(256) void kb_edge(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
+                                               EdgeArgs ea) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    EdgeArgs b = ea;
+    b.metric = ea.metric + d.off;
+    b.psi = ea.psi + d.off;
+    b.flux = ea.flux + d.off;
+    b.ga = ea.ga + d.off;
+    b.fp = ea.fp + d.off;
+    b.rhs = ea.rhs + d.off;
+    edge_body(d.g, b, (unsigned)m.tile);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rk(GD g, RKArgs ra) { rk_body(g, ra, my_tile()); }
+__global__ __launch_bounds__(256) void kb_rk(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
+                                             RKArgs ra) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    RKArgs b = ra;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b.u[q] = shifted(ra.u[q], d.off);
+    b.rhs = ra.rhs + d.off;
+    b.out = ra.out + d.off;
+    rk_body(d.g, b, (unsigned)m.tile);
+  }
+}
+
+// =======================================================================================
+// Adjoint (vector-Jacobian products) of one right-hand side evaluation with its c2p.
+// The linear parts (flux divergence, FCT averages, gauge terms, staggered curl and averages,
+// periodic ghost fills) are transposed exactly; the pointwise nonlinear parts build local
+// Jacobians with dual numbers (forward mode) and contract them with the incoming
+// cotangents; converged iterations (quartic roots, c2p) are differentiated through the
+// implicit-function theorem.  Non-smooth points take the active branch; an exact tie of
+// the two sides in the HLLE max/min splits the cotangent equally (the central derivative).
+
+// Adjoint workspace: fields of the block's index space.
+enum {
+  AW_CONS = 0, AW_PRIM = 5, AW_BC = 10, AW_PBAR = 13, AW_BCBAR = 18, AW_BFBAR = 21, AW_ABAR = 24, AW_PSIBAR = 27,
+  AW_AVBAR = 28, AW_FBAR = 31, AW_FIELDS = 52
+};
+
+DEV bool owned3(const GD& g, int i, int j, int k) {
+  return i >= 0 && j >= 0 && k >= 0 && i < g.n[0] && j < g.n[1] && k < g.n[2];
+}
+
+// Cotangent of one field at (i, j, k) if that point is owned, else 0.
+DEV double rb_at(const GD& g, const double* r, int i, int j, int k) {
+  return owned3(g, i, j, k) ? r[at(g, i, j, k)] : 0.0;
+}
+
+// Face-flux cotangents from the right-hand-side cotangent rbar (9 fields, owned points):
+// hydro components through the divergence, induction components through the FCT averages.
+struct FluxBarArgs {
+  const double* rbar;
+  double* fbar;
+};
+
+DEV void fluxbar_body(const GD& g, const FluxBarArgs& a, unsigned tile) {
+  int e[3] = {g.n[0] + 2, g.n[1] + 2, g.n[2] + 2};
+  int p, q, r;
+  if (!box_at<64, 4>(e, tile, threadIdx.x, p, q, r)) return;
+  const int i = p - 1, j = q - 1, k = r - 1;  // every index in [-1, n]
+  const int id = at(g, i, j, k);
+  const double* R = a.rbar;
+  auto rc = [&](int c, int ii, int jj, int kk) { return rb_at(g, R + (size_t)c * g.N, ii, jj, kk); };
+  const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int d = 0; d < 3; ++d) {
+    const int il = i - off[d][0], jl = j - off[d][1], kl = k - off[d][2];
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+      a.fbar[(size_t)(d * 7 + c) * g.N + id] = (rc(c, il, jl, kl) - rc(c, i, j, k)) * g.idx[d];
+  }
+  // dA/dt = -E: Ebar = -rbar_A; E components are quarter-sums of induction fluxes
+  double* fb = a.fbar;
+  fb[(size_t)(0 * 7 + 5) * g.N + id] = 0.25 * (rc(7, i, j, k) + rc(7, i, j + 1, k));   // Fx_By <- E_z
+  fb[(size_t)(0 * 7 + 6) * g.N + id] = -0.25 * (rc(6, i, j, k) + rc(6, i, j, k + 1));  // Fx_Bz <- E_y
+  fb[(size_t)(1 * 7 + 5) * g.N + id] = 0.25 * (rc(5, i, j, k) + rc(5, i, j, k + 1));   // Fy_Bz <- E_x
+  fb[(size_t)(1 * 7 + 6) * g.N + id] = -0.25 * (rc(7, i, j, k) + rc(7, i + 1, j, k));  // Fy_Bx <- E_z
+  fb[(size_t)(2 * 7 + 5) * g.N + id] = 0.25 * (rc(6, i, j, k) + rc(6, i + 1, j, k));   // Fz_Bx <- E_y
+  fb[(size_t)(2 * 7 + 6) * g.N + id] = -0.25 * (rc(5, i, j, k) + rc(5, i, j + 1, k));  // Fz_By <- E_x
+}
+
+// Local physics of one face side, as a function of (X[7], Bn, Gamma), in dual numbers with
+// the quartic roots already known (their tangents by implicit differentiation).
+template <int D>
+DEV void side_dual(const Geo& G, const Dual X[7], Dual Bn, Dual gam, int kind, double xp, double xm, Dual U[7],
+                   Dual F[7], Dual& cm, Dual& cp) {
+  constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  Dual Bt[3];
+  Bt[D] = Bn;
+  Bt[t1] = X[5];
+  Bt[t2] = X[6];
+  StateT<Dual> S;
+  Dual gfac = gam / (gam - 1.0);
+  state_make(G, X, Bt, gam, S, gfac);
+  flux_of<D>(G, S, U, F);
+  if (kind == 1) {
+    speeds_of<D>(G, S, gam, 1, cm, cp);
+    return;
+  }
+  // dispersion-relation coefficients in dual arithmetic, as in speeds_of
+  double ia = 1.0 / G.alp, bD = G.beta[D], ia2 = ia * ia;
+  Dual uD = S.W * (S.v[D] - bD * ia), u0 = S.W * ia, b0 = S.W * S.Bv * ia;
+  Dual bDc = (S.B[D] + G.alp * b0 * uD) / S.W;
+  Dual cs2 = gam * S.p / S.rhoh;
+  double G0 = G.gu[sym(D, D)] - bD * bD * ia2, G1 = -2.0 * bD * ia2, G2 = -ia2;
+  Dual a0 = uD, a1 = -u0;
+  Dual A4 = S.rhoh * (1.0 - cs2), Bq = S.rhoh * cs2 + S.bsq, Cq = cs2;
+  Dual s0 = a0 * a0, s1 = 2.0 * a0 * a1, s2 = a1 * a1;
+  Dual q0 = bDc * bDc, q1 = -2.0 * bDc * b0, q2 = b0 * b0;
+  Dual c[5];
+  c[0] = A4 * s0 * s0;
+  c[1] = A4 * 2.0 * s0 * s1;
+  c[2] = A4 * (s1 * s1 + 2.0 * s0 * s2);
+  c[3] = A4 * 2.0 * s1 * s2;
+  c[4] = A4 * s2 * s2;
+  Dual r0 = -Bq * s0 + Cq * q0, r1 = -Bq * s1 + Cq * q1, r2 = -Bq * s2 + Cq * q2;
+  c[0] += r0 * G0;
+  c[1] += r0 * G1 + r1 * G0;
+  c[2] += r0 * G2 + r1 * G1 + r2 * G0;
+  c[3] += r1 * G2 + r2 * G1;
+  c[4] += r2 * G2;
+  cp = root_tangent(c, xp);
+  cm = root_tangent(c, xm);
+}
+
+struct FaceAdjArgs {
+  const double* metric;
+  const double* prim;
+  const double* A;
+  const double* bc;
+  const double* fbar;
+  double* pbar;
+  double* bcbar;
+  double* bfbar;
+  double* gbar;
+  double gam, weno_eps, weno_q;
+  int speeds;
+};
+
+template <int D, int RECON>
+DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
+  constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  const int side = threadIdx.x & 1;
+  int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
+  int a, b, c;
+  bool valid = box_at<32, 4>(e, tile, threadIdx.x >> 1, a, b, c);
+  double gsum = 0.0;
+  if (valid) {
+    int ijk[3] = {a - 1, b - 1, c - 1};
+    ijk[D] += 1;
+    const int id = at(g, ijk[0], ijk[1], ijk[2]);
+    const int st[3] = {1, g.sy, g.sz};
+    const int sD = st[D], s1 = st[t1], s2 = st[t2];
+    const int o0 = side ? 2 : -3, os = side ? -1 : 1;
+    // forward recomputation of this lane's side
+    double sten[7][5], X[7];
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) sten[v][q] = f[id + (o0 + os * q) * sD];
+      X[v] = recon_right_face<RECON>(sten[v], fa.weno_eps, fa.weno_q);
+    }
+    double mine[5];
+    const int mb = id - s1 - s2;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const double* p = fa.metric + (size_t)(5 * side + q) * g.N + mb;
+      double rr[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double* row = p + r * s2;
+        rr[r] = lag(row[0], row[s1], row[2 * s1], row[3 * s1]);
+      }
+      mine[q] = lag(rr[0], rr[1], rr[2], rr[3]);
+    }
+    double m[10];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      double other = shfl1(mine[q]);
+      m[q] = side ? other : mine[q];
+      m[5 + q] = side ? mine[q] : other;
+    }
+    Geo G;
+    geo_from(m, G);
+    const double* Ax = fa.A;
+    const double* Ay = fa.A + g.N;
+    const double* Az = fa.A + 2 * g.N;
+    double Bn = D == 0 ? faceBx(Ay, Az, id, g.sy, g.sz, g)
+                       : (D == 1 ? faceBy(Ax, Az, id, g.sy, g.sz, g) : faceBz(Ax, Ay, id, g.sy, g.sz, g));
+    bool fallback;
+    {
+      double vl[3], v[3] = {X[2], X[3], X[4]};
+      lower(G.g, v, vl);
+      double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
+      fallback = !(X[0] > 0.0) || !(X[1] > 0.0) || !(v2 < 1.0);
+      if (fallback) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) X[q] = sten[q][2];
+      }
+    }
+    double Bt[3];
+    Bt[D] = Bn;
+    Bt[t1] = X[5];
+    Bt[t2] = X[6];
+    State S;
+    state_make(G, X, Bt, fa.gam, S);
+    double U[7], F[7], cm, cp;
+    flux_of<D>(G, S, U, F);
+    speeds_of<D>(G, S, fa.gam, fa.speeds, cm, cp);
+    double Uo[7], Fo[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      Uo[q] = shfl1(U[q]);
+      Fo[q] = shfl1(F[q]);
+    }
+    double cmo = shfl1(cm), cpo = shfl1(cp);
+    double cmax = fmax(0.0, fmax(cp, cpo));
+    double cmin = -fmin(0.0, fmin(cm, cmo));
+    double den = cmax + cmin;
+    // HLLE transposed for this lane's side
+    double fbar[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) fbar[q] = fa.fbar[(size_t)(D * 7 + q) * g.N + id];
+    double Ub[7], Fb[7], cmb = 0.0, cpb = 0.0;
+    if (den > 0.0) {
+      double id_ = 1.0 / den, cc = cmax * cmin;
+      double wF = (side ? cmin : cmax) * id_, wU = (side ? -cc : cc) * id_;
+      double dcmax = 0.0, dcmin = 0.0;
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        Fb[q] = fbar[q] * wF;
+        Ub[q] = fbar[q] * wU;
+        double FL = side ? Fo[q] : F[q], FR = side ? F[q] : Fo[q];
+        double UL = side ? Uo[q] : U[q], UR = side ? U[q] : Uo[q];
+        double fo = (cmin * FR + cmax * FL - cc * (UR - UL)) * id_;
+        dcmax += fbar[q] * (FL - cmin * (UR - UL) - fo) * id_;
+        dcmin += fbar[q] * (FR - cmax * (UR - UL) - fo) * id_;
+      }
+      // cmax = max(0, c+_L, c+_R), cmin = -min(0, c-_L, c-_R): to the active side, half each on a tie
+      if (cmax > 0.0) {
+        if (cp == cpo) cpb = 0.5 * dcmax;
+        else if (cp > cpo) cpb = dcmax;
+      }
+      if (cmin > 0.0) {
+        if (cm == cmo) cmb = -0.5 * dcmin;
+        else if (cm < cmo) cmb = -dcmin;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        Fb[q] = 0.5 * fbar[q];
+        Ub[q] = 0.0;
+      }
+    }
+    // local VJP through (X, Bn, Gamma) -> (U, F, c-, c+), one dual pass per input
+    double Xb[7], Bnb = 0.0, gb = 0.0;
+    for (int dir = 0; dir < 9; ++dir) {
+      Dual Xd[7];
+#pragma unroll
+      for (int q = 0; q < 7; ++q) Xd[q] = Dual(X[q], dir == q ? 1.0 : 0.0);
+      Dual Bnd(Bn, dir == 7 ? 1.0 : 0.0), gd(fa.gam, dir == 8 ? 1.0 : 0.0);
+      Dual Ud[7], Fd[7], cmd, cpd;
+      side_dual<D>(G, Xd, Bnd, gd, fa.speeds, cp, cm, Ud, Fd, cmd, cpd);
+      double s = cmb * cmd.d + cpb * cpd.d;
+#pragma unroll
+      for (int q = 0; q < 7; ++q) s += Ub[q] * Ud[q].d + Fb[q] * Fd[q].d;
+      if (dir < 7) Xb[dir] = s;
+      else if (dir == 7) Bnb = s;
+      else gb = s;
+    }
+    // through the reconstruction to the stencil cells
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      double* dst = v < 5 ? fa.pbar + v * g.N : fa.bcbar + (v == 5 ? t1 : t2) * g.N;
+      if (fallback) {
+        atomicAdd(dst + id + (o0 + os * 2) * sD, Xb[v]);
+        continue;
+      }
+      for (int q = 0; q < 5; ++q) {
+        Dual sd[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) sd[r] = Dual(sten[v][r], r == q ? 1.0 : 0.0);
+        Dual xr = recon_right_face<RECON>(sd, fa.weno_eps, fa.weno_q);
+        if (xr.d != 0.0) atomicAdd(dst + id + (o0 + os * q) * sD, Xb[v] * xr.d);
+      }
+    }
+    // the normal field is shared by both sides: sum the pair, one store per face
+    double bn_total = Bnb + shfl1(Bnb);
+    if (side == 0) fa.bfbar[(size_t)D * g.N + id] += bn_total;
+    gsum = gb;
+  }
+  double w = gsum;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) w += __shfl_xor(w, o, 64);
+  if (__lane_id() == 0 && w != 0.0) atomicAdd(fa.gbar, w);
+}
+
+// Geometric sources transposed, one owned cell per thread (direct 64-point interpolation of
+// the metric: the adjoint is not on the timed path).
+struct CellAdjArgs {
+  const double* metric;
+  const double* curv;
+  const double* prim;
+  const double* bc;
+  const double* rbar;
+  double* pbar;
+  double* bcbar;
+  double* gbar;
+  double gam;
+};
+
+DEV void centre_val_der_direct(const double* __restrict__ p, int sy, int sz, double& v, double d[3]) {
+  double vz[4], dyz[4], dxz[4];
+  for (int c = 0; c < 4; ++c) {
+    double vx[4], ddx[4];
+    for (int b = 0; b < 4; ++b) {
+      const double* r = p + b * sy + c * sz;
+      vx[b] = lag(r[0], r[1], r[2], r[3]);
+      ddx[b] = dlag(r[0], r[1], r[2], r[3]);
+    }
+    vz[c] = lag(vx[0], vx[1], vx[2], vx[3]);
+    dyz[c] = dlag(vx[0], vx[1], vx[2], vx[3]);
+    dxz[c] = lag(ddx[0], ddx[1], ddx[2], ddx[3]);
+  }
+  v = lag(vz[0], vz[1], vz[2], vz[3]);
+  d[2] = dlag(vz[0], vz[1], vz[2], vz[3]);
+  d[1] = lag(dyz[0], dyz[1], dyz[2], dyz[3]);
+  d[0] = lag(dxz[0], dxz[1], dxz[2], dxz[3]);
+}
+
+// Densitized sources alpha sqrt(gamma) (1/2 T^{mu nu} d_j g_{mu nu}, energy term) of one
+// state, in dual numbers (same formulas as the forward cell kernel).
+DEV void sources_dual(const Geo& G, const double dm[3][10], const double K[6], const Dual pr[5], const Dual Bt[3],
+                      Dual gam, Dual src[5]) {
+  StateT<Dual> St;
+  state_make(G, pr, Bt, gam, St, gam / (gam - 1.0));
+  double ia = 1.0 / G.alp, ia2 = ia * ia;
+  Dual u0 = St.W * ia, b0 = St.W * St.Bv * ia, u[3], bu[3];
+  for (int a = 0; a < 3; ++a) {
+    u[a] = St.W * (St.v[a] - G.beta[a] * ia);
+    bu[a] = (St.B[a] + G.alp * b0 * u[a]) / St.W;
+  }
+  Dual e = St.rhoh + St.bsq, pt = St.p + 0.5 * St.bsq;
+  Dual T00 = e * u0 * u0 - pt * ia2 - b0 * b0;
+  Dual T0[3], Tk[6];
+  for (int a = 0; a < 3; ++a) T0[a] = e * u0 * u[a] + pt * G.beta[a] * ia2 - b0 * bu[a];
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b)
+      Tk[sym(a, b)] = e * u[a] * u[b] + pt * (G.gu[sym(a, b)] - G.beta[a] * G.beta[b] * ia2) - bu[a] * bu[b];
+  double bl[3];
+  lower(G.g, G.beta, bl);
+  double as = G.alp * G.sqrtg;
+  src[0] = Dual(0.0);
+  for (int jj = 0; jj < 3; ++jj) {
+    const double* dg = &dm[jj][4];
+    double dal = dm[jj][0], db[3] = {dm[jj][1], dm[jj][2], dm[jj][3]};
+    double bbdg = 0.0;
+    Dual Tdg(0.0);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        bbdg += G.beta[a] * G.beta[b] * dg[sym(a, b)];
+        Tdg += Tk[sym(a, b)] * dg[sym(a, b)];
+      }
+    double d00 = -2.0 * G.alp * dal + bbdg + 2.0 * (bl[0] * db[0] + bl[1] * db[1] + bl[2] * db[2]);
+    Dual s0k(0.0);
+    for (int a = 0; a < 3; ++a) {
+      double d0a = 0.0;
+      for (int b = 0; b < 3; ++b) d0a += G.beta[b] * dg[sym(a, b)] + G.g[sym(a, b)] * db[b];
+      s0k += T0[a] * d0a;
+    }
+    src[1 + jj] = as * (0.5 * T00 * d00 + s0k + 0.5 * Tdg);
+  }
+  double dal[3] = {dm[0][0], dm[1][0], dm[2][0]}, bK[3];
+  for (int a = 0; a < 3; ++a) bK[a] = G.beta[0] * K[sym(a, 0)] + G.beta[1] * K[sym(a, 1)] + G.beta[2] * K[sym(a, 2)];
+  Dual se = T00 * (G.beta[0] * bK[0] + G.beta[1] * bK[1] + G.beta[2] * bK[2] -
+                   (G.beta[0] * dal[0] + G.beta[1] * dal[1] + G.beta[2] * dal[2]));
+  for (int a = 0; a < 3; ++a) se += T0[a] * (2.0 * bK[a] - dal[a]);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) se += Tk[sym(a, b)] * K[sym(a, b)];
+  src[4] = as * se;
+}
+
+DEV void cell_adj_body(const GD& g, const CellAdjArgs& ca, unsigned tile) {
+  int i, j, k;
+  bool valid = box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k);
+  double gsum = 0.0;
+  if (valid) {
+    const int id = at(g, i, j, k);
+    double rb[5];
+    bool any = false;
+    for (int c = 0; c < 5; ++c) {
+      rb[c] = ca.rbar[(size_t)c * g.N + id];
+      any = any || rb[c] != 0.0;
+    }
+    if (any) {
+      const int vb = id - 1 - g.sy - g.sz;
+      double m[10], dm[3][10], K[6];
+      bool flat = true;
+      for (int c = 0; c < 10; ++c) {
+        double d[3];
+        centre_val_der_direct(ca.metric + c * g.N + vb, g.sy, g.sz, m[c], d);
+        for (int a = 0; a < 3; ++a) {
+          dm[a][c] = d[a] * g.idx[a];
+          flat = flat && dm[a][c] == 0.0;
+        }
+      }
+      for (int c = 0; c < 6; ++c) {
+        K[c] = centre_val(ca.curv + c * g.N + vb, g.sy, g.sz);
+        flat = flat && K[c] == 0.0;
+      }
+      if (!flat) {  // a metric with no derivatives and no curvature has no sources
+        Geo G;
+        geo_from(m, G);
+        double pr[5], Bt[3];
+        for (int c = 0; c < 5; ++c) pr[c] = ca.prim[c * g.N + id];
+        for (int c = 0; c < 3; ++c) Bt[c] = ca.bc[c * g.N + id];
+        for (int dir = 0; dir < 9; ++dir) {
+          Dual pd[5], bd[3];
+          for (int c = 0; c < 5; ++c) pd[c] = Dual(pr[c], dir == c ? 1.0 : 0.0);
+          for (int c = 0; c < 3; ++c) bd[c] = Dual(Bt[c], dir == 5 + c ? 1.0 : 0.0);
+          Dual src[5];
+          sources_dual(G, dm, K, pd, bd, Dual(ca.gam, dir == 8 ? 1.0 : 0.0), src);
+          double s = 0.0;
+          for (int c = 0; c < 5; ++c) s += rb[c] * src[c].d;
+          if (dir < 5) ca.pbar[(size_t)dir * g.N + id] += s;
+          else if (dir < 8) ca.bcbar[(size_t)(dir - 5) * g.N + id] += s;
+          else gsum = s;
+        }
+      }
+    }
+  }
+  double w = gsum;
+  for (int o = 32; o >= 1; o >>= 1) w += __shfl_xor(w, o, 64);
+  if (__lane_id() == 0 && w != 0.0) atomicAdd(ca.gbar, w);
+}
+
+// Gauge terms transposed at vertices [-1, n]^3: G_A and F_Psi cotangents from the A and Psi
+// right-hand-side cotangents, then to Psi and to the vertex-averaged potential.
+struct VertexAdjArgs {
+  const double* metric;
+  const double* rbar;
+  double* psibar;
+  double* avbar;
+  double xi;
+  int gauge;
+};
+
+DEV void vertex_adj_body(const GD& g, const VertexAdjArgs& va, unsigned tile) {
+  int e[3] = {g.n[0] + 2, g.n[1] + 2, g.n[2] + 2};
+  int p, q, r;
+  if (!box_at<64, 4>(e, tile, threadIdx.x, p, q, r)) return;
+  const int i = p - 1, j = q - 1, k = r - 1;
+  const int id = at(g, i, j, k);
+  const double* R = va.rbar;
+  auto rc = [&](int c, int ii, int jj, int kk) { return rb_at(g, R + (size_t)c * g.N, ii, jj, kk); };
+  double mm_[10];
+  for (int c = 0; c < 10; ++c) mm_[c] = va.metric[(size_t)c * g.N + id];
+  Geo G;
+  geo_from(mm_, G);
+  double psb = 0.0, avb[3] = {0.0, 0.0, 0.0};
+  if (va.gauge == ASTERX_GAUGE_LORENZ) {
+    // dA_d/dt[edge] -= (G_A[edge + e_d] - G_A[edge]) / dx_d
+    double gb = (rc(5, i - 1, j, k) - rc(5, i, j, k)) * g.idx[0] + (rc(6, i, j - 1, k) - rc(6, i, j, k)) * g.idx[1] +
+                (rc(7, i, j, k - 1) - rc(7, i, j, k)) * g.idx[2];
+    // dPsi/dt[v] = -(F[v + e] - F[v - e]) / (2 dx) - xi alpha Psi[v]
+    double fb[3] = {(rc(8, i + 1, j, k) - rc(8, i - 1, j, k)) * 0.5 * g.idx[0],
+                    (rc(8, i, j + 1, k) - rc(8, i, j - 1, k)) * 0.5 * g.idx[1],
+                    (rc(8, i, j, k + 1) - rc(8, i, j, k - 1)) * 0.5 * g.idx[2]};
+    double as = G.alp * G.sqrtg;
+    psb = gb * G.alp / G.sqrtg - (fb[0] * G.beta[0] + fb[1] * G.beta[1] + fb[2] * G.beta[2]) -
+          va.xi * G.alp * rc(8, i, j, k);
+    for (int kk = 0; kk < 3; ++kk)
+      avb[kk] = -gb * G.beta[kk] +
+                as * (fb[0] * G.gu[sym(0, kk)] + fb[1] * G.gu[sym(1, kk)] + fb[2] * G.gu[sym(2, kk)]);
+  }
+  va.psibar[id] += psb;
+  for (int c = 0; c < 3; ++c) va.avbar[(size_t)c * g.N + id] = avb[c];
+}
+
+// Edge potential from the vertex averages (A^v_d[v] = (A_d[v - e_d] + A_d[v]) / 2), edges
+// [-2, n]^3 (gather, one edge per thread).
+DEV void edge_adj_body(const GD& g, const double* __restrict__ avbar, double* __restrict__ abar, unsigned tile) {
+  int e[3] = {g.n[0] + 3, g.n[1] + 3, g.n[2] + 3};
+  int p, q, r;
+  if (!box_at<64, 4>(e, tile, threadIdx.x, p, q, r)) return;
+  const int i = p - 2, j = q - 2, k = r - 2;
+  const int id = at(g, i, j, k);
+  const int st[3] = {1, g.sy, g.sz};
+  const int ijk[3] = {i, j, k};
+  for (int d = 0; d < 3; ++d) {
+    auto inv = [&](int dd) {  // vertex index shifted by dd along d within [-1, n]^3
+      for (int a = 0; a < 3; ++a) {
+        int v = ijk[a] + (a == d ? dd : 0);
+        if (v < -1 || v > g.n[a]) return false;
+      }
+      return true;
+    };
+    double s = 0.0;
+    if (inv(0)) s += 0.5 * avbar[(size_t)d * g.N + id];
+    if (inv(1)) s += 0.5 * avbar[(size_t)d * g.N + id + st[d]];
+    abar[(size_t)d * g.N + id] += s;
+  }
+}
+
+// Periodic ghost fill transposed along axis d: every ghost cotangent is added to its image
+// and cleared (axes are undone in the reverse order of the fill).
+struct FillTArgs {
+  double* f;
+  int nf;
+  int d;
+};
+
+DEV void fillT_body(const GD& g, const FillTArgs& a, unsigned tile) {
+  const int d = a.d;
+  int cnt[3] = {g.n[0] + 2 * g.ng + 1, g.n[1] + 2 * g.ng + 1, g.n[2] + 2 * g.ng + 1};
+  cnt[d] = 2 * g.ng + 1;
+  long long tid = (long long)tile * 256 + threadIdx.x;
+  if (tid >= (long long)cnt[0] * cnt[1] * cnt[2]) return;
+  int q0 = (int)(tid % cnt[0]);
+  long long r = tid / cnt[0];
+  int q1 = (int)(r % cnt[1]);
+  int q2 = (int)(r / cnt[1]);
+  int idx[3] = {q0 - g.ng, q1 - g.ng, q2 - g.ng};
+  int n = g.n[d];
+  int q = idx[d] + g.ng;
+  int s = q < g.ng ? q - g.ng : n + (q - g.ng);
+  idx[d] = s;
+  int dst = at(g, idx[0], idx[1], idx[2]);
+  int stride = d == 0 ? 1 : (d == 1 ? g.sy : g.sz);
+  int src = ((s % n) + n) % n;
+  for (int f = 0; f < a.nf; ++f) {
+    double* F = a.f + (size_t)f * g.N;
+    double v = F[dst];
+    if (v != 0.0) atomicAdd(F + dst + (src - s) * stride, v);
+    F[dst] = 0.0;
+  }
+}
+
+// c2p transposed at owned cells: cons = f(prim, Btilde, Gamma) at the recovered state, so
+// prim_bar -> lambda = J_prim^{-T} prim_bar, cons_bar += lambda, Btilde_bar -= J_B^T lambda,
+// Gamma_bar -= J_Gamma^T lambda.  Atmosphere cells (constant primitives) pass nothing.
+struct C2PAdjArgs {
+  const double* metric;
+  const double* prim;
+  const double* bc;
+  const uint8_t* flags;
+  const double* pbar;
+  double* consbar;
+  double* bcbar;
+  double* gbar;
+  double gam;
+  int mode;  // 0: c2p (solve with J_prim^T), 1: prim -> cons (multiply by J^T)
+};
+
+DEV void c2p_adj_body(const GD& g, const C2PAdjArgs& ca, unsigned tile) {
+  int i, j, k;
+  bool valid = box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k);
+  double gsum = 0.0;
+  if (valid) {
+    const int id = at(g, i, j, k);
+    double pb[5];
+    bool any = false;
+    for (int c = 0; c < 5; ++c) {
+      pb[c] = ca.pbar[(size_t)c * g.N + id];
+      any = any || pb[c] != 0.0;
+    }
+    bool atmo = ca.mode == 0 && ca.flags && (ca.flags[id] & 4u);
+    if (any && !atmo) {
+      double m[10];
+      centre_metric(ca.metric, g.N, id - 1 - g.sy - g.sz, g.sy, g.sz, m);
+      Geo G;
+      geo_from(m, G);
+      double pr[5], Bt[3];
+      for (int c = 0; c < 5; ++c) pr[c] = ca.prim[(size_t)c * g.N + id];
+      for (int c = 0; c < 3; ++c) Bt[c] = ca.bc[(size_t)c * g.N + id];
+      double J[5][9];
+      for (int dir = 0; dir < 9; ++dir) {
+        Dual pd[5], bd[3];
+        for (int c = 0; c < 5; ++c) pd[c] = Dual(pr[c], dir == c ? 1.0 : 0.0);
+        for (int c = 0; c < 3; ++c) bd[c] = Dual(Bt[c], dir == 5 + c ? 1.0 : 0.0);
+        Dual gd(ca.gam, dir == 8 ? 1.0 : 0.0);
+        StateT<Dual> S;
+        state_make(G, pd, bd, gd, S, gd / (gd - 1.0));
+        Dual U[5];
+        cons_of(G, S, U);
+        for (int c = 0; c < 5; ++c) J[c][dir] = U[c].d;
+      }
+      double lam[5];
+      if (ca.mode == 0) {
+        // solve J_prim^T lam = pb (Gaussian elimination with partial pivoting)
+        double M[5][6];
+        for (int r = 0; r < 5; ++r) {
+          for (int c = 0; c < 5; ++c) M[r][c] = J[c][r];
+          M[r][5] = pb[r];
+        }
+        for (int c = 0; c < 5; ++c) {
+          int piv = c;
+          for (int r = c + 1; r < 5; ++r)
+            if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+          for (int q = 0; q < 6; ++q) {
+            double t = M[c][q];
+            M[c][q] = M[piv][q];
+            M[piv][q] = t;
+          }
+          double inv = 1.0 / M[c][c];
+          for (int r = c + 1; r < 5; ++r) {
+            double f = M[r][c] * inv;
+            for (int q = c; q < 6; ++q) M[r][q] -= f * M[c][q];
+          }
+        }
+        for (int r = 4; r >= 0; --r) {
+          double s = M[r][5];
+          for (int q = r + 1; q < 5; ++q) s -= M[r][q] * lam[q];
+          lam[r] = s / M[r][r];
+        }
+        for (int c = 0; c < 5; ++c) ca.consbar[(size_t)c * g.N + id] += lam[c];
+        for (int b = 0; b < 3; ++b) {
+          double s = 0.0;
+          for (int c = 0; c < 5; ++c) s += J[c][5 + b] * lam[c];
+          ca.bcbar[(size_t)b * g.N + id] -= s;
+        }
+        double s = 0.0;
+        for (int c = 0; c < 5; ++c) s += J[c][8] * lam[c];
+        gsum = -s;
+      } else {
+        // cons = f(prim, B, Gamma): prim_bar' += J_prim^T cons_bar (pbar holds cons_bar here)
+        for (int r = 0; r < 5; ++r) {
+          double s = 0.0;
+          for (int c = 0; c < 5; ++c) s += J[c][r] * pb[c];
+          ca.consbar[(size_t)r * g.N + id] += s;  // consbar holds prim_bar in this mode
+        }
+        for (int b = 0; b < 3; ++b) {
+          double s = 0.0;
+          for (int c = 0; c < 5; ++c) s += J[c][5 + b] * pb[c];
+          ca.bcbar[(size_t)b * g.N + id] += s;
+        }
+        double s = 0.0;
+        for (int c = 0; c < 5; ++c) s += J[c][8] * pb[c];
+        gsum = s;
+      }
+    }
+  }
+  double w = gsum;
+  for (int o = 32; o >= 1; o >>= 1) w += __shfl_xor(w, o, 64);
+  if (__lane_id() == 0 && w != 0.0) atomicAdd(ca.gbar, w);
+}
+
+// Centre-field cotangents to face-field cotangents (gather over the two adjacent cells),
+// faces [-ng+1, n+ng]^3.
+DEV void bcface_adj_body(const GD& g, const double* __restrict__ bcbar, double* __restrict__ bfbar, unsigned tile) {
+  int e[3] = {g.n[0] + 2 * g.ng, g.n[1] + 2 * g.ng, g.n[2] + 2 * g.ng};
+  int p, q, r;
+  if (!box_at<64, 4>(e, tile, threadIdx.x, p, q, r)) return;
+  const int i = p - g.ng + 1, j = q - g.ng + 1, k = r - g.ng + 1;
+  const int id = at(g, i, j, k);
+  const int st[3] = {1, g.sy, g.sz};
+  const int ijk[3] = {i, j, k};
+  for (int d = 0; d < 3; ++d) {
+    double s = 0.0;
+    if (ijk[d] <= g.n[d] + g.ng - 1) s += 0.5 * bcbar[(size_t)d * g.N + id];
+    s += 0.5 * bcbar[(size_t)d * g.N + id - st[d]];
+    bfbar[(size_t)d * g.N + id] += s;
+  }
+}
+
+// Face-field cotangents to the edge potential (transposed curl, gather), edges [-ng+1, n+ng]^3.
+DEV void curlT_body(const GD& g, const double* __restrict__ bf, double* __restrict__ abar, unsigned tile) {
+  int e[3] = {g.n[0] + 2 * g.ng, g.n[1] + 2 * g.ng, g.n[2] + 2 * g.ng};
+  int p, q, r;
+  if (!box_at<64, 4>(e, tile, threadIdx.x, p, q, r)) return;
+  const int i = p - g.ng + 1, j = q - g.ng + 1, k = r - g.ng + 1;
+  const int id = at(g, i, j, k);
+  const double* Bx = bf;
+  const double* By = bf + g.N;
+  const double* Bz = bf + 2 * g.N;
+  const int sy = g.sy, sz = g.sz;
+  abar[id] += (By[id - sz] - By[id]) * g.idx[2] + (Bz[id] - Bz[id - sy]) * g.idx[1];
+  abar[g.N + id] += (Bx[id] - Bx[id - sz]) * g.idx[2] + (Bz[id - 1] - Bz[id]) * g.idx[0];
+  abar[2 * g.N + id] += (Bx[id - sy] - Bx[id]) * g.idx[1] + (By[id] - By[id - 1]) * g.idx[0];
+}
+
+// dst[owned] += src[owned] for nf fields.
+struct AccumArgs {
+  const double* src;
+  double* dst;
+  int nf;
+};
+
+DEV void accum_body(const GD& g, const AccumArgs& a, unsigned tile) {
+  int i, j, k;
+  if (!box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k)) return;
+  const int id = at(g, i, j, k);
+  for (int f = 0; f < a.nf; ++f) a.dst[(size_t)f * g.N + id] += a.src[(size_t)f * g.N + id];
+}
+
+template <class T>
+DEV void copy_body(const GD& g, const T* __restrict__ src, T* __restrict__ dst, long long n, unsigned tile) {
+  long long t = (long long)tile * 256 + threadIdx.x;
+  if (t < n) dst[t] = src[t];
+}
+
+__global__ __launch_bounds__(256) void k_fluxbar(GD g, FluxBarArgs a) { fluxbar_body(g, a, my_tile()); }
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_face_adj(GD g, FaceAdjArgs fa) {
+  face_adj_body<D, R>(g, fa, my_tile());
+}
+__global__ __launch_bounds__(256) void k_cell_adj(GD g, CellAdjArgs ca) { cell_adj_body(g, ca, my_tile()); }
+__global__ __launch_bounds__(256) void k_vertex_adj(GD g, VertexAdjArgs va) { vertex_adj_body(g, va, my_tile()); }
+__global__ __launch_bounds__(256) void k_edge_adj(GD g, const double* avbar, double* abar) {
+  edge_adj_body(g, avbar, abar, my_tile());
+}
+__global__ __launch_bounds__(256) void k_fillT(GD g, FillTArgs a) { fillT_body(g, a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_c2p_adj(GD g, C2PAdjArgs ca) { c2p_adj_body(g, ca, my_tile()); }
+__global__ __launch_bounds__(256) void k_bcface_adj(GD g, const double* bcbar, double* bfbar) {
+  bcface_adj_body(g, bcbar, bfbar, my_tile());
+}
+__global__ __launch_bounds__(256) void k_curlT(GD g, const double* bf, double* abar) { curlT_body(g, bf, abar, my_tile()); }
+__global__ __launch_bounds__(256) void k_accum(GD g, AccumArgs a) { accum_body(g, a, my_tile()); }
+__global__ __launch_bounds__(256) void k_copy(GD g, const double* src, double* dst, long long n) {
+  copy_body(g, src, dst, n, blockIdx.x);
 }
 
 __global__ void k_zero(double* p, long long n) {
@@ -837,10 +1781,10 @@ int launched() {
 // use while a stream is being captured into a graph.
 enum {
   KT_PRIM2CON, KT_C2P, KT_FILL, KT_BCENT, KT_FACE_X, KT_FACE_Y, KT_FACE_Z, KT_CELL, KT_VERTEX, KT_EDGE, KT_RK,
-  KT_ZERO, KT_N
+  KT_ZERO, KT_ADJ, KT_N
 };
 const char* const kt_names[KT_N] = {"prim2con", "c2p", "fill_ghosts", "centre_B", "face_x", "face_y",
-                                    "face_z", "cell", "vertex", "edge", "rk_stage", "zero"};
+                                    "face_z", "cell", "vertex", "edge", "rk_stage", "zero", "adjoint"};
 struct Pending {
   hipEvent_t a, b;
   int kind;
@@ -882,6 +1826,165 @@ int timed(int kind, hipStream_t s, F&& launch) {
   return rc;
 }
 
+// ---------------------------------------------------------------------------------------
+// Launch targets.  A single block launches one workgroup per tile of each phase; a batch
+// of patches launches a persistent grid over that phase's (patch, tile) work list.
+enum { PH_P2C, PH_C2P, PH_FILLX, PH_FILLY, PH_FILLZ, PH_BCENT, PH_FACE, PH_CELL, PH_VERTEX, PH_EDGE, PH_RK, PH_N };
+
+unsigned host_tile_blocks(const GD& g) {
+  return (unsigned)(((g.n[0] + CTX - 1) / CTX) * ((g.n[1] + CTY - 1) / CTY) * ((g.n[2] + CTZ - 1) / CTZ));
+}
+
+unsigned tiles_for(int phase, const GD& g) {
+  int e[3];
+  switch (phase) {
+    case PH_C2P:
+    case PH_CELL:
+      return host_tile_blocks(g);
+    case PH_FILLX:
+    case PH_FILLY:
+    case PH_FILLZ: {
+      int d = phase - PH_FILLX;
+      long long cnt = 2 * g.ng + 1;
+      for (int t = 0; t < 3; ++t)
+        if (t != d) cnt *= (g.n[t] + 2 * g.ng + 1);
+      return (unsigned)((cnt + 255) / 256);
+    }
+    case PH_BCENT:
+      for (int a = 0; a < 3; ++a) e[a] = g.n[a] + 2 * g.ng;
+      return box_blocks<64, 4>(e);
+    case PH_FACE:
+      for (int a = 0; a < 3; ++a) e[a] = g.n[a] + 1;
+      return box_blocks<32, 4>(e);
+    case PH_VERTEX:
+      for (int a = 0; a < 3; ++a) e[a] = g.n[a] + 2;
+      return box_blocks<64, 4>(e);
+    default:
+      return box_blocks<64, 4>(g.n);
+  }
+}
+
+}  // namespace
+
+struct asterx_batch {
+  int np = 0;
+  long long ntot = 0;
+  int blocks = 0;
+  std::vector<GD> gds;
+  std::vector<long long> off;
+  PatchDesc* d_patches = nullptr;
+  Item* d_items[PH_N] = {};
+  int nitems[PH_N] = {};
+};
+
+namespace {
+
+unsigned bgrid(const asterx_batch* b, int phase) {
+  return (unsigned)(b->nitems[phase] < b->blocks ? b->nitems[phase] : b->blocks);
+}
+
+// One phase on either target: KS(g, args...) one workgroup per tile, or
+// KB(patches, items, nitems, args...) persistent over the batch's work list.
+#define RUN_PHASE(KT, PHASE, KS, KB, ...)                                                                     \
+  (b ? (b->nitems[PHASE] ? timed(KT, s,                                                                      \
+                                 [&] {                                                                       \
+                                   hipLaunchKernelGGL(KB, dim3(bgrid(b, PHASE)), dim3(256), 0, s,           \
+                                                      b->d_patches, b->d_items[PHASE], b->nitems[PHASE],     \
+                                                      __VA_ARGS__);                                          \
+                                 })                                                                          \
+                         : 0)                                                                                \
+     : timed(KT, s, [&] { hipLaunchKernelGGL(KS, dim3(tiles_for(PHASE, g)), dim3(256), 0, s, g, __VA_ARGS__); }))
+
+template <int R>
+int faces_r(const GD& g, const asterx_batch* b, const FaceArgs& fa, hipStream_t s) {
+  int rc;
+  if ((rc = RUN_PHASE(KT_FACE_X, PH_FACE, (k_face<0, R>), (kb_face<0, R>), fa))) return rc;
+  if ((rc = RUN_PHASE(KT_FACE_Y, PH_FACE, (k_face<1, R>), (kb_face<1, R>), fa))) return rc;
+  return RUN_PHASE(KT_FACE_Z, PH_FACE, (k_face<2, R>), (kb_face<2, R>), fa);
+}
+
+int faces(const GD& g, const asterx_batch* b, const FaceArgs& fa, int recon, hipStream_t s) {
+  if (recon == ASTERX_RECON_MINMOD) return faces_r<ASTERX_RECON_MINMOD>(g, b, fa, s);
+  if (recon == ASTERX_RECON_PPM) return faces_r<ASTERX_RECON_PPM>(g, b, fa, s);
+  return faces_r<ASTERX_RECON_WENOZ>(g, b, fa, s);
+}
+
+// ---- the phases, shared by the single-block and the batched entry points ----
+int do_prim2con(const GD& g, const asterx_batch* b, const asterx_params* p, const double* metric, const double* A,
+                const double* prim, double* cons, hipStream_t s) {
+  return RUN_PHASE(KT_PRIM2CON, PH_P2C, k_prim2con, kb_prim2con, p->gamma, metric, A, prim, cons);
+}
+
+int do_c2p(const GD& g, const asterx_batch* b, const asterx_params* p, const double* metric, const double* A,
+           double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats, hipStream_t s) {
+  C2PParams cp = make_c2p_params(p);
+  C2PArgs a{metric, A, cons, prim, flags, (unsigned long long*)stats};
+  return RUN_PHASE(KT_C2P, PH_C2P, k_c2p, kb_c2p, cp, a);
+}
+
+int do_fill(const GD& g, const asterx_batch* b, double* f, int nf, const int32_t* kinds, hipStream_t s,
+            const double* shift = nullptr) {
+  int rc;
+  for (int a = 0; a < 3; ++a) {
+    FillArgs fa{f, nf, a, kinds[a], {0.0, 0.0, 0.0}};
+    if (shift)
+      for (int q = 0; q < 3 && q < nf; ++q) fa.shift[q] = shift[q * 3 + a];
+    if ((rc = RUN_PHASE(KT_FILL, PH_FILLX + a, k_fill, kb_fill, fa))) return rc;
+  }
+  return 0;
+}
+
+int do_bcent(const GD& g, const double* A, double* bc, hipStream_t s) {
+  const asterx_batch* b = nullptr;
+  return RUN_PHASE(KT_BCENT, PH_BCENT, k_bcent, kb_bcent, A, bc);
+}
+
+int do_rhs(const GD& g, const asterx_batch* b, const asterx_params* p, const double* metric, const double* curv,
+           const double* prim, const double* A, const double* psi, double dt_max, double* rhs, double* red,
+           double* ws, hipStream_t s) {
+  int rc;
+  double* bc = ws;
+  double* flux = ws + 3 * g.N;
+  double* ga = ws + 24 * g.N;
+  double* fp = ws + 25 * g.N;
+  if ((rc = RUN_PHASE(KT_BCENT, PH_BCENT, k_bcent, kb_bcent, A, bc))) return rc;
+  FaceArgs fa{metric, prim, A, bc, flux, red, p->gamma, p->weno_eps, p->weno_q, p->gamma / (p->gamma - 1.0),
+              p->recon, p->speeds};
+  if ((rc = faces(g, b, fa, p->recon, s))) return rc;
+  CellArgs ca{metric, curv, prim, A, bc, flux, rhs, red, p->gamma};
+  if ((rc = RUN_PHASE(KT_CELL, PH_CELL, k_cell, kb_cell, ca))) return rc;
+  if (p->gauge == ASTERX_GAUGE_LORENZ) {
+    VertexArgs va{metric, A, psi, ga, fp};
+    if ((rc = RUN_PHASE(KT_VERTEX, PH_VERTEX, k_vertex, kb_vertex, va))) return rc;
+  }
+  EdgeArgs ea{metric, psi, flux, ga, fp, rhs, p->xi / dt_max, p->gauge};
+  return RUN_PHASE(KT_EDGE, PH_EDGE, k_edge, kb_edge, ea);
+}
+
+int do_rk(const GD& g, const asterx_batch* b, int32_t nterms, const double* a, const double* const* u, double b_dt,
+          const double* rhs, double* out, hipStream_t s) {
+  if (nterms < 1 || nterms > 4 || !a || !u || !rhs || !out) return fail(ASTERX_EARG, "rk_stage: bad arguments");
+  RKArgs ra;
+  for (int m = 0; m < 4; ++m) {
+    ra.u[m] = m < nterms ? u[m] : nullptr;
+    ra.a[m] = m < nterms ? a[m] : 0.0;
+    if (m < nterms && !u[m]) return fail(ASTERX_EARG, "rk_stage: NULL state");
+  }
+  ra.nterms = nterms;
+  ra.b_dt = b_dt;
+  ra.rhs = rhs;
+  ra.out = out;
+  return RUN_PHASE(KT_RK, PH_RK, k_rk, kb_rk, ra);
+}
+
+int check_kinds(const asterx_grid* gr, const int32_t* kinds) {
+  for (int a = 0; a < 3; ++a) {
+    if (kinds[a] < 0 || kinds[a] > 2) return fail(ASTERX_EARG, "fill_ghosts: unknown boundary kind");
+    if (kinds[a] == ASTERX_BC_LINEAR && gr->n[a] < 2) return fail(ASTERX_EARG, "fill_ghosts: LINEAR needs n >= 2");
+  }
+  return 0;
+}
+
 }  // namespace
 
 // =======================================================================================
@@ -921,123 +2024,78 @@ int asterx_timing_reset(void) {
 
 const char* asterx_timing_name(int32_t k) { return (k >= 0 && k < KT_N) ? kt_names[k] : ""; }
 
-int asterx_version(void) { return 1; }
+int asterx_version(void) { return 2; }
 
 const char* asterx_last_error(void) { return g_err.c_str(); }
 
 size_t asterx_rhs_workspace_size(const asterx_grid* g) {
   if (!g) return 0;
   size_t N = (size_t)g->ld[0] * g->ld[1] * g->ld[2];
-  return (3 + 21 + 1 + 3) * N * sizeof(double);
+  return (size_t)WS_FIELDS * N * sizeof(double);
 }
 
-int asterx_prim2con(const asterx_grid* g, const asterx_params* p, const double* metric, const double* A,
+int asterx_prim2con(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* A,
                     const double* prim, double* cons, void* stream) {
   int rc;
-  if ((rc = check_grid(g, 2)) || (rc = check_params(p))) return rc;
+  if ((rc = check_grid(gr, 2)) || (rc = check_params(p))) return rc;
   if (!metric || !A || !prim || !cons) return fail(ASTERX_EARG, "prim2con: NULL array");
-  GD d = make_gd(g);
-  hipStream_t s = (hipStream_t)stream;
-  return timed(KT_PRIM2CON, s, [&] {
-    hipLaunchKernelGGL(k_prim2con, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, s, d, p->gamma, metric, A, prim,
-                       cons);
-  });
+  GD g = make_gd(gr);
+  const asterx_batch* b = nullptr;
+  return do_prim2con(g, b, p, metric, A, prim, cons, (hipStream_t)stream);
 }
 
-int asterx_c2p(const asterx_grid* g, const asterx_params* p, const double* metric, const double* A, double* cons,
+int asterx_c2p(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* A, double* cons,
                double* prim, uint8_t* flags, asterx_c2p_stats* stats, void* stream) {
   int rc;
-  if ((rc = check_grid(g, 2)) || (rc = check_params(p))) return rc;
+  if ((rc = check_grid(gr, 2)) || (rc = check_params(p))) return rc;
   if (!metric || !A || !prim || !cons) return fail(ASTERX_EARG, "c2p: NULL array");
-  GD d = make_gd(g);
-  hipStream_t s = (hipStream_t)stream;
-  C2PParams cp = make_c2p_params(p);
-  return timed(KT_C2P, s, [&] {
-    hipLaunchKernelGGL(k_c2p_t, dim3(tile_blocks(d)), dim3(256), 0, s, d, cp, metric, A, cons, prim, flags,
-                       (unsigned long long*)stats);
-  });
+  GD g = make_gd(gr);
+  const asterx_batch* b = nullptr;
+  return do_c2p(g, b, p, metric, A, cons, prim, flags, stats, (hipStream_t)stream);
 }
 
-int asterx_fill_ghosts(const asterx_grid* g, double* f, int32_t nf, const int32_t* kinds, void* stream) {
+int asterx_fill_ghosts(const asterx_grid* gr, double* f, int32_t nf, const int32_t* kinds, void* stream) {
   int rc;
-  if ((rc = check_grid(g, 1))) return rc;
+  if ((rc = check_grid(gr, 1))) return rc;
   if (!f || !kinds || nf < 1) return fail(ASTERX_EARG, "fill_ghosts: bad arguments");
-  GD d = make_gd(g);
-  for (int a = 0; a < 3; ++a) {
-    if (kinds[a] < 0 || kinds[a] > 2) return fail(ASTERX_EARG, "fill_ghosts: unknown boundary kind");
-    if (kinds[a] == ASTERX_BC_LINEAR && g->n[a] < 2) return fail(ASTERX_EARG, "fill_ghosts: LINEAR needs n >= 2");
-  }
-  for (int a = 0; a < 3; ++a) {
-    long long cnt = (long long)nf * (2 * g->ng + 1);
-    for (int b = 0; b < 3; ++b)
-      if (b != a) cnt *= (g->n[b] + 2 * g->ng + 1);
-    FillArgs fa{f, nf, a, kinds[a]};
-    unsigned nb = (unsigned)((cnt + 255) / 256);
-    hipStream_t s = (hipStream_t)stream;
-    if ((rc = timed(KT_FILL, s, [&] { hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, d, fa); }))) return rc;
-  }
-  return 0;
+  if ((rc = check_kinds(gr, kinds))) return rc;
+  GD g = make_gd(gr);
+  const asterx_batch* b = nullptr;
+  return do_fill(g, b, f, nf, kinds, (hipStream_t)stream);
 }
 
-int asterx_rhs(const asterx_grid* g, const asterx_params* p, const double* metric, const double* curv,
+int asterx_fill_ghosts_shift(const asterx_grid* gr, double* f, int32_t nf, const double* shift, void* stream) {
+  int rc;
+  if ((rc = check_grid(gr, 1))) return rc;
+  if (!f || !shift || nf < 1 || nf > 3) return fail(ASTERX_EARG, "fill_ghosts_shift: bad arguments");
+  GD g = make_gd(gr);
+  const asterx_batch* b = nullptr;
+  const int32_t per[3] = {ASTERX_BC_PERIODIC, ASTERX_BC_PERIODIC, ASTERX_BC_PERIODIC};
+  return do_fill(g, b, f, nf, per, (hipStream_t)stream, shift);
+}
+
+int asterx_rhs(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* curv,
                const double* prim, const double* A, const double* psi, double dt_max, double* rhs, double* red,
                void* workspace, size_t ws_bytes, void* stream) {
   int rc;
   if ((rc = check_params(p))) return rc;
   // the face kernels load a six-cell stencil (i-3..i+2) for every scheme
-  if ((rc = check_grid(g, 3))) return rc;
-  if (!metric || !curv || !prim || !A || !psi || !rhs || !workspace)
-    return fail(ASTERX_EARG, "rhs: NULL array");
-  if (ws_bytes < asterx_rhs_workspace_size(g)) return fail(ASTERX_EARG, "rhs: workspace too small");
+  if ((rc = check_grid(gr, 3))) return rc;
+  if (!metric || !curv || !prim || !A || !psi || !rhs || !workspace) return fail(ASTERX_EARG, "rhs: NULL array");
+  if (ws_bytes < asterx_rhs_workspace_size(gr)) return fail(ASTERX_EARG, "rhs: workspace too small");
   if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs: dt_max must be > 0");
-  hipStream_t s = (hipStream_t)stream;
-  GD d = make_gd(g);
-  double* ws = (double*)workspace;
-  double* bc = ws;
-  double* flux = ws + 3 * d.N;
-  double* ga = ws + 24 * d.N;
-  double* fp = ws + 25 * d.N;
-  int ebc[3] = {d.n[0] + 2 * d.ng, d.n[1] + 2 * d.ng, d.n[2] + 2 * d.ng};
-  if ((rc = timed(KT_BCENT, s, [&] { hipLaunchKernelGGL(k_bcent, dim3(box_blocks<64, 4>(ebc)), dim3(256), 0, s, d, A, bc); })))
-    return rc;
-  FaceArgs fa{metric, prim, A, bc, flux, red, p->gamma, p->weno_eps, p->weno_q, p->recon, p->speeds};
-  int ef[3] = {d.n[0] + 1, d.n[1] + 1, d.n[2] + 1};
-  unsigned nbf = box_blocks<32, 4>(ef);
-  if ((rc = timed(KT_FACE_X, s, [&] { hipLaunchKernelGGL(k_face2<0>, dim3(nbf), dim3(256), 0, s, d, fa); }))) return rc;
-  if ((rc = timed(KT_FACE_Y, s, [&] { hipLaunchKernelGGL(k_face2<1>, dim3(nbf), dim3(256), 0, s, d, fa); }))) return rc;
-  if ((rc = timed(KT_FACE_Z, s, [&] { hipLaunchKernelGGL(k_face2<2>, dim3(nbf), dim3(256), 0, s, d, fa); }))) return rc;
-  CellArgs ca{metric, curv, prim, A, bc, flux, rhs, red, p->gamma};
-  if ((rc = timed(KT_CELL, s, [&] { hipLaunchKernelGGL(k_cell_t, dim3(tile_blocks(d)), dim3(256), 0, s, d, ca); })))
-    return rc;
-  if (p->gauge == ASTERX_GAUGE_LORENZ) {
-    int ev[3] = {d.n[0] + 2, d.n[1] + 2, d.n[2] + 2};
-    if ((rc = timed(KT_VERTEX, s, [&] {
-           hipLaunchKernelGGL(k_vertex, dim3(box_blocks<64, 4>(ev)), dim3(256), 0, s, d, metric, A, psi, ga, fp);
-         })))
-      return rc;
-  }
-  EdgeArgs ea{metric, psi, flux, ga, fp, rhs, p->xi / dt_max, p->gauge};
-  return timed(KT_EDGE, s, [&] { hipLaunchKernelGGL(k_edge, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, s, d, ea); });
+  GD g = make_gd(gr);
+  const asterx_batch* b = nullptr;
+  return do_rhs(g, b, p, metric, curv, prim, A, psi, dt_max, rhs, red, (double*)workspace, (hipStream_t)stream);
 }
 
-int asterx_rk_stage(const asterx_grid* g, int32_t nterms, const double* a, const double* const* u, double b_dt,
+int asterx_rk_stage(const asterx_grid* gr, int32_t nterms, const double* a, const double* const* u, double b_dt,
                     const double* rhs, double* out, void* stream) {
   int rc;
-  if ((rc = check_grid(g, 1))) return rc;
-  if (nterms < 1 || nterms > 4 || !a || !u || !rhs || !out) return fail(ASTERX_EARG, "rk_stage: bad arguments");
-  RKArgs ra;
-  for (int m = 0; m < 4; ++m) {
-    ra.u[m] = m < nterms ? u[m] : nullptr;
-    ra.a[m] = m < nterms ? a[m] : 0.0;
-    if (m < nterms && !u[m]) return fail(ASTERX_EARG, "rk_stage: NULL state");
-  }
-  ra.nterms = nterms;
-  ra.b_dt = b_dt;
-  ra.rhs = rhs;
-  ra.out = out;
-  GD d = make_gd(g);
-  hipStream_t s = (hipStream_t)stream;
-  return timed(KT_RK, s, [&] { hipLaunchKernelGGL(k_rk, dim3(box_blocks<64, 4>(d.n)), dim3(256), 0, s, d, ra); });
+  if ((rc = check_grid(gr, 1))) return rc;
+  GD g = make_gd(gr);
+  const asterx_batch* b = nullptr;
+  return do_rk(g, b, nterms, a, u, b_dt, rhs, out, (hipStream_t)stream);
 }
 
 int asterx_zero(double* buf, int64_t count, void* stream) {
@@ -1046,6 +2104,336 @@ int asterx_zero(double* buf, int64_t count, void* stream) {
   return timed(KT_ZERO, s, [&] {
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, buf, (long long)count);
   });
+}
+
+// ---- batches of patches -------------------------------------------------------------------
+
+int asterx_batch_create(int32_t npatches, const asterx_grid* grids, const asterx_batch_tuning* tuning,
+                        asterx_batch** out) {
+  if (!out || npatches < 1 || !grids) return fail(ASTERX_EARG, "batch_create: bad arguments");
+  *out = nullptr;
+  int order = tuning ? tuning->order : 1;
+  int per_cu = tuning ? tuning->blocks_per_cu : 4;
+  if (order < 0 || order > 2 || per_cu < 1 || per_cu > 64) return fail(ASTERX_EARG, "batch_create: bad tuning");
+  asterx_batch* b = new asterx_batch();
+  b->np = npatches;
+  long long tot = 0;
+  for (int q = 0; q < npatches; ++q) {
+    int rc = check_grid(&grids[q], 3);
+    if (rc) {
+      delete b;
+      return rc;
+    }
+    b->off.push_back(tot);
+    tot += (long long)grids[q].ld[0] * grids[q].ld[1] * grids[q].ld[2];
+  }
+  b->ntot = tot;
+  std::vector<PatchDesc> pd(npatches);
+  for (int q = 0; q < npatches; ++q) {
+    GD g = make_gd(&grids[q]);
+    g.N = (size_t)tot;  // field stride of the pools
+    b->gds.push_back(g);
+    pd[q].g = g;
+    pd[q].off = b->off[q];
+  }
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  }
+  b->blocks = per_cu * ncu;
+  std::vector<std::vector<Item>> lists(PH_N);
+  for (int ph = 0; ph < PH_N; ++ph) {
+    std::vector<int> porder(npatches);
+    for (int q = 0; q < npatches; ++q) porder[q] = q;
+    if (order == 1)
+      std::stable_sort(porder.begin(), porder.end(),
+                       [&](int x, int y) { return tiles_for(ph, b->gds[x]) > tiles_for(ph, b->gds[y]); });
+    std::vector<Item>& L = lists[ph];
+    if (order == 2) {  // round robin over patches, largest first
+      std::stable_sort(porder.begin(), porder.end(),
+                       [&](int x, int y) { return tiles_for(ph, b->gds[x]) > tiles_for(ph, b->gds[y]); });
+      unsigned maxt = 0;
+      for (int q = 0; q < npatches; ++q) maxt = std::max(maxt, tiles_for(ph, b->gds[q]));
+      for (unsigned t = 0; t < maxt; ++t)
+        for (int q : porder)
+          if (t < tiles_for(ph, b->gds[q])) L.push_back(Item{q, (int)t});
+    } else {
+      for (int q : porder)
+        for (unsigned t = 0; t < tiles_for(ph, b->gds[q]); ++t) L.push_back(Item{q, (int)t});
+    }
+    b->nitems[ph] = (int)L.size();
+  }
+  bool ok = hipMalloc((void**)&b->d_patches, sizeof(PatchDesc) * npatches) == hipSuccess &&
+            hipMemcpy(b->d_patches, pd.data(), sizeof(PatchDesc) * npatches, hipMemcpyHostToDevice) == hipSuccess;
+  for (int ph = 0; ph < PH_N && ok; ++ph) {
+    ok = hipMalloc((void**)&b->d_items[ph], sizeof(Item) * lists[ph].size()) == hipSuccess &&
+         hipMemcpy(b->d_items[ph], lists[ph].data(), sizeof(Item) * lists[ph].size(), hipMemcpyHostToDevice) ==
+             hipSuccess;
+  }
+  if (!ok) {
+    asterx_batch_destroy(b);
+    return fail(ASTERX_ELAUNCH, "batch_create: device allocation failed");
+  }
+  *out = b;
+  return 0;
+}
+
+int asterx_batch_destroy(asterx_batch* b) {
+  if (!b) return 0;
+  if (b->d_patches) (void)hipFree(b->d_patches);
+  for (int ph = 0; ph < PH_N; ++ph)
+    if (b->d_items[ph]) (void)hipFree(b->d_items[ph]);
+  delete b;
+  return 0;
+}
+
+int64_t asterx_batch_points(const asterx_batch* b) { return b ? b->ntot : -1; }
+
+int64_t asterx_batch_offset(const asterx_batch* b, int32_t p) {
+  return (b && p >= 0 && p < b->np) ? b->off[p] : -1;
+}
+
+size_t asterx_batch_workspace_size(const asterx_batch* b) {
+  return b ? (size_t)WS_FIELDS * (size_t)b->ntot * sizeof(double) : 0;
+}
+
+int asterx_batch_prim2con(const asterx_batch* b, const asterx_params* p, const double* metric, const double* A,
+                          const double* prim, double* cons, void* stream) {
+  int rc;
+  if (!b) return fail(ASTERX_EARG, "batch is NULL");
+  if ((rc = check_params(p))) return rc;
+  if (!metric || !A || !prim || !cons) return fail(ASTERX_EARG, "batch_prim2con: NULL array");
+  const GD& g = b->gds[0];
+  return do_prim2con(g, b, p, metric, A, prim, cons, (hipStream_t)stream);
+}
+
+int asterx_batch_c2p(const asterx_batch* b, const asterx_params* p, const double* metric, const double* A,
+                     double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats, void* stream) {
+  int rc;
+  if (!b) return fail(ASTERX_EARG, "batch is NULL");
+  if ((rc = check_params(p))) return rc;
+  if (!metric || !A || !prim || !cons) return fail(ASTERX_EARG, "batch_c2p: NULL array");
+  const GD& g = b->gds[0];
+  return do_c2p(g, b, p, metric, A, cons, prim, flags, stats, (hipStream_t)stream);
+}
+
+int asterx_batch_fill_ghosts(const asterx_batch* b, double* f, int32_t nf, const int32_t* kinds, void* stream) {
+  if (!b || !f || !kinds || nf < 1) return fail(ASTERX_EARG, "batch_fill_ghosts: bad arguments");
+  for (int a = 0; a < 3; ++a) {
+    if (kinds[a] < 0 || kinds[a] > 2) return fail(ASTERX_EARG, "fill_ghosts: unknown boundary kind");
+    for (int q = 0; q < b->np; ++q)
+      if (kinds[a] == ASTERX_BC_LINEAR && b->gds[q].n[a] < 2)
+        return fail(ASTERX_EARG, "fill_ghosts: LINEAR needs n >= 2");
+  }
+  const GD& g = b->gds[0];
+  return do_fill(g, b, f, nf, kinds, (hipStream_t)stream);
+}
+
+int asterx_batch_rhs(const asterx_batch* b, const asterx_params* p, const double* metric, const double* curv,
+                     const double* prim, const double* A, const double* psi, double dt_max, double* rhs, double* red,
+                     void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if (!b) return fail(ASTERX_EARG, "batch is NULL");
+  if ((rc = check_params(p))) return rc;
+  if (!metric || !curv || !prim || !A || !psi || !rhs || !workspace) return fail(ASTERX_EARG, "rhs: NULL array");
+  if (ws_bytes < asterx_batch_workspace_size(b)) return fail(ASTERX_EARG, "rhs: workspace too small");
+  if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs: dt_max must be > 0");
+  const GD& g = b->gds[0];
+  return do_rhs(g, b, p, metric, curv, prim, A, psi, dt_max, rhs, red, (double*)workspace, (hipStream_t)stream);
+}
+
+int asterx_batch_rk_stage(const asterx_batch* b, int32_t nterms, const double* a, const double* const* u,
+                          double b_dt, const double* rhs, double* out, void* stream) {
+  if (!b) return fail(ASTERX_EARG, "batch is NULL");
+  const GD& g = b->gds[0];
+  return do_rk(g, b, nterms, a, u, b_dt, rhs, out, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---- adjoint -------------------------------------------------------------------------------
+
+namespace {
+
+unsigned pts_blocks(long long n) { return (unsigned)((n + 255) / 256); }
+
+int adj_fillT(const GD& g, double* f, int nf, hipStream_t s) {
+  int rc;
+  for (int a = 2; a >= 0; --a) {
+    FillTArgs fa{f, nf, a};
+    unsigned nb = tiles_for(PH_FILLX + a, g);
+    if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_fillT, dim3(nb), dim3(256), 0, s, g, fa); }))) return rc;
+  }
+  return 0;
+}
+
+template <int R>
+int adj_faces_r(const GD& g, const FaceAdjArgs& fa, hipStream_t s) {
+  int rc;
+  unsigned nb = tiles_for(PH_FACE, g);
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL((k_face_adj<0, R>), dim3(nb), dim3(256), 0, s, g, fa); })))
+    return rc;
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL((k_face_adj<1, R>), dim3(nb), dim3(256), 0, s, g, fa); })))
+    return rc;
+  return timed(KT_ADJ, s, [&] { hipLaunchKernelGGL((k_face_adj<2, R>), dim3(nb), dim3(256), 0, s, g, fa); });
+}
+
+int check_adjoint(const asterx_grid* gr, const asterx_params* p, size_t ws_bytes) {
+  int rc;
+  if ((rc = check_params(p)) || (rc = check_grid(gr, 3))) return rc;
+  for (int a = 0; a < 3; ++a)
+    if (gr->n[a] < gr->ng + 1) return fail(ASTERX_EARG, "adjoint: periodic blocks need n > ng on every axis");
+  if (ws_bytes < asterx_adjoint_workspace_size(gr)) return fail(ASTERX_EARG, "adjoint: workspace too small");
+  return 0;
+}
+
+// Zero the workspace, copy the stage input, recompute c2p (flags in the workspace tail) and the
+// centre field.
+int adj_prologue(const GD& g, const asterx_params* p, const double* metric, const double* cons,
+                 const double* prim_guess, const double* A, double* ws, uint8_t* flags, hipStream_t s, bool with_c2p) {
+  int rc;
+  long long nzero = (long long)AW_FIELDS * (long long)g.N;
+  if ((rc = timed(KT_ZERO, s, [&] { hipLaunchKernelGGL(k_zero, dim3(pts_blocks(nzero)), dim3(256), 0, s, ws, nzero); })))
+    return rc;
+  if ((rc = do_bcent(g, A, ws + AW_BC * g.N, s))) return rc;
+  if (!with_c2p) return 0;
+  long long n5 = 5LL * (long long)g.N;
+  if ((rc = timed(KT_ADJ, s, [&] {
+         hipLaunchKernelGGL(k_copy, dim3(pts_blocks(n5)), dim3(256), 0, s, g, cons, ws + AW_CONS * g.N, n5);
+       })))
+    return rc;
+  if ((rc = timed(KT_ADJ, s, [&] {
+         hipLaunchKernelGGL(k_copy, dim3(pts_blocks(n5)), dim3(256), 0, s, g, prim_guess, ws + AW_PRIM * g.N, n5);
+       })))
+    return rc;
+  const asterx_batch* b = nullptr;
+  if ((rc = do_c2p(g, b, p, metric, A, ws + AW_CONS * g.N, ws + AW_PRIM * g.N, flags, nullptr, s))) return rc;
+  const int32_t per[3] = {ASTERX_BC_PERIODIC, ASTERX_BC_PERIODIC, ASTERX_BC_PERIODIC};
+  return do_fill(g, b, ws + AW_PRIM * g.N, 5, per, s);
+}
+
+// Centre-field and face-field cotangents to the edge potential, fold ghosts, add to A_bar.
+int adj_epilogue(const GD& g, double* ws, double* A_bar, double* psi_bar, hipStream_t s) {
+  int rc;
+  unsigned nb = tiles_for(PH_BCENT, g);
+  if ((rc = timed(KT_ADJ, s, [&] {
+         hipLaunchKernelGGL(k_bcface_adj, dim3(nb), dim3(256), 0, s, g, ws + AW_BCBAR * g.N, ws + AW_BFBAR * g.N);
+       })))
+    return rc;
+  if ((rc = timed(KT_ADJ, s, [&] {
+         hipLaunchKernelGGL(k_curlT, dim3(nb), dim3(256), 0, s, g, ws + AW_BFBAR * g.N, ws + AW_ABAR * g.N);
+       })))
+    return rc;
+  if ((rc = adj_fillT(g, ws + AW_ABAR * g.N, 3, s))) return rc;
+  unsigned no = tiles_for(PH_RK, g);
+  if (A_bar) {
+    AccumArgs aa{ws + AW_ABAR * g.N, A_bar, 3};
+    if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_accum, dim3(no), dim3(256), 0, s, g, aa); }))) return rc;
+  }
+  if (psi_bar) {
+    if ((rc = adj_fillT(g, ws + AW_PSIBAR * g.N, 1, s))) return rc;
+    AccumArgs pa{ws + AW_PSIBAR * g.N, psi_bar, 1};
+    if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_accum, dim3(no), dim3(256), 0, s, g, pa); }))) return rc;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t asterx_adjoint_workspace_size(const asterx_grid* g) {
+  if (!g) return 0;
+  size_t N = (size_t)g->ld[0] * g->ld[1] * g->ld[2];
+  return (size_t)AW_FIELDS * N * sizeof(double) + ((N + 7) / 8) * 8;
+}
+
+int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* curv,
+                       const double* cons, const double* prim_guess, const double* A, const double* psi,
+                       double dt_max, const double* rhs_bar, double* cons_bar, double* A_bar, double* psi_bar,
+                       double* gamma_bar, void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_adjoint(gr, p, ws_bytes))) return rc;
+  if (!metric || !curv || !cons || !prim_guess || !A || !psi || !rhs_bar || !cons_bar || !A_bar || !psi_bar ||
+      !gamma_bar || !workspace)
+    return fail(ASTERX_EARG, "rhs_adjoint: NULL array");
+  if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs_adjoint: dt_max must be > 0");
+  hipStream_t s = (hipStream_t)stream;
+  GD g = make_gd(gr);
+  double* ws = (double*)workspace;
+  uint8_t* flags = (uint8_t*)(ws + (size_t)AW_FIELDS * g.N);
+  if ((rc = adj_prologue(g, p, metric, cons, prim_guess, A, ws, flags, s, true))) return rc;
+  unsigned nb;
+  FluxBarArgs fb{rhs_bar, ws + AW_FBAR * g.N};
+  nb = tiles_for(PH_VERTEX, g);
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_fluxbar, dim3(nb), dim3(256), 0, s, g, fb); }))) return rc;
+  FaceAdjArgs fa{metric, ws + AW_PRIM * g.N, A, ws + AW_BC * g.N, ws + AW_FBAR * g.N, ws + AW_PBAR * g.N,
+                 ws + AW_BCBAR * g.N, ws + AW_BFBAR * g.N, gamma_bar, p->gamma, p->weno_eps, p->weno_q, p->speeds};
+  if (p->recon == ASTERX_RECON_MINMOD) rc = adj_faces_r<ASTERX_RECON_MINMOD>(g, fa, s);
+  else if (p->recon == ASTERX_RECON_PPM) rc = adj_faces_r<ASTERX_RECON_PPM>(g, fa, s);
+  else rc = adj_faces_r<ASTERX_RECON_WENOZ>(g, fa, s);
+  if (rc) return rc;
+  CellAdjArgs ca{metric, curv, ws + AW_PRIM * g.N, ws + AW_BC * g.N, rhs_bar, ws + AW_PBAR * g.N,
+                 ws + AW_BCBAR * g.N, gamma_bar, p->gamma};
+  nb = tiles_for(PH_RK, g);
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_cell_adj, dim3(nb), dim3(256), 0, s, g, ca); }))) return rc;
+  VertexAdjArgs va{metric, rhs_bar, ws + AW_PSIBAR * g.N, ws + AW_AVBAR * g.N, p->xi / dt_max, p->gauge};
+  nb = tiles_for(PH_VERTEX, g);
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_vertex_adj, dim3(nb), dim3(256), 0, s, g, va); }))) return rc;
+  int ee[3] = {g.n[0] + 3, g.n[1] + 3, g.n[2] + 3};
+  nb = box_blocks<64, 4>(ee);
+  if ((rc = timed(KT_ADJ, s, [&] {
+         hipLaunchKernelGGL(k_edge_adj, dim3(nb), dim3(256), 0, s, g, ws + AW_AVBAR * g.N, ws + AW_ABAR * g.N);
+       })))
+    return rc;
+  if ((rc = adj_fillT(g, ws + AW_PBAR * g.N, 5, s))) return rc;
+  C2PAdjArgs cpa{metric, ws + AW_PRIM * g.N, ws + AW_BC * g.N, flags, ws + AW_PBAR * g.N, cons_bar,
+                 ws + AW_BCBAR * g.N, gamma_bar, p->gamma, 0};
+  nb = tiles_for(PH_RK, g);
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_c2p_adj, dim3(nb), dim3(256), 0, s, g, cpa); }))) return rc;
+  return adj_epilogue(g, ws, A_bar, psi_bar, s);
+}
+
+int asterx_c2p_adjoint(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* cons,
+                       const double* prim_guess, const double* A, const double* prim_bar, double* cons_bar,
+                       double* A_bar, double* gamma_bar, void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_adjoint(gr, p, ws_bytes))) return rc;
+  if (!metric || !cons || !prim_guess || !A || !prim_bar || !cons_bar || !A_bar || !gamma_bar || !workspace)
+    return fail(ASTERX_EARG, "c2p_adjoint: NULL array");
+  hipStream_t s = (hipStream_t)stream;
+  GD g = make_gd(gr);
+  double* ws = (double*)workspace;
+  uint8_t* flags = (uint8_t*)(ws + (size_t)AW_FIELDS * g.N);
+  if ((rc = adj_prologue(g, p, metric, cons, prim_guess, A, ws, flags, s, true))) return rc;
+  unsigned no = tiles_for(PH_RK, g);
+  AccumArgs cp{prim_bar, ws + AW_PBAR * g.N, 5};
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_accum, dim3(no), dim3(256), 0, s, g, cp); }))) return rc;
+  C2PAdjArgs cpa{metric, ws + AW_PRIM * g.N, ws + AW_BC * g.N, flags, ws + AW_PBAR * g.N, cons_bar,
+                 ws + AW_BCBAR * g.N, gamma_bar, p->gamma, 0};
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_c2p_adj, dim3(no), dim3(256), 0, s, g, cpa); }))) return rc;
+  return adj_epilogue(g, ws, A_bar, nullptr, s);
+}
+
+int asterx_prim2con_adjoint(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* A,
+                            const double* prim, const double* cons_bar, double* prim_bar, double* A_bar,
+                            double* gamma_bar, void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_adjoint(gr, p, ws_bytes))) return rc;
+  if (!metric || !A || !prim || !cons_bar || !prim_bar || !A_bar || !gamma_bar || !workspace)
+    return fail(ASTERX_EARG, "prim2con_adjoint: NULL array");
+  hipStream_t s = (hipStream_t)stream;
+  GD g = make_gd(gr);
+  double* ws = (double*)workspace;
+  if ((rc = adj_prologue(g, p, metric, nullptr, nullptr, A, ws, nullptr, s, false))) return rc;
+  unsigned no = tiles_for(PH_RK, g);
+  AccumArgs cp{cons_bar, ws + AW_PBAR * g.N, 5};
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_accum, dim3(no), dim3(256), 0, s, g, cp); }))) return rc;
+  C2PAdjArgs cpa{metric, prim, ws + AW_BC * g.N, nullptr, ws + AW_PBAR * g.N, prim_bar, ws + AW_BCBAR * g.N,
+                 gamma_bar, p->gamma, 1};
+  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_c2p_adj, dim3(no), dim3(256), 0, s, g, cpa); }))) return rc;
+  return adj_epilogue(g, ws, A_bar, nullptr, s);
 }
 
 }  // extern "C"

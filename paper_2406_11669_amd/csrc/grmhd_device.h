@@ -13,6 +13,73 @@
 
 namespace ax {
 
+// ---------------------------------------------------------------------------------------
+// Dual number (value, tangent) for forward-mode directional derivatives of the pointwise
+// physics; the adjoint kernels build local Jacobians with it.  Branches (max, min, limiter
+// cases) follow the value, i.e. the active branch.
+// the double versions stay visible next to the dual overloads below
+using ::copysign;
+using ::fabs;
+using ::fmax;
+using ::fmin;
+using ::pow;
+using ::sqrt;
+
+struct Dual {
+  double v, d;
+  DEV Dual() = default;
+  explicit DEV Dual(double x) : v(x), d(0.0) {}
+  DEV Dual(double x, double y) : v(x), d(y) {}
+};
+DEV Dual mkd(double v, double d = 0.0) { return Dual{v, d}; }
+DEV double val(double x) { return x; }
+DEV double val(const Dual& x) { return x.v; }
+DEV Dual operator+(Dual a, Dual b) { return Dual{a.v + b.v, a.d + b.d}; }
+DEV Dual operator-(Dual a, Dual b) { return Dual{a.v - b.v, a.d - b.d}; }
+DEV Dual operator-(Dual a) { return Dual{-a.v, -a.d}; }
+DEV Dual operator*(Dual a, Dual b) { return Dual{a.v * b.v, a.d * b.v + a.v * b.d}; }
+DEV Dual operator/(Dual a, Dual b) {
+  double r = 1.0 / b.v, q = a.v * r;
+  return Dual{q, (a.d - q * b.d) * r};
+}
+DEV Dual operator+(Dual a, double b) { return Dual{a.v + b, a.d}; }
+DEV Dual operator+(double a, Dual b) { return Dual{a + b.v, b.d}; }
+DEV Dual operator-(Dual a, double b) { return Dual{a.v - b, a.d}; }
+DEV Dual operator-(double a, Dual b) { return Dual{a - b.v, -b.d}; }
+DEV Dual operator*(Dual a, double b) { return Dual{a.v * b, a.d * b}; }
+DEV Dual operator*(double a, Dual b) { return Dual{a * b.v, a * b.d}; }
+DEV Dual operator/(Dual a, double b) { return Dual{a.v / b, a.d / b}; }
+DEV Dual operator/(double a, Dual b) {
+  double r = 1.0 / b.v, q = a * r;
+  return Dual{q, -q * b.d * r};
+}
+DEV Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
+DEV Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
+DEV bool operator<(Dual a, Dual b) { return a.v < b.v; }
+DEV bool operator>(Dual a, Dual b) { return a.v > b.v; }
+DEV bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+DEV bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+DEV bool operator<(Dual a, double b) { return a.v < b; }
+DEV bool operator>(Dual a, double b) { return a.v > b; }
+DEV bool operator<=(Dual a, double b) { return a.v <= b; }
+DEV bool operator>=(Dual a, double b) { return a.v >= b; }
+DEV Dual sqrt(Dual a) {
+  double s = ::sqrt(a.v);
+  return Dual{s, a.d * 0.5 / s};
+}
+DEV Dual fabs(Dual a) { return a.v < 0.0 ? -a : a; }
+DEV Dual fmax(Dual a, Dual b) { return a.v >= b.v ? a : b; }
+DEV Dual fmin(Dual a, Dual b) { return a.v <= b.v ? a : b; }
+DEV Dual fmax(Dual a, double b) { return a.v >= b ? a : Dual(b, 0.0); }
+DEV Dual fmax(double a, Dual b) { return a >= b.v ? Dual(a, 0.0) : b; }
+DEV Dual fmin(Dual a, double b) { return a.v <= b ? a : Dual(b, 0.0); }
+DEV Dual fmin(double a, Dual b) { return a <= b.v ? Dual(a, 0.0) : b; }
+DEV Dual copysign(Dual m, Dual s) { return (::signbit(m.v) != ::signbit(s.v)) ? -m : m; }
+DEV Dual pow(Dual a, double e) {
+  double p = ::pow(a.v, e);
+  return Dual{p, a.d * e * p / a.v};
+}
+
 // Symmetric 3x3 storage: xx, xy, xz, yy, yz, zz.
 struct Geo {
   double alp, beta[3];
@@ -46,7 +113,8 @@ DEV void geo_from(const double m[10], Geo& G) {
   G.sqrtg = sqrt(det);
 }
 
-DEV void lower(const double* g, const double v[3], double vl[3]) {
+template <class T>
+DEV void lower(const double* g, const T v[3], T vl[3]) {
   vl[0] = g[0] * v[0] + g[1] * v[1] + g[2] * v[2];
   vl[1] = g[1] * v[0] + g[3] * v[1] + g[4] * v[2];
   vl[2] = g[2] * v[0] + g[4] * v[1] + g[5] * v[2];
@@ -62,18 +130,21 @@ DEV int sym(int d, int e) {
 // A fluid state with its magnetic field (Sec. 2.2, comoving field from the Eulerian one).
 // All quantities needed by fluxes and speeds, expressed through
 // W^-2 = 1 - v^2, B.v and B^2 (b^2 = B^2/W^2 + (B.v)^2, alpha b^0 = W B.v).
-struct State {
-  double rho, p, v[3], vl[3], iW2, W, B[3], Bl[3], B2, Bv, bsq, rhoh;
+template <class T>
+struct StateT {
+  T rho, p, v[3], vl[3], iW2, W, B[3], Bl[3], B2, Bv, bsq, rhoh;
 };
+using State = StateT<double>;
 
-DEV void state_make(const Geo& G, const double pr[5], const double Bt[3], double gam, State& S) {
+template <class T>
+DEV void state_make(const Geo& G, const T pr[5], const T Bt[3], T gam, StateT<T>& S, T gfac) {
   S.rho = pr[0];
   S.p = pr[1];
   S.v[0] = pr[2];
   S.v[1] = pr[3];
   S.v[2] = pr[4];
   lower(G.g, S.v, S.vl);
-  double v2 = S.v[0] * S.vl[0] + S.v[1] * S.vl[1] + S.v[2] * S.vl[2];
+  T v2 = S.v[0] * S.vl[0] + S.v[1] * S.vl[1] + S.v[2] * S.vl[2];
   S.iW2 = 1.0 - v2;
   S.W = 1.0 / sqrt(S.iW2);
   double is = 1.0 / G.sqrtg;
@@ -84,15 +155,21 @@ DEV void state_make(const Geo& G, const double pr[5], const double Bt[3], double
   S.B2 = S.B[0] * S.Bl[0] + S.B[1] * S.Bl[1] + S.B[2] * S.Bl[2];
   S.Bv = S.B[0] * S.vl[0] + S.B[1] * S.vl[1] + S.B[2] * S.vl[2];
   S.bsq = S.B2 * S.iW2 + S.Bv * S.Bv;
-  S.rhoh = S.rho + gam / (gam - 1.0) * S.p;  // rho h = rho (1 + eps) + p (ideal gas, Sec. 3.7)
+  // rho h = rho (1 + eps) + p = rho + Gamma/(Gamma-1) p (ideal gas, Sec. 3.7); gfac = Gamma/(Gamma-1)
+  S.rhoh = S.rho + gfac * S.p;
+}
+
+DEV void state_make(const Geo& G, const double pr[5], const double Bt[3], double gam, State& S) {
+  state_make<double>(G, pr, Bt, gam, S, gam / (gam - 1.0));
 }
 
 // Densitized conserved variables, written with z = rho h W^2 (Sec. 3.5 rewriting of the
 // definitions): S_j = (z + B^2) v_j - (B.v) B_j, tau = z + B^2 - p - B^2/(2W^2) - (B.v)^2/2 - D.
-DEV void cons_of(const Geo& G, const State& S, double U[5]) {
-  double z = S.rhoh * S.W * S.W;
-  double D = S.rho * S.W;
-  double zb = z + S.B2;
+template <class T>
+DEV void cons_of(const Geo& G, const StateT<T>& S, T U[5]) {
+  T z = S.rhoh * S.W * S.W;
+  T D = S.rho * S.W;
+  T zb = z + S.B2;
   U[0] = G.sqrtg * D;
   U[1] = G.sqrtg * (zb * S.vl[0] - S.Bv * S.Bl[0]);
   U[2] = G.sqrtg * (zb * S.vl[1] - S.Bv * S.Bl[1]);
@@ -103,26 +180,26 @@ DEV void cons_of(const Geo& G, const State& S, double U[5]) {
 // Conserved vector and flux along D (eq. grmhdeqs times alpha sqrt(gamma)):
 // 5 hydro components and the two transverse densitized induction components
 // (t1 = (D+1)%3, t2 = (D+2)%3): Btilde^t vt^D - Btilde^D vt^t.
-template <int D>
-DEV void flux_of(const Geo& G, const State& S, double U[7], double F[7]) {
+template <int D, class T>
+DEV void flux_of(const Geo& G, const StateT<T>& S, T U[7], T F[7]) {
   constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
   cons_of(G, S, U);
-  double vt[3];
+  T vt[3];
   vt[0] = G.alp * S.v[0] - G.beta[0];
   vt[1] = G.alp * S.v[1] - G.beta[1];
   vt[2] = G.alp * S.v[2] - G.beta[2];
-  double ptot = S.p + 0.5 * S.bsq;
+  T ptot = S.p + 0.5 * S.bsq;
   double as = G.alp * G.sqrtg;
   // b_j B^D / W = B_j B^D / W^2 + (B.v) v_j B^D ;  alpha b^0 B^D / W = (B.v) B^D
-  double BD = S.B[D];
-  double m1 = BD * S.iW2, m2 = S.Bv * BD;
+  T BD = S.B[D];
+  T m1 = BD * S.iW2, m2 = S.Bv * BD;
   F[0] = U[0] * vt[D];
   F[1] = U[1] * vt[D] - as * (S.Bl[0] * m1 + S.vl[0] * m2);
   F[2] = U[2] * vt[D] - as * (S.Bl[1] * m1 + S.vl[1] * m2);
   F[3] = U[3] * vt[D] - as * (S.Bl[2] * m1 + S.vl[2] * m2);
   F[1 + D] += as * ptot;
   F[4] = U[4] * vt[D] + as * (ptot * S.v[D] - m2);
-  double Bt1 = G.sqrtg * S.B[t1], Bt2 = G.sqrtg * S.B[t2], BtD = G.sqrtg * BD;
+  T Bt1 = G.sqrtg * S.B[t1], Bt2 = G.sqrtg * S.B[t2], BtD = G.sqrtg * BD;
   F[5] = Bt1 * vt[D] - BtD * vt[t1];
   F[6] = Bt2 * vt[D] - BtD * vt[t2];
   U[5] = Bt1;
@@ -136,55 +213,80 @@ DEV void flux_of(const Geo& G, const State& S, double U[7], double F[7]) {
 // a = -lambda u^0 + u^D, bb = -lambda b^0 + b^D, G = g^00 lambda^2 - 2 g^0D lambda + g^DD,
 // expanded into a quartic in lambda and solved by Newton from the outer roots of the
 // isotropic bound (1 - w2) a^2 - w2 G = 0, w2 = cs^2 + cA^2 - cs^2 cA^2, inward.
-DEV void qroots(double qa, double qb, double qc, double& rp, double& rm) {
-  double disc = fmax(qb * qb - 4.0 * qa * qc, 0.0);
-  double sd = sqrt(disc);
-  double q = -0.5 * (qb + copysign(sd, qb));
-  double r1 = q / qa, r2 = qc / q;
-  if (q == 0.0) r1 = r2 = 0.0;
+template <class T>
+DEV void qroots(T qa, T qb, T qc, T& rp, T& rm) {
+  T disc = fmax(qb * qb - 4.0 * qa * qc, 0.0);
+  T sd = sqrt(disc);
+  T q = -0.5 * (qb + copysign(sd, qb));
+  T r1 = q / qa, r2 = qc / q;
+  if (val(q) == 0.0) r1 = r2 = q;
   rp = fmax(r1, r2);
   rm = fmin(r1, r2);
 }
 
-DEV double newton_root(const double c[5], double x) {
+// Newton on the quartic in Horner form, for both outer roots in one loop (two independent
+// dependency chains per iteration).  The step uses the hardware reciprocal estimate of Q':
+// an inexact step only scales the Newton correction by (1 + delta), which the next pass
+// corrects, so each root is still found to the stopping tolerance.
+DEV void quartic_outer_roots(const double c[5], double& xp, double& xm) {
+  const double d3 = 4.0 * c[4], d2 = 3.0 * c[3], d1 = 2.0 * c[2];
+  const double tol = 8.881784197001252e-16;
+  bool dp = false, dm = false;
   for (int it = 0; it < 30; ++it) {
-    double q = (((c[4] * x + c[3]) * x + c[2]) * x + c[1]) * x + c[0];
-    double dq = ((4.0 * c[4] * x + 3.0 * c[3]) * x + 2.0 * c[2]) * x + c[1];
-    if (dq == 0.0) break;
-    double s = q / dq;
-    x -= s;
-    if (fabs(s) <= 8.881784197001252e-16 * fmax(1.0, fabs(x))) break;
+    double qp = (((c[4] * xp + c[3]) * xp + c[2]) * xp + c[1]) * xp + c[0];
+    double qm = (((c[4] * xm + c[3]) * xm + c[2]) * xm + c[1]) * xm + c[0];
+    double gp = ((d3 * xp + d2) * xp + d1) * xp + c[1];
+    double gm = ((d3 * xm + d2) * xm + d1) * xm + c[1];
+    double sp = gp != 0.0 ? qp * __builtin_amdgcn_rcp(gp) : 0.0;
+    double sm = gm != 0.0 ? qm * __builtin_amdgcn_rcp(gm) : 0.0;
+    if (!dp) {
+      xp -= sp;
+      dp = fabs(sp) <= tol * fmax(1.0, fabs(xp));
+    }
+    if (!dm) {
+      xm -= sm;
+      dm = fabs(sm) <= tol * fmax(1.0, fabs(xm));
+    }
+    if (dp && dm) break;
   }
-  return x;
 }
 
-template <int D>
-DEV void speeds_of(const Geo& G, const State& S, double gam, int kind, double& cm, double& cp) {
+// Root of the quartic found on values; for dual coefficients its tangent follows from the
+// implicit function theorem, d lambda = -(sum_k dc_k lambda^k) / Q'(lambda).
+DEV double root_tangent(const double c[5], double x) { return x; }
+DEV Dual root_tangent(const Dual c[5], double x) {
+  double qd = (((c[4].d * x + c[3].d) * x + c[2].d) * x + c[1].d) * x + c[0].d;
+  double dq = ((4.0 * c[4].v * x + 3.0 * c[3].v) * x + 2.0 * c[2].v) * x + c[1].v;
+  return Dual{x, dq != 0.0 ? -qd / dq : 0.0};
+}
+
+template <int D, class T>
+DEV void speeds_of(const Geo& G, const StateT<T>& S, T gam, int kind, T& cm, T& cp) {
   double ia = 1.0 / G.alp;
   double bD = G.beta[D];
-  double uD = S.W * (S.v[D] - bD * ia);
-  double u0 = S.W * ia;
-  double b0 = S.W * S.Bv * ia;
-  double bDc = (S.B[D] + G.alp * b0 * uD) / S.W;
-  double cs2 = gam * S.p / S.rhoh;
-  double cA2 = S.bsq / (S.rhoh + S.bsq);
-  double w2 = cs2 + cA2 - cs2 * cA2;
+  T uD = S.W * (S.v[D] - bD * ia);
+  T u0 = S.W * ia;
+  T b0 = S.W * S.Bv * ia;
+  T bDc = (S.B[D] + G.alp * b0 * uD) / S.W;
+  T cs2 = gam * S.p / S.rhoh;
+  T cA2 = S.bsq / (S.rhoh + S.bsq);
+  T w2 = cs2 + cA2 - cs2 * cA2;
   double ia2 = ia * ia;
   double G0 = G.gu[sym(D, D)] - bD * bD * ia2, G1 = -2.0 * bD * ia2, G2 = -ia2;
-  double a0 = uD, a1 = -u0;
-  double om = 1.0 - w2;
-  double lp, lm;
+  T a0 = uD, a1 = -u0;
+  T om = 1.0 - w2;
+  T lp, lm;
   qroots(om * a1 * a1 - w2 * G2, 2.0 * om * a0 * a1 - w2 * G1, om * a0 * a0 - w2 * G0, lp, lm);
   if (kind == 1) {
     cp = lp;
     cm = lm;
     return;
   }
-  double A4 = S.rhoh * (1.0 - cs2), Bq = S.rhoh * cs2 + S.bsq, Cq = cs2;
+  T A4 = S.rhoh * (1.0 - cs2), Bq = S.rhoh * cs2 + S.bsq, Cq = cs2;
   // a^2 and bb^2 as quadratics, products with G as quartics
-  double s0 = a0 * a0, s1 = 2.0 * a0 * a1, s2 = a1 * a1;
-  double t0 = bDc * bDc, t1 = -2.0 * bDc * b0, t2 = b0 * b0;
-  double c[5];
+  T s0 = a0 * a0, s1 = 2.0 * a0 * a1, s2 = a1 * a1;
+  T t0 = bDc * bDc, t1 = -2.0 * bDc * b0, t2 = b0 * b0;
+  T c[5];
   // A4 a^4
   c[0] = A4 * s0 * s0;
   c[1] = A4 * 2.0 * s0 * s1;
@@ -192,124 +294,76 @@ DEV void speeds_of(const Geo& G, const State& S, double gam, int kind, double& c
   c[3] = A4 * 2.0 * s1 * s2;
   c[4] = A4 * s2 * s2;
   // (-Bq a^2 + Cq bb^2) G
-  double r0 = -Bq * s0 + Cq * t0, r1 = -Bq * s1 + Cq * t1, r2 = -Bq * s2 + Cq * t2;
+  T r0 = -Bq * s0 + Cq * t0, r1 = -Bq * s1 + Cq * t1, r2 = -Bq * s2 + Cq * t2;
   c[0] += r0 * G0;
   c[1] += r0 * G1 + r1 * G0;
   c[2] += r0 * G2 + r1 * G1 + r2 * G0;
   c[3] += r1 * G2 + r2 * G1;
   c[4] += r2 * G2;
-  cp = newton_root(c, lp);
-  cm = newton_root(c, lm);
-}
-
-// HLLE (Sec. 3.3, eq. HLLEfluxes).
-DEV void hlle7(const double UL[7], const double FL[7], double cmL, double cpL, const double UR[7],
-               const double FR[7], double cmR, double cpR, double Fo[7], double& smax) {
-  double cmax = fmax(0.0, fmax(cpL, cpR));
-  double cmin = -fmin(0.0, fmin(cmL, cmR));
-  double den = cmax + cmin;
-  smax = fmax(cmax, cmin);
-  if (den > 0.0) {
-    double id = 1.0 / den, cc = cmax * cmin;
-#pragma unroll
-    for (int c = 0; c < 7; ++c) Fo[c] = (cmin * FR[c] + cmax * FL[c] - cc * (UR[c] - UL[c])) * id;
-  } else {
-#pragma unroll
-    for (int c = 0; c < 7; ++c) Fo[c] = 0.5 * (FL[c] + FR[c]);
-  }
+  double cv[5] = {val(c[0]), val(c[1]), val(c[2]), val(c[3]), val(c[4])};
+  double xp = val(lp), xm = val(lm);
+  quartic_outer_roots(cv, xp, xm);
+  cp = root_tangent(c, xp);
+  cm = root_tangent(c, xm);
 }
 
 // ---------------------------------------------------------------------------------------
 // Reconstruction (Sec. 3.3) at the face between cells i-1 and i from a[0..5] = a_{i-3..i+2}:
 // L = right-face value of cell i-1, R = left-face value of cell i.
-DEV double mm(double x, double y) {
-  return (x * y > 0.0) ? copysign(fmin(fabs(x), fabs(y)), x) : 0.0;
-}
-
-DEV void rec_minmod(const double a[6], double& L, double& R) {
-  L = a[2] + 0.5 * mm(a[2] - a[1], a[3] - a[2]);
-  R = a[3] - 0.5 * mm(a[3] - a[2], a[4] - a[3]);
+template <class T>
+DEV T mm(T x, T y) {
+  return (val(x) * val(y) > 0.0) ? copysign(fmin(fabs(x), fabs(y)), x) : T(0.0 * val(x));
 }
 
 // Monotonized-central slope of PPM (Colella-Woodward).
-DEV double mc_slope(double am, double a0, double ap) {
-  double dl = a0 - am, dr = ap - a0;
-  if (dl * dr > 0.0) {
-    double dc = 0.5 * (ap - am);
+template <class T>
+DEV T mc_slope(T am, T a0, T ap) {
+  T dl = a0 - am, dr = ap - a0;
+  if (val(dl) * val(dr) > 0.0) {
+    T dc = 0.5 * (ap - am);
     return copysign(fmin(fabs(dc), 2.0 * fmin(fabs(dl), fabs(dr))), dc);
   }
-  return 0.0;
+  return T(0.0 * val(dl));
 }
 
 // PPM cell parabola limited per Colella-Woodward; returns (left, right) face values of
 // the cell with neighbour face values fl (c-1/2) and fr (c+1/2).
-DEV void ppm_limit(double ac, double& fl, double& fr) {
-  if ((fr - ac) * (ac - fl) <= 0.0) {
+template <class T>
+DEV void ppm_limit(T ac, T& fl, T& fr) {
+  if (val(fr - ac) * val(ac - fl) <= 0.0) {
     fl = ac;
     fr = ac;
     return;
   }
-  double dd = fr - fl;
-  double a6 = dd * (ac - 0.5 * (fl + fr));
-  double d2 = dd * dd * (1.0 / 6.0);
+  T dd = fr - fl;
+  T a6 = dd * (ac - 0.5 * (fl + fr));
+  T d2 = dd * dd * (1.0 / 6.0);
   if (a6 > d2)
     fl = 3.0 * ac - 2.0 * fr;
   else if (-d2 > a6)
     fr = 3.0 * ac - 2.0 * fl;
 }
 
-DEV void rec_ppm(const double a[6], double& L, double& R) {
-  // slopes of cells i-2 .. i+1 (a[1..4])
-  double s1 = mc_slope(a[0], a[1], a[2]);
-  double s2 = mc_slope(a[1], a[2], a[3]);
-  double s3 = mc_slope(a[2], a[3], a[4]);
-  double s4 = mc_slope(a[3], a[4], a[5]);
-  const double sixth = 1.0 / 6.0;
-  // unlimited face values at i-3/2, i-1/2, i+1/2
-  double fm = 0.5 * (a[1] + a[2]) - (s2 - s1) * sixth;
-  double f0 = 0.5 * (a[2] + a[3]) - (s3 - s2) * sixth;
-  double fp = 0.5 * (a[3] + a[4]) - (s4 - s3) * sixth;
-  double l1 = fm, r1 = f0;  // cell i-1
-  ppm_limit(a[2], l1, r1);
-  double l2 = f0, r2 = fp;  // cell i
-  ppm_limit(a[3], l2, r2);
-  L = r1;
-  R = l2;
-}
-
 // WENO-Z (Borges et al. 2008) value at the right face of the middle cell of (m2..p2).
-DEV double wenoz_face(double m2, double m1, double c0, double p1, double p2, double eps, double q) {
+template <class T>
+DEV T wenoz_face(T m2, T m1, T c0, T p1, T p2, double eps, double q) {
   const double t13 = 13.0 / 12.0;
-  double e0 = m2 - 2.0 * m1 + c0, f0 = m2 - 4.0 * m1 + 3.0 * c0;
-  double e1 = m1 - 2.0 * c0 + p1, f1 = m1 - p1;
-  double e2 = c0 - 2.0 * p1 + p2, f2 = 3.0 * c0 - 4.0 * p1 + p2;
-  double b0 = t13 * e0 * e0 + 0.25 * f0 * f0;
-  double b1 = t13 * e1 * e1 + 0.25 * f1 * f1;
-  double b2 = t13 * e2 * e2 + 0.25 * f2 * f2;
-  double tau = fabs(b0 - b2);
-  double r0 = tau / (b0 + eps), r1 = tau / (b1 + eps), r2 = tau / (b2 + eps);
+  T e0 = m2 - 2.0 * m1 + c0, f0 = m2 - 4.0 * m1 + 3.0 * c0;
+  T e1 = m1 - 2.0 * c0 + p1, f1 = m1 - p1;
+  T e2 = c0 - 2.0 * p1 + p2, f2 = 3.0 * c0 - 4.0 * p1 + p2;
+  T b0 = t13 * e0 * e0 + 0.25 * f0 * f0;
+  T b1 = t13 * e1 * e1 + 0.25 * f1 * f1;
+  T b2 = t13 * e2 * e2 + 0.25 * f2 * f2;
+  T tau = fabs(b0 - b2);
+  T r0 = tau / (b0 + eps), r1 = tau / (b1 + eps), r2 = tau / (b2 + eps);
   if (q != 1.0) {
     r0 = pow(r0, q);
     r1 = pow(r1, q);
     r2 = pow(r2, q);
   }
-  double w0 = 0.1 * (1.0 + r0), w1 = 0.6 * (1.0 + r1), w2 = 0.3 * (1.0 + r2);
-  double q0 = (2.0 * m2 - 7.0 * m1 + 11.0 * c0), q1 = (-m1 + 5.0 * c0 + 2.0 * p1), q2 = (2.0 * c0 + 5.0 * p1 - p2);
+  T w0 = 0.1 * (1.0 + r0), w1 = 0.6 * (1.0 + r1), w2 = 0.3 * (1.0 + r2);
+  T q0 = (2.0 * m2 - 7.0 * m1 + 11.0 * c0), q1 = (-m1 + 5.0 * c0 + 2.0 * p1), q2 = (2.0 * c0 + 5.0 * p1 - p2);
   return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0 * (w0 + w1 + w2));
-}
-
-DEV void rec_wenoz(const double a[6], double& L, double& R, double eps, double q) {
-  L = wenoz_face(a[0], a[1], a[2], a[3], a[4], eps, q);
-  R = wenoz_face(a[5], a[4], a[3], a[2], a[1], eps, q);
-}
-
-DEV void reconstruct(int kind, const double a[6], double& L, double& R, double eps, double q) {
-  if (kind == 0)
-    rec_minmod(a, L, R);
-  else if (kind == 1)
-    rec_ppm(a, L, R);
-  else
-    rec_wenoz(a, L, R, eps, q);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -18,6 +18,10 @@ Workloads (one block, one GPU):
                 problem split at x = 1/2, MINMOD, HLLE, Noble c2p, RK2, CFL 0.25.
   curved128  -- 128^3 periodic block in a static curved metric (low-k mode
                 sums), Gamma = 2, PPM or WENO-Z, RK4, CFL 0.25.
+  periodic_riemann64 -- the Riemann states on a 64^3 periodic box (interfaces
+                at x = 1/2 and at the wrap), flat, PPM, RK2, 20 steps, Gamma = 5/3;
+                the vector potential is periodic up to a constant per wrap.
+  patch_set  -- 512 Riemann-problem patches of uneven sides and levels.
 Both are also available at other sizes for tests.
 """
 from dataclasses import dataclass, field
@@ -145,6 +149,7 @@ class Workload:
     bc_cell: tuple
     bc_A: tuple
     info: dict = field(default_factory=dict)
+    A_shift: np.ndarray = None  # (3, 3): A_q gains A_shift[q, d] per period of wrap along axis d
 
     def state(self, cons):
         """9-field state array (Dt, St_x, St_y, St_z, taut, A_x, A_y, A_z, Psi) from conserved variables."""
@@ -165,14 +170,15 @@ def flat_metric(layout):
 
 
 def riemann_block(seed=0, n=32, ng=NG_DEFAULT, recon="minmod", nsteps=10, rk=2, cfl=0.25, gamma=5.0 / 3.0,
-                  split=0.5):
-    """Seeded relativistic MHD Riemann problem on [0,1]^3, split on the vertex plane x = split.
+                  split=0.5, dx=None):
+    """Seeded relativistic MHD Riemann problem on [0, n dx]^3 (dx = 1/n by default), split on the vertex plane
+    x = split.
 
     Left/right: rho, p ~ U[0.1, 1], v = 0, B^x ~ U[-1, 1] shared, B^y, B^z ~ U[-1, 1] per side.
     The edge potential A = (0, int_0^x B^z dx', B^x y - int_0^x B^y dx') reproduces the
     piecewise-constant face field exactly under the discrete curl."""
     nn = (n, n, n) if np.isscalar(n) else tuple(n)
-    L = Layout(nn, ng)
+    L = Layout(nn, ng, dx=None if dx is None else (dx, dx, dx))
     rng = np.random.default_rng(int(seed))
     rhoL, rhoR = rng.uniform(0.1, 1.0, 2)
     pL, pR = rng.uniform(0.1, 1.0, 2)
@@ -201,6 +207,62 @@ def riemann_block(seed=0, n=32, ng=NG_DEFAULT, recon="minmod", nsteps=10, rk=2, 
     info = dict(rhoL=rhoL, rhoR=rhoR, pL=pL, pR=pR, Bx=Bx, ByL=ByL, BzL=BzL, ByR=ByR, BzR=BzR, seed=seed)
     return Workload("riemann%d" % nn[0], L, params, metric, curv, prim, A, psi, dt, nsteps, rk,
                     ("copy",) * 3, ("linear",) * 3, info)
+
+
+def periodic_riemann_box(seed=0, n=64, ng=NG_DEFAULT, recon="ppm", nsteps=20, rk=2, cfl=0.25, gamma=5.0 / 3.0,
+                         v_amp=0.0):
+    """The seeded Riemann-problem states of riemann_block on a periodic unit box: interfaces on the vertex
+    planes x = 1/2 and x = 0 (the wrap).  Flat metric.
+
+    The face field is B = Bbar + dB with Bbar the box mean and dB a zero-mean square wave in x.  The potential
+    is A = Bbar x r / 2 + A_per with A_per the periodic sawtooth potential of dB, so A is periodic up to the
+    constant Bbar x (L e_d) / 2 per period along axis d (kept in A_shift).  v_amp > 0 adds a seeded smooth
+    velocity field of that maximum component (default 0: fluid at rest, as in the Riemann problem)."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    L = Layout(nn, ng)
+    rng = np.random.default_rng(int(seed))
+    rhoL, rhoR = rng.uniform(0.1, 1.0, 2)
+    pL, pR = rng.uniform(0.1, 1.0, 2)
+    Bx = rng.uniform(-1.0, 1.0)
+    ByL, BzL, ByR, BzR = rng.uniform(-1.0, 1.0, 4)
+    metric = flat_metric(L)
+    curv = L.zeros(6)
+    prim = L.zeros(5)
+    xc, yc, zc = L.coords("centre")
+    left = np.broadcast_to(np.mod(xc, 1.0) < 0.5, L.shape3)
+    prim[0] = np.where(left, rhoL, rhoR)
+    prim[1] = np.where(left, pL, pR)
+    if v_amp > 0.0:
+        for c, nm in enumerate(("vx", "vy", "vz")):
+            prim[2 + c] = v_amp * np.broadcast_to(ModeSum(seed, 100 + _TAGS[nm])(xc, yc, zc), L.shape3)
+    Bbar = np.array([Bx, 0.5 * (ByL + ByR), 0.5 * (BzL + BzR)])
+    hy, hz = 0.5 * (ByL - ByR), 0.5 * (BzL - BzR)
+
+    def saw(x, h):
+        # integral from 0 of the square wave (+h on [0, 1/2), -h on [1/2, 1)), periodic with period 1
+        xm = np.mod(x, 1.0)
+        return np.where(xm < 0.5, h * xm, h * (1.0 - xm))
+
+    A = L.zeros(3)
+    x, y, z = L.coords("xedge")
+    A[0] = np.broadcast_to(0.5 * (Bbar[1] * z - Bbar[2] * y) + 0.0 * x, L.shape3)
+    x, y, z = L.coords("yedge")
+    A[1] = np.broadcast_to(0.5 * (Bbar[2] * x - Bbar[0] * z) + saw(x, hz) + 0.0 * y, L.shape3)
+    x, y, z = L.coords("zedge")
+    A[2] = np.broadcast_to(0.5 * (Bbar[0] * y - Bbar[1] * x) - saw(x, hy) + 0.0 * z, L.shape3)
+    ext = [nn[d] * L.dx[d] for d in range(3)]
+    shift = np.zeros((3, 3))
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = ext[d]
+        shift[:, d] = 0.5 * np.cross(Bbar, e)
+    psi = L.zeros(1)
+    params = default_params(gamma=gamma, rho_atm=1e-7 * max(rhoL, rhoR), recon=recon)
+    dt = cfl * min(L.dx)
+    info = dict(rhoL=rhoL, rhoR=rhoR, pL=pL, pR=pR, Bx=Bx, ByL=ByL, BzL=BzL, ByR=ByR, BzR=BzR, seed=seed,
+                v_amp=v_amp)
+    return Workload("periodic_riemann%d" % nn[0], L, params, metric, curv, prim, A, psi, dt, nsteps, rk,
+                    ("periodic",) * 3, ("periodic",) * 3, info, shift)
 
 
 # ---- the curved periodic block -----------------------------------------------------------------------------
@@ -307,3 +369,29 @@ def curved_block(seed=0, n=128, ng=NG_DEFAULT, recon="ppm", nsteps=5, rk=4, cfl=
     dt = cfl * min(L.dx)
     return Workload("curved%d" % nn[0], L, params, metric, curv, prim, A, psi, dt, nsteps, rk,
                     ("periodic",) * 3, ("periodic",) * 3, dict(seed=seed, vscale=scale, a_B=1.0 / curl_max))
+
+
+# ---- AMR-like patches ---------------------------------------------------------------------------------------
+
+def patch_set(seed=0, npatches=512, sides=(16, 24, 32, 48), levels=3, ng=NG_DEFAULT, nsteps=10, cfl=0.25,
+              recon="minmod"):
+    """npatches Riemann-problem blocks with seeded sides in `sides` and refinement levels 0..levels-1
+    (spacing 2^-level / 32), each split at its own mid-x with its own seed; flat metric, copy/linear ghosts.
+    One global time step dt = cfl * (smallest spacing) for all patches (no subcycling)."""
+    rng = np.random.default_rng([int(seed), 7919])
+    side = rng.choice(np.array(sides), size=npatches)
+    level = rng.integers(0, levels, size=npatches)
+    out = []
+    for q in range(npatches):
+        n = int(side[q])
+        dx = 2.0 ** (-int(level[q])) / 32.0
+        w = riemann_block(seed=int(seed) * 100003 + q, n=n, ng=ng, recon=recon, nsteps=nsteps, rk=2, cfl=cfl,
+                          split=0.5 * n * dx, dx=dx)
+        out.append(w)
+    dt = cfl * 2.0 ** (-(levels - 1)) / 32.0
+    rho_max = max(max(w.info["rhoL"], w.info["rhoR"]) for w in out)
+    for w in out:
+        w.dt = dt
+        w.params["rho_atm"] = 1e-7 * rho_max  # one floor for the whole hierarchy
+        w.info["level"] = int(np.log2(1.0 / (32.0 * w.layout.dx[0])) + 0.5)
+    return out
