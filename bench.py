@@ -48,7 +48,23 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=56, help="edge of the block the CPU oracle times")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three plain device copies of 256 MiB (reference for the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """Three device-to-device copies of 256 MiB each: a kernel whose HBM traffic is known exactly (256 MiB read
+    and 256 MiB written per launch), so that FETCH_SIZE / WRITE_SIZE per dispatch can be scaled to bytes."""
+    import torch
+    n = 256 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
 def cpu_baseline(recon, n_cpu):
@@ -73,6 +89,9 @@ def cpu_baseline(recon, n_cpu):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one block on one GPU; runs on more than one GPU are not part of this build "
               "(the multi-GPU design is a domain decomposition with halo exchange, not implemented)",

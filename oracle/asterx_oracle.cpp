@@ -110,6 +110,45 @@ static inline Cnt fabs(const Cnt& a) { return Cnt(std::fabs(a.v)); }
 static inline Cnt pow(const Cnt& a, const Cnt& b) { ++Cnt::ops; return Cnt(std::pow(a.v, b.v)); }
 static inline Cnt pow(const Cnt& a, double b) { ++Cnt::ops; return Cnt(std::pow(a.v, b)); }
 
+// ---------------------------------------------------------------------------
+// Forward-mode dual number: value v and tangent d, so that running the plain
+// implementation on it yields the directional derivative (JVP) of any output
+// along a chosen input tangent.  Branches compare values only; converged
+// iterations carry the tangent of their final iterate (within a relative
+// error of the order of the last Newton step).
+struct Dl {
+  double v, d;
+  Dl() : v(0.0), d(0.0) {}
+  Dl(double x) : v(x), d(0.0) {}
+  Dl(double x, double t) : v(x), d(t) {}
+};
+static inline double value_of(const Dl& x) { return x.v; }
+static inline Dl operator+(const Dl& a, const Dl& b) { return Dl(a.v + b.v, a.d + b.d); }
+static inline Dl operator-(const Dl& a, const Dl& b) { return Dl(a.v - b.v, a.d - b.d); }
+static inline Dl operator*(const Dl& a, const Dl& b) { return Dl(a.v * b.v, a.d * b.v + a.v * b.d); }
+static inline Dl operator/(const Dl& a, const Dl& b) {
+  double q = a.v / b.v;
+  return Dl(q, (a.d - q * b.d) / b.v);
+}
+static inline Dl operator-(const Dl& a) { return Dl(-a.v, -a.d); }
+static inline bool operator<(const Dl& a, const Dl& b) { return a.v < b.v; }
+static inline bool operator>(const Dl& a, const Dl& b) { return a.v > b.v; }
+static inline bool operator<=(const Dl& a, const Dl& b) { return a.v <= b.v; }
+static inline bool operator>=(const Dl& a, const Dl& b) { return a.v >= b.v; }
+static inline bool operator==(const Dl& a, const Dl& b) { return a.v == b.v; }
+static inline bool operator!=(const Dl& a, const Dl& b) { return a.v != b.v; }
+static inline Dl sqrt(const Dl& a) {
+  double r = std::sqrt(a.v);
+  return Dl(r, a.d / (2.0 * r));
+}
+static inline Dl fabs(const Dl& a) { return a.v < 0.0 ? -a : a; }
+static inline Dl pow(const Dl& a, const Dl& b) {
+  double r = std::pow(a.v, b.v);
+  double t = (a.d != 0.0 ? b.v * std::pow(a.v, b.v - 1.0) * a.d : 0.0) + (b.d != 0.0 ? r * std::log(a.v) * b.d : 0.0);
+  return Dl(r, t);
+}
+static inline Dl pow(const Dl& a, double b) { return Dl(std::pow(a.v, b), a.d != 0.0 ? b * std::pow(a.v, b - 1.0) * a.d : 0.0); }
+
 // Phase marks: rhs_grid calls phase_mark(k) at the boundaries of its parts; for the
 // counting type the operations of each part are accumulated into g_phase_ops.
 static unsigned long long g_phase_ops[4];
@@ -1332,6 +1371,45 @@ void orc_run(const Grid* g, const Params* P, const double* metric, const double*
              unsigned long long* stats, double* redmax, const double* shiftA) {
   run_steps<double>(*g, *P, P->gamma, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A, flags, stats, redmax,
                     shiftA);
+}
+
+// Loss of the differentiation workload, (sum over owned cells of rho^2 dV)^(1/2) after nsteps
+// from the primitives prim0 (conserved variables by prim2con, cell ghosts by bc_cell), and its
+// directional derivative along the tangent (dprim0, dgamma) by forward-mode dual numbers.
+// out[0] = loss, out[1] = directional derivative.  stats: c2p counters of the whole run.
+void orc_loss_jvp(const Grid* g, const Params* P, double dgamma, const double* metric, const double* curv,
+                  const double* prim0, const double* dprim0, const double* A0, const double* psi0, double dt,
+                  int nsteps, int rk, const int* bc_cell, const int* bc_A, const double* shiftA, double* out,
+                  unsigned long long* stats) {
+  size_t N = npts(*g);
+  auto lift = [&](const double* a, const double* da, int nf) {
+    std::vector<Dl> r((size_t)nf * N);
+    for (size_t q = 0; q < (size_t)nf * N; ++q) r[q] = Dl(a[q], da ? da[q] : 0.0);
+    return r;
+  };
+  std::vector<Dl> m = lift(metric, nullptr, 10), K = lift(curv, nullptr, 6), prim = lift(prim0, dprim0, 5);
+  std::vector<Dl> state(9 * N);
+  std::vector<Dl> A = lift(A0, nullptr, 3), psi = lift(psi0, nullptr, 1);
+  Dl gam(P->gamma, dgamma);
+  prim2con_grid<Dl>(*g, *P, gam, m.data(), A.data(), prim.data(), state.data());
+  fill_ghosts<Dl>(*g, state.data(), 5, bc_cell);
+  std::copy(A.begin(), A.end(), state.begin() + 5 * N);
+  std::copy(psi.begin(), psi.end(), state.begin() + 8 * N);
+  std::vector<uint8_t> flags(N);
+  run_steps<Dl>(*g, *P, gam, m.data(), K.data(), state.data(), prim.data(), dt, nsteps, rk, bc_cell, bc_A,
+                flags.data(), stats, nullptr, shiftA);
+  c2p_grid<Dl>(*g, *P, gam, m.data(), state.data() + 5 * N, state.data(), prim.data(), flags.data(), stats);
+  Dl acc(0.0);
+  double dV = g->dx[0] * g->dx[1] * g->dx[2];
+  for (int k = 0; k < g->n[2]; ++k)
+    for (int j = 0; j < g->n[1]; ++j)
+      for (int i = 0; i < g->n[0]; ++i) {
+        Dl r = prim[at(*g, i, j, k)];
+        acc = acc + r * r * Dl(dV);
+      }
+  Dl L = sqrt(acc);
+  out[0] = L.v;
+  out[1] = L.d;
 }
 
 void orc_rk_stage(const Grid* g, int nterms, const double* a, const double* const* u, double b_dt, const double* rhs,

@@ -287,3 +287,20 @@ def pt_tmunu(m10, prim5, Bt3, gam):
     out = np.zeros(16)
     lib().orc_pt_tmunu(_p(_v(m10, 10)), _p(_v(prim5, 5)), _p(_v(Bt3, 3)), ctypes.c_double(gam), _p(out))
     return out.reshape(4, 4)
+
+
+def loss_jvp(layout, params, metric, curv, prim0, A0, psi0, dt, nsteps, rk, bc_cell, bc_A, dprim0=None, dgamma=0.0,
+             A_shift=None):
+    """Loss (sum over owned cells of rho^2 dV)^(1/2) after nsteps from prim0, and its directional derivative
+    along (dprim0, dgamma), by forward-mode dual numbers through the whole run.  Returns (loss, jvp, stats)."""
+    out = np.zeros(2, dtype=np.float64)
+    stats = np.zeros(6, dtype=np.uint64)
+    bcc = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_cell])
+    bca = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_A])
+    sh = None if A_shift is None else np.ascontiguousarray(A_shift, dtype=np.float64)
+    dp = None if dprim0 is None else np.ascontiguousarray(dprim0, dtype=np.float64)
+    lib().orc_loss_jvp(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), ctypes.c_double(dgamma),
+                       _p(metric), _p(curv), _p(np.ascontiguousarray(prim0)), None if dp is None else _p(dp),
+                       _p(A0), _p(psi0), ctypes.c_double(dt), ctypes.c_int(nsteps), ctypes.c_int(rk), bcc, bca,
+                       None if sh is None else _p(sh), _p(out), stats.ctypes.data_as(ctypes.c_void_p))
+    return float(out[0]), float(out[1]), stats

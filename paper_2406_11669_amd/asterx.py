@@ -47,7 +47,8 @@ EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "
            "asterx_timing_read", "asterx_timing_reset", "asterx_timing_name", "asterx_batch_create",
            "asterx_batch_destroy", "asterx_batch_points", "asterx_batch_offset", "asterx_batch_workspace_size",
            "asterx_batch_prim2con", "asterx_batch_c2p", "asterx_batch_fill_ghosts", "asterx_batch_rhs",
-           "asterx_batch_rk_stage"]
+           "asterx_batch_rk_stage", "asterx_adjoint_workspace_size", "asterx_rhs_adjoint", "asterx_c2p_adjoint",
+           "asterx_prim2con_adjoint"]
 
 
 def lib():
@@ -87,6 +88,12 @@ def lib():
         L.asterx_batch_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t,
                                        vp]
         L.asterx_batch_rk_stage.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
+        L.asterx_adjoint_workspace_size.restype = ctypes.c_size_t
+        L.asterx_adjoint_workspace_size.argtypes = [vp]
+        L.asterx_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp,
+                                         ctypes.c_size_t, vp]
+        L.asterx_c2p_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.asterx_prim2con_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         _lib = L
     return _lib
 
@@ -182,6 +189,42 @@ def rk_stage(layout, a, us, b_dt, rhs_t, out, stream=None):
         assert u.is_cuda and u.is_contiguous() and u.dtype == torch.float64
     _check(lib().asterx_rk_stage(ctypes.byref(make_grid(layout)), n, arr_a, arr_u, float(b_dt), _ptr(_f64(rhs_t)),
                                  _ptr(_f64(out)), _stream(stream)))
+
+
+def adjoint_workspace_size(layout):
+    return lib().asterx_adjoint_workspace_size(ctypes.byref(make_grid(layout)))
+
+
+def _ws(workspace):
+    return _ptr(workspace), workspace.numel() * workspace.element_size()
+
+
+def rhs_adjoint(layout, params, metric, curv, cons, prim_guess, A, psi, dt_max, rhs_bar, cons_bar, A_bar, psi_bar,
+                gamma_bar, workspace, stream=None):
+    """Adds the transposed Jacobian of (cons, A, psi) -> rhs(fill(c2p(cons, A)), A, psi) applied to rhs_bar."""
+    w, nb = _ws(workspace)
+    _check(lib().asterx_rhs_adjoint(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                                    _ptr(_f64(metric)), _ptr(_f64(curv)), _ptr(_f64(cons)), _ptr(_f64(prim_guess)),
+                                    _ptr(_f64(A)), _ptr(_f64(psi)), float(dt_max), _ptr(_f64(rhs_bar)),
+                                    _ptr(_f64(cons_bar)), _ptr(_f64(A_bar)), _ptr(_f64(psi_bar)),
+                                    _ptr(_f64(gamma_bar)), w, nb, _stream(stream)))
+
+
+def c2p_adjoint(layout, params, metric, cons, prim_guess, A, prim_bar, cons_bar, A_bar, gamma_bar, workspace,
+                stream=None):
+    w, nb = _ws(workspace)
+    _check(lib().asterx_c2p_adjoint(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                                    _ptr(_f64(metric)), _ptr(_f64(cons)), _ptr(_f64(prim_guess)), _ptr(_f64(A)),
+                                    _ptr(_f64(prim_bar)), _ptr(_f64(cons_bar)), _ptr(_f64(A_bar)),
+                                    _ptr(_f64(gamma_bar)), w, nb, _stream(stream)))
+
+
+def prim2con_adjoint(layout, params, metric, A, prim, cons_bar, prim_bar, A_bar, gamma_bar, workspace, stream=None):
+    w, nb = _ws(workspace)
+    _check(lib().asterx_prim2con_adjoint(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                                         _ptr(_f64(metric)), _ptr(_f64(A)), _ptr(_f64(prim)), _ptr(_f64(cons_bar)),
+                                         _ptr(_f64(prim_bar)), _ptr(_f64(A_bar)), _ptr(_f64(gamma_bar)), w, nb,
+                                         _stream(stream)))
 
 
 def zero(buf, stream=None):

@@ -395,3 +395,18 @@ def patch_set(seed=0, npatches=512, sides=(16, 24, 32, 48), levels=3, ng=NG_DEFA
         w.params["rho_atm"] = 1e-7 * rho_max  # one floor for the whole hierarchy
         w.info["level"] = int(np.log2(1.0 / (32.0 * w.layout.dx[0])) + 0.5)
     return out
+
+
+def gradient_direction(layout, seed, with_gamma=True):
+    """Seeded unit direction in the space of (initial velocity field on owned cells, Gamma): independent
+    standard normals, normalised.  Returns (dprim with the velocity part in fields 2..4 and periodic ghosts,
+    dGamma)."""
+    L = layout
+    rng = np.random.default_rng([int(seed), 4099])
+    d = L.zeros(5)
+    L.owned(d)[2:5] = rng.normal(size=(3, L.n[2], L.n[1], L.n[0]))
+    dg = float(rng.normal()) if with_gamma else 0.0
+    nrm = float(np.sqrt(np.sum(L.owned(d) ** 2) + dg * dg))
+    d /= nrm
+    L.periodic_wrap(d)
+    return d, dg / nrm
