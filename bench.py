@@ -38,6 +38,33 @@ FACE_BYTES = 8.0 * (5 + 2 + 10 + 2 + 7)
 STAGE_BYTES_RK4 = 514.0
 
 
+def library_source_sha():
+    """First 16 hex digits of the sha256 of the HIP sources the library is built from."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2406_11669_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("asterx.hip", "grmhd_device.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_face_traffic(recon, n):
+    """HBM bytes per face-kernel launch from the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE
+    scaled by a plain copy), or None when no summary exists for this workload or it was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "face_curved%d_%s_hbm_traffic.md" % (n, recon))
+    if not os.path.exists(path):
+        return None
+    value, sha = None, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("face kernel, average of the three directions: traffic bytes per launch:"):
+                value = float(line.rsplit(":", 1)[1])
+            elif line.startswith("library source sha256"):
+                sha = line.rsplit(":", 1)[1].strip()
+    return value if (value is not None and sha == library_source_sha()) else None
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,7 +183,8 @@ def main():
     achieved = FACE_FLOPS[args.recon] * faces_per_launch / avg_face_s / 1e12
     roofline = {"kernel": "face (x, y, z launches averaged)", "dominant_by_time": dominant,
                 "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": measured_face_traffic(args.recon, n),
                 "avg_launch_ms": round(avg_face_s * 1e3, 4),
                 "flops_per_face": FACE_FLOPS[args.recon], "faces_per_launch": faces_per_launch,
                 "algorithmic_GBs": round(FACE_BYTES * faces_per_launch / avg_face_s / 1e9, 1)}

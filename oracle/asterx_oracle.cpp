@@ -1412,6 +1412,66 @@ void orc_loss_jvp(const Grid* g, const Params* P, double dgamma, const double* m
   out[1] = L.d;
 }
 
+// Directional derivatives of the pieces of one stage, by forward-mode dual numbers (arrays with
+// ghosts as given; tangents d* with the same layout; NULL tangent = 0).
+static std::vector<Dl> lift_dl(const double* a, const double* da, size_t n) {
+  std::vector<Dl> r(n);
+  for (size_t q = 0; q < n; ++q) r[q] = Dl(a[q], da ? da[q] : 0.0);
+  return r;
+}
+
+// cons = prim2con(prim, A): writes cons and its tangent on owned points.
+void orc_prim2con_jvp(const Grid* g, const Params* P, double dgamma, const double* metric, const double* A,
+                      const double* dA, const double* prim, const double* dprim, double* cons, double* dcons) {
+  size_t N = npts(*g);
+  std::vector<Dl> m = lift_dl(metric, nullptr, 10 * N), a = lift_dl(A, dA, 3 * N), pr = lift_dl(prim, dprim, 5 * N);
+  std::vector<Dl> c(5 * N);
+  prim2con_grid<Dl>(*g, *P, Dl(P->gamma, dgamma), m.data(), a.data(), pr.data(), c.data());
+  for (size_t q = 0; q < 5 * N; ++q) {
+    cons[q] = c[q].v;
+    dcons[q] = c[q].d;
+  }
+}
+
+// prim = c2p(cons, A) warm-started from guess: writes prim and its tangent on owned points.
+void orc_c2p_jvp(const Grid* g, const Params* P, double dgamma, const double* metric, const double* A, const double* dA,
+                 const double* cons, const double* dcons, const double* guess, double* prim, double* dprim) {
+  size_t N = npts(*g);
+  std::vector<Dl> m = lift_dl(metric, nullptr, 10 * N), a = lift_dl(A, dA, 3 * N), c = lift_dl(cons, dcons, 5 * N);
+  std::vector<Dl> pr = lift_dl(guess, nullptr, 5 * N);
+  std::vector<uint8_t> flags(N);
+  unsigned long long st[6] = {0, 0, 0, 0, 0, 0};
+  c2p_grid<Dl>(*g, *P, Dl(P->gamma, dgamma), m.data(), a.data(), c.data(), pr.data(), flags.data(), st);
+  for (size_t q = 0; q < 5 * N; ++q) {
+    prim[q] = pr[q].v;
+    dprim[q] = pr[q].d;
+  }
+}
+
+// One stage's right-hand side L(cons, A, psi) = rhs(fill(c2p(cons, A)), A, psi) with the primitive
+// ghosts filled periodically: writes L (9 fields) and its tangent on owned points.
+void orc_stage_jvp(const Grid* g, const Params* P, double dgamma, const double* metric, const double* curv,
+                   const double* cons, const double* dcons, const double* A, const double* dA, const double* psi,
+                   const double* dpsi, const double* guess, double dt_max, double* out, double* dout) {
+  size_t N = npts(*g);
+  std::vector<Dl> m = lift_dl(metric, nullptr, 10 * N), K = lift_dl(curv, nullptr, 6 * N);
+  std::vector<Dl> a = lift_dl(A, dA, 3 * N), c = lift_dl(cons, dcons, 5 * N), ps = lift_dl(psi, dpsi, N);
+  std::vector<Dl> pr = lift_dl(guess, nullptr, 5 * N), r(9 * N);
+  std::vector<uint8_t> flags(N);
+  unsigned long long st[6] = {0, 0, 0, 0, 0, 0};
+  Dl gam(P->gamma, dgamma);
+  c2p_grid<Dl>(*g, *P, gam, m.data(), a.data(), c.data(), pr.data(), flags.data(), st);
+  const int per[3] = {BC_PERIODIC, BC_PERIODIC, BC_PERIODIC};
+  fill_ghosts<Dl>(*g, pr.data(), 5, per);
+  double red[2];
+  rhs_grid<Dl>(*g, *P, gam, m.data(), K.data(), pr.data(), a.data(), ps.data(), dt_max, r.data(), red,
+               (long long*)nullptr);
+  for (size_t q = 0; q < 9 * N; ++q) {
+    out[q] = r[q].v;
+    dout[q] = r[q].d;
+  }
+}
+
 void orc_rk_stage(const Grid* g, int nterms, const double* a, const double* const* u, double b_dt, const double* rhs,
                   double* out) {
   rk_combine<double>(*g, nterms, a, u, b_dt, rhs, out);

@@ -304,3 +304,42 @@ def loss_jvp(layout, params, metric, curv, prim0, A0, psi0, dt, nsteps, rk, bc_c
                        _p(A0), _p(psi0), ctypes.c_double(dt), ctypes.c_int(nsteps), ctypes.c_int(rk), bcc, bca,
                        None if sh is None else _p(sh), _p(out), stats.ctypes.data_as(ctypes.c_void_p))
     return float(out[0]), float(out[1]), stats
+
+
+def _opt(a):
+    return None if a is None else _p(np.ascontiguousarray(a, dtype=np.float64))
+
+
+def prim2con_jvp(layout, params, metric, A, prim, dA=None, dprim=None, dgamma=0.0):
+    """(cons, dcons) of prim2con along the tangent (dprim, dA, dgamma); owned points."""
+    cons = np.zeros((5,) + layout.shape3)
+    dcons = np.zeros_like(cons)
+    keep = [np.ascontiguousarray(x, dtype=np.float64) if x is not None else None for x in (dA, dprim)]
+    lib().orc_prim2con_jvp(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                           ctypes.c_double(dgamma), _p(metric), _p(A), _opt(keep[0]), _p(prim), _opt(keep[1]),
+                           _p(cons), _p(dcons))
+    return cons, dcons
+
+
+def c2p_jvp(layout, params, metric, A, cons, guess, dA=None, dcons=None, dgamma=0.0):
+    """(prim, dprim) of c2p (warm start guess) along the tangent (dcons, dA, dgamma); owned points."""
+    prim = np.zeros((5,) + layout.shape3)
+    dprim = np.zeros_like(prim)
+    keep = [np.ascontiguousarray(x, dtype=np.float64) if x is not None else None for x in (dA, dcons)]
+    lib().orc_c2p_jvp(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), ctypes.c_double(dgamma),
+                      _p(metric), _p(A), _opt(keep[0]), _p(np.ascontiguousarray(cons)), _opt(keep[1]),
+                      _p(np.ascontiguousarray(guess)), _p(prim), _p(dprim))
+    return prim, dprim
+
+
+def stage_jvp(layout, params, metric, curv, cons, A, psi, guess, dt_max, dcons=None, dA=None, dpsi=None,
+              dgamma=0.0):
+    """(L, dL) of one stage's right-hand side rhs(fill(c2p(cons, A)), A, psi) along the tangent; owned points."""
+    out = np.zeros((9,) + layout.shape3)
+    dout = np.zeros_like(out)
+    keep = [np.ascontiguousarray(x, dtype=np.float64) if x is not None else None for x in (dcons, dA, dpsi)]
+    lib().orc_stage_jvp(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), ctypes.c_double(dgamma),
+                        _p(metric), _p(curv), _p(np.ascontiguousarray(cons)), _opt(keep[0]),
+                        _p(np.ascontiguousarray(A)), _opt(keep[1]), _p(np.ascontiguousarray(psi)), _opt(keep[2]),
+                        _p(np.ascontiguousarray(guess)), ctypes.c_double(dt_max), _p(out), _p(dout))
+    return out, dout

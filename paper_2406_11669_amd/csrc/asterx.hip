@@ -1061,7 +1061,8 @@ DEV double rb_at(const GD& g, const double* r, int i, int j, int k) {
 }
 
 // Face-flux cotangents from the right-hand-side cotangent rbar (9 fields, owned points):
-// hydro components through the divergence, induction components through the FCT averages.
+// hydro components through the divergence (rhs[i] = -(F[i+e] - F[i]) / dx, so
+// Fbar[f] = (rbar[f] - rbar[f-e]) / dx), induction components through the FCT averages.
 struct FluxBarArgs {
   const double* rbar;
   double* fbar;
@@ -1080,7 +1081,7 @@ DEV void fluxbar_body(const GD& g, const FluxBarArgs& a, unsigned tile) {
     const int il = i - off[d][0], jl = j - off[d][1], kl = k - off[d][2];
 #pragma unroll
     for (int c = 0; c < 5; ++c)
-      a.fbar[(size_t)(d * 7 + c) * g.N + id] = (rc(c, il, jl, kl) - rc(c, i, j, k)) * g.idx[d];
+      a.fbar[(size_t)(d * 7 + c) * g.N + id] = (rc(c, i, j, k) - rc(c, il, jl, kl)) * g.idx[d];
   }
   // dA/dt = -E: Ebar = -rbar_A; E components are quarter-sums of induction fluxes
   double* fb = a.fbar;
@@ -1473,9 +1474,10 @@ DEV void vertex_adj_body(const GD& g, const VertexAdjArgs& va, unsigned tile) {
   geo_from(mm_, G);
   double psb = 0.0, avb[3] = {0.0, 0.0, 0.0};
   if (va.gauge == ASTERX_GAUGE_LORENZ) {
-    // dA_d/dt[edge] -= (G_A[edge + e_d] - G_A[edge]) / dx_d
-    double gb = (rc(5, i - 1, j, k) - rc(5, i, j, k)) * g.idx[0] + (rc(6, i, j - 1, k) - rc(6, i, j, k)) * g.idx[1] +
-                (rc(7, i, j, k - 1) - rc(7, i, j, k)) * g.idx[2];
+    // dA_d/dt[edge] -= (G_A[edge + e_d] - G_A[edge]) / dx_d, so G_A's cotangent at vertex v is
+    // sum_d (rbar_A_d[v] - rbar_A_d[v - e_d]) / dx_d
+    double gb = (rc(5, i, j, k) - rc(5, i - 1, j, k)) * g.idx[0] + (rc(6, i, j, k) - rc(6, i, j - 1, k)) * g.idx[1] +
+                (rc(7, i, j, k) - rc(7, i, j, k - 1)) * g.idx[2];
     // dPsi/dt[v] = -(F[v + e] - F[v - e]) / (2 dx) - xi alpha Psi[v]
     double fb[3] = {(rc(8, i + 1, j, k) - rc(8, i - 1, j, k)) * 0.5 * g.idx[0],
                     (rc(8, i, j + 1, k) - rc(8, i, j - 1, k)) * 0.5 * g.idx[1],

@@ -72,3 +72,136 @@ def test_adjoint_forward_equals_plain_driver(adj):
     prim = torch.from_numpy(w.prim.copy()).cuda()
     assert adj.density_loss_value(runner, prim, w.params["gamma"], 2) == loss
     assert np.all(np.isfinite(g)) and np.isfinite(gg)
+
+
+# ---- dot-product tests of each adjoint entry point against the oracle's JVP of the same map --------------------
+
+def _curved(recon, seed=44):
+    return W.curved_block(seed=seed, n=(12, 10, 9), recon=recon, nsteps=1, vmax=0.3)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _tangent(L, nf, rng, shift_free=True):
+    t = L.zeros(nf)
+    L.owned(t)[...] = rng.normal(size=L.owned(t).shape)
+    L.periodic_wrap(t)
+    return t
+
+
+def _cot(L, nf, rng):
+    t = L.zeros(nf)
+    L.owned(t)[...] = rng.normal(size=L.owned(t).shape)
+    return t
+
+
+def _dot(L, a, b):
+    return float(np.sum(L.owned(a) * L.owned(b))), float(np.sum(np.abs(L.owned(a) * L.owned(b))))
+
+
+def _stage_inputs(orc, w):
+    L = w.layout
+    cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+    orc.fill_ghosts(L, cons, w.bc_cell)
+    psi = L.zeros(1) + 0.01 * np.random.default_rng(5).normal(size=(1,) + L.shape3)
+    L.periodic_wrap(psi)
+    return cons, psi
+
+
+@pytest.mark.parametrize("part", ["cons", "A", "psi", "gamma"])
+@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz"])
+def test_rhs_adjoint_dot_product(adj, orc, recon, part):
+    """<ybar, J v> (oracle dual numbers) = <J^T ybar, v> (asterx_rhs_adjoint) for one stage's right-hand side,
+    tangent in one input at a time."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    w = _curved(recon)
+    L = w.layout
+    print("case rhs_adjoint", recon, part, flush=True)
+    cons, psi = _stage_inputs(orc, w)
+    rng = np.random.default_rng(7)
+    v = {"cons": None, "A": None, "psi": None}
+    dg = 0.0
+    if part == "gamma":
+        dg = 1.0
+    else:
+        v[part] = _tangent(L, {"cons": 5, "A": 3, "psi": 1}[part], rng)
+    ybar = _cot(L, 9, rng)
+    _, dL = orc.stage_jvp(L, w.params, w.metric, w.curv, cons, w.A, psi, w.prim, w.dt, dcons=v["cons"], dA=v["A"],
+                          dpsi=v["psi"], dgamma=dg)
+    lhs, lscale = _dot(L, ybar, dL)
+    cb = torch.zeros((5,) + L.shape3, dtype=torch.float64, device="cuda")
+    Ab = torch.zeros((3,) + L.shape3, dtype=torch.float64, device="cuda")
+    pb = torch.zeros((1,) + L.shape3, dtype=torch.float64, device="cuda")
+    gb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(-(-ax.adjoint_workspace_size(L) // 8), dtype=torch.float64, device="cuda")
+    ax.rhs_adjoint(L, w.params, _dev(w.metric), _dev(w.curv), _dev(cons), _dev(w.prim), _dev(w.A), _dev(psi), w.dt,
+                   _dev(ybar), cb, Ab, pb, gb, ws)
+    torch.cuda.synchronize()
+    bars = {"cons": cb, "A": Ab, "psi": pb}
+    if part == "gamma":
+        rhs, rscale = float(gb.item()), abs(float(gb.item()))
+    else:
+        rhs, rscale = _dot(L, bars[part].cpu().numpy(), v[part])
+    print("  <ybar, Jv> %.15e  <J^T ybar, v> %.15e" % (lhs, rhs), flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * max(lscale, rscale), (lhs, rhs, lscale)
+
+
+@pytest.mark.parametrize("part", ["cons", "A", "gamma"])
+def test_c2p_adjoint_dot_product(adj, orc, part):
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    w = _curved("ppm")
+    L = w.layout
+    print("case c2p_adjoint", part, flush=True)
+    cons, _ = _stage_inputs(orc, w)
+    rng = np.random.default_rng(8)
+    dA = _tangent(L, 3, rng) if part == "A" else None
+    dc = _tangent(L, 5, rng) if part == "cons" else None
+    dg = 1.0 if part == "gamma" else 0.0
+    ybar = _cot(L, 5, rng)
+    _, dp = orc.c2p_jvp(L, w.params, w.metric, w.A, cons, w.prim, dA=dA, dcons=dc, dgamma=dg)
+    lhs, lscale = _dot(L, ybar, dp)
+    cb = torch.zeros((5,) + L.shape3, dtype=torch.float64, device="cuda")
+    Ab = torch.zeros((3,) + L.shape3, dtype=torch.float64, device="cuda")
+    gb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(-(-ax.adjoint_workspace_size(L) // 8), dtype=torch.float64, device="cuda")
+    ax.c2p_adjoint(L, w.params, _dev(w.metric), _dev(cons), _dev(w.prim), _dev(w.A), _dev(ybar), cb, Ab, gb, ws)
+    torch.cuda.synchronize()
+    if part == "gamma":
+        rhs, rscale = float(gb.item()), abs(float(gb.item()))
+    else:
+        rhs, rscale = _dot(L, (cb if part == "cons" else Ab).cpu().numpy(), dc if part == "cons" else dA)
+    print("  <ybar, Jv> %.15e  <J^T ybar, v> %.15e" % (lhs, rhs), flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * max(lscale, rscale), (lhs, rhs, lscale)
+
+
+@pytest.mark.parametrize("part", ["prim", "A", "gamma"])
+def test_prim2con_adjoint_dot_product(adj, orc, part):
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    w = _curved("ppm")
+    L = w.layout
+    print("case prim2con_adjoint", part, flush=True)
+    rng = np.random.default_rng(9)
+    dA = _tangent(L, 3, rng) if part == "A" else None
+    dpr = _tangent(L, 5, rng) if part == "prim" else None
+    dg = 1.0 if part == "gamma" else 0.0
+    ybar = _cot(L, 5, rng)
+    _, dc = orc.prim2con_jvp(L, w.params, w.metric, w.A, w.prim, dA=dA, dprim=dpr, dgamma=dg)
+    lhs, lscale = _dot(L, ybar, dc)
+    pb = torch.zeros((5,) + L.shape3, dtype=torch.float64, device="cuda")
+    Ab = torch.zeros((3,) + L.shape3, dtype=torch.float64, device="cuda")
+    gb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(-(-ax.adjoint_workspace_size(L) // 8), dtype=torch.float64, device="cuda")
+    ax.prim2con_adjoint(L, w.params, _dev(w.metric), _dev(w.A), _dev(w.prim), _dev(ybar), pb, Ab, gb, ws)
+    torch.cuda.synchronize()
+    if part == "gamma":
+        rhs, rscale = float(gb.item()), abs(float(gb.item()))
+    else:
+        rhs, rscale = _dot(L, (pb if part == "prim" else Ab).cpu().numpy(), dpr if part == "prim" else dA)
+    print("  <ybar, Jv> %.15e  <J^T ybar, v> %.15e" % (lhs, rhs), flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * max(lscale, rscale), (lhs, rhs, lscale)
