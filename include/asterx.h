@@ -212,6 +212,58 @@ int asterx_prim2con_adjoint(const asterx_grid* g, const asterx_params* p, const 
                             const double* prim, const double* cons_bar, double* prim_bar, double* A_bar,
                             double* gamma_bar, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- Independent points and the learned c2p initial guess ---------------------------------
+ * Flat arrays of n points, field-major ([q * n + i]): metric 10 x n (alpha, beta^i, gamma_ij),
+ * Btilde 3 x n (densitized), prim 5 x n, cons 5 x n (densitized).  gam_pts: per-point adiabatic
+ * index (n doubles) or NULL for the scalar gam.  All arrays are device memory. */
+
+/* cons = prim2con(prim) per point (eqs. of the conserved variables, Sec. 2.2).  target (2 x n,
+ * optional): log W and log(z / D) with z = rho h W^2, the quantities the network predicts. */
+int asterx_prim2con_points(int64_t n, const double* gam_pts, double gam, const double* metric, const double* Bt,
+                           const double* prim, double* cons, double* target, void* stream);
+
+/* Multilayer perceptron 8 -> 64 -> 64 -> 2, tanh hidden activations, packed FP32 parameters
+ * (device, ASTERX_MLP_NPARAMS floats): W1[64][8], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
+ * Inputs are standardised as (f - in_shift) * in_scale; outputs are out_shift + out_scale * y.
+ * Contractions run on bfloat16 operands with FP32 accumulation (matrix cores). */
+#define ASTERX_MLP_NPARAMS 4866
+typedef struct {
+  const float* params;
+  float in_shift[8], in_scale[8];
+  float out_shift[2], out_scale[2];
+} asterx_mlp;
+
+/* The network's raw input features of conserved states (8 x n floats): log D, log(tau/D),
+ * log(1 + S^2/D^2), log(1 + B^2/D), log(1 + (B.S)^2/D^3), det(gamma) - 1, alpha - 1, Gamma, with
+ * D, S, tau, B undensitized.  States with D <= 0 or tau <= 0 give zeros. */
+int asterx_mlp_features(int64_t n, const double* gam_pts, double gam, const double* metric, const double* Bt,
+                        const double* cons, float* feat, void* stream);
+
+/* out (2 x n floats) = network outputs (log W, log(z / D)) of the raw features feat (8 x n). */
+int asterx_mlp_forward(const asterx_mlp* m, int64_t n, const float* feat, float* out, void* stream);
+
+/* Loss (1/n) sum_i |y_i - t_i|^2 / 2 on standardised outputs (t = (target - out_shift) / out_scale)
+ * and its gradient: grad[0..NPARAMS) = d loss / d params, grad[NPARAMS] = loss (device floats,
+ * overwritten).  Deterministic (fixed-order reductions).  workspace: asterx_mlp_grad_workspace_size. */
+size_t asterx_mlp_grad_workspace_size(int64_t n);
+int asterx_mlp_grad(const asterx_mlp* m, int64_t n, const float* feat, const float* target, float* grad,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on the ASTERX_MLP_NPARAMS FP32 parameters; m, v are
+ * the first and second moment buffers (device, zero before step 1). */
+int asterx_mlp_adam(float* params, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
+                    float eps, int32_t step, void* stream);
+
+/* c2p of independent points (Sec. 3.5 and 3.6), in place on cons for atmosphere resets.  Initial
+ * guess for Noble's iteration: the network's (W, z) when mlp is non-NULL (falling back to the
+ * plain start if it does not converge, flag 32), else the primitives guess (5 x n, NULL: cold
+ * start from the conserved variables).  flags (n bytes), iters (n int32) optional.  stats
+ * (optional, 8 counters, accumulated): Noble failures, fallbacks, atmosphere, hard failures,
+ * NaN inputs, max iterations (max), learned guesses not converged, total Newton iterations. */
+int asterx_c2p_points(const asterx_params* p, int64_t n, const double* gam_pts, const double* metric,
+                      const double* Bt, double* cons, const double* guess, const asterx_mlp* mlp, double* prim,
+                      uint8_t* flags, int32_t* iters, unsigned long long* stats, void* stream);
+
 /* Per-kernel timing (diagnostics).  When enabled, every launch of the library is bracketed
  * by two HIP events on its stream; asterx_timing_read waits for the recorded events and
  * returns, for each kernel class k < n, the accumulated milliseconds ms[k] and launch count

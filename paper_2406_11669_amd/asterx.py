@@ -32,6 +32,14 @@ class BatchTuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
+class MLP(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("in_shift", ctypes.c_float * 8), ("in_scale", ctypes.c_float * 8),
+                ("out_shift", ctypes.c_float * 2), ("out_scale", ctypes.c_float * 2)]
+
+
+MLP_NPARAMS = 4866
+
+
 class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("rho_atm", ctypes.c_double), ("k_atm", ctypes.c_double),
                 ("xi", ctypes.c_double), ("c2p_tol", ctypes.c_double), ("wmax", ctypes.c_double),
@@ -48,7 +56,8 @@ EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "
            "asterx_batch_destroy", "asterx_batch_points", "asterx_batch_offset", "asterx_batch_workspace_size",
            "asterx_batch_prim2con", "asterx_batch_c2p", "asterx_batch_fill_ghosts", "asterx_batch_rhs",
            "asterx_batch_rk_stage", "asterx_adjoint_workspace_size", "asterx_rhs_adjoint", "asterx_c2p_adjoint",
-           "asterx_prim2con_adjoint"]
+           "asterx_prim2con_adjoint", "asterx_prim2con_points", "asterx_mlp_features", "asterx_mlp_forward",
+           "asterx_mlp_grad_workspace_size", "asterx_mlp_grad", "asterx_mlp_adam", "asterx_c2p_points"]
 
 
 def lib():
@@ -88,6 +97,16 @@ def lib():
         L.asterx_batch_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t,
                                        vp]
         L.asterx_batch_rk_stage.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
+        i64 = ctypes.c_int64
+        L.asterx_prim2con_points.argtypes = [i64, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp]
+        L.asterx_mlp_features.argtypes = [i64, vp, ctypes.c_double, vp, vp, vp, vp, vp]
+        L.asterx_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+        L.asterx_mlp_grad_workspace_size.restype = ctypes.c_size_t
+        L.asterx_mlp_grad_workspace_size.argtypes = [i64]
+        L.asterx_mlp_grad.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.asterx_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_int32, vp]
+        L.asterx_c2p_points.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.asterx_adjoint_workspace_size.restype = ctypes.c_size_t
         L.asterx_adjoint_workspace_size.argtypes = [vp]
         L.asterx_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp,
@@ -225,6 +244,70 @@ def prim2con_adjoint(layout, params, metric, A, prim, cons_bar, prim_bar, A_bar,
                                          _ptr(_f64(metric)), _ptr(_f64(A)), _ptr(_f64(prim)), _ptr(_f64(cons_bar)),
                                          _ptr(_f64(prim_bar)), _ptr(_f64(A_bar)), _ptr(_f64(gamma_bar)), w, nb,
                                          _stream(stream)))
+
+
+# ---- independent points and the learned c2p guess -----------------------------------------------------------
+
+def make_mlp(params, stdz):
+    """asterx_mlp from a device float32 parameter tensor and the standardisation constants (dict of arrays)."""
+    assert params.is_cuda and params.dtype == torch.float32 and params.numel() == MLP_NPARAMS
+    m = MLP()
+    m.params = params.data_ptr()
+    for k in ("in_shift", "in_scale", "out_shift", "out_scale"):
+        arr = getattr(m, k)
+        vals = np.asarray(stdz[k], dtype=np.float64)
+        for i in range(len(arr)):
+            arr[i] = float(vals[i])
+    return m
+
+
+def _gp(gam):
+    """(per-point pointer, scalar) for an adiabatic index given as a tensor of n values or a float."""
+    if torch.is_tensor(gam):
+        return _ptr(_f64(gam)), 0.0
+    return None, float(gam)
+
+
+def prim2con_points(gam, metric, Bt, prim, cons, target=None, stream=None):
+    n = prim.shape[1]
+    gp, gs = _gp(gam)
+    _check(lib().asterx_prim2con_points(n, gp, gs, _ptr(_f64(metric)), _ptr(_f64(Bt)), _ptr(_f64(prim)),
+                                        _ptr(_f64(cons)), _ptr(target), _stream(stream)))
+
+
+def mlp_features(gam, metric, Bt, cons, feat, stream=None):
+    n = cons.shape[1]
+    gp, gs = _gp(gam)
+    _check(lib().asterx_mlp_features(n, gp, gs, _ptr(_f64(metric)), _ptr(_f64(Bt)), _ptr(_f64(cons)), _ptr(feat),
+                                     _stream(stream)))
+
+
+def mlp_forward(mlp, feat, out, stream=None):
+    _check(lib().asterx_mlp_forward(ctypes.byref(mlp), feat.shape[1], _ptr(feat), _ptr(out), _stream(stream)))
+
+
+def mlp_grad_workspace_size(n):
+    return lib().asterx_mlp_grad_workspace_size(n)
+
+
+def mlp_grad(mlp, feat, target, grad, workspace, stream=None):
+    _check(lib().asterx_mlp_grad(ctypes.byref(mlp), feat.shape[1], _ptr(feat), _ptr(target), _ptr(grad),
+                                 _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, step, stream=None):
+    _check(lib().asterx_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), float(lr), float(beta1), float(beta2),
+                                 float(eps), int(step), _stream(stream)))
+
+
+def c2p_points(params, gam, metric, Bt, cons, prim, guess=None, mlp=None, flags=None, iters=None, stats=None,
+               stream=None):
+    n = cons.shape[1]
+    gp, _ = _gp(gam)
+    p = make_params(params if gp is not None else dict(params, gamma=float(gam)))
+    _check(lib().asterx_c2p_points(ctypes.byref(p), n, gp, _ptr(_f64(metric)), _ptr(_f64(Bt)), _ptr(_f64(cons)),
+                                   _ptr(guess), None if mlp is None else ctypes.byref(mlp), _ptr(_f64(prim)),
+                                   _ptr(flags), _ptr(iters), _ptr(stats), _stream(stream)))
 
 
 def zero(buf, stream=None):

@@ -22,6 +22,7 @@
 
 #include "asterx.h"
 #include "grmhd_device.h"
+#include "host_internal.h"
 
 using namespace ax;
 
@@ -1664,35 +1665,39 @@ DEV void c2p_adj_body(const GD& g, const C2PAdjArgs& ca, unsigned tile) {
 // Centre-field cotangents to face-field cotangents (gather over the two adjacent cells),
 // faces [-ng+1, n+ng]^3.
 DEV void bcface_adj_body(const GD& g, const double* __restrict__ bcbar, double* __restrict__ bfbar, unsigned tile) {
-  int e[3] = {g.n[0] + 2 * g.ng, g.n[1] + 2 * g.ng, g.n[2] + 2 * g.ng};
+  // faces [-ng, n+ng]^3: the centre of cell c (in [-ng, n+ng-1]) averages faces c and c + e_d
+  int e[3] = {g.n[0] + 2 * g.ng + 1, g.n[1] + 2 * g.ng + 1, g.n[2] + 2 * g.ng + 1};
   int p, q, r;
   if (!box_at<64, 4>(e, tile, threadIdx.x, p, q, r)) return;
-  const int i = p - g.ng + 1, j = q - g.ng + 1, k = r - g.ng + 1;
+  const int i = p - g.ng, j = q - g.ng, k = r - g.ng;
   const int id = at(g, i, j, k);
   const int st[3] = {1, g.sy, g.sz};
   const int ijk[3] = {i, j, k};
   for (int d = 0; d < 3; ++d) {
     double s = 0.0;
     if (ijk[d] <= g.n[d] + g.ng - 1) s += 0.5 * bcbar[(size_t)d * g.N + id];
-    s += 0.5 * bcbar[(size_t)d * g.N + id - st[d]];
+    if (ijk[d] - 1 >= -g.ng) s += 0.5 * bcbar[(size_t)d * g.N + id - st[d]];
     bfbar[(size_t)d * g.N + id] += s;
   }
 }
 
-// Face-field cotangents to the edge potential (transposed curl, gather), edges [-ng+1, n+ng]^3.
+// Face-field cotangents to the edge potential (transposed curl, gather), edges [-ng, n+ng]^3
+// (a face f feeds the edges f and f + e_t of its two transverse directions t).
 DEV void curlT_body(const GD& g, const double* __restrict__ bf, double* __restrict__ abar, unsigned tile) {
-  int e[3] = {g.n[0] + 2 * g.ng, g.n[1] + 2 * g.ng, g.n[2] + 2 * g.ng};
+  int e[3] = {g.n[0] + 2 * g.ng + 1, g.n[1] + 2 * g.ng + 1, g.n[2] + 2 * g.ng + 1};
   int p, q, r;
   if (!box_at<64, 4>(e, tile, threadIdx.x, p, q, r)) return;
-  const int i = p - g.ng + 1, j = q - g.ng + 1, k = r - g.ng + 1;
+  const int i = p - g.ng, j = q - g.ng, k = r - g.ng;
   const int id = at(g, i, j, k);
   const double* Bx = bf;
   const double* By = bf + g.N;
   const double* Bz = bf + 2 * g.N;
   const int sy = g.sy, sz = g.sz;
-  abar[id] += (By[id - sz] - By[id]) * g.idx[2] + (Bz[id] - Bz[id - sy]) * g.idx[1];
-  abar[g.N + id] += (Bx[id] - Bx[id - sz]) * g.idx[2] + (Bz[id - 1] - Bz[id]) * g.idx[0];
-  abar[2 * g.N + id] += (Bx[id - sy] - Bx[id]) * g.idx[1] + (By[id] - By[id - 1]) * g.idx[0];
+  const bool im = i > -g.ng, jm = j > -g.ng, km = k > -g.ng;  // the face below exists
+  auto F = [](const double* f, int o, bool ok) { return ok ? f[o] : 0.0; };
+  abar[id] += (F(By, id - sz, km) - By[id]) * g.idx[2] + (Bz[id] - F(Bz, id - sy, jm)) * g.idx[1];
+  abar[g.N + id] += (Bx[id] - F(Bx, id - sz, km)) * g.idx[2] + (F(Bz, id - 1, im) - Bz[id]) * g.idx[0];
+  abar[2 * g.N + id] += (F(Bx, id - sy, jm) - Bx[id]) * g.idx[1] + (By[id] - F(By, id - 1, im)) * g.idx[0];
 }
 
 // dst[owned] += src[owned] for nf fields.
@@ -1990,6 +1995,10 @@ int check_kinds(const asterx_grid* gr, const int32_t* kinds) {
 }  // namespace
 
 // =======================================================================================
+namespace axh {
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace axh
+
 extern "C" {
 
 int asterx_timing_enable(int32_t on) {
@@ -2318,7 +2327,8 @@ int adj_prologue(const GD& g, const asterx_params* p, const double* metric, cons
 // Centre-field and face-field cotangents to the edge potential, fold ghosts, add to A_bar.
 int adj_epilogue(const GD& g, double* ws, double* A_bar, double* psi_bar, hipStream_t s) {
   int rc;
-  unsigned nb = tiles_for(PH_BCENT, g);
+  int ef[3] = {g.n[0] + 2 * g.ng + 1, g.n[1] + 2 * g.ng + 1, g.n[2] + 2 * g.ng + 1};
+  unsigned nb = box_blocks<64, 4>(ef);
   if ((rc = timed(KT_ADJ, s, [&] {
          hipLaunchKernelGGL(k_bcface_adj, dim3(nb), dim3(256), 0, s, g, ws + AW_BCBAR * g.N, ws + AW_BFBAR * g.N);
        })))

@@ -530,19 +530,9 @@ DEV void atmo(const Geo& G, const double Bt[3], const C2PParams& P, double pr[5]
   cons_of(G, S, U);
 }
 
-// Full recovery at a point.  U: densitized conserved (in/out), prev: warm start.
-DEV uint32_t c2p_point(const Geo& G, double U[5], const double Bt[3], const double prev[5], const C2PParams& P,
-                       double out[5], int& iters) {
-  uint32_t fl = 0;
-  iters = 0;
-  bool nan_in = !(isfinite(U[0]) && isfinite(U[1]) && isfinite(U[2]) && isfinite(U[3]) && isfinite(U[4]));
-  if (nan_in || !(U[0] >= G.sqrtg * P.rho_atm)) {
-    fl = 4u | (nan_in ? 16u : 0u);
-    atmo(G, Bt, P, out, U);
-    return fl;
-  }
+// Undensitized c2p input (D, S_i, tau, B^i and the invariants) from densitized U and Btilde.
+DEV void c2p_input(const Geo& G, const double U[5], const double Bt[3], C2PIn& c) {
   double is = 1.0 / G.sqrtg;
-  C2PIn c;
   c.D = U[0] * is;
   c.S[0] = U[1] * is;
   c.S[1] = U[2] * is;
@@ -560,25 +550,51 @@ DEV uint32_t c2p_point(const Geo& G, double U[5], const double Bt[3], const doub
   lower(G.g, c.B, Bl);
   c.B2 = c.B[0] * Bl[0] + c.B[1] * Bl[1] + c.B[2] * Bl[2];
   c.BS = c.B[0] * c.S[0] + c.B[1] * c.S[1] + c.B[2] * c.S[2];
+}
+
+// Full recovery at a point.  U: densitized conserved (in/out), prev: warm start.
+// zw_guess (optional): an initial (z, w) tried first by Noble's Newton iteration; if it does
+// not converge, flag 32 is set and the plain warm/cold start follows.  iters: total Newton
+// iterations.
+DEV uint32_t c2p_point(const Geo& G, double U[5], const double Bt[3], const double prev[5], const C2PParams& P,
+                       double out[5], int& iters, const double* zw_guess = nullptr) {
+  uint32_t fl = 0;
+  iters = 0;
+  bool nan_in = !(isfinite(U[0]) && isfinite(U[1]) && isfinite(U[2]) && isfinite(U[3]) && isfinite(U[4]));
+  if (nan_in || !(U[0] >= G.sqrtg * P.rho_atm)) {
+    fl = 4u | (nan_in ? 16u : 0u);
+    atmo(G, Bt, P, out, U);
+    return fl;
+  }
+  C2PIn c;
+  c2p_input(G, U, Bt, c);
   bool ok = false;
   const double wcap = 1.0 - 1.0 / (P.wmax * P.wmax);
   if (P.method != 2) {
-    // warm start from the previous primitives, cold start if they are unusable
-    double vl[3], v[3] = {prev[2], prev[3], prev[4]};
-    lower(G.g, v, vl);
-    double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
-    double z0, w0;
-    if (prev[0] > 0.0 && prev[1] >= 0.0 && v2 < wcap && isfinite(v2) && isfinite(prev[1])) {
-      double rhoh = prev[0] + P.gam / (P.gam - 1.0) * prev[1];
-      z0 = rhoh / (1.0 - v2);
-      w0 = v2;
-    } else {
-      z0 = c.tau + c.D;
-      double den = z0 + c.B2;
-      w0 = fmin(c.S2 / (den * den), wcap);
+    if (zw_guess) {
+      ok = noble(G, c, P, zw_guess[0], zw_guess[1], out, iters);
+      if (!ok) fl |= 32u;
     }
-    ok = noble(G, c, P, z0, w0, out, iters);
-    if (!ok) fl |= 1u;
+    if (!ok) {
+      // warm start from the previous primitives, cold start if they are unusable
+      double vl[3], v[3] = {prev[2], prev[3], prev[4]};
+      lower(G.g, v, vl);
+      double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
+      double z0, w0;
+      if (prev[0] > 0.0 && prev[1] >= 0.0 && v2 < wcap && isfinite(v2) && isfinite(prev[1])) {
+        double rhoh = prev[0] + P.gam / (P.gam - 1.0) * prev[1];
+        z0 = rhoh / (1.0 - v2);
+        w0 = v2;
+      } else {
+        z0 = c.tau + c.D;
+        double den = z0 + c.B2;
+        w0 = fmin(c.S2 / (den * den), wcap);
+      }
+      int it2 = 0;
+      ok = noble(G, c, P, z0, w0, out, it2);
+      iters += it2;
+      if (!ok) fl |= 1u;
+    }
   }
   if (!ok && P.method != 1) {
     ok = palenzuela(G, c, P, out);

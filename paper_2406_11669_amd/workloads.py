@@ -410,3 +410,81 @@ def gradient_direction(layout, seed, with_gamma=True):
     d /= nrm
     L.periodic_wrap(d)
     return d, dg / nrm
+
+
+# ---- independent c2p states (learned initial guess) ---------------------------------------------------------
+
+def metric_at_points(seed, x, y, z, alpha0=0.8, alpha_amp=0.15, beta_amp=0.05, gamma_amp=0.1):
+    """The curved metric family of curved_metric evaluated at arbitrary points: (10, n) array."""
+    names = ["alpha", "betax", "betay", "betaz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz"]
+    f = {nm: ModeSum(seed, _TAGS[nm]) for nm in names}
+    m = np.zeros((10, x.size))
+    m[0] = alpha0 + alpha_amp * f["alpha"](x, y, z)
+    for c, nm in enumerate(["betax", "betay", "betaz"]):
+        m[1 + c] = beta_amp * f[nm](x, y, z)
+    for c, nm in enumerate(["gxx", "gxy", "gxz", "gyy", "gyz", "gzz"]):
+        m[4 + c] = (1.0 if nm in ("gxx", "gyy", "gzz") else 0.0) + gamma_amp * f[nm](x, y, z)
+    return m
+
+
+def _gmat(m):
+    g = np.empty((m.shape[1], 3, 3))
+    for c, (a, b) in enumerate([(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
+        g[:, a, b] = g[:, b, a] = m[4 + c]
+    return g
+
+
+def _unit_in_metric(rng, g):
+    """Isotropic directions (flat normals), normalised in the metric g: g_ij n^i n^j = 1."""
+    n = rng.normal(size=(g.shape[0], 3))
+    nn = np.einsum("pi,pij,pj->p", n, g, n)
+    return n / np.sqrt(nn)[:, None]
+
+
+def c2p_states(seed, n, log10_rho=(-8.0, 0.0), W=(1.0, 10.0), sigma=(1e-3, 10.0), p_over_rho=(1e-3, 10.0),
+               gamma=(4.0 / 3.0, 2.0), flat_fraction=0.5, metric_seed=0):
+    """Seeded independent primitive states for the learned c2p guess: log10 rho ~ U, W ~ U, magnetisation
+    sigma = b^2 / rho ~ log-U, p / rho ~ log-U, Gamma ~ U; velocity and field directions isotropic and
+    independent; metric flat for a fraction flat_fraction of the points, else the curved family at uniform
+    random positions of the unit cube.  Returns dict(prim (5, n), Bt (3, n) densitized, metric (10, n), gam (n))."""
+    rng = np.random.default_rng([int(seed), 8191])
+    rho = 10.0 ** rng.uniform(log10_rho[0], log10_rho[1], n)
+    Wl = rng.uniform(W[0], W[1], n)
+    sig = np.exp(rng.uniform(np.log(sigma[0]), np.log(sigma[1]), n))
+    por = np.exp(rng.uniform(np.log(p_over_rho[0]), np.log(p_over_rho[1]), n))
+    gam = rng.uniform(gamma[0], gamma[1], n)
+    m = np.zeros((10, n))
+    m[0] = 1.0
+    m[4] = m[7] = m[9] = 1.0
+    curved = rng.uniform(size=n) >= flat_fraction
+    if np.any(curved):
+        pos = rng.uniform(size=(3, int(curved.sum())))
+        m[:, curved] = metric_at_points(metric_seed, pos[0], pos[1], pos[2])
+    g = _gmat(m)
+    vdir = _unit_in_metric(rng, g)
+    vmag = np.sqrt(1.0 - 1.0 / Wl ** 2)
+    v = vdir * vmag[:, None]
+    bdir = _unit_in_metric(rng, g)
+    bv = np.einsum("pi,pij,pj->p", bdir, g, v)           # (Bhat . v) in the metric
+    Bmag = np.sqrt(sig * rho / (1.0 / Wl ** 2 + bv ** 2))  # b^2 = B^2 / W^2 + (B . v)^2 = sigma rho
+    B = bdir * Bmag[:, None]
+    sqrtg = np.sqrt(np.linalg.det(g))
+    prim = np.stack([rho, por * rho, v[:, 0], v[:, 1], v[:, 2]])
+    Bt = (B * sqrtg[:, None]).T.copy()
+    return dict(prim=prim, Bt=Bt, metric=m, gam=gam)
+
+
+def c2p_block_states(seed, n=256, W=(1.0, 10.0), gamma=5.0 / 3.0):
+    """n^3 per-cell states of the Riemann-problem ranges (rho, p ~ U[0.1, 1], B^i ~ U[-1, 1]) with an isotropic
+    velocity of Lorentz factor W ~ U[W]; flat metric.  Returns dict(prim (5, N), Bt (3, N), gam scalar)."""
+    rng = np.random.default_rng([int(seed), 131071])
+    N = n ** 3
+    rho = rng.uniform(0.1, 1.0, N)
+    p = rng.uniform(0.1, 1.0, N)
+    Wl = rng.uniform(W[0], W[1], N)
+    d = rng.normal(size=(N, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    v = d * np.sqrt(1.0 - 1.0 / Wl ** 2)[:, None]
+    B = rng.uniform(-1.0, 1.0, (3, N))
+    prim = np.stack([rho, p, v[:, 0], v[:, 1], v[:, 2]])
+    return dict(prim=prim, Bt=B, gam=gamma)

@@ -1,0 +1,168 @@
+"""GPU: point prim->cons and c2p against the CPU oracle, the network's forward and backward kernels against the
+CPU reference network (oracle/mlp_ref.py), one Adam step, and what a briefly trained network gains over the
+plain start of the recovery on held-out states."""
+import numpy as np
+import pytest
+
+from paper_2406_11669_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_11669_amd import asterx, learned
+    asterx.lib()
+    return learned
+
+
+def _stdz(rng):
+    return dict(in_shift=rng.normal(size=8) * 0.3, in_scale=rng.uniform(0.5, 2.0, 8),
+                out_shift=rng.normal(size=2), out_scale=rng.uniform(0.5, 2.0, 2))
+
+
+def test_prim2con_points_vs_oracle(L, orc):
+    import torch
+    s = W.c2p_states(11, 777)
+    d = L.device_states(s)
+    cons, tgt = L.conserved(d, with_targets=True)
+    torch.cuda.synchronize()
+    c = cons.cpu().numpy()
+    for i in range(0, 777, 5):
+        ref = orc.pt_prim2con(s["metric"][:, i], s["prim"][:, i], s["Bt"][:, i], s["gam"][i])
+        assert np.max(np.abs(c[:, i] - ref)) <= 1e-13 * np.max(np.abs(ref)), i
+        f = orc.pt_fluid(s["metric"][:, i], s["prim"][:, i], s["Bt"][:, i], s["gam"][i])
+        t = tgt[:, i].cpu().numpy()
+        assert abs(t[0] - np.log(f["W"])) <= 1e-13 and abs(t[1] - np.log(f["h"] * f["W"])) <= 1e-12
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_c2p_points_vs_oracle(L, orc, warm):
+    """Plain point c2p (cold or warm start) against the oracle's: flags and iteration counts equal, primitives
+    within 1e-12 relative (the training ranges reach W = 10 and sigma = 10)."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    s = W.c2p_states(12, 500)
+    d = L.device_states(s)
+    cons, _ = L.conserved(d)
+    rng = np.random.default_rng(3)
+    guess = s["prim"] * (1.0 + 1e-3 * rng.uniform(-1, 1, s["prim"].shape)) if warm else np.zeros_like(s["prim"])
+    prim = torch.empty((5, 500), dtype=torch.float64, device="cuda")
+    flags = torch.empty(500, dtype=torch.uint8, device="cuda")
+    iters = torch.empty(500, dtype=torch.int32, device="cuda")
+    c_host = cons.cpu().numpy()
+    ax.c2p_points(L.C2P_PARAMS, d["gam"], d["metric"], d["Bt"], cons, prim,
+                  guess=L._dev(guess) if warm else None, flags=flags, iters=iters)
+    torch.cuda.synchronize()
+    pg, fg, ig = prim.cpu().numpy(), flags.cpu().numpy(), iters.cpu().numpy()
+    for i in range(500):
+        p = dict(L.C2P_PARAMS, gamma=float(s["gam"][i]))
+        pr, fl, it, _ = orc.pt_c2p(p, s["metric"][:, i], c_host[:, i], s["Bt"][:, i], guess[:, i])
+        # flags equal; the Newton stopping test may fall one iteration apart at the tolerance boundary
+        assert fl == fg[i] and abs(it - ig[i]) <= 1, (i, fl, fg[i], it, ig[i])
+        # cancellation-aware scales: rho, p + tau (p is recovered from the energy), velocities ~ 1
+        sc = np.array([pr[0], pr[1] + abs(c_host[4, i]), 1.0, 1.0, 1.0])
+        assert np.max(np.abs(pg[:, i] - pr) / sc) <= 1e-12, (i, pg[:, i], pr)
+
+
+def _net(L, seed):
+    import torch
+    from oracle import mlp_ref as M
+    rng = np.random.default_rng(seed)
+    p = M.init_params(seed)
+    p[512:576] = rng.normal(size=64) * 0.2      # non-zero biases exercise the bias paths
+    p[4672:4736] = rng.normal(size=64) * 0.2
+    p[4864:4866] = rng.normal(size=2) * 0.2
+    return p, torch.from_numpy(p).cuda(), _stdz(rng)
+
+
+def test_mlp_forward_vs_reference(L):
+    """Forward on the matrix cores against the reference network with the same bfloat16 roundings (ragged n)."""
+    import torch
+    from oracle import mlp_ref as M
+    from paper_2406_11669_amd import asterx as ax
+    p, pt, st = _net(L, 5)
+    rng = np.random.default_rng(6)
+    n = 1000
+    feat = rng.normal(size=(8, n)).astype(np.float32)
+    out = torch.empty((2, n), dtype=torch.float32, device="cuda")
+    ax.mlp_forward(ax.make_mlp(pt, st), torch.from_numpy(feat).cuda(), out)
+    torch.cuda.synchronize()
+    ref, _ = M.forward(p, feat, {k: np.asarray(v, np.float32) for k, v in st.items()})
+    g = out.cpu().numpy()
+    err = np.abs(g - ref)
+    scale = np.max(np.abs(ref))
+    # bfloat16 operands: one rounding decided differently (FP32 accumulation order) moves an output by at most a
+    # few parts in 1e3 of one term; most outputs agree to FP32 rounding
+    assert np.max(err) <= 2e-3 * scale, np.max(err)
+    assert np.median(err) <= 1e-5 * scale, np.median(err)
+
+
+def test_mlp_gradient_vs_reference(L):
+    import torch
+    from oracle import mlp_ref as M
+    from paper_2406_11669_amd import asterx as ax
+    p, pt, st = _net(L, 7)
+    rng = np.random.default_rng(8)
+    n = 999
+    feat = rng.normal(size=(8, n)).astype(np.float32)
+    tgt = rng.normal(size=(2, n)).astype(np.float32)
+    grad = torch.empty(ax.MLP_NPARAMS + 1, dtype=torch.float32, device="cuda")
+    ws = torch.empty(ax.mlp_grad_workspace_size(n) // 4 + 1, dtype=torch.float32, device="cuda")
+    ax.mlp_grad(ax.make_mlp(pt, st), torch.from_numpy(feat).cuda(), torch.from_numpy(tgt).cuda(), grad, ws)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy()
+    loss, gref = M.loss_grad(p, feat, tgt, {k: np.asarray(v, np.float32) for k, v in st.items()})
+    assert abs(g[-1] - loss) <= 1e-4 * loss
+    sl = {"W1": slice(0, 512), "b1": slice(512, 576), "W2": slice(576, 4672), "b2": slice(4672, 4736),
+          "W3": slice(4736, 4864), "b3": slice(4864, 4866)}
+    for name, s in sl.items():
+        a, b = g[:-1][s], gref[s]
+        scale = np.max(np.abs(b))
+        print("  %s: max err %.3e  median err %.3e  scale %.3e" % (name, np.max(np.abs(a - b)),
+                                                                  np.median(np.abs(a - b)), scale), flush=True)
+        assert np.max(np.abs(a - b)) <= 2e-2 * scale, name
+        assert np.median(np.abs(a - b)) <= 2e-3 * scale, name
+    # deterministic: a second evaluation is bitwise identical
+    grad2 = torch.empty_like(grad)
+    ax.mlp_grad(ax.make_mlp(pt, st), torch.from_numpy(feat).cuda(), torch.from_numpy(tgt).cuda(), grad2, ws)
+    assert torch.equal(grad, grad2)
+
+
+def test_adam_step_vs_reference(L):
+    import torch
+    from oracle import mlp_ref as M
+    from paper_2406_11669_amd import asterx as ax
+    rng = np.random.default_rng(9)
+    p = rng.normal(size=ax.MLP_NPARAMS).astype(np.float32)
+    g = rng.normal(size=ax.MLP_NPARAMS + 1).astype(np.float32)
+    m = rng.normal(size=ax.MLP_NPARAMS).astype(np.float32) * 0.1
+    v = np.abs(rng.normal(size=ax.MLP_NPARAMS)).astype(np.float32) * 0.1
+    pt, gt, mt, vt = (torch.from_numpy(x.copy()).cuda() for x in (p, g, m, v))
+    ax.mlp_adam(pt, gt, mt, vt, 1e-3, 0.9, 0.999, 1e-8, 3)
+    torch.cuda.synchronize()
+    pr, mr, vr = M.adam(p, g[:-1], m, v, 1e-3, 0.9, 0.999, 1e-8, 3)
+    assert np.allclose(pt.cpu().numpy(), pr, rtol=1e-6, atol=1e-7)
+    assert np.allclose(mt.cpu().numpy(), mr, rtol=1e-6, atol=1e-8)
+
+
+def test_trained_guess_cuts_newton_iterations(L):
+    """A network trained briefly on 2e5 states (the library's own kernels) seeds Noble's iteration on held-out
+    states: every state is recovered, to the same primitives as the plain cold start, in fewer iterations."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    feat, tgt = L.training_set(200_000, seed=21)
+    st = L.standardization(feat, tgt)
+    params, losses = L.train(feat, tgt, st, epochs=6, batch=4096, seed=3)
+    assert losses[-1] < 0.5 * losses[0], losses
+    mlp = ax.make_mlp(params, st)
+    d = L.device_states(W.c2p_states(22, 20_000))
+    res = L.evaluate(d, mlp, seed=1)
+    print(res, flush=True)
+    cold, learned = res["cold"], res["learned"]
+    assert cold["hard_fail_frac"] == 0.0 and learned["hard_fail_frac"] == 0.0
+    assert learned["iters_mean"] < cold["iters_mean"]
+    assert learned["rho_rel_diff_vs_cold_max"] <= 1e-12 and learned["p_diff_vs_cold_max"] <= 1e-12
