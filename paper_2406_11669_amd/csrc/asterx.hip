@@ -2,14 +2,16 @@
 //
 // One block, one GPU.  Per RK stage the caller runs: asterx_c2p -> asterx_fill_ghosts(prim)
 // -> asterx_rhs -> asterx_rk_stage -> asterx_fill_ghosts(state).  asterx_rhs itself is
-// four launches:
-//   face<D> (D = x, y, z): reconstruction + face metric + prim->cons + fluxes + speeds + HLLE
-//                          for every face, one thread per face, x-pencil coalesced;
-//   cell:                  flux divergence + geometric sources + div B, one thread per cell;
+// centre field + six launches:
+//   face<D> (D = x, y, z): reconstruction + face metric + prim->cons + fluxes + speeds + HLLE,
+//                          two lanes per face (left and right state), x-pencil coalesced;
+//   cell:                  flux divergence + geometric sources + div B, LDS-tiled metric;
 //   vertex:                gauge quantities G_A and F_Psi at vertices;
 //   edge:                  FCT electric field, dA/dt and dPsi/dt.
 // Threads map to x fastest so every stencil load is coalesced across a wavefront; the
-// block -> tile map keeps neighbouring tiles on one XCD (shared L2).
+// block -> tile map keeps neighbouring tiles on one XCD (shared L2).  The same bodies run in
+// persistent launches over work lists of (patch, tile) items for batches of patches, and the
+// reverse-mode (adjoint) kernels at the end of the file transpose one stage.
 // Section/equation references are to AsterX, arXiv 2406.11669.
 
 #include <hip/hip_runtime.h>
