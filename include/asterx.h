@@ -258,8 +258,8 @@ int asterx_mlp_adam(float* params, const float* grad, float* m, float* v, float 
  * guess for Noble's iteration: the network's (W, z) when mlp is non-NULL (falling back to the
  * plain start if it does not converge, flag 32), else the primitives guess (5 x n, NULL: cold
  * start from the conserved variables).  flags (n bytes), iters (n int32) optional.  stats
- * (optional, 8 counters, accumulated): Noble failures, fallbacks, atmosphere, hard failures,
- * NaN inputs, max iterations (max), learned guesses not converged, total Newton iterations. */
+ * (optional, 7 counters, accumulated): Noble failures, fallbacks, atmosphere, hard failures,
+ * NaN inputs, max iterations (max), learned guesses not converged. */
 int asterx_c2p_points(const asterx_params* p, int64_t n, const double* gam_pts, const double* metric,
                       const double* Bt, double* cons, const double* guess, const asterx_mlp* mlp, double* prim,
                       uint8_t* flags, int32_t* iters, unsigned long long* stats, void* stream);

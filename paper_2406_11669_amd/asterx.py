@@ -365,6 +365,9 @@ class Block:
         fill_ghosts(self.L, self.state[0:5], wl.bc_cell)
 
     def fill_state(self, U):
+        if self.wl.A_shift is None and tuple(self.wl.bc_A) == tuple(self.wl.bc_cell):
+            fill_ghosts(self.L, U, self.wl.bc_cell)  # all nine fields alike: one launch per axis
+            return
         fill_ghosts(self.L, U[0:5], self.wl.bc_cell)
         if self.wl.A_shift is not None:
             fill_ghosts_shift(self.L, U[5:8], self.wl.A_shift)

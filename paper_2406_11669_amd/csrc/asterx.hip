@@ -102,17 +102,24 @@ unsigned box_blocks(const int e[3]) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Wavefront reductions (64 lanes): max of non-negative doubles and flag counts, then one
-// device atomic per wavefront.  Max is order independent, so results are deterministic.
+// Wavefront reductions (64 lanes): max of non-negative doubles and flag counts, then at most
+// one device atomic per wavefront.  Max is order independent, so results are deterministic.
+// Atomics to one address serialize in L2 (tens of thousands of wavefronts per launch would
+// cost about a millisecond), so a maximum is only pushed when it exceeds the running value,
+// read first with a device-scope load: the running value only grows, so skipping is exact.
 DEV double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
 
+DEV void atomic_max_u64(unsigned long long* addr, unsigned long long v) {
+  if (__hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) atomicMax(addr, v);
+}
+
 DEV void atomic_max_pos(double* addr, double v) {
   // non-negative doubles order like their bit patterns
-  atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
+  atomic_max_u64((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
 }
 
 DEV void wave_count(bool pred, unsigned long long* ctr) {
@@ -405,7 +412,7 @@ DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S,
     wave_count(fl & 8u, stats + 3);
     wave_count(fl & 16u, stats + 4);
     double im = wave_max((double)iters);
-    if (__lane_id() == 0 && im > 0.0) atomicMax(stats + 5, (unsigned long long)im);
+    if (__lane_id() == 0 && im > 0.0) atomic_max_u64(stats + 5, (unsigned long long)im);
   }
 }
 
@@ -659,12 +666,17 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
   const TileIdx x = tile_index(g, t);
   double m[10], K[6], pre[NFETCH];
   tile_fetch(comp(0), x, pre);
-#pragma unroll
+  // rolled loops keep the register footprint of one round; values land by select chains
+  // (no dynamically indexed register arrays)
+#pragma unroll 1
   for (int c = 0; c < 16; ++c) {
     tile_store(x, pre, S.v);
     tile_fetch(comp(c + 1), x, pre);
     double v = tile_value(S, x);
-    if (c < 10) m[c] = v; else K[c - 10] = v;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) m[q] = c == q ? v : m[q];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) K[q] = c == 10 + q ? v : K[q];
   }
   const int id = t.valid ? at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz) : 0;
   double w[10], wa[3], src[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, as = 0.0;
@@ -725,16 +737,19 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) wa[a] = -(T00 * G.beta[a] + T0[a]);
   }
-#pragma unroll
+#pragma unroll 1
   for (int c = 0; c < 10; ++c) {
     tile_store(x, pre, S.v);
     if (c < 9) tile_fetch(comp(17 + c), x, pre);
     double d[3];
     tile_derivs(S, x, g, d);
     if (t.valid) {
-      src[1] += w[c] * d[0];
-      src[2] += w[c] * d[1];
-      src[3] += w[c] * d[2];
+      double wc = w[0];
+#pragma unroll
+      for (int q = 1; q < 10; ++q) wc = c == q ? w[q] : wc;
+      src[1] += wc * d[0];
+      src[2] += wc * d[1];
+      src[3] += wc * d[2];
       if (c == 0) src[4] += wa[0] * d[0] + wa[1] * d[1] + wa[2] * d[2];
     }
   }

@@ -592,18 +592,16 @@ __global__ __launch_bounds__(256) void k_c2p_points(C2PPtsArgs a) {
         __ballot(valid && (fl & 1u)), __ballot(valid && (fl & 2u)), __ballot(valid && (fl & 4u)),
         __ballot(valid && (fl & 8u)), __ballot(valid && (fl & 16u)), __ballot(valid && (fl & 32u))};
     int mx = valid ? it : 0;
-    long long sum = valid ? it : 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      mx = max(mx, __shfl_xor(mx, o, 64));
-      sum += __shfl_xor(sum, o, 64);
-    }
+    for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    // counts are pushed only when non-zero and the maximum only when it grows: atomics to one
+    // address serialize, and almost every wavefront has nothing new to report
     if (l == 0) {
       for (int q = 0; q < 5; ++q)
         if (b[q]) atomicAdd(&a.stats[q], (unsigned long long)__popcll(b[q]));
-      if (mx) atomicMax(&a.stats[5], (unsigned long long)mx);
+      if (mx && __hip_atomic_load(&a.stats[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned long long)mx)
+        atomicMax(&a.stats[5], (unsigned long long)mx);
       if (b[5]) atomicAdd(&a.stats[6], (unsigned long long)__popcll(b[5]));
-      if (sum) atomicAdd(&a.stats[7], (unsigned long long)sum);
     }
   }
 }

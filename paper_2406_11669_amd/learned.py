@@ -126,7 +126,7 @@ def c2p_run(d, cons0, mode, mlp=None, guess=None, repeat=3):
     best = None
     for r in range(repeat):
         cons = cons0.clone()
-        stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+        stats = torch.zeros(7, dtype=torch.int64, device="cuda")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         ax.c2p_points(C2P_PARAMS, d["gam"], d["metric"], d["Bt"], cons, prim, guess=guess if mode == "warm" else None,
