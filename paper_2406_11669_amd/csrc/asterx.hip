@@ -529,54 +529,140 @@ DEV T recon_right_face(const T a[5], double eps, double q) {
   return wenoz_face(a[0], a[1], a[2], a[3], a[4], eps, q);
 }
 
+// The x-face metric goes through LDS: a workgroup's 32 x 4 x 1 faces need a vertex block of
+// 32 x 7 x 4 points per component (interpolation in y and z only), loaded once, coalesced
+// along x, into a double buffer (one barrier per component, the next component's loads in
+// flight meanwhile); gathered directly, each wavefront would touch 16 separate rows.  (The
+// same staging serves z faces under WENO-Z, with a 35 x 7 x 1 block.)  The two lanes of a face each
+// interpolate two of the four Lagrange rows and swap them, so both hold all ten components;
+// the arithmetic (rows along t1, then across t2) is the direct 16-point formula's.
+template <int D>
+struct FaceBlk {
+  static constexpr int BX = D == 0 ? 32 : 35, BY = D == 1 ? 4 : 7, BZ = D == 2 ? 1 : 4;
+  static constexpr int N = BX * BY * BZ, NR = (N + 255) / 256;
+};
+constexpr int FACE_LDS = 32 * 7 * 4;
+struct FaceLDS {
+  double m[2][FACE_LDS];
+};
+static_assert(FaceBlk<0>::N <= FACE_LDS && FaceBlk<1>::N <= FACE_LDS && FaceBlk<2>::N <= FACE_LDS, "face LDS");
+
 template <int D, int RECON>
-DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile) {
+DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  using FB = FaceBlk<D>;
   const int side = threadIdx.x & 1;
   int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
   int a, b, c;
   bool valid = box_at<32, 4>(e, tile, threadIdx.x >> 1, a, b, c);
   // keep both lanes of a pair valid or invalid together (they share the face)
+  int ijk[3] = {a - 1, b - 1, c - 1};
+  ijk[D] += 1;
+  const int id = valid ? at(g, ijk[0], ijk[1], ijk[2]) : 0;
+  const int st[3] = {1, g.sy, g.sz};
+  const int sD = st[D];
+  // reconstruction of this lane's side: left lane cells i-3..i+1, right lane i+2..i-2
+  double X[7], C[7];
+  if (valid) {
+    const int o0 = side ? 2 : -3, os = side ? -1 : 1;
+    if constexpr (RECON == ASTERX_RECON_WENOZ) {
+      // one variable at a time: the WENO-Z weights of seven variables interleaved would not
+      // fit the register file
+#pragma unroll 1
+      for (int v = 0; v < 7; ++v) {
+        const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
+        double s5[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
+        const double xv = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          X[k] = v == k ? xv : X[k];
+          C[k] = v == k ? s5[2] : C[k];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 7; ++v) {
+        const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
+        double s5[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
+        X[v] = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
+        C[v] = s5[2];
+      }
+    }
+  }
+  double m[10];
+  if constexpr (D == 1 || (D == 2 && RECON != ASTERX_RECON_WENOZ)) {
+    // y and z faces: the direct 16-point gather (one transverse direction is x, so a
+    // wavefront's loads are contiguous rows) measured faster than the staged block, except
+    // for z faces under WENO-Z
+    (void)L;
+    if (valid) {
+      const int s1 = st[t1], s2 = st[t2];
+      const int mb = id - s1 - s2;
+      double mine[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const double* p = fa.metric + (size_t)(5 * side + q) * g.N + mb;
+        double rr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double* row = p + r * s2;
+          rr[r] = lag(row[0], row[s1], row[2 * s1], row[3 * s1]);
+        }
+        mine[q] = lag(rr[0], rr[1], rr[2], rr[3]);
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        double other = shfl1(mine[q]);
+        m[q] = side ? other : mine[q];
+        m[5 + q] = side ? mine[q] : other;
+      }
+    }
+  } else {
+    const unsigned nbx = (e[0] + 31) / 32, nby = (e[1] + 3) / 4;
+    const int ax0 = (int)(tile % nbx) * 32, by0 = (int)((tile / nbx) % nby) * 4, cz = (int)(tile / (nbx * nby));
+    const int X0 = D == 0 ? ax0 : ax0 - 2, Y0 = D == 1 ? by0 : by0 - 2, Z0 = D == 2 ? cz : cz - 2;
+    int foff[FB::NR];
+    double pre[FB::NR];
+#pragma unroll
+    for (int r = 0; r < FB::NR; ++r) {
+      const int q = threadIdx.x + 256 * r;
+      const int X = X0 + q % FB::BX, Y = Y0 + (q / FB::BX) % FB::BY, Z = Z0 + q / (FB::BX * FB::BY);
+      const bool in = q < FB::N && X <= g.n[0] + g.ng && Y <= g.n[1] + g.ng && Z <= g.n[2] + g.ng;
+      foff[r] = in ? at(g, X, Y, Z) : -1;
+      pre[r] = in ? fa.metric[foff[r]] : 0.0;
+    }
+    const int lst[3] = {1, FB::BX, FB::BX * FB::BY};
+    const int ls1 = lst[t1], ls2 = lst[t2];
+    const int lbase = valid ? (a - ax0) + FB::BX * (b - by0) + 2 * side * ls2 : 0;
+#pragma unroll 1
+    for (int q = 0; q < 10; ++q) {
+      double* buf = L.m[q & 1];
+#pragma unroll
+      for (int r = 0; r < FB::NR; ++r)
+        if (threadIdx.x + 256 * r < FB::N) buf[threadIdx.x + 256 * r] = pre[r];
+      __syncthreads();
+      if (q < 9)
+#pragma unroll
+        for (int r = 0; r < FB::NR; ++r) pre[r] = foff[r] >= 0 ? fa.metric[(size_t)(q + 1) * g.N + foff[r]] : 0.0;
+      double ra = 0.0, rb = 0.0;
+      if (valid) {
+        const double* p = buf + lbase;
+        ra = lag(p[0], p[ls1], p[2 * ls1], p[3 * ls1]);
+        p += ls2;
+        rb = lag(p[0], p[ls1], p[2 * ls1], p[3 * ls1]);
+      }
+      const double oa = shfl1(ra), ob = shfl1(rb);
+      const double v = side ? lag(oa, ob, ra, rb) : lag(ra, rb, oa, ob);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m[k] = q == k ? v : m[k];
+    }
+  }
   double smax = 0.0;
   if (valid) {
-    int ijk[3] = {a - 1, b - 1, c - 1};
-    ijk[D] += 1;
-    const int id = at(g, ijk[0], ijk[1], ijk[2]);
-    const int st[3] = {1, g.sy, g.sz};
-    const int sD = st[D], s1 = st[t1], s2 = st[t2];
-    // reconstruction of this lane's side: left lane cells i-3..i+1, right lane i+2..i-2
-    double X[7], C[7];
-    const int o0 = side ? 2 : -3, os = side ? -1 : 1;
-#pragma unroll
-    for (int v = 0; v < 7; ++v) {
-      const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
-      double s5[5];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
-      X[v] = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
-      C[v] = s5[2];
-    }
-    // face metric: this lane interpolates components [5 side, 5 side + 5)
-    double mine[5];
-    const int mb = id - s1 - s2;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const double* p = fa.metric + (size_t)(5 * side + q) * g.N + mb;
-      double rr[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double* row = p + r * s2;
-        rr[r] = lag(row[0], row[s1], row[2 * s1], row[3 * s1]);
-      }
-      mine[q] = lag(rr[0], rr[1], rr[2], rr[3]);
-    }
-    double m[10];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      double other = shfl1(mine[q]);
-      m[q] = side ? other : mine[q];
-      m[5 + q] = side ? mine[q] : other;
-    }
     Geo G;
     geo_from(m, G);
     const double* Ax = fa.A;
@@ -971,11 +1057,13 @@ __global__ __launch_bounds__(256) void kb_bcent(const PatchDesc* __restrict__ P,
 
 template <int D, int R>
 __global__ __launch_bounds__(256) void k_face(GD g, FaceArgs fa) {
-  face_body<D, R>(g, fa, my_tile());
+  __shared__ FaceLDS L;
+  face_body<D, R>(g, fa, my_tile(), L);
 }
 template <int D, int R>
 __global__ __launch_bounds__(256) void kb_face(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                                FaceArgs fa) {
+  __shared__ FaceLDS L;
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item m = it[w];
     const PatchDesc d = P[m.patch];
@@ -985,7 +1073,7 @@ __global__ __launch_bounds__(256) void kb_face(const PatchDesc* __restrict__ P, 
     b.A = fa.A + d.off;
     b.bc = fa.bc + d.off;
     b.flux = fa.flux + d.off;
-    face_body<D, R>(d.g, b, (unsigned)m.tile);
+    face_body<D, R>(d.g, b, (unsigned)m.tile, L);
   }
 }
 
