@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=56, help="edge of the block the CPU oracle times")
+    ap.add_argument("--learned-c2p", action="store_true",
+                    help="seed every c2p with the learned guess (network trained first, outside the timed region)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain device copies of 256 MiB (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -134,6 +136,19 @@ def main():
     n = args.n
     w = W.curved_block(seed=0, n=n, recon=args.recon, nsteps=args.steps)
     blk = asterx.Block(w)
+    learned_info = None
+    if args.learned_c2p:
+        from paper_2406_11669_amd import learned
+        t0 = time.perf_counter()
+        feat, tgt = learned.training_set(2_000_000, seed=0)
+        stdz = learned.standardization(feat, tgt)
+        params, losses = learned.train(feat, tgt, stdz, epochs=10, batch=16384, seed=0)
+        del feat, tgt
+        blk.mlp = asterx.make_mlp(params, stdz)
+        blk._mlp_params = params  # keep the parameters alive
+        torch.cuda.synchronize()
+        learned_info = {"train_states": 2_000_000, "epochs": 10, "final_loss": losses[-1],
+                        "setup_seconds": round(time.perf_counter() - t0, 1)}
     torch.cuda.synchronize()
     print("bench: %s n=%d recon=%s, block resident (%.2f GB device memory)" % (
         w.name, n, args.recon, torch.cuda.memory_allocated() / 1e9), file=sys.stderr, flush=True)
@@ -196,9 +211,12 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "curved%d-%s-rk4" % (n, args.recon), "n": n, "ng": w.layout.ng,
                       "recon": args.recon, "rk": 4, "stages_per_step": stages, "cfl": 0.25, "gamma": 2.0,
-                      "speeds": "quartic", "graph": graph is not None},
+                      "speeds": "quartic", "graph": graph is not None,
+                      "c2p_guess": "learned" if args.learned_c2p else "warm"},
            "roofline": roofline, "hbm_roofline_stage": hbm, "kernel_ms_per_stage": per_stage,
            "c2p_stats": [int(v) for v in blk.stats.cpu().tolist()]}
+    if learned_info:
+        out["learned_c2p"] = learned_info
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a %d^3 sample" % args.cpu_n, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.recon, args.cpu_n)

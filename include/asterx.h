@@ -264,6 +264,15 @@ int asterx_c2p_points(const asterx_params* p, int64_t n, const double* gam_pts, 
                       const double* Bt, double* cons, const double* guess, const asterx_mlp* mlp, double* prim,
                       uint8_t* flags, int32_t* iters, unsigned long long* stats, void* stream);
 
+/* asterx_c2p with the learned guess: each cell's Noble iteration starts from the network's
+ * (W, z) (Sec. 3.5 solver unchanged); if that start does not converge, flag 32 is set and
+ * the warm start from prim (cold start if unusable), Palenzuela and the atmosphere follow as
+ * in asterx_c2p.  Cells below the density floor or with non-finite input skip the network.
+ * Arguments as asterx_c2p, plus the network (see asterx_mlp). */
+int asterx_c2p_learned(const asterx_grid* g, const asterx_params* p, const double* metric, const double* A,
+                       double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats, const asterx_mlp* mlp,
+                       void* stream);
+
 /* Per-kernel timing (diagnostics).  When enabled, every launch of the library is bracketed
  * by two HIP events on its stream; asterx_timing_read waits for the recorded events and
  * returns, for each kernel class k < n, the accumulated milliseconds ms[k] and launch count

@@ -57,7 +57,8 @@ EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "
            "asterx_batch_prim2con", "asterx_batch_c2p", "asterx_batch_fill_ghosts", "asterx_batch_rhs",
            "asterx_batch_rk_stage", "asterx_adjoint_workspace_size", "asterx_rhs_adjoint", "asterx_c2p_adjoint",
            "asterx_prim2con_adjoint", "asterx_prim2con_points", "asterx_mlp_features", "asterx_mlp_forward",
-           "asterx_mlp_grad_workspace_size", "asterx_mlp_grad", "asterx_mlp_adam", "asterx_c2p_points"]
+           "asterx_mlp_grad_workspace_size", "asterx_mlp_grad", "asterx_mlp_adam", "asterx_c2p_points",
+           "asterx_c2p_learned"]
 
 
 def lib():
@@ -107,6 +108,7 @@ def lib():
         L.asterx_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_int32, vp]
         L.asterx_c2p_points.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.asterx_c2p_learned.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.asterx_adjoint_workspace_size.restype = ctypes.c_size_t
         L.asterx_adjoint_workspace_size.argtypes = [vp]
         L.asterx_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp,
@@ -174,7 +176,13 @@ def prim2con(layout, params, metric, A, prim, cons, stream=None):
                                  _stream(stream)))
 
 
-def c2p(layout, params, metric, A, cons, prim, flags=None, stats=None, stream=None):
+def c2p(layout, params, metric, A, cons, prim, flags=None, stats=None, stream=None, mlp=None):
+    """asterx_c2p, or asterx_c2p_learned when an asterx_mlp (make_mlp) is given."""
+    if mlp is not None:
+        _check(lib().asterx_c2p_learned(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                                        _ptr(_f64(metric)), _ptr(_f64(A)), _ptr(_f64(cons)), _ptr(_f64(prim)),
+                                        _ptr(flags), _ptr(stats), ctypes.byref(mlp), _stream(stream)))
+        return
     _check(lib().asterx_c2p(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
                             _ptr(_f64(metric)), _ptr(_f64(A)), _ptr(_f64(cons)), _ptr(_f64(prim)), _ptr(flags),
                             _ptr(stats), _stream(stream)))
@@ -361,6 +369,7 @@ class Block:
         self.stats = torch.zeros(6, dtype=torch.int64, device=dev)
         self.flags = torch.zeros(self.L.shape3, dtype=torch.uint8, device=dev)
         self.dt = wl.dt
+        self.mlp = None  # an asterx_mlp (make_mlp) switches every stage's c2p to the learned guess
         prim2con(self.L, self.params, self.metric, self.state[5:8], self.prim, self.state[0:5])
         fill_ghosts(self.L, self.state[0:5], wl.bc_cell)
 
@@ -377,7 +386,7 @@ class Block:
 
     def eval_rhs(self, U, out):
         """c2p on U (in place for atmosphere cells), primitive ghosts, right-hand side into out."""
-        c2p(self.L, self.params, self.metric, U[5:8], U[0:5], self.prim, self.flags, self.stats)
+        c2p(self.L, self.params, self.metric, U[5:8], U[0:5], self.prim, self.flags, self.stats, mlp=self.mlp)
         fill_ghosts(self.L, self.prim, self.wl.bc_cell)
         rhs(self.L, self.params, self.metric, self.curv, self.prim, U[5:8], U[8:9], self.dt, out, self.red,
             self.ws)

@@ -25,6 +25,7 @@
 #include "asterx.h"
 #include "grmhd_device.h"
 #include "host_internal.h"
+#include "mlp_device.h"
 
 using namespace ax;
 
@@ -363,8 +364,13 @@ struct C2PArgs {
   double* prim;
   uint8_t* flags;
   unsigned long long* stats;
+  const float* mlp;  // learned guess (LEARNED instantiation only)
+  mlpd::Stdz z;
 };
 
+// LEARNED: each wavefront first evaluates the learned guess's network on its 64 cells (through
+// the tile's LDS, free once the metric passes are done) and seeds Noble's iteration with it.
+template <bool LEARNED>
 DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S, unsigned tile) {
   const double* __restrict__ metric = a.metric;
   const double* __restrict__ A = a.A;
@@ -385,18 +391,57 @@ DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S,
   }
   uint32_t fl = 0;
   int iters = 0;
+  const int id = t.valid ? at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz) : 0;
+  Geo G;
+  double Bt[3], U[5], prev[5], out[5];
   if (t.valid) {
-    const int id = at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz);
-    Geo G;
     geo_from(m, G);
-    double Bt[3], U[5], prev[5], out[5];
     centre_B(A, g, id, Bt);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       U[c] = cons[c * g.N + id];
       prev[c] = prim[c * g.N + id];
     }
-    fl = c2p_point(G, U, Bt, prev, P, out, iters);
+  }
+  double zw[2] = {0.0, 0.0};
+  bool use_guess = false;
+  if constexpr (LEARNED) {
+    using namespace mlpd;
+    // S.z and S.y are free: every thread has passed the barrier after the last y pass, and
+    // the barrier below orders the last x pass (reads S.y) before the outputs land there
+    float(*F)[64][NI] = reinterpret_cast<float(*)[64][NI]>(S.z);
+    float(*Y)[64][NO] = reinterpret_cast<float(*)[64][NO]>(S.y);
+    const int w = threadIdx.x >> 6, l = __lane_id(), lr = l & 15, lg = l >> 4;
+    float f[NI];
+    bool usable = false;
+    C2PIn c;
+    bool in = t.valid && isfinite(U[0]) && isfinite(U[1]) && isfinite(U[2]) && isfinite(U[3]) && isfinite(U[4]) &&
+              U[0] >= G.sqrtg * P.rho_atm;
+    if (in) {
+      c2p_input(G, U, Bt, c);
+      features(G, c, P.gam, f, usable);
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) F[w][l][k] = usable ? (f[k] - a.z.is[k]) * a.z.isc[k] : 0.0f;
+    __syncthreads();
+    f4 y[4];
+    mlp_fwd<false>(a.mlp, F[w], y, nullptr);
+    if (lg == 0)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int q = 0; q < NO; ++q) Y[w][nt * 16 + lr][q] = a.z.os[q] + y[nt][q] / a.z.osc[q];
+    __syncthreads();
+    if (usable) {
+      const double W = exp((double)Y[w][l][0]);
+      const double wcap = 1.0 - 1.0 / (P.wmax * P.wmax);
+      zw[0] = c.D * exp((double)Y[w][l][1]);
+      zw[1] = fmin(fmax(1.0 - 1.0 / (W * W), 0.0), wcap);
+      use_guess = isfinite(zw[0]) && zw[0] > 0.0;
+    }
+  }
+  if (t.valid) {
+    fl = c2p_point(G, U, Bt, prev, P, out, iters, use_guess ? zw : nullptr);
 #pragma unroll
     for (int c = 0; c < 5; ++c) prim[c * g.N + id] = out[c];
     if (fl & 4u) {
@@ -1015,7 +1060,11 @@ __global__ __launch_bounds__(256) void kb_prim2con(const PatchDesc* __restrict__
 
 __global__ __launch_bounds__(256) void k_c2p(GD g, C2PParams cp, C2PArgs a) {
   __shared__ TileLDS S;
-  c2p_body(g, cp, a, S, my_tile());
+  c2p_body<false>(g, cp, a, S, my_tile());
+}
+__global__ __launch_bounds__(256) void k_c2p_learned(GD g, C2PParams cp, C2PArgs a) {
+  __shared__ TileLDS S;
+  c2p_body<true>(g, cp, a, S, my_tile());
 }
 __global__ __launch_bounds__(256) void kb_c2p(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                               C2PParams cp, C2PArgs a) {
@@ -1029,7 +1078,7 @@ __global__ __launch_bounds__(256) void kb_c2p(const PatchDesc* __restrict__ P, c
     b.cons = a.cons + d.off;
     b.prim = a.prim + d.off;
     b.flags = shifted(a.flags, d.off);
-    c2p_body(d.g, cp, b, S, (unsigned)m.tile);
+    c2p_body<false>(d.g, cp, b, S, (unsigned)m.tile);
   }
 }
 
@@ -2030,8 +2079,18 @@ int do_prim2con(const GD& g, const asterx_batch* b, const asterx_params* p, cons
 int do_c2p(const GD& g, const asterx_batch* b, const asterx_params* p, const double* metric, const double* A,
            double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats, hipStream_t s) {
   C2PParams cp = make_c2p_params(p);
-  C2PArgs a{metric, A, cons, prim, flags, (unsigned long long*)stats};
+  C2PArgs a{metric, A, cons, prim, flags, (unsigned long long*)stats, nullptr, {}};
   return RUN_PHASE(KT_C2P, PH_C2P, k_c2p, kb_c2p, cp, a);
+}
+
+int do_c2p_learned(const GD& g, const asterx_params* p, const double* metric, const double* A, double* cons,
+                   double* prim, uint8_t* flags, asterx_c2p_stats* stats, const float* mlp, const mlpd::Stdz& z,
+                   hipStream_t s) {
+  C2PParams cp = make_c2p_params(p);
+  C2PArgs a{metric, A, cons, prim, flags, (unsigned long long*)stats, mlp, z};
+  return timed(KT_C2P, s, [&] {
+    hipLaunchKernelGGL(k_c2p_learned, dim3(tiles_for(PH_C2P, g)), dim3(256), 0, s, g, cp, a);
+  });
 }
 
 int do_fill(const GD& g, const asterx_batch* b, double* f, int nf, const int32_t* kinds, hipStream_t s,
@@ -2168,6 +2227,27 @@ int asterx_c2p(const asterx_grid* gr, const asterx_params* p, const double* metr
   GD g = make_gd(gr);
   const asterx_batch* b = nullptr;
   return do_c2p(g, b, p, metric, A, cons, prim, flags, stats, (hipStream_t)stream);
+}
+
+int asterx_c2p_learned(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* A,
+                       double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats, const asterx_mlp* mlp,
+                       void* stream) {
+  int rc;
+  if ((rc = check_grid(gr, 2)) || (rc = check_params(p))) return rc;
+  if (!metric || !A || !prim || !cons || !mlp || !mlp->params) return fail(ASTERX_EARG, "c2p_learned: NULL array");
+  mlpd::Stdz z;
+  for (int k = 0; k < mlpd::NI; ++k) {
+    if (!(mlp->in_scale[k] > 0.0f)) return fail(ASTERX_EARG, "c2p_learned: network scales must be > 0");
+    z.is[k] = mlp->in_shift[k];
+    z.isc[k] = mlp->in_scale[k];
+  }
+  for (int k = 0; k < mlpd::NO; ++k) {
+    if (!(mlp->out_scale[k] > 0.0f)) return fail(ASTERX_EARG, "c2p_learned: network scales must be > 0");
+    z.os[k] = mlp->out_shift[k];
+    z.osc[k] = 1.0f / mlp->out_scale[k];
+  }
+  GD g = make_gd(gr);
+  return do_c2p_learned(g, p, metric, A, cons, prim, flags, stats, mlp->params, z, (hipStream_t)stream);
 }
 
 int asterx_fill_ghosts(const asterx_grid* gr, double* f, int32_t nf, const int32_t* kinds, void* stream) {

@@ -1,0 +1,160 @@
+// mlp_device.h -- device code of the learned c2p guess's network, shared by the point kernels
+// and the grid c2p kernel: parameter packing, bfloat16 rounding, the input features and the
+// forward pass of one wavefront on the matrix cores.  (See learned_c2p.hip for the design.)
+#ifndef ASTERX_MLP_DEVICE_H
+#define ASTERX_MLP_DEVICE_H
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "asterx.h"
+#include "grmhd_device.h"
+
+namespace mlpd {
+using namespace ax;
+
+constexpr int NI = 8, NH = 64, NO = 2;
+constexpr int OW1 = 0, OB1 = OW1 + NH * NI, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH;
+constexpr int OB3 = OW3 + NO * NH, NP = OB3 + NO;
+static_assert(NP == ASTERX_MLP_NPARAMS, "parameter packing");
+
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+DEV short bf16(float x) {  // round to nearest even (finite x)
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+DEV float act(float x) {  // tanh(x) = 1 - 2 / (exp(2x) + 1)
+  float e = __expf(2.0f * x);
+  return 1.0f - 2.0f / (e + 1.0f);
+}
+
+DEV f4 mfma(bf4 a, bf4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+
+DEV bf4 ld4(const float* __restrict__ P, int o, bool on) {
+  bf4 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = on ? bf16(P[o + i]) : (short)0;
+  return r;
+}
+
+struct Stdz {
+  float is[NI], isc[NI], os[NO], osc[NO];
+};
+
+// Features of a conserved state (undensitized input c): log D, log(tau/D), log(1 + S^2/D^2),
+// log(1 + B^2/D), log(1 + (B.S)^2/D^3), det(gamma) - 1, alpha - 1, Gamma.  usable = false when
+// the state cannot be fed to the network (non-positive D or tau, non-finite values).
+DEV void features(const Geo& G, const C2PIn& c, double gam, float f[NI], bool& usable) {
+  double D = c.D;
+  usable = D > 0.0 && c.tau > 0.0 && isfinite(c.S2) && isfinite(c.B2) && isfinite(c.tau);
+  if (!usable) {
+#pragma unroll
+    for (int k = 0; k < NI; ++k) f[k] = 0.0f;
+    return;
+  }
+  double iD = 1.0 / D;
+  f[0] = (float)log(D);
+  f[1] = (float)log(c.tau * iD);
+  f[2] = (float)log1p(c.S2 * iD * iD);
+  f[3] = (float)log1p(c.B2 * iD);
+  f[4] = (float)log1p(c.BS * c.BS * iD * iD * iD);
+  f[5] = (float)(G.sqrtg * G.sqrtg - 1.0);
+  f[6] = (float)(G.alp - 1.0);
+  f[7] = (float)gam;
+}
+
+// ---- one wavefront, 64 samples ------------------------------------------------------------------
+// feat: LDS [64][8] standardised inputs.  y[nt]: output tile nt (lanes 0..15 hold rows 0, 1 =
+// outputs of sample nt*16 + lane).  With TRAIN the FP32 activations and the bfloat16 operands of
+// every layer are kept for the backward pass.
+struct Acts {
+  f4 t1[4][4], t2[4][4];
+  bf4 x1[4], x2[4][4], x3[4][4];
+};
+
+template <bool TRAIN>
+DEV void mlp_fwd(const float* __restrict__ P, const float (*feat)[NI], f4 y[4], Acts* A) {
+  const int l = __lane_id(), lr = l & 15, lg = l >> 4;
+  bf4 x1[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x1[nt][i] = lg < 2 ? bf16(feat[nt * 16 + lr][4 * lg + i]) : (short)0;
+  f4 h[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    bf4 a = ld4(P, OW1 + (mt * 16 + lr) * NI + 4 * lg, lg < 2);
+    f4 bias;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bias[i] = P[OB1 + mt * 16 + 4 * lg + i];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) h[mt][nt] = mfma(a, x1[nt], bias);
+  }
+  bf4 x2[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float t = act(h[mt][nt][i]);
+        if (TRAIN) A->t1[mt][nt][i] = t;
+        x2[mt][nt][i] = bf16(t);
+      }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f4 bias;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bias[i] = P[OB2 + mt * 16 + 4 * lg + i];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) h[mt][nt] = bias;
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+      bf4 a = ld4(P, OW2 + (mt * 16 + lr) * NH + kt * 16 + 4 * lg, true);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) h[mt][nt] = mfma(a, x2[kt][nt], h[mt][nt]);
+    }
+  }
+  bf4 x3[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float t = act(h[mt][nt][i]);
+        if (TRAIN) A->t2[mt][nt][i] = t;
+        x3[mt][nt][i] = bf16(t);
+      }
+  f4 b3;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) b3[i] = (4 * lg + i < NO) ? P[OB3 + 4 * lg + i] : 0.0f;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) y[nt] = b3;
+#pragma unroll
+  for (int kt = 0; kt < 4; ++kt) {
+    bf4 a = ld4(P, OW3 + lr * NH + kt * 16 + 4 * lg, lr < NO);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) y[nt] = mfma(a, x3[kt][nt], y[nt]);
+  }
+  if (TRAIN) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) A->x1[nt] = x1[nt];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        A->x2[mt][nt] = x2[mt][nt];
+        A->x3[mt][nt] = x3[mt][nt];
+      }
+  }
+}
+
+}  // namespace mlpd
+
+#endif

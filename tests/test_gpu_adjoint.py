@@ -205,3 +205,31 @@ def test_prim2con_adjoint_dot_product(adj, orc, part):
         rhs, rscale = _dot(L, (pb if part == "prim" else Ab).cpu().numpy(), dpr if part == "prim" else dA)
     print("  <ybar, Jv> %.15e  <J^T ybar, v> %.15e" % (lhs, rhs), flush=True)
     assert abs(lhs - rhs) <= 1e-10 * max(lscale, rscale), (lhs, rhs, lscale)
+
+
+def test_adjoint_full_size_vs_golden_jvp(adj):
+    """The differentiation workload at full size (64^3 periodic Riemann box, PPM, 20 RK2 steps): the adjoint
+    gradient's directional derivatives against the oracle's dual-number JVPs stored in tests/golden (written by
+    the script beside them, which calls only the oracle), within 1e-10 of the term scale."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "periodic_riemann64_jvp.json")
+    with open(path) as f:
+        gold = json.load(f)
+    w = W.periodic_riemann_box(seed=0, n=64, nsteps=20, v_amp=0.1)
+    L = w.layout
+    print("case adjoint periodic_riemann64 full size", flush=True)
+    loss, g, gg, _ = _grad(adj, w, 20)
+    checked = 0
+    for c in gold["cases"]:
+        if c["v_amp"] != 0.1:
+            continue
+        d, dg = (L.zeros(5), 1.0) if c["dir_seed"] is None else W.gradient_direction(L, c["dir_seed"], c["with_gamma"])
+        terms = L.owned(g)[2:5] * L.owned(d)[2:5]
+        mine = float(np.sum(terms)) + gg * dg
+        scale = float(np.sum(np.abs(terms))) + abs(gg * dg)
+        print("  jvp oracle %.15e  adjoint %.15e  scale %.3e" % (c["jvp"], mine, scale), flush=True)
+        assert abs(loss - c["loss"]) <= 1e-12 * c["loss"]
+        assert abs(mine - c["jvp"]) <= 1e-10 * scale
+        checked += 1
+    assert checked == 4

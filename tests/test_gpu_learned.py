@@ -149,15 +149,21 @@ def test_adam_step_vs_reference(L):
     assert np.allclose(mt.cpu().numpy(), mr, rtol=1e-6, atol=1e-8)
 
 
-def test_trained_guess_cuts_newton_iterations(L):
-    """A network trained briefly (2e6 states, 10 epochs, the library's own kernels) seeds Noble's iteration on
-    held-out states: every state is recovered, to the same primitives as the plain cold start, in fewer
-    iterations on average."""
-    import torch
-    from paper_2406_11669_amd import asterx as ax
+@pytest.fixture(scope="module")
+def trained(L):
+    """A network trained briefly (2e6 states, 10 epochs) by the library's own kernels."""
     feat, tgt = L.training_set(2_000_000, seed=21)
     st = L.standardization(feat, tgt)
     params, losses = L.train(feat, tgt, st, epochs=10, batch=16384, seed=3)
+    return params, st, losses
+
+
+def test_trained_guess_cuts_newton_iterations(L, trained):
+    """The trained network seeds Noble's iteration on held-out states: every state is recovered, to the same
+    primitives as the plain cold start, in fewer iterations on average."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    params, st, losses = trained
     assert losses[-1] < 0.75 * losses[0], losses
     mlp = ax.make_mlp(params, st)
     d = L.device_states(W.c2p_states(22, 20_000))
@@ -167,3 +173,28 @@ def test_trained_guess_cuts_newton_iterations(L):
     assert cold["hard_fail_frac"] == 0.0 and learned["hard_fail_frac"] == 0.0
     assert learned["iters_mean"] < cold["iters_mean"]
     assert learned["rho_rel_diff_vs_cold_max"] <= 1e-12 and learned["p_diff_vs_cold_max"] <= 1e-12
+
+
+def test_grid_c2p_learned_matches_plain(L, trained, orc):
+    """asterx_c2p_learned on a curved block (warm starts present, as inside a step) recovers the same primitives
+    as the oracle's c2p within 1e-12 (cancellation-aware), with the same flags apart from bit 32."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    from tests.parity import assert_fields_close
+    params, st, _ = trained
+    w = W.curved_block(seed=12, n=(20, 13, 11), recon="ppm", rho_atm=1e-6)
+    Lg = w.layout
+    cons = orc.prim2con(Lg, w.params, w.metric, w.A, w.prim)
+    rng = np.random.default_rng(4)
+    guess = w.prim * (1.0 + rng.uniform(-0.02, 0.02, w.prim.shape))
+    c_ref, p_ref = cons.copy(), guess.copy()
+    fl_ref, _ = orc.c2p(Lg, w.params, w.metric, w.A, c_ref, p_ref)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    c_g, p_g = dev(cons), dev(guess)
+    flags = torch.zeros(Lg.shape3, dtype=torch.uint8, device="cuda")
+    stats = torch.zeros(6, dtype=torch.int64, device="cuda")
+    ax.c2p(Lg, w.params, dev(w.metric), dev(w.A), c_g, p_g, flags, stats, mlp=ax.make_mlp(params, st))
+    torch.cuda.synchronize()
+    fg = Lg.owned(flags.cpu().numpy()).astype(np.int32)
+    assert np.array_equal(fg & ~32, Lg.owned(fl_ref).astype(np.int32))
+    assert_fields_close(p_g.cpu().numpy(), p_ref, 1e-12, Lg.owned, ["rho", "p", "vx", "vy", "vz"])
