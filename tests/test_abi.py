@@ -94,3 +94,49 @@ def test_oracle_ghost_fill_matches_definitions(orc):
     # linear extrapolation along z below the block, at an owned (i, j)
     k0, k1 = c[0, g, g + 1, g + 1], c[0, g + 1, g + 1, g + 1]
     assert np.isclose(c[0, g - 2, g + 1, g + 1], k0 - 2 * (k1 - k0), rtol=1e-14)
+
+
+def test_extension_entry_points_validate_on_host(lib):
+    """Adjoint, point, network and batch entry points reject bad arguments before any launch, and empty point
+    sets are a no-op (nothing is touched)."""
+    from paper_2406_11669_amd import asterx
+    from paper_2406_11669_amd.workloads import Layout, default_params
+    L = Layout((8, 8, 8), 3)
+    g = asterx.make_grid(L)
+    p = asterx.make_params(default_params(recon="ppm"))
+    dummy = ctypes.c_void_p(16)
+    # adjoint: workspace too small; periodic blocks need n > ng
+    rc = lib.asterx_rhs_adjoint(ctypes.byref(g), ctypes.byref(p), dummy, dummy, dummy, dummy, dummy, dummy, 0.01,
+                                dummy, dummy, dummy, dummy, dummy, dummy, 8, None)
+    assert rc == -1 and b"workspace" in lib.asterx_last_error()
+    g3 = asterx.make_grid(Layout((3, 8, 8), 3))
+    rc = lib.asterx_c2p_adjoint(ctypes.byref(g3), ctypes.byref(p), dummy, dummy, dummy, dummy, dummy, dummy, dummy,
+                                dummy, dummy, 1 << 40, None)
+    assert rc == -1 and b"n > ng" in lib.asterx_last_error()
+    assert lib.asterx_adjoint_workspace_size(ctypes.byref(g)) >= 52 * 8 * L.npts
+    # points: negative n, NULL arrays; n = 0 is a no-op
+    assert lib.asterx_prim2con_points(-1, None, 5.0 / 3.0, dummy, dummy, dummy, dummy, None, None) == -1
+    assert lib.asterx_prim2con_points(4, None, 5.0 / 3.0, dummy, dummy, None, dummy, None, None) == -1
+    assert lib.asterx_prim2con_points(0, None, 5.0 / 3.0, dummy, dummy, dummy, dummy, None, None) == 0
+    assert lib.asterx_c2p_points(ctypes.byref(p), 0, None, dummy, dummy, dummy, None, None, dummy, None, None, None,
+                                 None) == 0
+    assert lib.asterx_prim2con_points(4, None, 1.0, dummy, dummy, dummy, dummy, None, None) == -1  # Gamma <= 1
+    # network: zero scale rejected; workspace sizing and too-small workspace
+    m = asterx.MLP()
+    m.params = 16
+    for k in range(8):
+        m.in_scale[k] = 1.0
+    m.out_scale[0] = 1.0
+    m.out_scale[1] = 0.0
+    assert lib.asterx_mlp_forward(ctypes.byref(m), 10, dummy, dummy, None) == -1
+    assert b"scale" in lib.asterx_last_error()
+    m.out_scale[1] = 1.0
+    assert lib.asterx_mlp_forward(ctypes.byref(m), 0, dummy, dummy, None) == 0
+    assert lib.asterx_mlp_grad_workspace_size(65) == 2 * (asterx.MLP_NPARAMS + 1) * 4
+    assert lib.asterx_mlp_grad(ctypes.byref(m), 65, dummy, dummy, dummy, dummy, 8, None) == -1
+    assert lib.asterx_mlp_adam(dummy, dummy, dummy, dummy, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1  # step >= 1
+    assert lib.asterx_c2p_learned(ctypes.byref(g), ctypes.byref(p), dummy, dummy, dummy, dummy, None, None, None,
+                                  None) == -1
+    # batch: at least one patch, sane ghosts
+    h = ctypes.c_void_p()
+    assert lib.asterx_batch_create(0, None, None, ctypes.byref(h)) == -1
