@@ -222,7 +222,7 @@ int asterx_prim2con_adjoint(const asterx_grid* g, const asterx_params* p, const 
 int asterx_prim2con_points(int64_t n, const double* gam_pts, double gam, const double* metric, const double* Bt,
                            const double* prim, double* cons, double* target, void* stream);
 
-/* Multilayer perceptron 8 -> 64 -> 64 -> 2, tanh hidden activations, packed FP32 parameters
+/* Multilayer perceptron 8 -> 64 -> 64 -> 2, ReLU hidden activations, packed FP32 parameters
  * (device, ASTERX_MLP_NPARAMS floats): W1[64][8], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
  * Inputs are standardised as (f - in_shift) * in_scale; outputs are out_shift + out_scale * y.
  * Contractions run on bfloat16 operands with FP32 accumulation (matrix cores). */

@@ -3,12 +3,12 @@
 Only tests/, the entry-point smoke check and the benchmark's CPU baseline may import this module;
 the library never does.
 
-The network: 8 -> 64 -> 64 -> 2, tanh hidden activations, parameters packed as W1[64][8], b1[64],
+The network: 8 -> 64 -> 64 -> 2, ReLU hidden activations, parameters packed as W1[64][8], b1[64],
 W2[64][64], b2[64], W3[2][64], b3[2] (4866 floats).  The library's arithmetic is restated here
 step by step: inputs standardised in float32, then every matrix product takes bfloat16 operands
 (round to nearest even) -- weights, layer inputs, activations and the backward cotangents -- with
 the products accumulated exactly (float64 here; the matrix cores accumulate in float32, so the two
-differ by float32 rounding), biases and activations in float32, tanh(x) = 1 - 2 / (exp(2x) + 1).
+differ by float32 rounding), biases and activations in float32.
 
 precise=True drops every bfloat16 rounding and works in float64: the plain network, whose gradient
 the tests pin against central differences.
@@ -43,10 +43,15 @@ def bf16(x):
 
 
 def act(x, precise=False):
+    """ReLU."""
     if precise:
-        return np.tanh(x)
-    x = np.asarray(x, dtype=np.float32)
-    return (np.float32(1.0) - np.float32(2.0) / (np.exp(np.float32(2.0) * x) + np.float32(1.0))).astype(np.float32)
+        return np.maximum(x, 0.0)
+    return np.maximum(np.asarray(x, dtype=np.float32), np.float32(0.0))
+
+
+def dact(t):
+    """ReLU' from the activation's value (1 where it is positive)."""
+    return (t > 0).astype(t.dtype)
 
 
 def init_params(seed):
@@ -93,11 +98,11 @@ def loss_grad(params, feat, target, stdz, precise=False):
     gW3 = _r(d3, precise) @ c["x3"].T
     gb3 = d3.astype(np.float64).sum(1)
     g2 = (_r(W3, precise).T @ _r(d3, precise)).astype(dt)
-    d2 = (g2 * (dt(1.0) - c["t2"] * c["t2"])).astype(dt)
+    d2 = (g2 * dact(c["t2"])).astype(dt)
     gW2 = _r(d2, precise) @ c["x2"].T
     gb2 = d2.astype(np.float64).sum(1)
     g1 = (_r(W2, precise).T @ _r(d2, precise)).astype(dt)
-    d1 = (g1 * (dt(1.0) - c["t1"] * c["t1"])).astype(dt)
+    d1 = (g1 * dact(c["t1"])).astype(dt)
     gW1 = _r(d1, precise) @ c["x1"].T
     gb1 = d1.astype(np.float64).sum(1)
     return loss, pack(gW1, gb1, gW2, gb2, gW3, gb3)

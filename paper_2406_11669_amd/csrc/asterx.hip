@@ -433,9 +433,9 @@ DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S,
         for (int q = 0; q < NO; ++q) Y[w][nt * 16 + lr][q] = a.z.os[q] + y[nt][q] / a.z.osc[q];
     __syncthreads();
     if (usable) {
-      const double W = exp((double)Y[w][l][0]);
+      const double W = (double)__expf(Y[w][l][0]);
       const double wcap = 1.0 - 1.0 / (P.wmax * P.wmax);
-      zw[0] = c.D * exp((double)Y[w][l][1]);
+      zw[0] = c.D * (double)__expf(Y[w][l][1]);
       zw[1] = fmin(fmax(1.0 - 1.0 / (W * W), 0.0), wcap);
       use_guess = isfinite(zw[0]) && zw[0] > 0.0;
     }

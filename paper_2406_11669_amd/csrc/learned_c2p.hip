@@ -1,6 +1,6 @@
 // learned_c2p.hip -- learned initial guess for the conservative-to-primitive recovery (gfx950).
 //
-// A multilayer perceptron 8 -> 64 -> 64 -> 2 (tanh hidden activations) maps eight features of
+// A multilayer perceptron 8 -> 64 -> 64 -> 2 (ReLU hidden activations) maps eight features of
 // a conserved state to (log W, log(z / D)), z = rho h W^2, which seed Noble's 2D Newton
 // iteration (Sec. 3.5).  The FP64 iteration polishes the guess to the same tolerance as the
 // plain recovery; if it does not converge, the plain warm/cold start, Palenzuela's 1D
@@ -8,7 +8,9 @@
 //
 // Arithmetic of the network: weights, inputs and hidden activations are rounded to bfloat16
 // (round to nearest even) and contracted on the matrix cores with v_mfma_f32_16x16x16_bf16
-// (FP32 accumulate); biases, activations and the loss are FP32.  One wavefront evaluates 64
+// (FP32 accumulate); biases, activations and the loss are FP32.  ReLU rather than tanh: the
+// network runs inside the recovery, where a tanh (exponential and reciprocal, quarter-rate) per
+// hidden unit cost more than the Newton iterations the guess saves.  One wavefront evaluates 64
 // samples: every layer is computed transposed (H^T = W X^T), so that the accumulator layout
 // of one layer (lane l holds rows 4(l/16)..4(l/16)+3 of column l%16) is exactly the B-operand
 // layout of the next and activations never leave registers; the weight gradients, which
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ P, lo
         for (int i = 0; i < NO; ++i) out[OW3 + i * NH + nt * 16 + lr] = acc[nt][i];
     __syncthreads();
   }
-  // delta2 = (W3^T delta3) * (1 - t2^2)
+  // delta2 = (W3^T delta3) * ReLU'(t2)
   bf4 d2b[4][4];
   {
     float gb2[4][4];
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ P, lo
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           float t = A.t2[mt][nt][i];
-          float d = g[i] * (1.0f - t * t);
+          float d = t > 0.0f ? g[i] : 0.0f;  // ReLU'
           d2b[mt][nt][i] = bf16(d);
           gb2[mt][i] = (nt == 0 ? 0.0f : gb2[mt][i]) + d;
         }
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ P, lo
     }
     __syncthreads();
   }
-  // delta1 = (W2^T delta2) * (1 - t1^2)
+  // delta1 = (W2^T delta2) * ReLU'(t1)
   bf4 d1b[4][4];
   {
     float gb1[4][4];
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ P, lo
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           float t = A.t1[mt][nt][i];
-          float d = g[nt][i] * (1.0f - t * t);
+          float d = t > 0.0f ? g[nt][i] : 0.0f;  // ReLU'
           d1b[mt][nt][i] = bf16(d);
           gb1[mt][i] = (nt == 0 ? 0.0f : gb1[mt][i]) + d;
         }
@@ -424,10 +426,9 @@ __global__ __launch_bounds__(256) void k_c2p_points(C2PPtsArgs a) {
         for (int q = 0; q < NO; ++q) Y[w][nt * 16 + lr][q] = a.z.os[q] + y[nt][q] / a.z.osc[q];
     __syncthreads();
     if (usable) {
-      double lW = Y[w][l][0], lx = Y[w][l][1];
-      double W = exp(lW);
+      double W = (double)__expf(Y[w][l][0]);
       const double wcap = 1.0 - 1.0 / (a.cp.wmax * a.cp.wmax);
-      zw[0] = c.D * exp(lx);
+      zw[0] = c.D * (double)__expf(Y[w][l][1]);
       zw[1] = fmin(fmax(1.0 - 1.0 / (W * W), 0.0), wcap);
       use_guess = isfinite(zw[0]) && zw[0] > 0.0;
     }

@@ -1,6 +1,6 @@
 // mlp_device.h -- device code of the learned c2p guess's network, shared by the point kernels
 // and the grid c2p kernel: parameter packing, bfloat16 rounding, the input features and the
-// forward pass of one wavefront on the matrix cores.  (See learned_c2p.hip for the design.)
+// forward pass of one wavefront on the matrix cores.  Hidden activations: ReLU.  (See learned_c2p.hip for the design.)
 #ifndef ASTERX_MLP_DEVICE_H
 #define ASTERX_MLP_DEVICE_H
 
@@ -22,15 +22,12 @@ static_assert(NP == ASTERX_MLP_NPARAMS, "parameter packing");
 typedef short bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-DEV short bf16(float x) {  // round to nearest even (finite x)
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
+DEV short bf16(float x) {  // round to nearest even: one v_cvt_pk_bf16_f32 on gfx950
+  return __builtin_bit_cast(short, (__bf16)x);
 }
 
-DEV float act(float x) {  // tanh(x) = 1 - 2 / (exp(2x) + 1)
-  float e = __expf(2.0f * x);
-  return 1.0f - 2.0f / (e + 1.0f);
+DEV float act(float x) {  // ReLU: one instruction per activation, where tanh would cost an exp and a reciprocal
+  return fmaxf(x, 0.0f);
 }
 
 DEV f4 mfma(bf4 a, bf4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
@@ -57,12 +54,13 @@ DEV void features(const Geo& G, const C2PIn& c, double gam, float f[NI], bool& u
     for (int k = 0; k < NI; ++k) f[k] = 0.0f;
     return;
   }
-  double iD = 1.0 / D;
-  f[0] = (float)log(D);
-  f[1] = (float)log(c.tau * iD);
-  f[2] = (float)log1p(c.S2 * iD * iD);
-  f[3] = (float)log1p(c.B2 * iD);
-  f[4] = (float)log1p(c.BS * c.BS * iD * iD * iD);
+  // single precision is plenty for a network input (hardware logarithm)
+  const double iD = 1.0 / D;
+  f[0] = __logf((float)D);
+  f[1] = __logf((float)(c.tau * iD));
+  f[2] = __logf(1.0f + (float)(c.S2 * iD * iD));
+  f[3] = __logf(1.0f + (float)(c.B2 * iD));
+  f[4] = __logf(1.0f + (float)(c.BS * c.BS * iD * iD * iD));
   f[5] = (float)(G.sqrtg * G.sqrtg - 1.0);
   f[6] = (float)(G.alp - 1.0);
   f[7] = (float)gam;

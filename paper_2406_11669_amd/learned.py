@@ -184,7 +184,7 @@ def evaluate(d, mlp, warm_noise=1e-2, seed=0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--train", type=int, default=10_000_000)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--heldout", type=int, default=1_000_000)
     ap.add_argument("--block", type=int, default=256)
