@@ -1205,6 +1205,18 @@ enum {
   AW_CONS = 0, AW_PRIM = 5, AW_BC = 10, AW_PBAR = 13, AW_BCBAR = 18, AW_BFBAR = 21, AW_ABAR = 24, AW_PSIBAR = 27,
   AW_AVBAR = 28, AW_FBAR = 31, AW_FIELDS = 52
 };
+// The Gamma cotangent is accumulated into GSLOTS workspace slots (workgroup id modulo GSLOTS):
+// per-wavefront FP64 atomics to one address would serialize in L2.  The slots are summed in a
+// fixed order into the caller's gamma_bar at the end of each adjoint call.
+constexpr int GSLOTS = 64;
+
+DEV void gslots_body(const double* __restrict__ slots, double* __restrict__ gamma_bar) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < GSLOTS; ++q) t += slots[q];
+    gamma_bar[0] += t;
+  }
+}
 
 DEV bool owned3(const GD& g, int i, int j, int k) {
   return i >= 0 && j >= 0 && k >= 0 && i < g.n[0] && j < g.n[1] && k < g.n[2];
@@ -1462,7 +1474,7 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
   double w = gsum;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) w += __shfl_xor(w, o, 64);
-  if (__lane_id() == 0 && w != 0.0) atomicAdd(fa.gbar, w);
+  if (__lane_id() == 0 && w != 0.0) atomicAdd(fa.gbar + (blockIdx.x & (GSLOTS - 1)), w);
 }
 
 // Geometric sources transposed, one owned cell per thread (direct 64-point interpolation of
@@ -1601,7 +1613,7 @@ DEV void cell_adj_body(const GD& g, const CellAdjArgs& ca, unsigned tile) {
   }
   double w = gsum;
   for (int o = 32; o >= 1; o >>= 1) w += __shfl_xor(w, o, 64);
-  if (__lane_id() == 0 && w != 0.0) atomicAdd(ca.gbar, w);
+  if (__lane_id() == 0 && w != 0.0) atomicAdd(ca.gbar + (blockIdx.x & (GSLOTS - 1)), w);
 }
 
 // Gauge terms transposed at vertices [-1, n]^3: G_A and F_Psi cotangents from the A and Psi
@@ -1813,7 +1825,7 @@ DEV void c2p_adj_body(const GD& g, const C2PAdjArgs& ca, unsigned tile) {
   }
   double w = gsum;
   for (int o = 32; o >= 1; o >>= 1) w += __shfl_xor(w, o, 64);
-  if (__lane_id() == 0 && w != 0.0) atomicAdd(ca.gbar, w);
+  if (__lane_id() == 0 && w != 0.0) atomicAdd(ca.gbar + (blockIdx.x & (GSLOTS - 1)), w);
 }
 
 // Centre-field cotangents to face-field cotangents (gather over the two adjacent cells),
@@ -1886,6 +1898,7 @@ __global__ __launch_bounds__(256) void k_edge_adj(GD g, const double* avbar, dou
 }
 __global__ __launch_bounds__(256) void k_fillT(GD g, FillTArgs a) { fillT_body(g, a, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_c2p_adj(GD g, C2PAdjArgs ca) { c2p_adj_body(g, ca, my_tile()); }
+__global__ __launch_bounds__(64) void k_gslots(const double* slots, double* gamma_bar) { gslots_body(slots, gamma_bar); }
 __global__ __launch_bounds__(256) void k_bcface_adj(GD g, const double* bcbar, double* bfbar) {
   bcface_adj_body(g, bcbar, bfbar, my_tile());
 }
@@ -2509,6 +2522,17 @@ int adj_prologue(const GD& g, const asterx_params* p, const double* metric, cons
   return do_fill(g, b, ws + AW_PRIM * g.N, 5, per, s);
 }
 
+// Gamma cotangent slots: after the flags in the workspace tail.
+double* gamma_slots(const GD& g, double* ws) { return ws + (size_t)AW_FIELDS * g.N + ((size_t)g.N + 7) / 8; }
+
+int gslots_zero(double* slots, hipStream_t s) {
+  return timed(KT_ZERO, s, [&] { hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, slots, (long long)GSLOTS); });
+}
+
+int gslots_finish(const double* slots, double* gamma_bar, hipStream_t s) {
+  return timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_gslots, dim3(1), dim3(64), 0, s, slots, gamma_bar); });
+}
+
 // Centre-field and face-field cotangents to the edge potential, fold ghosts, add to A_bar.
 int adj_epilogue(const GD& g, double* ws, double* A_bar, double* psi_bar, hipStream_t s) {
   int rc;
@@ -2543,7 +2567,7 @@ extern "C" {
 size_t asterx_adjoint_workspace_size(const asterx_grid* g) {
   if (!g) return 0;
   size_t N = (size_t)g->ld[0] * g->ld[1] * g->ld[2];
-  return (size_t)AW_FIELDS * N * sizeof(double) + ((N + 7) / 8) * 8;
+  return (size_t)AW_FIELDS * N * sizeof(double) + ((N + 7) / 8) * 8 + GSLOTS * sizeof(double);
 }
 
 int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* curv,
@@ -2560,19 +2584,21 @@ int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
   GD g = make_gd(gr);
   double* ws = (double*)workspace;
   uint8_t* flags = (uint8_t*)(ws + (size_t)AW_FIELDS * g.N);
+  double* slots = gamma_slots(g, ws);
   if ((rc = adj_prologue(g, p, metric, cons, prim_guess, A, ws, flags, s, true))) return rc;
+  if ((rc = gslots_zero(slots, s))) return rc;
   unsigned nb;
   FluxBarArgs fb{rhs_bar, ws + AW_FBAR * g.N};
   nb = tiles_for(PH_VERTEX, g);
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_fluxbar, dim3(nb), dim3(256), 0, s, g, fb); }))) return rc;
   FaceAdjArgs fa{metric, ws + AW_PRIM * g.N, A, ws + AW_BC * g.N, ws + AW_FBAR * g.N, ws + AW_PBAR * g.N,
-                 ws + AW_BCBAR * g.N, ws + AW_BFBAR * g.N, gamma_bar, p->gamma, p->weno_eps, p->weno_q, p->speeds};
+                 ws + AW_BCBAR * g.N, ws + AW_BFBAR * g.N, slots, p->gamma, p->weno_eps, p->weno_q, p->speeds};
   if (p->recon == ASTERX_RECON_MINMOD) rc = adj_faces_r<ASTERX_RECON_MINMOD>(g, fa, s);
   else if (p->recon == ASTERX_RECON_PPM) rc = adj_faces_r<ASTERX_RECON_PPM>(g, fa, s);
   else rc = adj_faces_r<ASTERX_RECON_WENOZ>(g, fa, s);
   if (rc) return rc;
   CellAdjArgs ca{metric, curv, ws + AW_PRIM * g.N, ws + AW_BC * g.N, rhs_bar, ws + AW_PBAR * g.N,
-                 ws + AW_BCBAR * g.N, gamma_bar, p->gamma};
+                 ws + AW_BCBAR * g.N, slots, p->gamma};
   nb = tiles_for(PH_RK, g);
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_cell_adj, dim3(nb), dim3(256), 0, s, g, ca); }))) return rc;
   VertexAdjArgs va{metric, rhs_bar, ws + AW_PSIBAR * g.N, ws + AW_AVBAR * g.N, p->xi / dt_max, p->gauge};
@@ -2586,10 +2612,11 @@ int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
     return rc;
   if ((rc = adj_fillT(g, ws + AW_PBAR * g.N, 5, s))) return rc;
   C2PAdjArgs cpa{metric, ws + AW_PRIM * g.N, ws + AW_BC * g.N, flags, ws + AW_PBAR * g.N, cons_bar,
-                 ws + AW_BCBAR * g.N, gamma_bar, p->gamma, 0};
+                 ws + AW_BCBAR * g.N, slots, p->gamma, 0};
   nb = tiles_for(PH_RK, g);
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_c2p_adj, dim3(nb), dim3(256), 0, s, g, cpa); }))) return rc;
-  return adj_epilogue(g, ws, A_bar, psi_bar, s);
+  if ((rc = adj_epilogue(g, ws, A_bar, psi_bar, s))) return rc;
+  return gslots_finish(slots, gamma_bar, s);
 }
 
 int asterx_c2p_adjoint(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* cons,
@@ -2603,14 +2630,17 @@ int asterx_c2p_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
   GD g = make_gd(gr);
   double* ws = (double*)workspace;
   uint8_t* flags = (uint8_t*)(ws + (size_t)AW_FIELDS * g.N);
+  double* slots = gamma_slots(g, ws);
   if ((rc = adj_prologue(g, p, metric, cons, prim_guess, A, ws, flags, s, true))) return rc;
+  if ((rc = gslots_zero(slots, s))) return rc;
   unsigned no = tiles_for(PH_RK, g);
   AccumArgs cp{prim_bar, ws + AW_PBAR * g.N, 5};
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_accum, dim3(no), dim3(256), 0, s, g, cp); }))) return rc;
   C2PAdjArgs cpa{metric, ws + AW_PRIM * g.N, ws + AW_BC * g.N, flags, ws + AW_PBAR * g.N, cons_bar,
-                 ws + AW_BCBAR * g.N, gamma_bar, p->gamma, 0};
+                 ws + AW_BCBAR * g.N, slots, p->gamma, 0};
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_c2p_adj, dim3(no), dim3(256), 0, s, g, cpa); }))) return rc;
-  return adj_epilogue(g, ws, A_bar, nullptr, s);
+  if ((rc = adj_epilogue(g, ws, A_bar, nullptr, s))) return rc;
+  return gslots_finish(slots, gamma_bar, s);
 }
 
 int asterx_prim2con_adjoint(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* A,
@@ -2623,14 +2653,17 @@ int asterx_prim2con_adjoint(const asterx_grid* gr, const asterx_params* p, const
   hipStream_t s = (hipStream_t)stream;
   GD g = make_gd(gr);
   double* ws = (double*)workspace;
+  double* slots = gamma_slots(g, ws);
   if ((rc = adj_prologue(g, p, metric, nullptr, nullptr, A, ws, nullptr, s, false))) return rc;
+  if ((rc = gslots_zero(slots, s))) return rc;
   unsigned no = tiles_for(PH_RK, g);
   AccumArgs cp{cons_bar, ws + AW_PBAR * g.N, 5};
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_accum, dim3(no), dim3(256), 0, s, g, cp); }))) return rc;
   C2PAdjArgs cpa{metric, prim, ws + AW_BC * g.N, nullptr, ws + AW_PBAR * g.N, prim_bar, ws + AW_BCBAR * g.N,
-                 gamma_bar, p->gamma, 1};
+                 slots, p->gamma, 1};
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_c2p_adj, dim3(no), dim3(256), 0, s, g, cpa); }))) return rc;
-  return adj_epilogue(g, ws, A_bar, nullptr, s);
+  if ((rc = adj_epilogue(g, ws, A_bar, nullptr, s))) return rc;
+  return gslots_finish(slots, gamma_bar, s);
 }
 
 }  // extern "C"
