@@ -265,3 +265,17 @@ def test_gpu_determinism_and_conservation(ax, torch_mod):
     D1 = math.fsum(L.owned(sa[0]).ravel())
     assert abs(D1 - D0) <= 1e-13 * abs(D0)
     assert _host(a.red)[1] <= 1e-12 * 16 * 10
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 1), (7, 5, 3)])
+def test_rhs_and_step_parity_tiny_ragged(ax, torch_mod, orc, shape):
+    """Degenerate and ragged periodic blocks (one cell; a single layer; sizes below one tile in every axis):
+    right-hand side within 1e-12 and one RK4 step within 1e-10 of the oracle."""
+    w = W.curved_block(seed=23, n=shape, recon="ppm", nsteps=1)
+    w.psi = w.layout.zeros(1) + 0.01 * np.random.default_rng(5).normal(size=(1,) + w.layout.shape3)
+    w.layout.periodic_wrap(w.psi)
+    print("case tiny/ragged", shape, flush=True)
+    g, c, red, red_ref = _rhs_case(ax, torch_mod, orc, w)
+    assert_fields_close(g, c, 1e-12, w.layout.owned, STATE_NAMES)
+    blk, state, prim, stats, red = _run_both(ax, torch_mod, orc, w, 1)
+    assert_fields_close(_host(blk.state), state, 1e-10, w.layout.owned, STATE_NAMES)
