@@ -19,8 +19,8 @@ def ax():
     return asterx
 
 
-def _patches(n=10, nsteps=2):
-    return W.patch_set(seed=3, npatches=n, sides=(16, 24), levels=3, nsteps=nsteps)
+def _patches(n=10, nsteps=2, recon="minmod"):
+    return W.patch_set(seed=3, npatches=n, sides=(16, 24), levels=3, nsteps=nsteps, recon=recon)
 
 
 def _per_patch(ax, wls, nsteps):
@@ -37,6 +37,22 @@ def test_batch_bitwise_equals_per_patch_loop(ax, tuning):
     wls = _patches()
     print("case batch vs loop", tuning, flush=True)
     bt = ax.Batch(wls, tuning=tuning)
+    bt.run(2)
+    blocks = _per_patch(ax, wls, 2)
+    torch.cuda.synchronize()
+    for p, b in enumerate(blocks):
+        assert torch.equal(bt.unpack(bt.state, p), b.state), p
+        assert torch.equal(bt.unpack(bt.prim, p), b.prim), p
+
+
+@pytest.mark.parametrize("recon", ["ppm", "wenoz"])
+def test_batch_bitwise_equals_per_patch_loop_recon(ax, recon):
+    """PPM and WENO-Z patches: the persistent face launches (including the LDS-staged stencils, whose
+    workgroups move from item to item) equal the per-patch loop bitwise."""
+    import torch
+    wls = _patches(n=8, recon=recon)
+    print("case batch vs loop", recon, flush=True)
+    bt = ax.Batch(wls, tuning=(1, 2))
     bt.run(2)
     blocks = _per_patch(ax, wls, 2)
     torch.cuda.synchronize()
