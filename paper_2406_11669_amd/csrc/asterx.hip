@@ -303,6 +303,49 @@ DEV double tile_value(TileLDS& S, const TileIdx& x) {
   return lag(p[0], p[1], p[2], p[3]);
 }
 
+// Two components per round (values only): the passes of both run between the same three
+// barriers, halving the barrier count of the value rounds.
+struct TileLDS2 {
+  double v[2][NV];
+  double z[2][NZP];
+  double y[2][NYP];
+};
+
+DEV void tile_store2(const TileIdx& x, const double pre[2][NFETCH], TileLDS2& S) {
+#pragma unroll
+  for (int r = 0; r < NFETCH; ++r)
+    if (x.fetch[r] != -1) {
+      S.v[0][threadIdx.x + 256 * r] = pre[0][r];
+      S.v[1][threadIdx.x + 256 * r] = pre[1][r];
+    }
+}
+
+DEV void tile_value2(TileLDS2& S, const TileIdx& x, double& v0, double& v1) {
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NZR; ++r)
+    if (x.zsrc[r] >= 0)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double* p = S.v[c] + x.zsrc[r];
+        S.z[c][threadIdx.x + 256 * r] = lag(p[0], p[VX * VY], p[2 * VX * VY], p[3 * VX * VY]);
+      }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NYR; ++r)
+    if (x.ysrc[r] >= 0)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double* p = S.z[c] + x.ysrc[r];
+        S.y[c][threadIdx.x + 256 * r] = lag(p[0], p[VX], p[2 * VX], p[3 * VX]);
+      }
+  __syncthreads();
+  const double* p = S.y[0] + x.xsrc;
+  v0 = lag(p[0], p[1], p[2], p[3]);
+  p = S.y[1] + x.xsrc;
+  v1 = lag(p[0], p[1], p[2], p[3]);
+}
+
 // Centre derivatives (d/dx, d/dy, d/dz, scaled) of the staged component.
 DEV void tile_derivs(TileLDS& S, const TileIdx& x, const GD& g, double d[3]) {
   __syncthreads();
@@ -380,14 +423,19 @@ DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S,
   unsigned long long* __restrict__ stats = a.stats;
   const TileCell t = tile_cell(g, tile);
   const TileIdx x = tile_index(g, t);
-  double m[10], pre[NFETCH];
-  tile_fetch(metric, x, pre);
+  double m[10], pre[2][NFETCH];
+  TileLDS2& S2 = *reinterpret_cast<TileLDS2*>(&S);
+  tile_fetch(metric, x, pre[0]);
+  tile_fetch(metric + g.N, x, pre[1]);
 #pragma unroll
-  for (int c = 0; c < 10; ++c) {
-    // the previous component's passes no longer read S.v (three barriers ago)
-    tile_store(x, pre, S.v);
-    if (c < 9) tile_fetch(metric + (c + 1) * g.N, x, pre);
-    m[c] = tile_value(S, x);
+  for (int c = 0; c < 10; c += 2) {
+    // the previous pair's passes no longer read S2.v (three barriers ago)
+    tile_store2(x, pre, S2);
+    if (c < 8) {
+      tile_fetch(metric + (c + 2) * g.N, x, pre[0]);
+      tile_fetch(metric + (c + 3) * g.N, x, pre[1]);
+    }
+    tile_value2(S2, x, m[c], m[c + 1]);
   }
   uint32_t fl = 0;
   int iters = 0;
@@ -839,18 +887,29 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
   auto comp = [&](int r) { return r < 10 ? ca.metric + r * g.N : (r < 16 ? ca.curv + (r - 10) * g.N : ca.metric + (r - 16) * g.N); };
   const TileIdx x = tile_index(g, t);
   double m[10], K[6], pre[NFETCH];
-  tile_fetch(comp(0), x, pre);
-  // rolled loops keep the register footprint of one round; values land by select chains
-  // (no dynamically indexed register arrays)
+  // value rounds two components at a time (one set of barriers per pair); rolled loops keep
+  // the register footprint of one round, values landing by select chains (no dynamically
+  // indexed register arrays)
+  {
+    TileLDS2& S2 = *reinterpret_cast<TileLDS2*>(&S);
+    double pp[2][NFETCH];
+    tile_fetch(comp(0), x, pp[0]);
+    tile_fetch(comp(1), x, pp[1]);
 #pragma unroll 1
-  for (int c = 0; c < 16; ++c) {
-    tile_store(x, pre, S.v);
-    tile_fetch(comp(c + 1), x, pre);
-    double v = tile_value(S, x);
+    for (int c = 0; c < 16; c += 2) {
+      tile_store2(x, pp, S2);
+      tile_fetch(comp(c + 2), x, pp[0]);
+      if (c < 14) tile_fetch(comp(c + 3), x, pp[1]);
+      double v0, v1;
+      tile_value2(S2, x, v0, v1);
 #pragma unroll
-    for (int q = 0; q < 10; ++q) m[q] = c == q ? v : m[q];
+      for (int q = 0; q < 10; ++q) m[q] = c == q ? v0 : (c + 1 == q ? v1 : m[q]);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) K[q] = c == 10 + q ? v : K[q];
+      for (int q = 0; q < 6; ++q) K[q] = c == 10 + q ? v0 : (c + 1 == 10 + q ? v1 : K[q]);
+    }
+    // comp(16) (the first derivative round's component) is already in pp[0]
+#pragma unroll
+    for (int r = 0; r < NFETCH; ++r) pre[r] = pp[0][r];
   }
   const int id = t.valid ? at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz) : 0;
   double w[10], wa[3], src[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, as = 0.0;
@@ -1101,17 +1160,23 @@ __global__ __launch_bounds__(256) void kb_prim2con(const PatchDesc* __restrict__
   }
 }
 
+// c2p stages two components per value round (TileLDS2); the learned guess reuses the buffer
+union C2PLDS {
+  TileLDS t;
+  TileLDS2 t2;
+};
+
 __global__ __launch_bounds__(256) void k_c2p(GD g, C2PParams cp, C2PArgs a) {
-  __shared__ TileLDS S;
-  c2p_body<false>(g, cp, a, S, my_tile());
+  __shared__ C2PLDS S;
+  c2p_body<false>(g, cp, a, S.t, my_tile());
 }
 __global__ __launch_bounds__(256) void k_c2p_learned(GD g, C2PParams cp, C2PArgs a) {
-  __shared__ TileLDS S;
-  c2p_body<true>(g, cp, a, S, my_tile());
+  __shared__ C2PLDS S;
+  c2p_body<true>(g, cp, a, S.t, my_tile());
 }
 __global__ __launch_bounds__(256) void kb_c2p(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                               C2PParams cp, C2PArgs a) {
-  __shared__ TileLDS S;
+  __shared__ C2PLDS S;
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item m = it[w];
     const PatchDesc d = P[m.patch];
@@ -1121,7 +1186,7 @@ __global__ __launch_bounds__(256) void kb_c2p(const PatchDesc* __restrict__ P, c
     b.cons = a.cons + d.off;
     b.prim = a.prim + d.off;
     b.flags = shifted(a.flags, d.off);
-    c2p_body<false>(d.g, cp, b, S, (unsigned)m.tile);
+    c2p_body<false>(d.g, cp, b, S.t, (unsigned)m.tile);
   }
 }
 
@@ -1170,12 +1235,12 @@ __global__ __launch_bounds__(256) void kb_face(const PatchDesc* __restrict__ P, 
 }
 
 __global__ __launch_bounds__(256) void k_cell(GD g, CellArgs ca) {
-  __shared__ TileLDS S;
-  cell_body(g, ca, S, my_tile());
+  __shared__ C2PLDS S;
+  cell_body(g, ca, S.t, my_tile());
 }
 __global__ __launch_bounds__(256) void kb_cell(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                                CellArgs ca) {
-  __shared__ TileLDS S;
+  __shared__ C2PLDS S;
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item m = it[w];
     const PatchDesc d = P[m.patch];
@@ -1187,7 +1252,7 @@ __global__ __launch_bounds__(256) void kb_cell(const PatchDesc* __restrict__ P, 
     b.bc = ca.bc + d.off;
     b.flux = ca.flux + d.off;
     b.rhs = ca.rhs + d.off;
-    cell_body(d.g, b, S, (unsigned)m.tile);
+    cell_body(d.g, b, S.t, (unsigned)m.tile);
   }
 }
 
