@@ -346,6 +346,66 @@ DEV void tile_value2(TileLDS2& S, const TileIdx& x, double& v0, double& v1) {
   v1 = lag(p[0], p[1], p[2], p[3]);
 }
 
+// Derivatives of two staged components per round (cell kernel): 2 x (value, d/dz) after the z
+// pass and 2 x (value, d/dy, d/dz-carry) after the y pass.
+// The y-pass output reuses the staged values' storage (dead after the z pass), so a round must not
+// store new values before every wave has finished the previous round's x pass.
+struct TileLDS2D {
+  union {
+    double v[2][NV];
+    double y[6][NYP];
+  };
+  double z[4][NZP];
+};
+static_assert(6 * NYP <= 2 * NV, "y-pass output must fit in the staged values' storage");
+
+DEV void tile_store2d(const TileIdx& x, const double pre[2][NFETCH], TileLDS2D& S) {
+#pragma unroll
+  for (int r = 0; r < NFETCH; ++r)
+    if (x.fetch[r] != -1) {
+      S.v[0][threadIdx.x + 256 * r] = pre[0][r];
+      S.v[1][threadIdx.x + 256 * r] = pre[1][r];
+    }
+}
+
+DEV void tile_derivs2(TileLDS2D& S, const TileIdx& x, const GD& g, double d0[3], double d1[3]) {
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NZR; ++r)
+    if (x.zsrc[r] >= 0)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double* p = S.v[c] + x.zsrc[r];
+        double a = p[0], b = p[VX * VY], cc = p[2 * VX * VY], e = p[3 * VX * VY];
+        S.z[2 * c][threadIdx.x + 256 * r] = lag(a, b, cc, e);
+        S.z[2 * c + 1][threadIdx.x + 256 * r] = dlag(a, b, cc, e);
+      }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NYR; ++r)
+    if (x.ysrc[r] >= 0)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double* p = S.z[2 * c] + x.ysrc[r];
+        const double* q = S.z[2 * c + 1] + x.ysrc[r];
+        double a = p[0], b = p[VX], cc = p[2 * VX], e = p[3 * VX];
+        S.y[3 * c][threadIdx.x + 256 * r] = lag(a, b, cc, e);
+        S.y[3 * c + 1][threadIdx.x + 256 * r] = dlag(a, b, cc, e);
+        S.y[3 * c + 2][threadIdx.x + 256 * r] = lag(q[0], q[VX], q[2 * VX], q[3 * VX]);
+      }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    double* d = c ? d1 : d0;
+    const double* p = S.y[3 * c] + x.xsrc;
+    const double* q = S.y[3 * c + 1] + x.xsrc;
+    const double* w = S.y[3 * c + 2] + x.xsrc;
+    d[0] = dlag(p[0], p[1], p[2], p[3]) * g.idx[0];
+    d[1] = lag(q[0], q[1], q[2], q[3]) * g.idx[1];
+    d[2] = lag(w[0], w[1], w[2], w[3]) * g.idx[2];
+  }
+}
+
 // Centre derivatives (d/dx, d/dy, d/dz, scaled) of the staged component.
 DEV void tile_derivs(TileLDS& S, const TileIdx& x, const GD& g, double d[3]) {
   __syncthreads();
@@ -970,20 +1030,38 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) wa[a] = -(T00 * G.beta[a] + T0[a]);
   }
-#pragma unroll 1
-  for (int c = 0; c < 10; ++c) {
-    tile_store(x, pre, S.v);
-    if (c < 9) tile_fetch(comp(17 + c), x, pre);
-    double d[3];
-    tile_derivs(S, x, g, d);
-    if (t.valid) {
-      double wc = w[0];
+  {
+    // derivative rounds, two components at a time
+    TileLDS2D& SD = *reinterpret_cast<TileLDS2D*>(&S);
+    double pp[2][NFETCH];
 #pragma unroll
-      for (int q = 1; q < 10; ++q) wc = c == q ? w[q] : wc;
-      src[1] += wc * d[0];
-      src[2] += wc * d[1];
-      src[3] += wc * d[2];
-      if (c == 0) src[4] += wa[0] * d[0] + wa[1] * d[1] + wa[2] * d[2];
+    for (int r = 0; r < NFETCH; ++r) pp[0][r] = pre[r];
+    tile_fetch(comp(17), x, pp[1]);
+#pragma unroll 1
+    for (int c = 0; c < 10; c += 2) {
+      __syncthreads();
+      tile_store2d(x, pp, SD);
+      if (c < 8) {
+        tile_fetch(comp(18 + c), x, pp[0]);
+        tile_fetch(comp(19 + c), x, pp[1]);
+      }
+      double d0[3], d1[3];
+      tile_derivs2(SD, x, g, d0, d1);
+      if (t.valid) {
+        double w0 = w[0], w1 = w[1];
+#pragma unroll
+        for (int q = 2; q < 10; ++q) {
+          w0 = c == q ? w[q] : w0;
+          w1 = c + 1 == q ? w[q] : w1;
+        }
+        src[1] += w0 * d0[0];
+        src[2] += w0 * d0[1];
+        src[3] += w0 * d0[2];
+        if (c == 0) src[4] += wa[0] * d0[0] + wa[1] * d0[1] + wa[2] * d0[2];
+        src[1] += w1 * d1[0];
+        src[2] += w1 * d1[1];
+        src[3] += w1 * d1[2];
+      }
     }
   }
   double divb = 0.0;
@@ -1165,6 +1243,12 @@ union C2PLDS {
   TileLDS t;
   TileLDS2 t2;
 };
+// the cell kernel's value and derivative rounds share one buffer
+union CellLDS {
+  TileLDS t;
+  TileLDS2 t2;
+  TileLDS2D t2d;
+};
 
 __global__ __launch_bounds__(256) void k_c2p(GD g, C2PParams cp, C2PArgs a) {
   __shared__ C2PLDS S;
@@ -1235,12 +1319,12 @@ __global__ __launch_bounds__(256) void kb_face(const PatchDesc* __restrict__ P, 
 }
 
 __global__ __launch_bounds__(256) void k_cell(GD g, CellArgs ca) {
-  __shared__ C2PLDS S;
+  __shared__ CellLDS S;
   cell_body(g, ca, S.t, my_tile());
 }
 __global__ __launch_bounds__(256) void kb_cell(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                                CellArgs ca) {
-  __shared__ C2PLDS S;
+  __shared__ CellLDS S;
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item m = it[w];
     const PatchDesc d = P[m.patch];
