@@ -94,6 +94,61 @@ DEV bool box_at(const int e[3], unsigned tile, unsigned tid, int& a, int& b, int
   return a < e[0] && b < e[1] && c < e[2];
 }
 
+// Linear decomposition of a 3-D box into tiles of 256 consecutive points (x fastest): for
+// per-point kernels over extents that are not multiples of a tile row (n + 2, n + 2 ng).
+DEV bool lin_at(const int e[3], unsigned tile, unsigned tid, int& a, int& b, int& c) {
+  const long long q = (long long)tile * 256 + tid;
+  a = (int)(q % e[0]);
+  const long long t = q / e[0];
+  b = (int)(t % e[1]);
+  c = (int)(t / e[1]);
+  return c < e[2];
+}
+inline unsigned lin_blocks(const int e[3]) { return (unsigned)(((long long)e[0] * e[1] * e[2] + 255) / 256); }
+
+// Face tiles.  Face grids are n + 1 wide (129 for n = 128), so 32-wide tile rows would leave
+// up to 31 of every 160 lanes idle.  In each z plane, the x range rounded down to a multiple
+// of 32 is tiled 32 x 4 (x, y); the remaining x columns (fewer than 32) follow in the same
+// plane, 128 faces per tile, x fastest.  Keeping them beside their plane's main tiles spreads
+// these slower, uncoalesced tiles evenly over the XCDs.  Rows narrower than 32 are tiled whole.
+struct FacePlan {
+  int e0m, r;           // main x range [0, e0m), remainder width r
+  unsigned nbx, nby;    // main tiles per plane: nbx x nby
+  unsigned pm, per;     // main tiles per plane, all tiles per plane
+};
+__host__ __device__ inline FacePlan face_plan(const int e[3]) {
+  FacePlan P;
+  P.e0m = e[0] >= 32 ? (e[0] & ~31) : e[0];
+  P.r = e[0] - P.e0m;
+  P.nbx = (unsigned)((P.e0m + 31) / 32);
+  P.nby = (unsigned)((e[1] + 3) / 4);
+  P.pm = P.nbx * P.nby;
+  P.per = P.pm + (unsigned)((P.r * e[1] + 127) / 128);
+  return P;
+}
+inline unsigned face_tiles(const int e[3]) { return face_plan(e).per * (unsigned)e[2]; }
+// Face f (0..127) of `tile`: position (a, b, c), whether the tile is a remainder tile (the
+// same for the whole workgroup), and a main tile's origin (ax0, by0) in its plane c.
+DEV bool face_at(const int e[3], unsigned tile, unsigned f, int& a, int& b, int& c, bool& rest, int& ax0,
+                 int& by0) {
+  const FacePlan P = face_plan(e);
+  const unsigned w = tile % P.per;
+  c = (int)(tile / P.per);
+  rest = w >= P.pm;
+  if (!rest) {
+    ax0 = (int)(w % P.nbx) * 32;
+    by0 = (int)(w / P.nbx) * 4;
+    a = ax0 + (int)(f % 32);
+    b = by0 + (int)(f / 32);
+    return a < P.e0m && b < e[1] && c < e[2];
+  }
+  ax0 = by0 = 0;
+  const int q = (int)(w - P.pm) * 128 + (int)f;
+  a = P.e0m + q % P.r;
+  b = q / P.r;
+  return b < e[1] && c < e[2];
+}
+
 // Logical tile of a one-tile-per-workgroup launch.
 DEV unsigned my_tile() { return xcd_block(blockIdx.x, gridDim.x); }
 
@@ -634,7 +689,7 @@ DEV void fill_body(const GD& g, const FillArgs& a, unsigned tile) {
 DEV void bcent_body(const GD& g, const double* __restrict__ A, double* __restrict__ bc, unsigned tile) {
   int e[3] = {g.n[0] + 2 * g.ng, g.n[1] + 2 * g.ng, g.n[2] + 2 * g.ng};
   int a, b, c;
-  if (!box_at<64, 4>(e, tile, threadIdx.x, a, b, c)) return;
+  if (!lin_at(e, tile, threadIdx.x, a, b, c)) return;
   int id = at(g, a - g.ng, b - g.ng, c - g.ng);
   double Bt[3];
   centre_B(A, g, id, Bt);
@@ -712,8 +767,12 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   const int side = threadIdx.x & 1;
   int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
   int a, b, c;
-  bool valid = box_at<32, 4>(e, tile, threadIdx.x >> 1, a, b, c);
-  // keep both lanes of a pair valid or invalid together (they share the face)
+  bool rest;
+  int ax0, by0;
+  // both lanes of a pair are valid or invalid together (they share the face); LDS staging
+  // assumes a 32 x 4 tile, so remainder tiles gather directly
+  const bool valid = face_at(e, tile, threadIdx.x >> 1, a, b, c, rest, ax0, by0);
+  const int cz = c;
   int ijk[3] = {a - 1, b - 1, c - 1};
   ijk[D] += 1;
   const int id = valid ? at(g, ijk[0], ijk[1], ijk[2]) : 0;
@@ -721,13 +780,41 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   const int sD = st[D];
   // reconstruction of this lane's side: left lane cells i-3..i+1, right lane i+2..i-2
   double X[7], C[7];
-  if constexpr (D == 1 && RECON == ASTERX_RECON_WENOZ) {
+  auto direct_recon = [&]() {
+    const int o0 = side ? 2 : -3, os = side ? -1 : 1;
+    if constexpr (RECON == ASTERX_RECON_WENOZ) {
+      // one variable at a time: the WENO-Z weights of seven variables interleaved would not
+      // fit the register file
+#pragma unroll 1
+      for (int v = 0; v < 7; ++v) {
+        const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
+        double s5[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
+        const double xv = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          X[k] = v == k ? xv : X[k];
+          C[k] = v == k ? s5[2] : C[k];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 7; ++v) {
+        const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
+        double s5[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
+        X[v] = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
+        C[v] = s5[2];
+      }
+    }
+  };
+  if (D == 1 && RECON == ASTERX_RECON_WENOZ && !rest) {
     // y faces under WENO-Z: the seven stencil fields of the workgroup's 32 x 4 faces (cells y
     // in [by0 - 3, by0 + 5], x in [ax0 - 1, ax0 + 30]) go through LDS once, coalesced along x
     // (measured faster for WENO-Z only; PPM and MINMOD keep the direct gather).  The leading
     // barrier keeps a persistent workgroup's previous item from being overwritten.
-    const unsigned nbx = (e[0] + 31) / 32, nby = (e[1] + 3) / 4;
-    const int ax0 = (int)(tile % nbx) * 32, by0 = (int)((tile / nbx) % nby) * 4, cz = (int)(tile / (nbx * nby));
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < (FACE_RN + 255) / 256; ++r) {
@@ -760,41 +847,14 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       }
     }
   } else if (valid) {
-    const int o0 = side ? 2 : -3, os = side ? -1 : 1;
-    if constexpr (RECON == ASTERX_RECON_WENOZ) {
-      // one variable at a time: the WENO-Z weights of seven variables interleaved would not
-      // fit the register file
-#pragma unroll 1
-      for (int v = 0; v < 7; ++v) {
-        const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
-        double s5[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
-        const double xv = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
-#pragma unroll
-        for (int k = 0; k < 7; ++k) {
-          X[k] = v == k ? xv : X[k];
-          C[k] = v == k ? s5[2] : C[k];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < 7; ++v) {
-        const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
-        double s5[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
-        X[v] = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
-        C[v] = s5[2];
-      }
-    }
+    direct_recon();
   }
   double m[10];
-  if constexpr (D == 1 || (D == 2 && RECON != ASTERX_RECON_WENOZ)) {
-    // y and z faces: the direct 16-point gather (one transverse direction is x, so a
-    // wavefront's loads are contiguous rows) measured faster than the staged block, except
-    // for z faces under WENO-Z
-    (void)L;
+  // y and z faces: the direct 16-point gather (one transverse direction is x, so a
+  // wavefront's loads are contiguous rows) measured faster than the staged block, except
+  // for z faces under WENO-Z
+  constexpr bool METRIC_LDS = !(D == 1 || (D == 2 && RECON != ASTERX_RECON_WENOZ));
+  if (!METRIC_LDS || rest) {
     if (valid) {
       const int s1 = st[t1], s2 = st[t2];
       const int mb = id - s1 - s2;
@@ -818,8 +878,6 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       }
     }
   } else {
-    const unsigned nbx = (e[0] + 31) / 32, nby = (e[1] + 3) / 4;
-    const int ax0 = (int)(tile % nbx) * 32, by0 = (int)((tile / nbx) % nby) * 4, cz = (int)(tile / (nbx * nby));
     const int X0 = D == 0 ? ax0 : ax0 - 2, Y0 = D == 1 ? by0 : by0 - 2, Z0 = D == 2 ? cz : cz - 2;
     int foff[FB::NR];
     double pre[FB::NR];
@@ -1113,7 +1171,7 @@ DEV void vertex_body(const GD& g, const VertexArgs& va, unsigned tile) {
   double* __restrict__ fp = va.fp;
   int e[3] = {g.n[0] + 2, g.n[1] + 2, g.n[2] + 2};
   int a, b, c;
-  if (!box_at<64, 4>(e, tile, threadIdx.x, a, b, c)) return;
+  if (!lin_at(e, tile, threadIdx.x, a, b, c)) return;
   const int id = at(g, a - 1, b - 1, c - 1);
   double m[10];
 #pragma unroll
@@ -1516,7 +1574,9 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
   const int side = threadIdx.x & 1;
   int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
   int a, b, c;
-  bool valid = box_at<32, 4>(e, tile, threadIdx.x >> 1, a, b, c);
+  bool rest;
+  int ax0, by0;
+  bool valid = face_at(e, tile, threadIdx.x >> 1, a, b, c, rest, ax0, by0);
   double gsum = 0.0;
   if (valid) {
     int ijk[3] = {a - 1, b - 1, c - 1};
@@ -2218,13 +2278,13 @@ unsigned tiles_for(int phase, const GD& g) {
     }
     case PH_BCENT:
       for (int a = 0; a < 3; ++a) e[a] = g.n[a] + 2 * g.ng;
-      return box_blocks<64, 4>(e);
+      return lin_blocks(e);
     case PH_FACE:
       for (int a = 0; a < 3; ++a) e[a] = g.n[a] + 1;
-      return box_blocks<32, 4>(e);
+      return face_tiles(e);
     case PH_VERTEX:
       for (int a = 0; a < 3; ++a) e[a] = g.n[a] + 2;
-      return box_blocks<64, 4>(e);
+      return lin_blocks(e);
     default:
       return box_blocks<64, 4>(g.n);
   }
@@ -2780,8 +2840,10 @@ int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
   if ((rc = adj_prologue(g, p, metric, cons, prim_guess, A, ws, flags, s, true))) return rc;
   if ((rc = gslots_zero(slots, s))) return rc;
   unsigned nb;
+  // fluxbar and vertex_adj tile the (n + 2)^3 vertex box 64 x 4
+  int ev[3] = {g.n[0] + 2, g.n[1] + 2, g.n[2] + 2};
   FluxBarArgs fb{rhs_bar, ws + AW_FBAR * g.N};
-  nb = tiles_for(PH_VERTEX, g);
+  nb = box_blocks<64, 4>(ev);
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_fluxbar, dim3(nb), dim3(256), 0, s, g, fb); }))) return rc;
   FaceAdjArgs fa{metric, ws + AW_PRIM * g.N, A, ws + AW_BC * g.N, ws + AW_FBAR * g.N, ws + AW_PBAR * g.N,
                  ws + AW_BCBAR * g.N, ws + AW_BFBAR * g.N, slots, p->gamma, p->weno_eps, p->weno_q, p->speeds};
@@ -2794,7 +2856,7 @@ int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
   nb = tiles_for(PH_RK, g);
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_cell_adj, dim3(nb), dim3(256), 0, s, g, ca); }))) return rc;
   VertexAdjArgs va{metric, rhs_bar, ws + AW_PSIBAR * g.N, ws + AW_AVBAR * g.N, p->xi / dt_max, p->gauge};
-  nb = tiles_for(PH_VERTEX, g);
+  nb = box_blocks<64, 4>(ev);
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_vertex_adj, dim3(nb), dim3(256), 0, s, g, va); }))) return rc;
   int ee[3] = {g.n[0] + 3, g.n[1] + 3, g.n[2] + 3};
   nb = box_blocks<64, 4>(ee);
