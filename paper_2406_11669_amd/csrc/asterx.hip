@@ -799,14 +799,18 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
         }
       }
     } else {
+      // all 35 stencil values are loaded before the first reconstruction
+      double s5[7][5];
 #pragma unroll
       for (int v = 0; v < 7; ++v) {
         const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
-        double s5[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
-        X[v] = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
-        C[v] = s5[2];
+        for (int q = 0; q < 5; ++q) s5[v][q] = f[id + (o0 + os * q) * sD];
+      }
+#pragma unroll
+      for (int v = 0; v < 7; ++v) {
+        X[v] = recon_right_face<RECON>(s5[v], fa.weno_eps, fa.weno_q);
+        C[v] = s5[v][2];
       }
     }
   };

@@ -318,30 +318,28 @@ DEV T mm(T x, T y) {
 // Monotonized-central slope of PPM (Colella-Woodward).
 template <class T>
 DEV T mc_slope(T am, T a0, T ap) {
+  // both outcomes evaluated and selected: no branch, so a face kernel's stencil loads can all
+  // be in flight before the first limiter runs
   T dl = a0 - am, dr = ap - a0;
-  if (val(dl) * val(dr) > 0.0) {
-    T dc = 0.5 * (ap - am);
-    return copysign(fmin(fabs(dc), 2.0 * fmin(fabs(dl), fabs(dr))), dc);
-  }
-  return T(0.0 * val(dl));
+  T dc = 0.5 * (ap - am);
+  T lim = copysign(fmin(fabs(dc), 2.0 * fmin(fabs(dl), fabs(dr))), dc);
+  return val(dl) * val(dr) > 0.0 ? lim : T(0.0 * val(dl));
 }
 
 // PPM cell parabola limited per Colella-Woodward; returns (left, right) face values of
 // the cell with neighbour face values fl (c-1/2) and fr (c+1/2).
 template <class T>
 DEV void ppm_limit(T ac, T& fl, T& fr) {
-  if (val(fr - ac) * val(ac - fl) <= 0.0) {
-    fl = ac;
-    fr = ac;
-    return;
-  }
+  // branch-free form of: local extremum -> flat; else steepen the side the parabola overshoots
+  const bool flat = val(fr - ac) * val(ac - fl) <= 0.0;
   T dd = fr - fl;
   T a6 = dd * (ac - 0.5 * (fl + fr));
   T d2 = dd * dd * (1.0 / 6.0);
-  if (a6 > d2)
-    fl = 3.0 * ac - 2.0 * fr;
-  else if (-d2 > a6)
-    fr = 3.0 * ac - 2.0 * fl;
+  const bool over_l = a6 > d2;
+  const bool over_r = !over_l && -d2 > a6;
+  T nl = 3.0 * ac - 2.0 * fr, nr = 3.0 * ac - 2.0 * fl;
+  fl = flat ? ac : (over_l ? nl : fl);
+  fr = flat ? ac : (over_r ? nr : fr);
 }
 
 // WENO-Z (Borges et al. 2008) value at the right face of the middle cell of (m2..p2).
