@@ -782,9 +782,32 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   double X[7], C[7];
   auto direct_recon = [&]() {
     const int o0 = side ? 2 : -3, os = side ? -1 : 1;
-    if constexpr (RECON == ASTERX_RECON_WENOZ) {
-      // one variable at a time: the WENO-Z weights of seven variables interleaved would not
-      // fit the register file
+    if constexpr (RECON == ASTERX_RECON_WENOZ && D == 2) {
+      // one variable at a time (the WENO-Z weights of seven variables interleaved would not
+      // fit the register file), the next variable's stencil loading meanwhile (z faces: their
+      // stencil rows are a plane apart; x faces measured faster without the extra registers)
+      auto field = [&](int v) { return v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N; };
+      double nx[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) nx[q] = field(0)[id + (o0 + os * q) * sD];
+#pragma unroll 1
+      for (int v = 0; v < 7; ++v) {
+        double s5[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s5[q] = nx[q];
+        if (v < 6) {
+          const double* f = field(v + 1);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) nx[q] = f[id + (o0 + os * q) * sD];
+        }
+        const double xv = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          X[k] = v == k ? xv : X[k];
+          C[k] = v == k ? s5[2] : C[k];
+        }
+      }
+    } else if constexpr (RECON == ASTERX_RECON_WENOZ) {
 #pragma unroll 1
       for (int v = 0; v < 7; ++v) {
         const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
