@@ -326,9 +326,13 @@ DEV TileIdx tile_index(const GD& g, const TileCell& t) {
   return x;
 }
 
+// Points a tile does not need (fetch < 0) load the component's first element instead: the
+// loads stay unconditional (a load under a branch is joined by a copy that waits for it, which
+// would stall the interpolation pass it was meant to overlap), and such points only feed
+// cells outside the block, whose results are discarded.
 DEV void tile_fetch(const double* __restrict__ f, const TileIdx& x, double pre[NFETCH]) {
 #pragma unroll
-  for (int r = 0; r < NFETCH; ++r) pre[r] = x.fetch[r] >= 0 ? f[x.fetch[r]] : 0.0;
+  for (int r = 0; r < NFETCH; ++r) pre[r] = f[x.fetch[r] >= 0 ? x.fetch[r] : 0];
 }
 
 DEV void tile_store(const TileIdx& x, const double pre[NFETCH], double* sv) {
@@ -1403,7 +1407,7 @@ __global__ __launch_bounds__(256) void kb_face(const PatchDesc* __restrict__ P, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_cell(GD g, CellArgs ca) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cell(GD g, CellArgs ca) {
   __shared__ CellLDS S;
   cell_body(g, ca, S.t, my_tile());
 }
