@@ -136,11 +136,35 @@ int asterx_rhs(const asterx_grid* g, const asterx_params* p, const double* metri
                const double* prim, const double* A, const double* psi, double dt_max, double* rhs, double* red,
                void* workspace, size_t ws_bytes, void* stream);
 
-/* Runge-Kutta stage combine on owned points of the 9 state fields:
+/* Runge-Kutta stage combine on owned points of the 9 state fields (the RK4 and RK2 time
+ * integrators of the tests and benchmarks, Sec. 4 and 5):
  * out = sum_m a[m] u[m] + b_dt rhs.  a: host double[nterms]; u: host array of nterms
  * device pointers (each a 9-field state); 1 <= nterms <= 4; out may alias any u[m]. */
 int asterx_rk_stage(const asterx_grid* g, int32_t nterms, const double* a, const double* const* u, double b_dt,
                     const double* rhs, double* out, void* stream);
+
+/* One Runge-Kutta stage output of asterx_rhs_rk: out = sum_m a[m] u[m] + b_dt rhs on owned
+ * points of the 9 state fields, rhs being the right-hand side the call evaluates.  u: nterms
+ * (1 or 2) device 9-field states; out: device 9-field state. */
+typedef struct {
+  int32_t nterms;
+  double a[2];
+  const double* u[2];
+  double b_dt;
+  double* out;
+} asterx_rk_out;
+
+/* asterx_rhs followed by asterx_rk_stage for each of nout (1 or 2) outputs, without storing
+ * the right-hand side: the cell and edge kernels combine each point's value into the outputs
+ * as they produce it (the Runge-Kutta stage update of Sec. 4 and 5), with the same
+ * arithmetic as asterx_rk_stage, so the results agree bit for bit.  outs: host
+ * asterx_rk_out[nout].  An output may be one of its own states u[m] (updated in place) but
+ * must not overlap the other output or the states it reads, nor metric, curv, prim, A, psi
+ * or the workspace: the state whose right-hand side is evaluated is read by neighbouring
+ * points while outputs are written (ASTERX_EARG otherwise).  Other arguments as asterx_rhs. */
+int asterx_rhs_rk(const asterx_grid* g, const asterx_params* p, const double* metric, const double* curv,
+                  const double* prim, const double* A, const double* psi, double dt_max, int32_t nout,
+                  const asterx_rk_out* outs, double* red, void* workspace, size_t ws_bytes, void* stream);
 
 /* Sets red[0..1] to 0 (device double[2]); a kernel, not a memset, so that it can be
  * recorded in a captured graph. */
@@ -183,6 +207,9 @@ int asterx_batch_rhs(const asterx_batch* b, const asterx_params* p, const double
                      void* workspace, size_t ws_bytes, void* stream);
 int asterx_batch_rk_stage(const asterx_batch* b, int32_t nterms, const double* a, const double* const* u,
                           double b_dt, const double* rhs, double* out, void* stream);
+int asterx_batch_rhs_rk(const asterx_batch* b, const asterx_params* p, const double* metric, const double* curv,
+                        const double* prim, const double* A, const double* psi, double dt_max, int32_t nout,
+                        const asterx_rk_out* outs, double* red, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---- Adjoint (reverse mode) ---------------------------------------------------------------
  * Vector-Jacobian products for differentiating whole RK steps with respect to the state and

@@ -48,6 +48,28 @@ class Params(ctypes.Structure):
                 ("gauge", ctypes.c_int32), ("speeds", ctypes.c_int32), ("c2p_method", ctypes.c_int32)]
 
 
+class RKOut(ctypes.Structure):
+    """asterx_rk_out: out = sum_m a[m] u[m] + b_dt rhs (nterms = 1 or 2)."""
+    _fields_ = [("nterms", ctypes.c_int32), ("a", ctypes.c_double * 2), ("u", ctypes.c_void_p * 2),
+                ("b_dt", ctypes.c_double), ("out", ctypes.c_void_p)]
+
+
+def make_rk_outs(outs):
+    """outs: [(a list, u list of tensors, b_dt, out tensor)] -> host asterx_rk_out array."""
+    arr = (RKOut * len(outs))()
+    for k, (a, us, b_dt, out) in enumerate(outs):
+        assert 1 <= len(a) == len(us) <= 2
+        for u in list(us) + [out]:
+            assert u.is_cuda and u.is_contiguous() and u.dtype == torch.float64
+        arr[k].nterms = len(a)
+        for m in range(len(a)):
+            arr[k].a[m] = float(a[m])
+            arr[k].u[m] = us[m].data_ptr()
+        arr[k].b_dt = float(b_dt)
+        arr[k].out = out.data_ptr()
+    return arr
+
+
 _lib = None
 
 EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "asterx_prim2con", "asterx_c2p",
@@ -58,7 +80,7 @@ EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "
            "asterx_batch_rk_stage", "asterx_adjoint_workspace_size", "asterx_rhs_adjoint", "asterx_c2p_adjoint",
            "asterx_prim2con_adjoint", "asterx_prim2con_points", "asterx_mlp_features", "asterx_mlp_forward",
            "asterx_mlp_grad_workspace_size", "asterx_mlp_grad", "asterx_mlp_adam", "asterx_c2p_points",
-           "asterx_c2p_learned"]
+           "asterx_c2p_learned", "asterx_rhs_rk", "asterx_batch_rhs_rk"]
 
 
 def lib():
@@ -79,6 +101,10 @@ def lib():
         L.asterx_fill_ghosts_shift.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
         L.asterx_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
         L.asterx_rk_stage.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
+        L.asterx_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
+                                    ctypes.c_size_t, vp]
+        L.asterx_batch_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
+                                          ctypes.c_size_t, vp]
         L.asterx_zero.argtypes = [vp, ctypes.c_int64, vp]
         L.asterx_timing_enable.argtypes = [ctypes.c_int32]
         L.asterx_timing_read.argtypes = [vp, vp, ctypes.c_int32]
@@ -218,6 +244,15 @@ def rk_stage(layout, a, us, b_dt, rhs_t, out, stream=None):
                                  _ptr(_f64(out)), _stream(stream)))
 
 
+def rhs_rk(layout, params, metric, curv, prim, A, psi, dt_max, outs, red, workspace, stream=None):
+    """Right-hand side combined straight into RK stage outputs (asterx_rhs_rk); outs as make_rk_outs."""
+    arr = make_rk_outs(outs)
+    _check(lib().asterx_rhs_rk(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                               _ptr(_f64(metric)), _ptr(_f64(curv)), _ptr(_f64(prim)), _ptr(_f64(A)),
+                               _ptr(_f64(psi)), float(dt_max), len(outs), arr, _ptr(red), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def adjoint_workspace_size(layout):
     return lib().asterx_adjoint_workspace_size(ctypes.byref(make_grid(layout)))
 
@@ -346,9 +381,13 @@ class Block:
 
     Per stage: c2p (resets atmosphere cells of the stage input in place) -> ghost fill of
     the primitives -> right-hand side -> RK combine -> ghost fill of the new state.
-    RK2 is Heun's method, RK4 the classical scheme (accumulator form)."""
+    RK2 is Heun's method, RK4 the classical scheme (accumulator form).  With fused=True (the
+    default) the right-hand side goes straight into the stage outputs (asterx_rhs_rk; RK4
+    alternates two stage buffers so that no output is the state being evaluated); fused=False
+    stores it and combines with asterx_rk_stage.  Both give bitwise equal states."""
 
-    def __init__(self, wl, device="cuda"):
+    def __init__(self, wl, device="cuda", fused=True):
+        self.fused = fused
         self.wl = wl
         self.L = wl.layout
         self.params = wl.params
@@ -364,6 +403,7 @@ class Block:
         self.tmp = torch.zeros_like(self.state)
         self.acc = torch.zeros_like(self.state)
         self.k = torch.zeros_like(self.state)
+        self.tmp2 = torch.zeros_like(self.state) if fused and wl.rk == 4 else None
         self.ws = torch.empty(workspace_size(self.L) // 8, dtype=torch.float64, device=dev)
         self.red = torch.zeros(2, dtype=torch.float64, device=dev)
         self.stats = torch.zeros(6, dtype=torch.int64, device=dev)
@@ -384,14 +424,50 @@ class Block:
             fill_ghosts(self.L, U[5:8], self.wl.bc_A)
         fill_ghosts(self.L, U[8:9], self.wl.bc_cell)
 
-    def eval_rhs(self, U, out):
-        """c2p on U (in place for atmosphere cells), primitive ghosts, right-hand side into out."""
+    def recover(self, U):
+        """c2p on U (in place for atmosphere cells) and the primitives' ghosts."""
         c2p(self.L, self.params, self.metric, U[5:8], U[0:5], self.prim, self.flags, self.stats, mlp=self.mlp)
         fill_ghosts(self.L, self.prim, self.wl.bc_cell)
+
+    def eval_rhs(self, U, out):
+        """c2p on U (in place for atmosphere cells), primitive ghosts, right-hand side into out."""
+        self.recover(U)
         rhs(self.L, self.params, self.metric, self.curv, self.prim, U[5:8], U[8:9], self.dt, out, self.red,
             self.ws)
 
+    def stage(self, U, outs):
+        """c2p on U, then its right-hand side combined into outs = [(a, us, b_dt, out)]."""
+        self.recover(U)
+        rhs_rk(self.L, self.params, self.metric, self.curv, self.prim, U[5:8], U[8:9], self.dt, outs, self.red,
+               self.ws)
+
     def step(self):
+        if self.fused:
+            self._step_fused()
+        else:
+            self._step_stored()
+
+    def _step_fused(self):
+        dt = self.dt
+        U0 = self.state
+        if self.wl.rk == 2:
+            U1 = self.tmp
+            self.stage(U0, [([1.0], [U0], dt, U1)])
+            self.fill_state(U1)
+            self.stage(U1, [([0.5, 0.5], [U0, U1], 0.5 * dt, U0)])
+            self.fill_state(U0)
+        else:
+            Ua, Ub, acc = self.tmp, self.tmp2, self.acc
+            self.stage(U0, [([1.0], [U0], dt / 6.0, acc), ([1.0], [U0], 0.5 * dt, Ua)])
+            self.fill_state(Ua)
+            self.stage(Ua, [([1.0], [acc], dt / 3.0, acc), ([1.0], [U0], 0.5 * dt, Ub)])
+            self.fill_state(Ub)
+            self.stage(Ub, [([1.0], [acc], dt / 3.0, acc), ([1.0], [U0], dt, Ua)])
+            self.fill_state(Ua)
+            self.stage(Ua, [([1.0], [acc], dt / 6.0, U0)])
+            self.fill_state(U0)
+
+    def _step_stored(self):
         dt = self.dt
         U0, K = self.state, self.k
         if self.wl.rk == 2:
@@ -437,7 +513,8 @@ class Batch:
     Arrays are field-major pools of shape (nfields, points) with points = sum of the patches' padded
     sizes; patch p's field f is the slice [f, off[p] : off[p] + npts_p], laid out like a single block."""
 
-    def __init__(self, workloads, tuning=(4, 1), device="cuda"):
+    def __init__(self, workloads, tuning=(4, 1), device="cuda", fused=True):
+        self.fused = fused
         self.wls = list(workloads)
         n = len(self.wls)
         grids = (Grid * n)(*[make_grid(w.layout) for w in self.wls])
@@ -504,16 +581,35 @@ class Batch:
         arr_u = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
         self._call("asterx_batch_rk_stage", n, arr_a, arr_u, float(b_dt), _ptr(rhs_t), _ptr(out), _stream(None))
 
-    def eval_rhs(self, U, out):
+    def recover(self, U):
         self._call("asterx_batch_c2p", self._P(), _ptr(self.metric), _ptr(U[5:8]), _ptr(U[0:5]), _ptr(self.prim),
                    _ptr(self.flags), _ptr(self.stats), _stream(None))
         self.fill(self.prim, self.bc_cell)
+
+    def eval_rhs(self, U, out):
+        self.recover(U)
         self._call("asterx_batch_rhs", self._P(), _ptr(self.metric), _ptr(self.curv), _ptr(self.prim), _ptr(U[5:8]),
                    _ptr(U[8:9]), float(self.dt), _ptr(out), _ptr(self.red), _ptr(self.ws),
                    self.ws.numel() * 8, _stream(None))
 
+    def stage(self, U, outs):
+        self.recover(U)
+        arr = make_rk_outs(outs)
+        self._call("asterx_batch_rhs_rk", self._P(), _ptr(self.metric), _ptr(self.curv), _ptr(self.prim),
+                   _ptr(U[5:8]), _ptr(U[8:9]), float(self.dt), len(outs), arr, _ptr(self.red), _ptr(self.ws),
+                   self.ws.numel() * 8, _stream(None))
+
     def step(self):
-        """One Heun (RK2) step of every patch."""
+        """One Heun (RK2) step of every patch (right-hand sides combined straight into the stage outputs)."""
+        if not self.fused:
+            return self._step_stored()
+        U0, U1, dt = self.state, self.tmp, self.dt
+        self.stage(U0, [([1.0], [U0], dt, U1)])
+        self.fill_state(U1)
+        self.stage(U1, [([0.5, 0.5], [U0, U1], 0.5 * dt, U0)])
+        self.fill_state(U0)
+
+    def _step_stored(self):
         U0, U1, K, dt = self.state, self.tmp, self.k, self.dt
         self.eval_rhs(U0, K)
         self.rk([1.0], [U0], dt, K, U1)

@@ -1012,6 +1012,40 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
 
 // ---------------------------------------------------------------------------------------
 // Cells: flux divergence (eq. fluxconseqs) + geometric sources (eq. grmhdsrc) + div B.
+// Runge-Kutta stage outputs written in place of the right-hand side: per owned point,
+// out = b_dt rhs + sum_m a[m] u[m], with the products and sums in the order of the
+// stage-combine kernel (so the two paths agree bit for bit).
+struct RKOut {
+  const double* u[2];
+  double a[2];
+  double b_dt;
+  double* out;
+  int nterms;
+};
+struct Combine {
+  RKOut o[2];
+  int nout;  // 0: the right-hand side itself is stored
+};
+
+template <int MAXT>
+DEV double rk_point(double b_dt, double r, const double* const* u, const double* a, int nterms, size_t o) {
+  double s = b_dt * r;
+#pragma unroll
+  for (int m = 0; m < MAXT; ++m)
+    if (m < nterms) s = fma(a[m], u[m][o], s);
+  return s;
+}
+
+DEV void emit(const Combine& cb, double* rhs, size_t o, double v) {
+  if (cb.nout == 0) {
+    rhs[o] = v;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (k < cb.nout) cb.o[k].out[o] = rk_point<2>(cb.o[k].b_dt, v, cb.o[k].u, cb.o[k].a, cb.o[k].nterms, o);
+}
+
 struct CellArgs {
   const double* metric;
   const double* curv;
@@ -1022,6 +1056,7 @@ struct CellArgs {
   double* rhs;
   double* red;
   double gam;
+  Combine cmb;
 };
 
 // Tiled cell kernel.  Pass 1 interpolates the values of the 10 metric and 6 curvature
@@ -1164,7 +1199,7 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
         const double* F = ca.flux + (size_t)(d * 7 + c) * g.N;
         sdiv += (F[id + st[d]] - F[id]) * g.idx[d];
       }
-      ca.rhs[c * g.N + id] = as * src[c] - sdiv;
+      emit(ca.cmb, ca.rhs, (size_t)c * g.N + id, as * src[c] - sdiv);
     }
     if (ca.red) {
       const double* Ax = ca.A;
@@ -1232,6 +1267,7 @@ struct EdgeArgs {
   double* rhs;
   double xi;
   int gauge;
+  Combine cmb;
 };
 
 DEV void edge_body(const GD& g, const EdgeArgs& ea, unsigned tile) {
@@ -1249,22 +1285,23 @@ DEV void edge_body(const GD& g, const EdgeArgs& ea, unsigned tile) {
   double Ex = 0.25 * (-Fy_Bz[id] - Fy_Bz[id - sz] + Fz_By[id] + Fz_By[id - sy]);
   double Ey = 0.25 * (-Fz_Bx[id] - Fz_Bx[id - 1] + Fx_Bz[id] + Fx_Bz[id - sz]);
   double* r = ea.rhs;
+  const size_t N = g.N;
   if (ea.gauge == ASTERX_GAUGE_LORENZ) {
     double G0 = ea.ga[id];
-    r[5 * g.N + id] = -Ex - (ea.ga[id + 1] - G0) * g.idx[0];
-    r[6 * g.N + id] = -Ey - (ea.ga[id + sy] - G0) * g.idx[1];
-    r[7 * g.N + id] = -Ez - (ea.ga[id + sz] - G0) * g.idx[2];
     const double* f0 = ea.fp;
     const double* f1 = ea.fp + g.N;
     const double* f2 = ea.fp + 2 * g.N;
     double div = (f0[id + 1] - f0[id - 1]) * (0.5 * g.idx[0]) + (f1[id + sy] - f1[id - sy]) * (0.5 * g.idx[1]) +
                  (f2[id + sz] - f2[id - sz]) * (0.5 * g.idx[2]);
-    r[8 * g.N + id] = -div - ea.xi * ea.metric[id] * ea.psi[id];
+    emit(ea.cmb, r, 5 * N + id, -Ex - (ea.ga[id + 1] - G0) * g.idx[0]);
+    emit(ea.cmb, r, 6 * N + id, -Ey - (ea.ga[id + sy] - G0) * g.idx[1]);
+    emit(ea.cmb, r, 7 * N + id, -Ez - (ea.ga[id + sz] - G0) * g.idx[2]);
+    emit(ea.cmb, r, 8 * N + id, -div - ea.xi * ea.metric[id] * ea.psi[id]);
   } else {
-    r[5 * g.N + id] = -Ex;
-    r[6 * g.N + id] = -Ey;
-    r[7 * g.N + id] = -Ez;
-    r[8 * g.N + id] = 0.0;
+    emit(ea.cmb, r, 5 * N + id, -Ex);
+    emit(ea.cmb, r, 6 * N + id, -Ey);
+    emit(ea.cmb, r, 7 * N + id, -Ez);
+    emit(ea.cmb, r, 8 * N + id, 0.0);
   }
 }
 
@@ -1286,11 +1323,7 @@ DEV void rk_body(const GD& g, const RKArgs& ra, unsigned tile) {
 #pragma unroll
   for (int f = 0; f < 9; ++f) {
     size_t o = (size_t)f * g.N + id;
-    double s = ra.b_dt * ra.rhs[o];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      if (m < ra.nterms) s += ra.a[m] * ra.u[m][o];
-    ra.out[o] = s;
+    ra.out[o] = rk_point<4>(ra.b_dt, ra.rhs[o], ra.u, ra.a, ra.nterms, o);
   }
 }
 
@@ -1311,6 +1344,16 @@ struct Item {
 template <class T>
 DEV T* shifted(T* p, long long off) {
   return p ? p + off : p;
+}
+DEV Combine shifted(const Combine& c, long long off) {
+  Combine r = c;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    r.o[k].out = shifted(c.o[k].out, off);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) r.o[k].u[m] = shifted(c.o[k].u[m], off);
+  }
+  return r;
 }
 
 __global__ __launch_bounds__(256) void k_prim2con(GD g, double gam, const double* metric, const double* A,
@@ -1424,7 +1467,8 @@ __global__ __launch_bounds__(256) void kb_cell(const PatchDesc* __restrict__ P, 
     b.A = ca.A + d.off;
     b.bc = ca.bc + d.off;
     b.flux = ca.flux + d.off;
-    b.rhs = ca.rhs + d.off;
+    b.rhs = shifted(ca.rhs, d.off);
+    b.cmb = shifted(ca.cmb, d.off);
     cell_body(d.g, b, S.t, (unsigned)m.tile);
   }
 }
@@ -1452,7 +1496,8 @@ __global__ __launch_bounds__(256) void kb_edge(const PatchDesc* __restrict__ P, 
     b.flux = ea.flux + d.off;
     b.ga = ea.ga + d.off;
     b.fp = ea.fp + d.off;
-    b.rhs = ea.rhs + d.off;
+    b.rhs = shifted(ea.rhs, d.off);
+    b.cmb = shifted(ea.cmb, d.off);
     edge_body(d.g, b, (unsigned)m.tile);
   }
 }
@@ -2408,7 +2453,7 @@ int do_bcent(const GD& g, const double* A, double* bc, hipStream_t s) {
 
 int do_rhs(const GD& g, const asterx_batch* b, const asterx_params* p, const double* metric, const double* curv,
            const double* prim, const double* A, const double* psi, double dt_max, double* rhs, double* red,
-           double* ws, hipStream_t s) {
+           double* ws, hipStream_t s, const Combine& cmb = Combine{}) {
   int rc;
   double* bc = ws;
   double* flux = ws + 3 * g.N;
@@ -2418,14 +2463,57 @@ int do_rhs(const GD& g, const asterx_batch* b, const asterx_params* p, const dou
   FaceArgs fa{metric, prim, A, bc, flux, red, p->gamma, p->weno_eps, p->weno_q, p->gamma / (p->gamma - 1.0),
               p->recon, p->speeds};
   if ((rc = faces(g, b, fa, p->recon, s))) return rc;
-  CellArgs ca{metric, curv, prim, A, bc, flux, rhs, red, p->gamma};
+  CellArgs ca{metric, curv, prim, A, bc, flux, rhs, red, p->gamma, cmb};
   if ((rc = RUN_PHASE(KT_CELL, PH_CELL, k_cell, kb_cell, ca))) return rc;
   if (p->gauge == ASTERX_GAUGE_LORENZ) {
     VertexArgs va{metric, A, psi, ga, fp};
     if ((rc = RUN_PHASE(KT_VERTEX, PH_VERTEX, k_vertex, kb_vertex, va))) return rc;
   }
-  EdgeArgs ea{metric, psi, flux, ga, fp, rhs, p->xi / dt_max, p->gauge};
+  EdgeArgs ea{metric, psi, flux, ga, fp, rhs, p->xi / dt_max, p->gauge, cmb};
   return RUN_PHASE(KT_EDGE, PH_EDGE, k_edge, kb_edge, ea);
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char *pa = (const char*)a, *pb = (const char*)b;
+  return a && b && pa < pb + nb && pb < pa + na;
+}
+
+// Checks of the stage outputs against the right-hand side's inputs and each other; npts is the
+// per-field stride (the block's points, or a batch's pool).
+int make_combine(int32_t nout, const asterx_rk_out* outs, size_t npts, const double* const* ins, const size_t* nin,
+                 int nins, Combine& cmb) {
+  if (nout < 1 || nout > 2 || !outs) return fail(ASTERX_EARG, "rhs_rk: nout must be 1 or 2");
+  const size_t st = 9 * npts * sizeof(double);
+  cmb = Combine{};
+  cmb.nout = nout;
+  for (int k = 0; k < nout; ++k) {
+    const asterx_rk_out& o = outs[k];
+    if (o.nterms < 1 || o.nterms > 2 || !o.out) return fail(ASTERX_EARG, "rhs_rk: bad output");
+    for (int m = 0; m < o.nterms; ++m)
+      if (!o.u[m]) return fail(ASTERX_EARG, "rhs_rk: NULL state");
+    for (int i = 0; i < nins; ++i)
+      if (overlap(o.out, st, ins[i], nin[i] * sizeof(double)))
+        return fail(ASTERX_EARG, "rhs_rk: an output overlaps an input of the right-hand side");
+    for (int m = 0; m < o.nterms; ++m)
+      if (o.u[m] != o.out && overlap(o.out, st, o.u[m], st))
+        return fail(ASTERX_EARG, "rhs_rk: an output partially overlaps one of its own states");
+    for (int j = 0; j < nout; ++j) {
+      if (j == k) continue;
+      if (overlap(o.out, st, outs[j].out, st)) return fail(ASTERX_EARG, "rhs_rk: outputs overlap");
+      for (int m = 0; m < outs[j].nterms; ++m)
+        if (overlap(o.out, st, outs[j].u[m], st))
+          return fail(ASTERX_EARG, "rhs_rk: an output overlaps a state the other output reads");
+    }
+    RKOut& r = cmb.o[k];
+    r.nterms = o.nterms;
+    r.b_dt = o.b_dt;
+    r.out = o.out;
+    for (int m = 0; m < 2; ++m) {
+      r.u[m] = m < o.nterms ? o.u[m] : nullptr;
+      r.a[m] = m < o.nterms ? o.a[m] : 0.0;
+    }
+  }
+  return 0;
 }
 
 int do_rk(const GD& g, const asterx_batch* b, int32_t nterms, const double* a, const double* const* u, double b_dt,
@@ -2495,7 +2583,7 @@ int asterx_timing_reset(void) {
 
 const char* asterx_timing_name(int32_t k) { return (k >= 0 && k < KT_N) ? kt_names[k] : ""; }
 
-int asterx_version(void) { return 2; }
+int asterx_version(void) { return 3; }
 
 const char* asterx_last_error(void) { return g_err.c_str(); }
 
@@ -2588,6 +2676,23 @@ int asterx_rk_stage(const asterx_grid* gr, int32_t nterms, const double* a, cons
   GD g = make_gd(gr);
   const asterx_batch* b = nullptr;
   return do_rk(g, b, nterms, a, u, b_dt, rhs, out, (hipStream_t)stream);
+}
+
+int asterx_rhs_rk(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* curv,
+                  const double* prim, const double* A, const double* psi, double dt_max, int32_t nout,
+                  const asterx_rk_out* outs, double* red, void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_params(p)) || (rc = check_grid(gr, 3))) return rc;
+  if (!metric || !curv || !prim || !A || !psi || !workspace) return fail(ASTERX_EARG, "rhs_rk: NULL array");
+  if (ws_bytes < asterx_rhs_workspace_size(gr)) return fail(ASTERX_EARG, "rhs_rk: workspace too small");
+  if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs_rk: dt_max must be > 0");
+  GD g = make_gd(gr);
+  const double* ins[6] = {metric, curv, prim, A, psi, (const double*)workspace};
+  const size_t nin[6] = {10 * g.N, 6 * g.N, 5 * g.N, 3 * g.N, g.N, ws_bytes / sizeof(double)};
+  Combine cmb;
+  if ((rc = make_combine(nout, outs, g.N, ins, nin, 6, cmb))) return rc;
+  return do_rhs(g, nullptr, p, metric, curv, prim, A, psi, dt_max, nullptr, red, (double*)workspace,
+                (hipStream_t)stream, cmb);
 }
 
 int asterx_zero(double* buf, int64_t count, void* stream) {
@@ -2733,6 +2838,25 @@ int asterx_batch_rhs(const asterx_batch* b, const asterx_params* p, const double
   if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs: dt_max must be > 0");
   const GD& g = b->gds[0];
   return do_rhs(g, b, p, metric, curv, prim, A, psi, dt_max, rhs, red, (double*)workspace, (hipStream_t)stream);
+}
+
+int asterx_batch_rhs_rk(const asterx_batch* b, const asterx_params* p, const double* metric, const double* curv,
+                        const double* prim, const double* A, const double* psi, double dt_max, int32_t nout,
+                        const asterx_rk_out* outs, double* red, void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if (!b) return fail(ASTERX_EARG, "batch is NULL");
+  if ((rc = check_params(p))) return rc;
+  if (!metric || !curv || !prim || !A || !psi || !workspace) return fail(ASTERX_EARG, "rhs_rk: NULL array");
+  if (ws_bytes < asterx_batch_workspace_size(b)) return fail(ASTERX_EARG, "rhs_rk: workspace too small");
+  if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs_rk: dt_max must be > 0");
+  const size_t n = (size_t)b->ntot;
+  const double* ins[6] = {metric, curv, prim, A, psi, (const double*)workspace};
+  const size_t nin[6] = {10 * n, 6 * n, 5 * n, 3 * n, n, ws_bytes / sizeof(double)};
+  Combine cmb;
+  if ((rc = make_combine(nout, outs, n, ins, nin, 6, cmb))) return rc;
+  const GD& g = b->gds[0];
+  return do_rhs(g, b, p, metric, curv, prim, A, psi, dt_max, nullptr, red, (double*)workspace, (hipStream_t)stream,
+                cmb);
 }
 
 int asterx_batch_rk_stage(const asterx_batch* b, int32_t nterms, const double* a, const double* const* u,

@@ -75,6 +75,58 @@ def test_host_side_argument_validation(lib):
     assert lib.asterx_rhs_workspace_size(ctypes.byref(asterx.make_grid(L))) == 28 * 8 * L.npts
 
 
+def test_rk_out_layout_and_fused_stage_validation(lib, tmp_path):
+    """asterx_rk_out matches its ctypes mirror; asterx_rhs_rk refuses bad output sets before any launch (the
+    pointers below are never dereferenced)."""
+    from paper_2406_11669_amd import asterx
+    from paper_2406_11669_amd.workloads import Layout, default_params
+    src = tmp_path / "rkout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "asterx.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(asterx_rk_out), '
+                   'offsetof(asterx_rk_out, a), offsetof(asterx_rk_out, u), offsetof(asterx_rk_out, b_dt), '
+                   'offsetof(asterx_rk_out, out));return 0;}\n')
+    exe = tmp_path / "rkout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    R = asterx.RKOut
+    assert [int(v) for v in subprocess.check_output([str(exe)]).split()] == [
+        ctypes.sizeof(R), R.a.offset, R.u.offset, R.b_dt.offset, R.out.offset]
+    L = Layout((8, 8, 8), 3)
+    g = asterx.make_grid(L)
+    p = asterx.make_params(default_params(recon="ppm"))
+    span = 9 * 8 * L.npts
+    wsb = lib.asterx_rhs_workspace_size(ctypes.byref(g))
+    base = 1 << 40
+    ptr = lambda k: ctypes.c_void_p(base + k * (1 << 32))   # disjoint fake device addresses
+    metric, curv, prim, ws = ptr(1), ptr(2), ptr(3), ptr(4)
+    U, T1, T2 = base + 5 * (1 << 32), base + 6 * (1 << 32), base + 7 * (1 << 32)
+    A, psi = ctypes.c_void_p(U + 5 * 8 * L.npts), ctypes.c_void_p(U + 8 * 8 * L.npts)
+
+    def call(outs, nout=None):
+        arr = (asterx.RKOut * max(1, len(outs)))()
+        for k, (a, us, out) in enumerate(outs):
+            arr[k].nterms = len(a)
+            for m in range(len(a)):
+                arr[k].a[m] = a[m]
+                arr[k].u[m] = us[m]
+            arr[k].b_dt = 0.1
+            arr[k].out = out
+        n = len(outs) if nout is None else nout
+        return lib.asterx_rhs_rk(ctypes.byref(g), ctypes.byref(p), metric, curv, prim, A, psi, 0.01, n, arr, None,
+                                 ws, wsb, None)
+
+    assert call([], nout=0) == -1 and b"nout" in lib.asterx_last_error()
+    assert call([([1.0, 1.0, 1.0][:2], [U, U], T1)], nout=3) == -1
+    assert call([([1.0], [U], U)]) == -1 and b"overlaps an input" in lib.asterx_last_error()
+    assert call([([1.0], [T1 + 8], T1)]) == -1 and b"partially" in lib.asterx_last_error()
+    assert call([([1.0], [U], T1), ([1.0], [U], T1 + span - 8)]) == -1 and b"outputs overlap" in lib.asterx_last_error()
+    assert call([([1.0], [U], T1), ([1.0], [T1], T2)]) == -1 and b"other output reads" in lib.asterx_last_error()
+    bad = (asterx.RKOut * 1)()
+    bad[0].nterms = 3
+    bad[0].out = T1
+    assert lib.asterx_rhs_rk(ctypes.byref(g), ctypes.byref(p), metric, curv, prim, A, psi, 0.01, 1, bad, None, ws,
+                             wsb, None) == -1 and b"bad output" in lib.asterx_last_error()
+
+
 def test_oracle_ghost_fill_matches_definitions(orc):
     import numpy as np
     from paper_2406_11669_amd.workloads import Layout

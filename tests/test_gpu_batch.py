@@ -31,6 +31,24 @@ def _per_patch(ax, wls, nsteps):
     return blocks
 
 
+def test_batch_fused_equals_stored_per_patch_loop(ax):
+    """The batch with right-hand sides combined into the stage outputs (asterx_batch_rhs_rk) against per-patch
+    blocks that store the right-hand side and combine with asterx_rk_stage: bitwise equal."""
+    import torch
+    wls = _patches(recon="ppm")
+    print("case batch fused vs stored loop", flush=True)
+    bt = ax.Batch(wls, tuning=(4, 1))
+    bt.run(2)
+    blocks = [ax.Block(w, fused=False) for w in wls]
+    for _ in range(2):
+        for b in blocks:
+            b.step()
+    torch.cuda.synchronize()
+    for p, b in enumerate(blocks):
+        assert torch.equal(bt.unpack(bt.state, p), b.state), p
+        assert torch.equal(bt.unpack(bt.prim, p), b.prim), p
+
+
 @pytest.mark.parametrize("tuning", [(1, 0), (4, 1), (8, 2)])
 def test_batch_bitwise_equals_per_patch_loop(ax, tuning):
     import torch

@@ -210,6 +210,40 @@ def test_steps_parity_curved(ax, torch_mod, orc, recon):
     assert_fields_close(_host(blk.prim), prim, 1e-10, w.layout.owned, PRIM_NAMES)
 
 
+@pytest.mark.parametrize("recon,rk,shape", [("ppm", 4, (24, 13, 11)), ("wenoz", 4, (70, 9, 7)),
+                                             ("minmod", 2, (33, 12, 10))])
+def test_fused_stage_outputs_bitwise_equal_stored(ax, torch_mod, recon, rk, shape):
+    """asterx_rhs_rk (the right-hand side combined into the stage outputs by the cell and edge kernels) against
+    asterx_rhs + asterx_rk_stage: bitwise equal states, primitives, reductions and c2p counters after 3 steps."""
+    torch = torch_mod
+    w = W.curved_block(seed=33, n=shape, recon=recon, nsteps=3, rk=rk)
+    print("case fused vs stored", recon, rk, shape, flush=True)
+    a = ax.Block(w, fused=True)
+    b = ax.Block(w, fused=False)
+    a.run(3)
+    b.run(3)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state, b.state)
+    assert torch.equal(a.prim, b.prim)
+    assert torch.equal(a.red, b.red) and torch.equal(a.stats, b.stats)
+
+
+def test_fused_stage_rejects_aliased_outputs(ax, torch_mod):
+    """An output that is the state being evaluated, or two outputs on one buffer, are refused before any launch."""
+    torch = torch_mod
+    w = W.curved_block(seed=34, n=(8, 8, 8), recon="ppm", nsteps=1)
+    blk = ax.Block(w)
+    blk.recover(blk.state)
+    U, T = blk.state, blk.tmp
+    with pytest.raises(RuntimeError, match="overlaps an input"):
+        ax.rhs_rk(blk.L, blk.params, blk.metric, blk.curv, blk.prim, U[5:8], U[8:9], blk.dt,
+                  [([1.0], [U], blk.dt, U)], blk.red, blk.ws)
+    with pytest.raises(RuntimeError, match="outputs overlap"):
+        ax.rhs_rk(blk.L, blk.params, blk.metric, blk.curv, blk.prim, U[5:8], U[8:9], blk.dt,
+                  [([1.0], [U], blk.dt, T), ([1.0], [U], blk.dt, T)], blk.red, blk.ws)
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("recon", ["ppm"])
 def test_full_size_curved128_first_stage(ax, torch_mod, orc, recon):
     """The 128^3 curved workload at full size in the benchmark's launch configuration: c2p of the initial
