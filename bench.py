@@ -36,6 +36,11 @@ FACE_BYTES = 8.0 * (5 + 2 + 10 + 2 + 7)
 # state (9), metric and curvature (16), previous primitives (5), RK base state and accumulator (9 + 9 when
 # used); writes of primitives (5), next state (9) and accumulator (9 when used).
 STAGE_BYTES_RK4 = 514.0
+# Whole-stage algorithmic FP64 operations per zone-stage at 128^3 (same counting scalar, over one
+# right-hand side and one c2p of the 128^3 block of this workload: centre field 41, faces of the
+# three directions 7994 / 12145 / 6211, cell sources and divergence 5598, constrained transport and
+# gauge 139, c2p 3265; the RK combine's 2 operations per field are not counted).
+STAGE_FLOPS = {"ppm": 17036.9, "wenoz": 21188.6, "minmod": 15254.4}
 
 
 def library_source_sha():
@@ -206,6 +211,10 @@ def main():
     stage_gbs = STAGE_BYTES_RK4 * value / 1e9
     hbm = {"bytes_per_zone_stage": STAGE_BYTES_RK4, "achieved": round(stage_gbs, 1), "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": round(stage_gbs / HBM_PEAK_GBS, 4)}
+    stage_tf = STAGE_FLOPS[args.recon] * value / 1e12 if n == 128 else None
+    fp64 = {"flops_per_zone_stage": STAGE_FLOPS[args.recon] if n == 128 else None,
+            "achieved": None if stage_tf is None else round(stage_tf, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": None if stage_tf is None else round(stage_tf / FP64_VECTOR_PEAK_TFLOPS, 4)}
     out = {"metric": METRIC, "value": value, "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -213,7 +222,8 @@ def main():
                       "recon": args.recon, "rk": 4, "stages_per_step": stages, "cfl": 0.25, "gamma": 2.0,
                       "speeds": "quartic", "graph": graph is not None,
                       "c2p_guess": "learned" if args.learned_c2p else "warm"},
-           "roofline": roofline, "hbm_roofline_stage": hbm, "kernel_ms_per_stage": per_stage,
+           "roofline": roofline, "hbm_roofline_stage": hbm, "fp64_roofline_stage": fp64,
+           "kernel_ms_per_stage": per_stage,
            "c2p_stats": [int(v) for v in blk.stats.cpu().tolist()]}
     if learned_info:
         out["learned_c2p"] = learned_info
