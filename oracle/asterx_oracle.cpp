@@ -60,9 +60,11 @@ struct Params {
   int32_t gauge;        // 0 generalized Lorenz, 1 algebraic
   int32_t speeds;       // 0 quartic, 1 quadratic bound
   int32_t c2p_method;   // 0 Noble then Palenzuela, 1 Noble only, 2 Palenzuela only
+  int32_t riemann;      // 0 HLLE, 1 Lax-Friedrichs
 };
 
-enum { REC_MINMOD = 0, REC_PPM = 1, REC_WENOZ = 2 };
+enum { REC_MINMOD = 0, REC_PPM = 1, REC_WENOZ = 2, REC_MP5 = 3 };
+enum { RIEMANN_HLLE = 0, RIEMANN_LXF = 1 };
 enum { GAUGE_LORENZ = 0, GAUGE_ALGEBRAIC = 1 };
 enum { SPEED_QUARTIC = 0, SPEED_BOUND = 1 };
 enum { BC_PERIODIC = 0, BC_COPY = 1, BC_LINEAR = 2 };
@@ -417,6 +419,33 @@ template <class T> void hlle(const T UL[7], const T FL[7], const T& cmL, const T
   }
 }
 
+// Lax-Friedrichs flux (Sec. 3.3, eq. LxFfluxes): the mean of the two side fluxes
+// minus c_wave/2 times the jump of the state vector, with c_wave = max(c_max,
+// c_min) and c_max, c_min as for HLLE.
+template <class T> void lxf(const T UL[7], const T FL[7], const T& cmL, const T& cpL, const T UR[7], const T FR[7],
+                            const T& cmR, const T& cpR, T Fo[7], T& cmax_out, T& cmin_out) {
+  T cmax = T(0);
+  if (cpL > cmax) cmax = cpL;
+  if (cpR > cmax) cmax = cpR;
+  T mn = T(0);
+  if (cmL < mn) mn = cmL;
+  if (cmR < mn) mn = cmR;
+  T cmin = -mn;
+  cmax_out = cmax;
+  cmin_out = cmin;
+  T cwave = cmax > cmin ? cmax : cmin;
+  for (int c = 0; c < 7; ++c) Fo[c] = (FR[c] + FL[c] - cwave * (UR[c] - UL[c])) / T(2);
+}
+
+template <class T> void riemann_flux(int kind, const T UL[7], const T FL[7], const T& cmL, const T& cpL,
+                                     const T UR[7], const T FR[7], const T& cmR, const T& cpR, T Fo[7], T& cmax,
+                                     T& cmin) {
+  if (kind == RIEMANN_LXF)
+    lxf(UL, FL, cmL, cpL, UR, FR, cmR, cpR, Fo, cmax, cmin);
+  else
+    hlle(UL, FL, cmL, cpL, UR, FR, cmR, cpR, Fo, cmax, cmin);
+}
+
 // ---------------------------------------------------------------------------
 // Reconstruction (Sec. 3.3).  Each routine takes the five cell values
 // a[0..4] = a_{c-2}..a_{c+2} around cell c and returns the values at its left
@@ -494,11 +523,56 @@ template <class T> void rec_wenoz(const T a[5], T& aL, T& aR, double eps, double
   aL = wenoz_right_face(a[4], a[3], a[2], a[1], a[0], eps, qexp);
 }
 
+// MP5 (Suresh & Huynh 1997), the paper's fifth scheme (Sec. 3.3, cited only).
+// Left-biased value at c+1/2 from a_{c-2..c+2}: the fifth-order interpolant is
+// kept when it lies between a_c and the monotonicity-preserving bound
+// a_c + minmod(a_{c+1} - a_c, alpha (a_c - a_{c-1})); otherwise it is replaced by
+// the median of itself and the accuracy-preserving interval [f_min, f_max]
+// built from the M4 curvature measures.  alpha = 4.
+template <class T> T tmin(const T& x, const T& y) { return y < x ? y : x; }
+template <class T> T tmax(const T& x, const T& y) { return y > x ? y : x; }
+
+// minmod of four numbers: the one of least magnitude if all share a sign, else 0
+template <class T> T minmod4(const T& w, const T& x, const T& y, const T& z) {
+  if (w > T(0) && x > T(0) && y > T(0) && z > T(0)) return tmin(tmin(w, x), tmin(y, z));
+  if (w < T(0) && x < T(0) && y < T(0) && z < T(0)) return tmax(tmax(w, x), tmax(y, z));
+  return T(0);
+}
+
+// median of three numbers
+template <class T> T median3(const T& x, const T& y, const T& z) { return x + minmod2(y - x, z - x); }
+
+template <class T> T mp5_right_face(const T& am2, const T& am1, const T& a0, const T& ap1, const T& ap2) {
+  const T alpha = T(4);
+  T f_or = (T(2) * am2 - T(13) * am1 + T(47) * a0 + T(27) * ap1 - T(3) * ap2) / T(60);
+  T f_mp = a0 + minmod2(ap1 - a0, alpha * (a0 - am1));
+  if ((f_or - a0) * (f_or - f_mp) <= T(0)) return f_or;
+  T d_m = am2 - T(2) * am1 + a0;
+  T d_0 = am1 - T(2) * a0 + ap1;
+  T d_p = a0 - T(2) * ap1 + ap2;
+  T dm4_right = minmod4(T(4) * d_0 - d_p, T(4) * d_p - d_0, d_0, d_p);
+  T dm4_left = minmod4(T(4) * d_0 - d_m, T(4) * d_m - d_0, d_0, d_m);
+  T f_ul = a0 + alpha * (a0 - am1);
+  T f_av = (a0 + ap1) / T(2);
+  T f_md = f_av - dm4_right / T(2);
+  T f_lc = a0 + (a0 - am1) / T(2) + T(4) / T(3) * dm4_left;
+  T f_min = tmax(tmin(tmin(a0, ap1), f_md), tmin(tmin(a0, f_ul), f_lc));
+  T f_max = tmin(tmax(tmax(a0, ap1), f_md), tmax(tmax(a0, f_ul), f_lc));
+  return median3(f_or, f_min, f_max);
+}
+
+template <class T> void rec_mp5(const T a[5], T& aL, T& aR) {
+  aR = mp5_right_face(a[0], a[1], a[2], a[3], a[4]);
+  aL = mp5_right_face(a[4], a[3], a[2], a[1], a[0]);
+}
+
 template <class T> void reconstruct_cell(int kind, const T a[5], T& aL, T& aR, const Params& P) {
   if (kind == REC_MINMOD)
     rec_minmod(a, aL, aR);
   else if (kind == REC_PPM)
     rec_ppm(a, aL, aR);
+  else if (kind == REC_MP5)
+    rec_mp5(a, aL, aR);
   else
     rec_wenoz(a, aL, aR, P.weno_eps, P.weno_q);
 }
@@ -1137,7 +1211,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
           speeds_point(G, FLd, d, gam, P.speeds, cmL, cpL);
           speeds_point(G, FRd, d, gam, P.speeds, cmR, cpR);
           T Fo[7], cmax, cmin;
-          hlle(UL, FL, cmL, cpL, UR, FR, cmR, cpR, Fo, cmax, cmin);
+          riemann_flux(P.riemann, UL, FL, cmL, cpL, UR, FR, cmR, cpR, Fo, cmax, cmin);
           for (int c = 0; c < 7; ++c) flux[(d * 7 + c) * N + at(g, i, j, k)] = Fo[c];
           bool owned = true;
           int id[3] = {i, j, k};
@@ -1592,6 +1666,12 @@ void orc_pt_hlle(const double* UL, const double* FL, double cmL, double cpL, con
                  double cmR, double cpR, double* Fo) {
   double a, b;
   hlle(UL, FL, cmL, cpL, UR, FR, cmR, cpR, Fo, a, b);
+}
+
+void orc_pt_lxf(const double* UL, const double* FL, double cmL, double cpL, const double* UR, const double* FR,
+                double cmR, double cpR, double* Fo) {
+  double a, b;
+  lxf(UL, FL, cmL, cpL, UR, FR, cmR, cpR, Fo, a, b);
 }
 
 // 1-D reconstruction of an array a[0..n): for every cell c in [2, n-3] the

@@ -31,10 +31,12 @@ class Params(ctypes.Structure):
                 ("xi", ctypes.c_double), ("c2p_tol", ctypes.c_double), ("wmax", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("weno_q", ctypes.c_double),
                 ("c2p_maxit", ctypes.c_int32), ("brent_maxit", ctypes.c_int32), ("recon", ctypes.c_int32),
-                ("gauge", ctypes.c_int32), ("speeds", ctypes.c_int32), ("c2p_method", ctypes.c_int32)]
+                ("gauge", ctypes.c_int32), ("speeds", ctypes.c_int32), ("c2p_method", ctypes.c_int32),
+                ("riemann", ctypes.c_int32)]
 
 
-RECON = {"minmod": 0, "ppm": 1, "wenoz": 2}
+RECON = {"minmod": 0, "ppm": 1, "wenoz": 2, "mp5": 3}
+RIEMANN = {"hlle": 0, "lxf": 1}
 BC = {"periodic": 0, "copy": 1, "linear": 2}
 
 
@@ -93,6 +95,8 @@ def make_params(p):
     P.gauge = {"lorenz": 0, "algebraic": 1}[p["gauge"]] if isinstance(p["gauge"], str) else p["gauge"]
     P.speeds = {"quartic": 0, "bound": 1}[p["speeds"]] if isinstance(p["speeds"], str) else p["speeds"]
     P.c2p_method = p.get("c2p_method", 0)
+    r = p.get("riemann", "hlle")
+    P.riemann = RIEMANN[r] if isinstance(r, str) else r
     return P
 
 
@@ -236,6 +240,13 @@ def pt_hlle(UL, FL, cmL, cpL, UR, FR, cmR, cpR):
     out = np.zeros(7)
     lib().orc_pt_hlle(_p(_v(UL, 7)), _p(_v(FL, 7)), ctypes.c_double(cmL), ctypes.c_double(cpL), _p(_v(UR, 7)),
                       _p(_v(FR, 7)), ctypes.c_double(cmR), ctypes.c_double(cpR), _p(out))
+    return out
+
+
+def pt_lxf(UL, FL, cmL, cpL, UR, FR, cmR, cpR):
+    out = np.zeros(7)
+    lib().orc_pt_lxf(_p(_v(UL, 7)), _p(_v(FL, 7)), ctypes.c_double(cmL), ctypes.c_double(cpL), _p(_v(UR, 7)),
+                     _p(_v(FR, 7)), ctypes.c_double(cmR), ctypes.c_double(cpR), _p(out))
     return out
 
 

@@ -39,13 +39,14 @@ def _uniform_setup(n=8, seed=0, vel=(0.3, -0.2, 0.1), B=(0.375, -0.25, 0.625)):
     return L, m10, metric, prim, A, np.array(B)
 
 
-@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz"])
-def test_uniform_state_constant_metric(orc, recon):
+@pytest.mark.parametrize("recon,riemann", [("minmod", "hlle"), ("ppm", "hlle"), ("wenoz", "hlle"), ("mp5", "hlle"),
+                                           ("ppm", "lxf")])
+def test_uniform_state_constant_metric(orc, recon, riemann):
     """Uniform (rho, p, v, B) in a constant metric: hydro right-hand side bitwise 0; dA/dt = vt x Btilde
     (the FCT field of a uniform state, E = -vt x Btilde) to round-off; dPsi/dt = -alpha sqrt(gamma)
     gamma^jk d_j A_k - xi alpha Psi."""
     L, m10, metric, prim, A, Bt = _uniform_setup()
-    P = default_params(gamma=5.0 / 3.0, recon=recon)
+    P = default_params(gamma=5.0 / 3.0, recon=recon, riemann=riemann)
     psi = L.zeros(1) + 0.25
     dt = 0.01
     out, red, nfix = orc.rhs(L, P, metric, L.zeros(6), prim, A, psi, dt)
@@ -99,11 +100,12 @@ def _init_state(orc, w):
     return w.state(cons)
 
 
-@pytest.mark.parametrize("recon", ["ppm", "wenoz"])
-def test_conservation_and_divB_curved_periodic(orc, recon):
+@pytest.mark.parametrize("recon,riemann", [("ppm", "hlle"), ("wenoz", "hlle"), ("mp5", "hlle"), ("ppm", "lxf")])
+def test_conservation_and_divB_curved_periodic(orc, recon, riemann):
     """Periodic block in a curved metric: sum of D-tilde is constant to round-off (the flux form telescopes) and
     the discrete divergence of the face field stays at round-off under constrained transport."""
     w = W.curved_block(seed=3, n=10, recon=recon, nsteps=2)
+    w.params["riemann"] = riemann
     L = w.layout
     state = _init_state(orc, w)
     prim = w.prim.copy()
@@ -187,11 +189,12 @@ def _entropy_wave(orc, N, recon, metric10, t_final=0.25):
     return np.mean(np.abs(L.owned(prim[0]) - L.owned(np.broadcast_to(ex, L.shape3))))
 
 
-@pytest.mark.parametrize("recon,min_order", [("minmod", 1.8), ("ppm", 2.0)])
+@pytest.mark.parametrize("recon,min_order", [("minmod", 1.8), ("ppm", 2.0), ("mp5", 1.9)])
 @pytest.mark.parametrize("curved", [False, True])
 def test_entropy_wave_convergence(orc, recon, min_order, curved):
     """A smooth entropy wave (uniform p, v, B) translates exactly with coordinate speed alpha v^x - beta^x;
-    the L1 error converges at second order (flat and constant non-trivial metric)."""
+    the L1 error converges at second order (flat and constant non-trivial metric).  The RK2 time error caps
+    the observed order at 2, also for fifth-order MP5 (measured 1.94, 1.99)."""
     m10 = np.array([1.0, 0, 0, 0, 1.0, 0, 0, 1.0, 0, 1.0])
     if curved:
         m10 = np.array([0.9, 0.05, -0.02, 0.01, 1.0, 0.0, 0.0, 1.1, 0.05, 0.95])

@@ -337,3 +337,41 @@ def test_hlle_consistency_and_upwinding(orc):
         cmax, cmin = 0.7, 0.4
         ref = (cmin * F2 + cmax * F - cmax * cmin * (U2 - U)) / (cmax + cmin)
         np.testing.assert_allclose(orc.pt_hlle(U, F, -0.4, 0.7, U2, F2, -0.1, 0.2), ref, rtol=1e-13, atol=1e-14)
+
+
+def test_lxf_consistency_and_relation_to_hlle(orc):
+    """Lax-Friedrichs (eq. LxFfluxes): F(U, U) = F(U); with c_max = c_min it coincides with HLLE (both reduce to
+    (F_l + F_r - c (U_r - U_l)) / 2); otherwise it uses the larger of the two speeds on both sides."""
+    rng = np.random.default_rng(14)
+    for _ in range(100):
+        U, F = rng.normal(size=7), rng.normal(size=7)
+        U2, F2 = rng.normal(size=7), rng.normal(size=7)
+        np.testing.assert_allclose(orc.pt_lxf(U, F, -0.3, 0.5, U, F, -0.2, 0.7), F, rtol=1e-14, atol=1e-15)
+        # symmetric speeds: c_max = max(0.4, 0.6) = 0.6 = c_min = -min(-0.6, -0.2)
+        np.testing.assert_allclose(orc.pt_lxf(U, F, -0.6, 0.4, U2, F2, -0.2, 0.6),
+                                   orc.pt_hlle(U, F, -0.6, 0.4, U2, F2, -0.2, 0.6), rtol=1e-13, atol=1e-14)
+        # c_max = 0.7 > c_min = 0.1: the same as with symmetric speeds +-0.7
+        np.testing.assert_allclose(orc.pt_lxf(U, F, -0.1, 0.7, U2, F2, 0.05, 0.2),
+                                   orc.pt_hlle(U, F, -0.7, 0.7, U2, F2, -0.7, 0.7), rtol=1e-13, atol=1e-14)
+        # supersonic flow: unlike HLLE, LxF does not reduce to the upwind flux
+        assert np.max(np.abs(orc.pt_lxf(U, F, 0.1, 0.5, U2, F2, 0.2, 0.7) - F)) > 1e-3
+
+
+def test_lxf_equals_hlle_for_resting_flat_states(orc):
+    """Flat metric, v = 0 on both sides (different rho, p, B): the fast speeds are symmetric about zero on each
+    side, so c_max = c_min and the LxF face flux equals the HLLE one."""
+    rng = np.random.default_rng(15)
+    m10 = np.array([1.0, 0, 0, 0, 1.0, 0, 0, 1.0, 0, 1.0])
+    for _ in range(20):
+        sides = []
+        Bn = rng.uniform(-1, 1)
+        for _s in range(2):
+            prim = np.array([rng.uniform(0.1, 1.0), rng.uniform(0.1, 1.0), 0.0, 0.0, 0.0])
+            Bt = np.array([Bn, rng.uniform(-1, 1), rng.uniform(-1, 1)])
+            U, F = orc.pt_flux(m10, prim, Bt, 5.0 / 3.0, 0)
+            cm, cp = orc.pt_speeds(m10, prim, Bt, 5.0 / 3.0, 0)[:2]
+            sides.append((U, F, cm, cp))
+        (UL, FL, cmL, cpL), (UR, FR, cmR, cpR) = sides
+        np.testing.assert_allclose(cmL, -cpL, rtol=1e-13)
+        np.testing.assert_allclose(orc.pt_lxf(UL, FL, cmL, cpL, UR, FR, cmR, cpR),
+                                   orc.pt_hlle(UL, FL, cmL, cpL, UR, FR, cmR, cpR), rtol=1e-12, atol=1e-14)

@@ -14,16 +14,16 @@ P = default_params()
 # ---------------------------------------------------------------- reconstruction
 
 
-@pytest.mark.parametrize("kind", ["minmod", "ppm", "wenoz"])
+@pytest.mark.parametrize("kind", ["minmod", "ppm", "wenoz", "mp5"])
 def test_recon_constants_exact(orc, kind):
     a = np.full(20, 0.37)
     aL, aR = orc.recon_1d(P, kind, a)
     assert np.all(aL[2:-2] == 0.37) and np.all(aR[2:-2] == 0.37)
 
 
-@pytest.mark.parametrize("kind", ["minmod", "ppm", "wenoz"])
+@pytest.mark.parametrize("kind", ["minmod", "ppm", "wenoz", "mp5"])
 def test_recon_linear_exact(orc, kind):
-    """Linear data are reproduced at the faces by all three schemes."""
+    """Linear data are reproduced at the faces by every scheme."""
     x = np.arange(30, dtype=float)
     a = 0.3 + 0.7 * x
     aL, aR = orc.recon_1d(P, kind, a)
@@ -56,7 +56,7 @@ def test_recon_no_new_extrema(orc, kind):
             assert lo <= aL[c] <= hi and lo <= aR[c] <= hi
 
 
-@pytest.mark.parametrize("kind", ["minmod", "ppm", "wenoz"])
+@pytest.mark.parametrize("kind", ["minmod", "ppm", "wenoz", "mp5"])
 def test_recon_mirror_symmetry(orc, kind):
     """Reversing the data swaps left and right face values bitwise."""
     rng = np.random.default_rng(31)
@@ -75,6 +75,63 @@ def test_wenoz_fifth_order_on_smooth_averages(orc):
         h = x[1] - x[0]
         a = -(np.cos(2 * np.pi * x[1:]) - np.cos(2 * np.pi * x[:-1])) / (2 * np.pi * h) + 2.0
         aL, aR = orc.recon_1d(P, "wenoz", a)
+        ex = np.sin(2 * np.pi * x[3:-2]) + 2.0
+        errs.append(np.max(np.abs(aR[2:-2] - ex)))
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(order > 4.5), (errs, order)
+
+
+def test_mp5_exact_on_quartic_averages(orc):
+    """The MP5 interpolant (2, -13, 47, 27, -3)/60 is exact for cell averages of a quartic, and on a smooth
+    monotone quartic the monotonicity test leaves it untouched."""
+    x = np.linspace(1.0, 2.0, 41)  # faces
+    F = lambda t: 0.05 * t ** 5 / 5 + 0.2 * t ** 4 / 4 + 0.1 * t ** 3 / 3 + t ** 2 / 2 + t
+    f = lambda t: 0.05 * t ** 4 + 0.2 * t ** 3 + 0.1 * t ** 2 + t + 1
+    a = (F(x[1:]) - F(x[:-1])) / (x[1] - x[0])
+    aL, aR = orc.recon_1d(P, "mp5", a)
+    np.testing.assert_allclose(aR[2:-2], f(x[3:-2]), rtol=1e-12)
+    np.testing.assert_allclose(aL[2:-2], f(x[2:-3]), rtol=1e-12)
+
+
+@pytest.mark.parametrize("data,left,right", [
+    # isolated maximum: interpolant 47/60 at the right face; the curvature measures have mixed signs, so the
+    # accuracy-preserving interval collapses to [1, 1] and both faces take the cell value
+    ((0.0, 0.0, 1.0, 0.0, 0.0), 1.0, 1.0),
+    # last cell before a unit step: interpolant 24/60, limited to 0 (no overshoot)
+    ((0.0, 0.0, 0.0, 1.0, 1.0), 0.0, 0.0),
+    # first cell after the step: interpolants 71/60 (right) and 36/60 (left), both limited to 1
+    ((0.0, 0.0, 1.0, 1.0, 1.0), 1.0, 1.0),
+    # linear data: the interpolant (0 - 13 + 94 + 81 - 12)/60 = 2.5 passes the monotonicity test
+    ((0.0, 1.0, 2.0, 3.0, 4.0), 1.5, 2.5),
+])
+def test_mp5_worked_examples(orc, data, left, right):
+    """Face values of the middle cell worked out by hand from the MP5 definition (Suresh & Huynh 1997, alpha =
+    4): an extremum is flattened, a step stays sharp, linear data pass."""
+    aL, aR = orc.recon_1d(P, "mp5", np.array(data))
+    assert aL[2] == left and aR[2] == right
+
+
+def test_mp5_affine_invariance(orc):
+    """MP5 commutes with a -> s a + t for s of either sign (a sign error in a limiter breaks this)."""
+    rng = np.random.default_rng(33)
+    for _ in range(20):
+        a = rng.normal(size=30) * rng.uniform(0.1, 3.0)
+        aL, aR = orc.recon_1d(P, "mp5", a)
+        for s_, t_ in ((2.0, 0.5), (-0.5, 3.0)):
+            bL, bR = orc.recon_1d(P, "mp5", s_ * a + t_)
+            np.testing.assert_allclose(bL[2:-2], s_ * aL[2:-2] + t_, rtol=1e-12, atol=1e-12)
+            np.testing.assert_allclose(bR[2:-2], s_ * aR[2:-2] + t_, rtol=1e-12, atol=1e-12)
+
+
+def test_mp5_fifth_order_on_smooth_averages(orc):
+    """MP5 face values from exact cell averages of a smooth periodic function (with extrema) converge at fifth
+    order: the curvature-based bounds keep the limiter from clipping smooth extrema."""
+    errs = []
+    for n in (20, 40, 80):
+        x = np.linspace(0, 1, n + 1)
+        h = x[1] - x[0]
+        a = -(np.cos(2 * np.pi * x[1:]) - np.cos(2 * np.pi * x[:-1])) / (2 * np.pi * h) + 2.0
+        aL, aR = orc.recon_1d(P, "mp5", a)
         ex = np.sin(2 * np.pi * x[3:-2]) + 2.0
         errs.append(np.max(np.abs(aR[2:-2] - ex)))
     order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
