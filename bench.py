@@ -25,10 +25,11 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 128 FLOP/clk x 2.4 GHz)
 
 # Algorithmic FP64 operations per face of the face kernel (reconstruction of 7 variables on both sides,
-# 16-point face metric of 10 components, prim->cons, fluxes, quartic speeds, HLLE), counted by running the
-# plain serial implementation on an operation-counting scalar (+, -, *, /, sqrt, pow = 1 each) over the
-# faces of a 24^3 block of this workload (same seed and recipe).
-FACE_FLOPS = {"ppm": 2548.0, "wenoz": 3955.0, "minmod": 2020.0}
+# 16-point face metric of 10 components, prim->cons, fluxes, quartic speeds, HLLE or LxF), counted by running
+# the plain serial implementation on an operation-counting scalar (+, -, *, /, sqrt, pow = 1 each) over the
+# 3 x 129^3 faces of the 128^3 block of this workload (same seed and recipe; limiter branches make the count
+# data dependent).
+FACE_FLOPS = {"ppm": 2603.1, "wenoz": 3955.0, "minmod": 2022.6, "mp5": 2480.3, "ppm+lxf": 2581.1}
 # Algorithmic bytes per face: read 5 primitives + 2 centre fields + 10 face-metric components + 2 potential
 # components, write 7 face fluxes (each value once, stencil reuse served on chip).
 FACE_BYTES = 8.0 * (5 + 2 + 10 + 2 + 7)
@@ -37,10 +38,10 @@ FACE_BYTES = 8.0 * (5 + 2 + 10 + 2 + 7)
 # used); writes of primitives (5), next state (9) and accumulator (9 when used).
 STAGE_BYTES_RK4 = 514.0
 # Whole-stage algorithmic FP64 operations per zone-stage at 128^3 (same counting scalar, over one
-# right-hand side and one c2p of the 128^3 block of this workload: centre field 41, faces of the
-# three directions 7994 / 12145 / 6211, cell sources and divergence 5598, constrained transport and
-# gauge 139, c2p 3265; the RK combine's 2 operations per field are not counted).
-STAGE_FLOPS = {"ppm": 17036.9, "wenoz": 21188.6, "minmod": 15254.4}
+# right-hand side and one c2p of the 128^3 block of this workload; for PPM: centre field 41, faces of
+# the three directions 7994, cell sources and divergence 5598, constrained transport and gauge 139, c2p
+# 3265; the RK combine's 2 operations per field are not counted).
+STAGE_FLOPS = {"ppm": 17036.9, "wenoz": 21188.6, "minmod": 15254.4, "mp5": 16659.9, "ppm+lxf": 16969.3}
 
 
 def library_source_sha():
@@ -76,7 +77,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--recon", default="ppm", choices=["ppm", "wenoz", "minmod"])
+    ap.add_argument("--recon", default="ppm", choices=["ppm", "wenoz", "minmod", "mp5"])
+    ap.add_argument("--riemann", default="hlle", choices=["hlle", "lxf"])
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=56, help="edge of the block the CPU oracle times")
@@ -101,12 +103,13 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
-def cpu_baseline(recon, n_cpu):
+def cpu_baseline(recon, riemann, n_cpu):
     """The serial oracle, as it stands, on an n_cpu^3 block of the same workload: one RK4 step."""
     from oracle import oracle as O
     from paper_2406_11669_amd import workloads as W
     O.build(force=False)
     w = W.curved_block(seed=0, n=n_cpu, recon=recon, nsteps=1)
+    w.params["riemann"] = riemann
     L = w.layout
     cons = O.prim2con(L, w.params, w.metric, w.A, w.prim)
     O.fill_ghosts(L, cons, w.bc_cell)
@@ -140,6 +143,8 @@ def main():
     torch.cuda.set_device(0)
     n = args.n
     w = W.curved_block(seed=0, n=n, recon=args.recon, nsteps=args.steps)
+    w.params["riemann"] = args.riemann
+    scheme = args.recon if args.riemann == "hlle" else args.recon + "+" + args.riemann
     blk = asterx.Block(w)
     learned_info = None
     if args.learned_c2p:
@@ -200,26 +205,29 @@ def main():
     dominant = max(((k, v[0]) for k, v in kt.items()), key=lambda kv: kv[1])[0]
     faces_per_launch = (n + 1) ** 3
     avg_face_s = face_ms * 1e-3 / face_launches
-    achieved = FACE_FLOPS[args.recon] * faces_per_launch / avg_face_s / 1e12
+    face_flops = FACE_FLOPS.get(scheme)
+    achieved = face_flops * faces_per_launch / avg_face_s / 1e12 if face_flops else None
     roofline = {"kernel": "face (x, y, z launches averaged)", "dominant_by_time": dominant,
-                "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": measured_face_traffic(args.recon, n),
+                "bound": "alu", "achieved": None if achieved is None else round(achieved, 3),
+                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": None if achieved is None else round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": measured_face_traffic(scheme, n),
                 "avg_launch_ms": round(avg_face_s * 1e3, 4),
-                "flops_per_face": FACE_FLOPS[args.recon], "faces_per_launch": faces_per_launch,
+                "flops_per_face": face_flops, "faces_per_launch": faces_per_launch,
                 "algorithmic_GBs": round(FACE_BYTES * faces_per_launch / avg_face_s / 1e9, 1)}
     stage_gbs = STAGE_BYTES_RK4 * value / 1e9
     hbm = {"bytes_per_zone_stage": STAGE_BYTES_RK4, "achieved": round(stage_gbs, 1), "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": round(stage_gbs / HBM_PEAK_GBS, 4)}
-    stage_tf = STAGE_FLOPS[args.recon] * value / 1e12 if n == 128 else None
-    fp64 = {"flops_per_zone_stage": STAGE_FLOPS[args.recon] if n == 128 else None,
+    stage_flops = STAGE_FLOPS.get(scheme) if n == 128 else None
+    stage_tf = stage_flops * value / 1e12 if stage_flops else None
+    fp64 = {"flops_per_zone_stage": stage_flops,
             "achieved": None if stage_tf is None else round(stage_tf, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": None if stage_tf is None else round(stage_tf / FP64_VECTOR_PEAK_TFLOPS, 4)}
     out = {"metric": METRIC, "value": value, "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "curved%d-%s-rk4" % (n, args.recon), "n": n, "ng": w.layout.ng,
-                      "recon": args.recon, "rk": 4, "stages_per_step": stages, "cfl": 0.25, "gamma": 2.0,
+           "config": {"workload": "curved%d-%s-rk4" % (n, scheme.replace("+", "-")), "n": n, "ng": w.layout.ng,
+                      "recon": args.recon, "riemann": args.riemann, "rk": 4, "stages_per_step": stages, "cfl": 0.25, "gamma": 2.0,
                       "speeds": "quartic", "graph": graph is not None,
                       "c2p_guess": "learned" if args.learned_c2p else "warm"},
            "roofline": roofline, "hbm_roofline_stage": hbm, "fp64_roofline_stage": fp64,
@@ -229,7 +237,7 @@ def main():
         out["learned_c2p"] = learned_info
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a %d^3 sample" % args.cpu_n, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.recon, args.cpu_n)
+        out["cpu_baseline"] = cpu_baseline(args.recon, args.riemann, args.cpu_n)
     print(json.dumps(out), flush=True)
 
 

@@ -44,7 +44,8 @@ extern "C" {
 #define ASTERX_EARG (-1)
 #define ASTERX_ELAUNCH (-2)
 
-enum { ASTERX_RECON_MINMOD = 0, ASTERX_RECON_PPM = 1, ASTERX_RECON_WENOZ = 2 };
+enum { ASTERX_RECON_MINMOD = 0, ASTERX_RECON_PPM = 1, ASTERX_RECON_WENOZ = 2, ASTERX_RECON_MP5 = 3 };
+enum { ASTERX_RIEMANN_HLLE = 0, ASTERX_RIEMANN_LXF = 1 };
 enum { ASTERX_GAUGE_LORENZ = 0, ASTERX_GAUGE_ALGEBRAIC = 1 };
 enum { ASTERX_SPEEDS_QUARTIC = 0, ASTERX_SPEEDS_BOUND = 1 };
 enum { ASTERX_C2P_NOBLE_PALENZUELA = 0, ASTERX_C2P_NOBLE_ONLY = 1, ASTERX_C2P_PALENZUELA_ONLY = 2 };
@@ -83,6 +84,7 @@ typedef struct {
   int32_t gauge;       /* ASTERX_GAUGE_* */
   int32_t speeds;      /* ASTERX_SPEEDS_* */
   int32_t c2p_method;  /* ASTERX_C2P_* */
+  int32_t riemann;     /* ASTERX_RIEMANN_*: HLLE (Sec. 3.3 eq. HLLEfluxes) or Lax-Friedrichs (eq. LxFfluxes) */
 } asterx_params;
 
 /* Device-side counters, accumulated (never reset) by asterx_c2p. */

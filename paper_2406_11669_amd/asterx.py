@@ -16,7 +16,8 @@ from . import workloads as W
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libasterx.so")
 
-RECON = {"minmod": 0, "ppm": 1, "wenoz": 2}
+RECON = {"minmod": 0, "ppm": 1, "wenoz": 2, "mp5": 3}
+RIEMANN = {"hlle": 0, "lxf": 1}
 GAUGE = {"lorenz": 0, "algebraic": 1}
 SPEEDS = {"quartic": 0, "bound": 1}
 BC = {"periodic": 0, "copy": 1, "linear": 2}
@@ -45,7 +46,8 @@ class Params(ctypes.Structure):
                 ("xi", ctypes.c_double), ("c2p_tol", ctypes.c_double), ("wmax", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("weno_q", ctypes.c_double),
                 ("c2p_maxit", ctypes.c_int32), ("brent_maxit", ctypes.c_int32), ("recon", ctypes.c_int32),
-                ("gauge", ctypes.c_int32), ("speeds", ctypes.c_int32), ("c2p_method", ctypes.c_int32)]
+                ("gauge", ctypes.c_int32), ("speeds", ctypes.c_int32), ("c2p_method", ctypes.c_int32),
+                ("riemann", ctypes.c_int32)]
 
 
 class RKOut(ctypes.Structure):
@@ -170,6 +172,8 @@ def make_params(p):
     P.gauge = GAUGE[p["gauge"]] if isinstance(p["gauge"], str) else int(p["gauge"])
     P.speeds = SPEEDS[p["speeds"]] if isinstance(p["speeds"], str) else int(p["speeds"])
     P.c2p_method = int(p.get("c2p_method", 0))
+    r = p.get("riemann", "hlle")
+    P.riemann = RIEMANN[r] if isinstance(r, str) else int(r)
     return P
 
 

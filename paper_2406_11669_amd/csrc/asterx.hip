@@ -713,7 +713,7 @@ struct FaceArgs {
   double* flux;
   double* red;
   double gam, weno_eps, weno_q, gfac;
-  int recon, speeds;
+  int recon, speeds, riemann;
 };
 
 // Paired-lane variant: lanes 2f and 2f+1 of a wavefront handle the left and the right state
@@ -738,6 +738,7 @@ DEV T recon_right_face(const T a[5], double eps, double q) {
     ppm_limit(a[2], fl, fr);
     return fr;
   }
+  if (kind == ASTERX_RECON_MP5) return mp5_face(a[0], a[1], a[2], a[3], a[4]);
   return wenoz_face(a[0], a[1], a[2], a[3], a[4], eps, q);
 }
 
@@ -985,13 +986,21 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
     double cmax = fmax(0.0, fmax(cp, cpo));
     double cmin = -fmin(0.0, fmin(cm, cmo));
     double den = cmax + cmin;
-    // (cmin F_R + cmax F_L - cmax cmin (U_R - U_L)) / (cmax + cmin), written from this
-    // lane's point of view (own side, other side) so no per-component side selects
-    double id_ = den > 0.0 ? 1.0 / den : 0.0;
-    double cc = cmax * cmin;
-    double w_own = den > 0.0 ? (side ? cmin : cmax) * id_ : 0.5;
-    double w_oth = den > 0.0 ? (side ? cmax : cmin) * id_ : 0.5;
-    double w_u = den > 0.0 ? (side ? -cc : cc) * id_ : 0.0;
+    // HLLE: (cmin F_R + cmax F_L - cmax cmin (U_R - U_L)) / (cmax + cmin); LxF (eq. LxFfluxes):
+    // (F_R + F_L - c_wave (U_R - U_L)) / 2, c_wave = max(cmax, cmin).  Written from this lane's
+    // point of view (own side, other side) so no per-component side selects.
+    double w_own, w_oth, w_u;
+    if (fa.riemann == ASTERX_RIEMANN_LXF) {
+      const double hw = 0.5 * fmax(cmax, cmin);
+      w_own = w_oth = 0.5;
+      w_u = side ? -hw : hw;
+    } else {
+      double id_ = den > 0.0 ? 1.0 / den : 0.0;
+      double cc = cmax * cmin;
+      w_own = den > 0.0 ? (side ? cmin : cmax) * id_ : 0.5;
+      w_oth = den > 0.0 ? (side ? cmax : cmin) * id_ : 0.5;
+      w_u = den > 0.0 ? (side ? -cc : cc) * id_ : 0.0;
+    }
     double out[7];
 #pragma unroll
     for (int q = 0; q < 7; ++q) out[q] = w_own * F[q] + w_oth * Fo[q] + w_u * (U[q] - Uo[q]);
@@ -1641,7 +1650,7 @@ struct FaceAdjArgs {
   double* bfbar;
   double* gbar;
   double gam, weno_eps, weno_q;
-  int speeds;
+  int speeds, riemann;
 };
 
 template <int D, int RECON>
@@ -1732,7 +1741,28 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
 #pragma unroll
     for (int q = 0; q < 7; ++q) fbar[q] = fa.fbar[(size_t)(D * 7 + q) * g.N + id];
     double Ub[7], Fb[7], cmb = 0.0, cpb = 0.0;
-    if (den > 0.0) {
+    if (fa.riemann == ASTERX_RIEMANN_LXF) {
+      // (F_L + F_R - c_wave (U_R - U_L)) / 2 transposed; c_wave = max(cmax, cmin)
+      const double cw = fmax(cmax, cmin);
+      double dcw = 0.0;
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        Fb[q] = 0.5 * fbar[q];
+        Ub[q] = (side ? -0.5 : 0.5) * cw * fbar[q];
+        const double UL = side ? Uo[q] : U[q], UR = side ? U[q] : Uo[q];
+        dcw -= 0.5 * fbar[q] * (UR - UL);
+      }
+      double dcmax = cmax > cmin ? dcw : (cmax == cmin ? 0.5 * dcw : 0.0);
+      double dcmin = cmin > cmax ? dcw : (cmax == cmin ? 0.5 * dcw : 0.0);
+      if (cmax > 0.0) {
+        if (cp == cpo) cpb = 0.5 * dcmax;
+        else if (cp > cpo) cpb = dcmax;
+      }
+      if (cmin > 0.0) {
+        if (cm == cmo) cmb = -0.5 * dcmin;
+        else if (cm < cmo) cmb = -dcmin;
+      }
+    } else if (den > 0.0) {
       double id_ = 1.0 / den, cc = cmax * cmin;
       double wF = (side ? cmin : cmax) * id_, wU = (side ? -cc : cc) * id_;
       double dcmax = 0.0, dcmin = 0.0;
@@ -2258,7 +2288,8 @@ int check_grid(const asterx_grid* g, int min_ng) {
 int check_params(const asterx_params* p) {
   if (!p) return fail(ASTERX_EARG, "params is NULL");
   if (!(p->gamma > 1.0)) return fail(ASTERX_EARG, "params: gamma must be > 1");
-  if (p->recon < 0 || p->recon > 2) return fail(ASTERX_EARG, "params: unknown reconstruction");
+  if (p->recon < 0 || p->recon > 3) return fail(ASTERX_EARG, "params: unknown reconstruction");
+  if (p->riemann < 0 || p->riemann > 1) return fail(ASTERX_EARG, "params: unknown Riemann solver");
   if (p->gauge < 0 || p->gauge > 1) return fail(ASTERX_EARG, "params: unknown gauge");
   if (p->speeds < 0 || p->speeds > 1) return fail(ASTERX_EARG, "params: unknown speed estimate");
   if (p->c2p_method < 0 || p->c2p_method > 2) return fail(ASTERX_EARG, "params: unknown c2p method");
@@ -2408,6 +2439,7 @@ int faces_r(const GD& g, const asterx_batch* b, const FaceArgs& fa, hipStream_t 
 int faces(const GD& g, const asterx_batch* b, const FaceArgs& fa, int recon, hipStream_t s) {
   if (recon == ASTERX_RECON_MINMOD) return faces_r<ASTERX_RECON_MINMOD>(g, b, fa, s);
   if (recon == ASTERX_RECON_PPM) return faces_r<ASTERX_RECON_PPM>(g, b, fa, s);
+  if (recon == ASTERX_RECON_MP5) return faces_r<ASTERX_RECON_MP5>(g, b, fa, s);
   return faces_r<ASTERX_RECON_WENOZ>(g, b, fa, s);
 }
 
@@ -2461,7 +2493,7 @@ int do_rhs(const GD& g, const asterx_batch* b, const asterx_params* p, const dou
   double* fp = ws + 25 * g.N;
   if ((rc = RUN_PHASE(KT_BCENT, PH_BCENT, k_bcent, kb_bcent, A, bc))) return rc;
   FaceArgs fa{metric, prim, A, bc, flux, red, p->gamma, p->weno_eps, p->weno_q, p->gamma / (p->gamma - 1.0),
-              p->recon, p->speeds};
+              p->recon, p->speeds, p->riemann};
   if ((rc = faces(g, b, fa, p->recon, s))) return rc;
   CellArgs ca{metric, curv, prim, A, bc, flux, rhs, red, p->gamma, cmb};
   if ((rc = RUN_PHASE(KT_CELL, PH_CELL, k_cell, kb_cell, ca))) return rc;
@@ -2583,7 +2615,7 @@ int asterx_timing_reset(void) {
 
 const char* asterx_timing_name(int32_t k) { return (k >= 0 && k < KT_N) ? kt_names[k] : ""; }
 
-int asterx_version(void) { return 3; }
+int asterx_version(void) { return 4; }
 
 const char* asterx_last_error(void) { return g_err.c_str(); }
 
@@ -3001,9 +3033,11 @@ int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
   nb = box_blocks<64, 4>(ev);
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_fluxbar, dim3(nb), dim3(256), 0, s, g, fb); }))) return rc;
   FaceAdjArgs fa{metric, ws + AW_PRIM * g.N, A, ws + AW_BC * g.N, ws + AW_FBAR * g.N, ws + AW_PBAR * g.N,
-                 ws + AW_BCBAR * g.N, ws + AW_BFBAR * g.N, slots, p->gamma, p->weno_eps, p->weno_q, p->speeds};
+                 ws + AW_BCBAR * g.N, ws + AW_BFBAR * g.N, slots, p->gamma, p->weno_eps, p->weno_q, p->speeds,
+                 p->riemann};
   if (p->recon == ASTERX_RECON_MINMOD) rc = adj_faces_r<ASTERX_RECON_MINMOD>(g, fa, s);
   else if (p->recon == ASTERX_RECON_PPM) rc = adj_faces_r<ASTERX_RECON_PPM>(g, fa, s);
+  else if (p->recon == ASTERX_RECON_MP5) rc = adj_faces_r<ASTERX_RECON_MP5>(g, fa, s);
   else rc = adj_faces_r<ASTERX_RECON_WENOZ>(g, fa, s);
   if (rc) return rc;
   CellAdjArgs ca{metric, curv, ws + AW_PRIM * g.N, ws + AW_BC * g.N, rhs_bar, ws + AW_PBAR * g.N,

@@ -364,6 +364,40 @@ DEV T wenoz_face(T m2, T m1, T c0, T p1, T p2, double eps, double q) {
   return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0 * (w0 + w1 + w2));
 }
 
+// MP5 (Suresh & Huynh 1997; cited in Sec. 3.3) value at the right face of the middle cell of
+// (m2..p2): the fifth-order interpolant, or, when it leaves the monotonicity-preserving range
+// between c0 and c0 + minmod(p1 - c0, 4 (c0 - m1)), its median with the accuracy-preserving
+// bounds built from the M4 curvatures.  The median is continuous across that test, so a
+// rounding-level change of the interpolant never switches the result between branches.
+template <class T>
+DEV T tmin(T x, T y) { return val(y) < val(x) ? y : x; }
+template <class T>
+DEV T tmax(T x, T y) { return val(y) > val(x) ? y : x; }
+template <class T>
+DEV T minmod4(T w, T x, T y, T z) {
+  const bool pos = val(w) > 0.0 && val(x) > 0.0 && val(y) > 0.0 && val(z) > 0.0;
+  const bool neg = val(w) < 0.0 && val(x) < 0.0 && val(y) < 0.0 && val(z) < 0.0;
+  T lo = tmin(tmin(w, x), tmin(y, z)), hi = tmax(tmax(w, x), tmax(y, z));
+  return pos ? lo : (neg ? hi : T(0.0 * val(w)));
+}
+
+template <class T>
+DEV T mp5_face(T m2, T m1, T c0, T p1, T p2) {
+  const double alpha = 4.0;
+  T f_or = (2.0 * m2 - 13.0 * m1 + 47.0 * c0 + 27.0 * p1 - 3.0 * p2) * (1.0 / 60.0);
+  T f_mp = c0 + mm(p1 - c0, alpha * (c0 - m1));
+  T d_m = m2 - 2.0 * m1 + c0, d_0 = m1 - 2.0 * c0 + p1, d_p = c0 - 2.0 * p1 + p2;
+  T dr = minmod4(4.0 * d_0 - d_p, 4.0 * d_p - d_0, d_0, d_p);
+  T dl = minmod4(4.0 * d_0 - d_m, 4.0 * d_m - d_0, d_0, d_m);
+  T f_ul = c0 + alpha * (c0 - m1);
+  T f_md = 0.5 * (c0 + p1) - 0.5 * dr;
+  T f_lc = c0 + 0.5 * (c0 - m1) + (4.0 / 3.0) * dl;
+  T f_min = tmax(tmin(tmin(c0, p1), f_md), tmin(tmin(c0, f_ul), f_lc));
+  T f_max = tmin(tmax(tmax(c0, p1), f_md), tmax(tmax(c0, f_ul), f_lc));
+  T lim = f_or + mm(f_min - f_or, f_max - f_or);
+  return val(f_or - c0) * val(f_or - f_mp) <= 0.0 ? f_or : lim;
+}
+
 // ---------------------------------------------------------------------------------------
 // Conservative-to-primitive recovery (Sec. 3.5) and atmosphere (Sec. 3.6).
 struct C2PParams {

@@ -36,16 +36,16 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2406_11669_amd import asterx
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "asterx.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(asterx_grid), '
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(asterx_grid), '
                    'offsetof(asterx_grid, dx), sizeof(asterx_params), offsetof(asterx_params, c2p_maxit), '
                    'offsetof(asterx_params, c2p_method), sizeof(asterx_c2p_stats), '
-                   'offsetof(asterx_params, weno_q));return 0;}\n')
+                   'offsetof(asterx_params, weno_q), offsetof(asterx_params, riemann));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert vals == [ctypes.sizeof(asterx.Grid), asterx.Grid.dx.offset, ctypes.sizeof(asterx.Params),
                     asterx.Params.c2p_maxit.offset, asterx.Params.c2p_method.offset, 48,
-                    asterx.Params.weno_q.offset]
+                    asterx.Params.weno_q.offset, asterx.Params.riemann.offset]
 
 
 def test_host_side_argument_validation(lib):

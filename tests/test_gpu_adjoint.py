@@ -53,11 +53,13 @@ def test_adjoint_periodic_riemann_vs_oracle_jvp(adj, orc):
     _check_dirs(orc, w, 2, loss, g, gg, dirs, 1e-10)
 
 
-@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz"])
-def test_adjoint_curved_rk4_vs_oracle_jvp(adj, orc, recon):
+@pytest.mark.parametrize("recon,riemann", [("minmod", "hlle"), ("ppm", "hlle"), ("wenoz", "hlle"), ("mp5", "hlle"),
+                                           ("ppm", "lxf")])
+def test_adjoint_curved_rk4_vs_oracle_jvp(adj, orc, recon, riemann):
     """Periodic block in a curved static metric (lapse, shift, curvature sources active), RK4, one step."""
     w = W.curved_block(seed=42, n=(12, 10, 9), recon=recon, nsteps=1, vmax=0.3)
-    print("case adjoint curved", recon, flush=True)
+    w.params["riemann"] = riemann
+    print("case adjoint curved", recon, riemann, flush=True)
     loss, g, gg, _ = _grad(adj, w, 1)
     dirs = [W.gradient_direction(w.layout, 3), (w.layout.zeros(5), 1.0)]
     _check_dirs(orc, w, 1, loss, g, gg, dirs, 1e-10)
@@ -77,7 +79,11 @@ def test_adjoint_forward_equals_plain_driver(adj):
 # ---- dot-product tests of each adjoint entry point against the oracle's JVP of the same map --------------------
 
 def _curved(recon, seed=44):
-    return W.curved_block(seed=seed, n=(12, 10, 9), recon=recon, nsteps=1, vmax=0.3)
+    """recon may carry a Riemann solver: "ppm+lxf"."""
+    rec, _, riemann = recon.partition("+")
+    w = W.curved_block(seed=seed, n=(12, 10, 9), recon=rec, nsteps=1, vmax=0.3)
+    w.params["riemann"] = riemann or "hlle"
+    return w
 
 
 def _dev(a):
@@ -112,7 +118,7 @@ def _stage_inputs(orc, w):
 
 
 @pytest.mark.parametrize("part", ["cons", "A", "psi", "gamma"])
-@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz"])
+@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz", "mp5", "ppm+lxf"])
 def test_rhs_adjoint_dot_product(adj, orc, recon, part):
     """<ybar, J v> (oracle dual numbers) = <J^T ybar, v> (asterx_rhs_adjoint) for one stage's right-hand side,
     tangent in one input at a time."""

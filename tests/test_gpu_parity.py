@@ -157,10 +157,12 @@ def _rhs_case(ax, torch, orc, w):
     return _host(out), ref, _host(red), red_ref
 
 
-@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz"])
+@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz", "mp5", "ppm+lxf", "mp5+lxf"])
 @pytest.mark.parametrize("shape", [(70, 9, 7), (13, 11, 9)])
 def test_rhs_parity_curved(ax, torch_mod, orc, recon, shape):
-    w = W.curved_block(seed=15, n=shape, recon=recon)
+    rec, _, riemann = recon.partition("+")
+    w = W.curved_block(seed=15, n=shape, recon=rec)
+    w.params["riemann"] = riemann or "hlle"
     w.psi = w.layout.zeros(1) + 0.01 * np.random.default_rng(3).normal(size=(1,) + w.layout.shape3)
     print("case rhs", recon, shape, flush=True)
     g, c, red, red_ref = _rhs_case(ax, torch_mod, orc, w)
@@ -169,9 +171,11 @@ def test_rhs_parity_curved(ax, torch_mod, orc, recon, shape):
     assert red[1] <= 1e-12 * 1e3 and red_ref[1] <= 1e-12 * 1e3
 
 
-def test_rhs_parity_riemann32(ax, torch_mod, orc):
-    w = W.riemann_block(seed=16, n=32)
-    print("case rhs riemann32", flush=True)
+@pytest.mark.parametrize("recon,riemann", [("minmod", "hlle"), ("mp5", "lxf")])
+def test_rhs_parity_riemann32(ax, torch_mod, orc, recon, riemann):
+    w = W.riemann_block(seed=16, n=32, recon=recon)
+    w.params["riemann"] = riemann
+    print("case rhs riemann32", recon, riemann, flush=True)
     g, c, red, red_ref = _rhs_case(ax, torch_mod, orc, w)
     assert_fields_close(g, c, 1e-12, w.layout.owned, STATE_NAMES)
 
@@ -201,9 +205,11 @@ def test_steps_parity_riemann32(ax, torch_mod, orc):
     assert st[3] == 0 and stats[3] == 0
 
 
-@pytest.mark.parametrize("recon", ["ppm", "wenoz"])
+@pytest.mark.parametrize("recon", ["ppm", "wenoz", "mp5", "ppm+lxf"])
 def test_steps_parity_curved(ax, torch_mod, orc, recon):
-    w = W.curved_block(seed=18, n=(20, 13, 11), recon=recon, nsteps=2)
+    rec, _, riemann = recon.partition("+")
+    w = W.curved_block(seed=18, n=(20, 13, 11), recon=rec, nsteps=2)
+    w.params["riemann"] = riemann or "hlle"
     print("case steps curved", recon, flush=True)
     blk, state, prim, stats, red = _run_both(ax, torch_mod, orc, w, 2)
     assert_fields_close(_host(blk.state), state, 1e-10, w.layout.owned, STATE_NAMES)
