@@ -61,10 +61,12 @@ struct Params {
   int32_t speeds;       // 0 quartic, 1 quadratic bound
   int32_t c2p_method;   // 0 Noble then Palenzuela, 1 Noble only, 2 Palenzuela only
   int32_t riemann;      // 0 HLLE, 1 Lax-Friedrichs
+  int32_t ct;           // electric field on edges: 0 flux CT, 1 upwind CT
 };
 
 enum { REC_MINMOD = 0, REC_PPM = 1, REC_WENOZ = 2, REC_MP5 = 3 };
 enum { RIEMANN_HLLE = 0, RIEMANN_LXF = 1 };
+enum { CT_FCT = 0, CT_UCT = 1 };
 enum { GAUGE_LORENZ = 0, GAUGE_ALGEBRAIC = 1 };
 enum { SPEED_QUARTIC = 0, SPEED_BOUND = 1 };
 enum { BC_PERIODIC = 0, BC_COPY = 1, BC_LINEAR = 2 };
@@ -1182,12 +1184,18 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
         for (int c = 0; c < 3; ++c) Bc[c * N + at(g, i, j, k)] = b[c];
       }
   phase_mark<T>(0);
-  // face fluxes: 3 directions x 7 components
+  // face fluxes: 3 directions x 7 components.  Upwind CT also keeps, per face, the upwind
+  // transverse velocities (eq. uct1) and the two speeds a_+ = c_max, a_- = c_min (eq. uct2), on
+  // the faces its PPM reconstruction to the edges reaches: transverse indices [-3, n+1].
+  const bool uct = P.ct == CT_UCT;
+  const int tlo = uct ? -3 : -1, thi_ext = uct ? 1 : -1;
   std::vector<T> flux(21 * N, T(0));
+  std::vector<T> vbar(uct ? 9 * N : 0, T(0));  // [d][component]: transverse ones set
+  std::vector<T> apm(uct ? 6 * N : 0, T(0));   // [d][+/-]
   double vmax = 0.0;
   long long nfix = 0;
   for (int d = 0; d < 3; ++d) {
-    int lo[3] = {-1, -1, -1}, hi[3] = {g.n[0] - 1, g.n[1] - 1, g.n[2] - 1};
+    int lo[3] = {tlo, tlo, tlo}, hi[3] = {g.n[0] + thi_ext, g.n[1] + thi_ext, g.n[2] + thi_ext};
     lo[d] = 0;
     hi[d] = g.n[d];
     for (int k = lo[2]; k <= hi[2]; ++k)
@@ -1213,10 +1221,21 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
           T Fo[7], cmax, cmin;
           riemann_flux(P.riemann, UL, FL, cmL, cpL, UR, FR, cmR, cpR, Fo, cmax, cmin);
           for (int c = 0; c < 7; ++c) flux[(d * 7 + c) * N + at(g, i, j, k)] = Fo[c];
+          if (uct) {
+            // transport velocities vt^j = alpha v^j - beta^j of both sides, upwinded (eq. uct1)
+            for (int t : {t1, t2}) {
+              T vL = G.alp * L[2 + t] - G.beta[t], vR = G.alp * R[2 + t] - G.beta[t];
+              T den = cmax + cmin;
+              vbar[(d * 3 + t) * N + at(g, i, j, k)] =
+                  den > T(0) ? (cmax * vL + cmin * vR) / den : (vL + vR) / T(2);
+            }
+            apm[(d * 2 + 0) * N + at(g, i, j, k)] = cmax;
+            apm[(d * 2 + 1) * N + at(g, i, j, k)] = cmin;
+          }
           bool owned = true;
           int id[3] = {i, j, k};
           for (int t = 0; t < 3; ++t)
-            if (t != d && id[t] < 0) owned = false;
+            if (t != d && (id[t] < 0 || id[t] >= g.n[t])) owned = false;
           if (owned) {
             double s = std::max(value_of(cmax), value_of(cmin));
             if (s > vmax) vmax = s;
@@ -1292,15 +1311,51 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
           FP[a * N + at(g, i, j, k)] = G.alp * G.sqrtg * Au - G.beta[a] * ps;
         }
       }
+  // Upwind CT (Sec. 3.4, eq. eq3.20): E_c on the c-edge owned by point p, with a = c+1, b = c+2
+  // (cyclic).  The a-directed term takes the b-faces in the row through the edge along a: their
+  // upwind velocity component a and their normal field B^b, PPM-reconstructed to the edge from
+  // either side (L: right face of the element below the edge, R: left face of the element above),
+  // with the speeds of the two a-faces that meet at the edge (the larger of each); the b-directed
+  // term likewise with a and b exchanged.  E_c = -(a term) + (b term); for c = z this is eq3.20.
+  auto uct_term = [&](int dir, int fd, const int p[3], int sdir) -> T {
+    // dir: direction of the 1-D Riemann problem at the edge; fd: normal of the faces sampled along
+    // dir; sdir: the direction separating the two dir-faces that meet at the edge
+    T v6[6], b6[6];
+    for (int s = 0; s < 6; ++s) {
+      int q[3] = {p[0], p[1], p[2]};
+      q[dir] += s - 3;
+      v6[s] = vbar[(fd * 3 + dir) * N + at(g, q[0], q[1], q[2])];
+      b6[s] = face_B(g, A, fd, q[0], q[1], q[2]);
+    }
+    T vL, vR, bL, bR;
+    reconstruct_face(REC_PPM, v6, vL, vR, P);
+    reconstruct_face(REC_PPM, b6, bL, bR, P);
+    int q[3] = {p[0], p[1], p[2]};
+    q[sdir] -= 1;
+    T ap0 = apm[(dir * 2 + 0) * N + at(g, p[0], p[1], p[2])], ap1 = apm[(dir * 2 + 0) * N + at(g, q[0], q[1], q[2])];
+    T am0 = apm[(dir * 2 + 1) * N + at(g, p[0], p[1], p[2])], am1 = apm[(dir * 2 + 1) * N + at(g, q[0], q[1], q[2])];
+    T ap = ap0 > ap1 ? ap0 : ap1, am = am0 > am1 ? am0 : am1;
+    T den = ap + am;
+    if (!(den > T(0))) return (vL * bL + vR * bR) / T(2);
+    return (ap * vL * bL + am * vR * bR - ap * am * (bR - bL)) / den;
+  };
   double xi = P.xi / dt_max;
   for (int k = 0; k < g.n[2]; ++k)
     for (int j = 0; j < g.n[1]; ++j)
       for (int i = 0; i < g.n[0]; ++i) {
         size_t id = at(g, i, j, k);
-        T Ez = (-FX(0, 1, i, j, k) - FX(0, 1, i, j - 1, k) + FX(1, 0, i, j, k) + FX(1, 0, i - 1, j, k)) / T(4);
-        T Ex = (-FX(1, 2, i, j, k) - FX(1, 2, i, j, k - 1) + FX(2, 1, i, j, k) + FX(2, 1, i, j - 1, k)) / T(4);
-        T Ey = (-FX(2, 0, i, j, k) - FX(2, 0, i - 1, j, k) + FX(0, 2, i, j, k) + FX(0, 2, i, j, k - 1)) / T(4);
-        T E[3] = {Ex, Ey, Ez};
+        T E[3];
+        if (uct) {
+          const int p[3] = {i, j, k};
+          for (int c = 0; c < 3; ++c) {
+            int a = (c + 1) % 3, b = (c + 2) % 3;
+            E[c] = -uct_term(a, b, p, b) + uct_term(b, a, p, a);
+          }
+        } else {
+          E[2] = (-FX(0, 1, i, j, k) - FX(0, 1, i, j - 1, k) + FX(1, 0, i, j, k) + FX(1, 0, i - 1, j, k)) / T(4);
+          E[0] = (-FX(1, 2, i, j, k) - FX(1, 2, i, j, k - 1) + FX(2, 1, i, j, k) + FX(2, 1, i, j - 1, k)) / T(4);
+          E[1] = (-FX(2, 0, i, j, k) - FX(2, 0, i - 1, j, k) + FX(0, 2, i, j, k) + FX(0, 2, i, j, k - 1)) / T(4);
+        }
         size_t nb[3] = {at(g, i + 1, j, k), at(g, i, j + 1, k), at(g, i, j, k + 1)};
         for (int a = 0; a < 3; ++a) {
           T r = -E[a];

@@ -32,11 +32,12 @@ class Params(ctypes.Structure):
                 ("weno_eps", ctypes.c_double), ("weno_q", ctypes.c_double),
                 ("c2p_maxit", ctypes.c_int32), ("brent_maxit", ctypes.c_int32), ("recon", ctypes.c_int32),
                 ("gauge", ctypes.c_int32), ("speeds", ctypes.c_int32), ("c2p_method", ctypes.c_int32),
-                ("riemann", ctypes.c_int32)]
+                ("riemann", ctypes.c_int32), ("ct", ctypes.c_int32)]
 
 
 RECON = {"minmod": 0, "ppm": 1, "wenoz": 2, "mp5": 3}
 RIEMANN = {"hlle": 0, "lxf": 1}
+CT = {"fct": 0, "uct": 1}
 BC = {"periodic": 0, "copy": 1, "linear": 2}
 
 
@@ -97,7 +98,16 @@ def make_params(p):
     P.c2p_method = p.get("c2p_method", 0)
     r = p.get("riemann", "hlle")
     P.riemann = RIEMANN[r] if isinstance(r, str) else r
+    c = p.get("ct", "fct")
+    P.ct = CT[c] if isinstance(c, str) else c
     return P
+
+
+def _check_ct(layout, params):
+    """Upwind CT reconstructs face values three faces beyond the edge, whose face metric reaches the
+    fourth vertex layer: it needs ng >= 4."""
+    if params.get("ct", "fct") in ("uct", 1) and layout.ng < 4:
+        raise ValueError("upwind CT needs ng >= 4")
 
 
 def prim2con(layout, params, metric, A, prim):
@@ -131,6 +141,7 @@ def fill_ghosts(layout, f, kinds):
 
 
 def rhs(layout, params, metric, curv, prim, A, psi, dt_max):
+    _check_ct(layout, params)
     out = np.zeros((9,) + layout.shape3, dtype=np.float64)
     red = np.zeros(2, dtype=np.float64)
     nfix = ctypes.c_longlong(0)
@@ -150,6 +161,7 @@ def rk_stage(layout, a, us, b_dt, rhs_arr, out):
 def run(layout, params, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A, A_shift=None):
     """Advance state (9 fields) and prim in place by nsteps.  Returns (flags, stats, redmax).
     A_shift (3x3, optional): periodic fill of A with A_shift[q, d] added per period along axis d."""
+    _check_ct(layout, params)
     flags = np.zeros(layout.shape3, dtype=np.uint8)
     stats = np.zeros(6, dtype=np.uint64)
     redmax = np.zeros(2, dtype=np.float64)
@@ -166,6 +178,7 @@ def run(layout, params, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A
 def count_ops(layout, params, metric, curv, prim, A, psi, dt_max):
     """Algorithmic FP64 operation counts of one right-hand side and one c2p on this block:
     dict(centre_B, faces, cells, ct, c2p) in operations (each +, -, *, /, sqrt, pow counts one)."""
+    _check_ct(layout, params)
     out = np.zeros(5, dtype=np.uint64)
     lib().orc_count_ops(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), _p(metric), _p(curv),
                         _p(prim), _p(A), _p(psi), ctypes.c_double(dt_max), out.ctypes.data_as(ctypes.c_void_p))
@@ -304,6 +317,7 @@ def loss_jvp(layout, params, metric, curv, prim0, A0, psi0, dt, nsteps, rk, bc_c
              A_shift=None):
     """Loss (sum over owned cells of rho^2 dV)^(1/2) after nsteps from prim0, and its directional derivative
     along (dprim0, dgamma), by forward-mode dual numbers through the whole run.  Returns (loss, jvp, stats)."""
+    _check_ct(layout, params)
     out = np.zeros(2, dtype=np.float64)
     stats = np.zeros(6, dtype=np.uint64)
     bcc = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_cell])
@@ -346,6 +360,7 @@ def c2p_jvp(layout, params, metric, A, cons, guess, dA=None, dcons=None, dgamma=
 def stage_jvp(layout, params, metric, curv, cons, A, psi, guess, dt_max, dcons=None, dA=None, dpsi=None,
               dgamma=0.0):
     """(L, dL) of one stage's right-hand side rhs(fill(c2p(cons, A)), A, psi) along the tangent; owned points."""
+    _check_ct(layout, params)
     out = np.zeros((9,) + layout.shape3)
     dout = np.zeros_like(out)
     keep = [np.ascontiguousarray(x, dtype=np.float64) if x is not None else None for x in (dcons, dA, dpsi)]

@@ -90,7 +90,7 @@ class Layout:
 def default_params(**kw):
     p = dict(gamma=5.0 / 3.0, rho_atm=1e-10, k_atm=1.0, xi=1.5, c2p_tol=1e-14, wmax=1e3, weno_eps=1e-40,
              weno_q=1.0, c2p_maxit=50, brent_maxit=100, recon="minmod", gauge="lorenz", speeds="quartic",
-             c2p_method=0, riemann="hlle")
+             c2p_method=0, riemann="hlle", ct="fct")
     p.update(kw)
     return p
 
