@@ -29,7 +29,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 128 FLOP/clk x 
 # the plain serial implementation on an operation-counting scalar (+, -, *, /, sqrt, pow = 1 each) over the
 # 3 x 129^3 faces of the 128^3 block of this workload (same seed and recipe; limiter branches make the count
 # data dependent).
-FACE_FLOPS = {"ppm": 2603.1, "wenoz": 3955.0, "minmod": 2022.6, "mp5": 2480.3, "ppm+lxf": 2581.1}
+FACE_FLOPS = {"ppm": 2603.1, "wenoz": 3955.0, "minmod": 2022.6, "mp5": 2480.3, "ppm+lxf": 2581.1,
+              "ppm+hlle+uct": 2620.8}
 # Algorithmic bytes per face: read 5 primitives + 2 centre fields + 10 face-metric components + 2 potential
 # components, write 7 face fluxes (each value once, stencil reuse served on chip).
 FACE_BYTES = 8.0 * (5 + 2 + 10 + 2 + 7)
@@ -41,7 +42,8 @@ STAGE_BYTES_RK4 = 514.0
 # right-hand side and one c2p of the 128^3 block of this workload; for PPM: centre field 41, faces of
 # the three directions 7994, cell sources and divergence 5598, constrained transport and gauge 139, c2p
 # 3265; the RK combine's 2 operations per field are not counted).
-STAGE_FLOPS = {"ppm": 17036.9, "wenoz": 21188.6, "minmod": 15254.4, "mp5": 16659.9, "ppm+lxf": 16969.3}
+STAGE_FLOPS = {"ppm": 17036.9, "wenoz": 21188.6, "minmod": 15254.4, "mp5": 16659.9, "ppm+lxf": 16969.3,
+               "ppm+hlle+uct": 19021.8}  # upwind CT: 129 x 133^2 faces per direction, edge field 1561
 
 
 def library_source_sha():
@@ -79,6 +81,8 @@ def parse():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--recon", default="ppm", choices=["ppm", "wenoz", "minmod", "mp5"])
     ap.add_argument("--riemann", default="hlle", choices=["hlle", "lxf"])
+    ap.add_argument("--ct", default="fct", choices=["fct", "uct"],
+                    help="edge electric field: flux CT or upwind CT (4 ghost layers)")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=56, help="edge of the block the CPU oracle times")
@@ -103,13 +107,14 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
-def cpu_baseline(recon, riemann, n_cpu):
+def cpu_baseline(recon, riemann, ct, n_cpu):
     """The serial oracle, as it stands, on an n_cpu^3 block of the same workload: one RK4 step."""
     from oracle import oracle as O
     from paper_2406_11669_amd import workloads as W
     O.build(force=False)
-    w = W.curved_block(seed=0, n=n_cpu, recon=recon, nsteps=1)
+    w = W.curved_block(seed=0, n=n_cpu, recon=recon, nsteps=1, ng=4 if ct == "uct" else 3)
     w.params["riemann"] = riemann
+    w.params["ct"] = ct
     L = w.layout
     cons = O.prim2con(L, w.params, w.metric, w.A, w.prim)
     O.fill_ghosts(L, cons, w.bc_cell)
@@ -142,9 +147,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     n = args.n
-    w = W.curved_block(seed=0, n=n, recon=args.recon, nsteps=args.steps)
+    w = W.curved_block(seed=0, n=n, recon=args.recon, nsteps=args.steps, ng=4 if args.ct == "uct" else 3)
     w.params["riemann"] = args.riemann
-    scheme = args.recon if args.riemann == "hlle" else args.recon + "+" + args.riemann
+    w.params["ct"] = args.ct
+    scheme = args.recon
+    if args.riemann != "hlle" or args.ct != "fct":
+        scheme += "+" + args.riemann
+    if args.ct != "fct":
+        scheme += "+" + args.ct
     blk = asterx.Block(w)
     learned_info = None
     if args.learned_c2p:
@@ -203,7 +213,7 @@ def main():
     face_ms = sum(kt[k][0] for k in ("face_x", "face_y", "face_z"))
     face_launches = sum(kt[k][1] for k in ("face_x", "face_y", "face_z"))
     dominant = max(((k, v[0]) for k, v in kt.items()), key=lambda kv: kv[1])[0]
-    faces_per_launch = (n + 1) ** 3
+    faces_per_launch = (n + 1) ** 3 if args.ct == "fct" else (n + 1) * (n + 5) ** 2
     avg_face_s = face_ms * 1e-3 / face_launches
     face_flops = FACE_FLOPS.get(scheme)
     achieved = face_flops * faces_per_launch / avg_face_s / 1e12 if face_flops else None
@@ -227,7 +237,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "curved%d-%s-rk4" % (n, scheme.replace("+", "-")), "n": n, "ng": w.layout.ng,
-                      "recon": args.recon, "riemann": args.riemann, "rk": 4, "stages_per_step": stages, "cfl": 0.25, "gamma": 2.0,
+                      "recon": args.recon, "riemann": args.riemann, "ct": args.ct, "rk": 4, "stages_per_step": stages, "cfl": 0.25, "gamma": 2.0,
                       "speeds": "quartic", "graph": graph is not None,
                       "c2p_guess": "learned" if args.learned_c2p else "warm"},
            "roofline": roofline, "hbm_roofline_stage": hbm, "fp64_roofline_stage": fp64,
@@ -237,7 +247,7 @@ def main():
         out["learned_c2p"] = learned_info
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a %d^3 sample" % args.cpu_n, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.recon, args.riemann, args.cpu_n)
+        out["cpu_baseline"] = cpu_baseline(args.recon, args.riemann, args.ct, args.cpu_n)
     print(json.dumps(out), flush=True)
 
 

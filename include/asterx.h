@@ -46,6 +46,7 @@ extern "C" {
 
 enum { ASTERX_RECON_MINMOD = 0, ASTERX_RECON_PPM = 1, ASTERX_RECON_WENOZ = 2, ASTERX_RECON_MP5 = 3 };
 enum { ASTERX_RIEMANN_HLLE = 0, ASTERX_RIEMANN_LXF = 1 };
+enum { ASTERX_CT_FCT = 0, ASTERX_CT_UCT = 1 };
 enum { ASTERX_GAUGE_LORENZ = 0, ASTERX_GAUGE_ALGEBRAIC = 1 };
 enum { ASTERX_SPEEDS_QUARTIC = 0, ASTERX_SPEEDS_BOUND = 1 };
 enum { ASTERX_C2P_NOBLE_PALENZUELA = 0, ASTERX_C2P_NOBLE_ONLY = 1, ASTERX_C2P_PALENZUELA_ONLY = 2 };
@@ -85,6 +86,11 @@ typedef struct {
   int32_t speeds;      /* ASTERX_SPEEDS_* */
   int32_t c2p_method;  /* ASTERX_C2P_* */
   int32_t riemann;     /* ASTERX_RIEMANN_*: HLLE (Sec. 3.3 eq. HLLEfluxes) or Lax-Friedrichs (eq. LxFfluxes) */
+  int32_t ct;          /* ASTERX_CT_*: edge electric field by flux CT (averaged face induction fluxes) or
+                          upwind CT (Sec. 3.4, eqs. uct1, uct2, eq3.20: upwind face velocities and face
+                          fields reconstructed to the edges by PPM).  Upwind CT needs ng >= 4, is for
+                          single blocks (asterx_rhs, asterx_rhs_rk; the batch calls refuse it) and is
+                          not differentiated (asterx_rhs_adjoint refuses it). */
 } asterx_params;
 
 /* Device-side counters, accumulated (never reset) by asterx_c2p. */

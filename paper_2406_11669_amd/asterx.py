@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libasterx.so")
 
 RECON = {"minmod": 0, "ppm": 1, "wenoz": 2, "mp5": 3}
 RIEMANN = {"hlle": 0, "lxf": 1}
+CT = {"fct": 0, "uct": 1}
 GAUGE = {"lorenz": 0, "algebraic": 1}
 SPEEDS = {"quartic": 0, "bound": 1}
 BC = {"periodic": 0, "copy": 1, "linear": 2}
@@ -47,7 +48,7 @@ class Params(ctypes.Structure):
                 ("weno_eps", ctypes.c_double), ("weno_q", ctypes.c_double),
                 ("c2p_maxit", ctypes.c_int32), ("brent_maxit", ctypes.c_int32), ("recon", ctypes.c_int32),
                 ("gauge", ctypes.c_int32), ("speeds", ctypes.c_int32), ("c2p_method", ctypes.c_int32),
-                ("riemann", ctypes.c_int32)]
+                ("riemann", ctypes.c_int32), ("ct", ctypes.c_int32)]
 
 
 class RKOut(ctypes.Structure):
@@ -174,6 +175,8 @@ def make_params(p):
     P.c2p_method = int(p.get("c2p_method", 0))
     r = p.get("riemann", "hlle")
     P.riemann = RIEMANN[r] if isinstance(r, str) else int(r)
+    c = p.get("ct", "fct")
+    P.ct = CT[c] if isinstance(c, str) else int(c)
     return P
 
 

@@ -34,7 +34,8 @@ namespace {
 thread_local std::string g_err;
 
 // rhs workspace: centre field (3) + face fluxes (3 directions x 7) + G_A (1) + F_Psi (3)
-constexpr int WS_FIELDS = 3 + 21 + 1 + 3;
+// right-hand side workspace: centre field 3, face fluxes 21, G_A 1, F_Psi 3, upwind-CT speeds 6
+constexpr int WS_FIELDS = 3 + 21 + 1 + 3 + 6;
 
 int fail(int code, const char* msg) {
   g_err = msg;
@@ -714,6 +715,7 @@ struct FaceArgs {
   double* red;
   double gam, weno_eps, weno_q, gfac;
   int recon, speeds, riemann;
+  double* apm;  // UCT: a_+ and a_- per direction
 };
 
 // Paired-lane variant: lanes 2f and 2f+1 of a wavefront handle the left and the right state
@@ -765,12 +767,17 @@ struct FaceLDS {
 };
 static_assert(FaceBlk<0>::N <= FACE_LDS && FaceBlk<1>::N <= FACE_LDS && FaceBlk<2>::N <= FACE_LDS, "face LDS");
 
-template <int D, int RECON>
+// UCT: the faces cover transverse indices [-3, n+1] (the upwind edge field reconstructs face
+// values three faces beyond each edge) instead of [-1, n-1], gather directly, and also store the
+// upwind transverse velocities (slots 5, 6 in place of the induction fluxes) and the two speeds.
+template <int D, int RECON, bool UCT = false>
 DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  constexpr int LO = UCT ? 3 : 1;
   using FB = FaceBlk<D>;
   const int side = threadIdx.x & 1;
-  int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
+  int e[3] = {g.n[0] + 2 * LO - 1, g.n[1] + 2 * LO - 1, g.n[2] + 2 * LO - 1};
+  e[D] = g.n[D] + 1;
   int a, b, c;
   bool rest;
   int ax0, by0;
@@ -778,8 +785,8 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   // assumes a 32 x 4 tile, so remainder tiles gather directly
   const bool valid = face_at(e, tile, threadIdx.x >> 1, a, b, c, rest, ax0, by0);
   const int cz = c;
-  int ijk[3] = {a - 1, b - 1, c - 1};
-  ijk[D] += 1;
+  int ijk[3] = {a - LO, b - LO, c - LO};
+  ijk[D] += LO;
   const int id = valid ? at(g, ijk[0], ijk[1], ijk[2]) : 0;
   const int st[3] = {1, g.sy, g.sz};
   const int sD = st[D];
@@ -842,7 +849,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       }
     }
   };
-  if (D == 1 && RECON == ASTERX_RECON_WENOZ && !rest) {
+  if (D == 1 && RECON == ASTERX_RECON_WENOZ && !UCT && !rest) {
     // y faces under WENO-Z: the seven stencil fields of the workgroup's 32 x 4 faces (cells y
     // in [by0 - 3, by0 + 5], x in [ax0 - 1, ax0 + 30]) go through LDS once, coalesced along x
     // (measured faster for WENO-Z only; PPM and MINMOD keep the direct gather).  The leading
@@ -885,7 +892,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   // y and z faces: the direct 16-point gather (one transverse direction is x, so a
   // wavefront's loads are contiguous rows) measured faster than the staged block, except
   // for z faces under WENO-Z
-  constexpr bool METRIC_LDS = !(D == 1 || (D == 2 && RECON != ASTERX_RECON_WENOZ));
+  constexpr bool METRIC_LDS = !UCT && !(D == 1 || (D == 2 && RECON != ASTERX_RECON_WENOZ));
   if (!METRIC_LDS || rest) {
     if (valid) {
       const int s1 = st[t1], s2 = st[t2];
@@ -1004,14 +1011,37 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
     double out[7];
 #pragma unroll
     for (int q = 0; q < 7; ++q) out[q] = w_own * F[q] + w_oth * Fo[q] + w_u * (U[q] - Uo[q]);
-    if (side == 0) {
+    if constexpr (UCT) {
+      // upwind transverse velocities (eq. uct1) with a_+ = cmax, a_- = cmin (eq. uct2)
+      double vbar[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = out[q];
+      for (int k = 0; k < 2; ++k) {
+        const int t = k ? t2 : t1;
+        const double vown = G.alp * X[2 + t] - G.beta[t], voth = shfl1(vown);
+        const double vl = side ? voth : vown, vr = side ? vown : voth;
+        vbar[k] = den > 0.0 ? (cmax * vl + cmin * vr) / den : 0.5 * (vl + vr);
+      }
+      if (side == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = out[q];
+        fa.apm[(size_t)(D * 2) * g.N + id] = cmax;
+        fa.apm[(size_t)(D * 2 + 1) * g.N + id] = cmin;
+      } else {
+        fa.flux[(size_t)(D * 7 + 4) * g.N + id] = out[4];
+        fa.flux[(size_t)(D * 7 + 5) * g.N + id] = vbar[0];
+        fa.flux[(size_t)(D * 7 + 6) * g.N + id] = vbar[1];
+      }
+      if ((unsigned)ijk[t1] < (unsigned)g.n[t1] && (unsigned)ijk[t2] < (unsigned)g.n[t2]) smax = fmax(cmax, cmin);
     } else {
+      if (side == 0) {
 #pragma unroll
-      for (int q = 4; q < 7; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = out[q];
+        for (int q = 0; q < 4; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = out[q];
+      } else {
+#pragma unroll
+        for (int q = 4; q < 7; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = out[q];
+      }
+      if (ijk[t1] >= 0 && ijk[t2] >= 0) smax = fmax(cmax, cmin);
     }
-    if (ijk[t1] >= 0 && ijk[t2] >= 0) smax = fmax(cmax, cmin);
   }
   if (fa.red) {
     double w = wave_max(smax);
@@ -1277,22 +1307,72 @@ struct EdgeArgs {
   double xi;
   int gauge;
   Combine cmb;
+  const double* A;    // UCT: the face fields come from the curl of A
+  const double* apm;  // UCT: a_+ and a_- per face direction
 };
 
+// Normal densitized field on a face of direction FD.
+template <int FD>
+DEV double face_Bn(const GD& g, const double* A, int id) {
+  const double* Ax = A;
+  const double* Ay = A + g.N;
+  const double* Az = A + 2 * g.N;
+  if constexpr (FD == 0) return faceBx(Ay, Az, id, g.sy, g.sz, g);
+  else if constexpr (FD == 1) return faceBy(Ax, Az, id, g.sy, g.sz, g);
+  else return faceBz(Ax, Ay, id, g.sy, g.sz, g);
+}
+
+// One term of the upwind edge field (Sec. 3.4, eq. eq3.20) at the edge owned by point id: the 1-D
+// Riemann problem along DIR, from the FD-faces in the row through the edge along DIR (their upwind
+// velocity component DIR and normal field, PPM-reconstructed to the edge from below (L) and above
+// (R)), with the larger speeds of the two DIR-faces meeting at the edge (offset along SDIR).
+template <int DIR, int FD, int SDIR>
+DEV double uct_term(const GD& g, const EdgeArgs& ea, int id) {
+  const int st[3] = {1, g.sy, g.sz};
+  const int sd = st[DIR];
+  constexpr int slot = DIR == (FD + 1) % 3 ? 5 : 6;
+  const double* vb = ea.flux + (size_t)(FD * 7 + slot) * g.N;
+  double v6[6], b6[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    v6[s] = vb[id + (s - 3) * sd];
+    b6[s] = face_Bn<FD>(g, ea.A, id + (s - 3) * sd);
+  }
+  const double vm[5] = {v6[5], v6[4], v6[3], v6[2], v6[1]}, bm[5] = {b6[5], b6[4], b6[3], b6[2], b6[1]};
+  const double vl = recon_right_face<ASTERX_RECON_PPM>(v6, 0.0, 1.0), vr = recon_right_face<ASTERX_RECON_PPM>(vm, 0.0, 1.0);
+  const double bl = recon_right_face<ASTERX_RECON_PPM>(b6, 0.0, 1.0), br = recon_right_face<ASTERX_RECON_PPM>(bm, 0.0, 1.0);
+  const double* ap = ea.apm + (size_t)(DIR * 2) * g.N;
+  const double* am = ea.apm + (size_t)(DIR * 2 + 1) * g.N;
+  const int o = st[SDIR];
+  const double a_p = fmax(ap[id], ap[id - o]), a_m = fmax(am[id], am[id - o]);
+  const double den = a_p + a_m;
+  if (!(den > 0.0)) return 0.5 * (vl * bl + vr * br);
+  return (a_p * vl * bl + a_m * vr * br - a_p * a_m * (br - bl)) / den;
+}
+
+template <bool UCT = false>
 DEV void edge_body(const GD& g, const EdgeArgs& ea, unsigned tile) {
   int i, j, k;
   if (!box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k)) return;
   const int id = at(g, i, j, k);
   const int sy = g.sy, sz = g.sz;
-  const double* Fx_By = ea.flux + (size_t)(0 * 7 + 5) * g.N;
-  const double* Fx_Bz = ea.flux + (size_t)(0 * 7 + 6) * g.N;
-  const double* Fy_Bz = ea.flux + (size_t)(1 * 7 + 5) * g.N;
-  const double* Fy_Bx = ea.flux + (size_t)(1 * 7 + 6) * g.N;
-  const double* Fz_Bx = ea.flux + (size_t)(2 * 7 + 5) * g.N;
-  const double* Fz_By = ea.flux + (size_t)(2 * 7 + 6) * g.N;
-  double Ez = 0.25 * (-Fx_By[id] - Fx_By[id - sy] + Fy_Bx[id] + Fy_Bx[id - 1]);
-  double Ex = 0.25 * (-Fy_Bz[id] - Fy_Bz[id - sz] + Fz_By[id] + Fz_By[id - sy]);
-  double Ey = 0.25 * (-Fz_Bx[id] - Fz_Bx[id - 1] + Fx_Bz[id] + Fx_Bz[id - sz]);
+  double Ex, Ey, Ez;
+  if constexpr (UCT) {
+    // E_c = -(term along c+1 from the (c+2)-faces) + (term along c+2 from the (c+1)-faces)
+    Ex = -uct_term<1, 2, 2>(g, ea, id) + uct_term<2, 1, 1>(g, ea, id);
+    Ey = -uct_term<2, 0, 0>(g, ea, id) + uct_term<0, 2, 2>(g, ea, id);
+    Ez = -uct_term<0, 1, 1>(g, ea, id) + uct_term<1, 0, 0>(g, ea, id);
+  } else {
+    const double* Fx_By = ea.flux + (size_t)(0 * 7 + 5) * g.N;
+    const double* Fx_Bz = ea.flux + (size_t)(0 * 7 + 6) * g.N;
+    const double* Fy_Bz = ea.flux + (size_t)(1 * 7 + 5) * g.N;
+    const double* Fy_Bx = ea.flux + (size_t)(1 * 7 + 6) * g.N;
+    const double* Fz_Bx = ea.flux + (size_t)(2 * 7 + 5) * g.N;
+    const double* Fz_By = ea.flux + (size_t)(2 * 7 + 6) * g.N;
+    Ez = 0.25 * (-Fx_By[id] - Fx_By[id - sy] + Fy_Bx[id] + Fy_Bx[id - 1]);
+    Ex = 0.25 * (-Fy_Bz[id] - Fy_Bz[id - sz] + Fz_By[id] + Fz_By[id - sy]);
+    Ey = 0.25 * (-Fz_Bx[id] - Fz_Bx[id - 1] + Fx_Bz[id] + Fx_Bz[id - sz]);
+  }
   double* r = ea.rhs;
   const size_t N = g.N;
   if (ea.gauge == ASTERX_GAUGE_LORENZ) {
@@ -1443,6 +1523,11 @@ __global__ __launch_bounds__(256) void k_face(GD g, FaceArgs fa) {
   face_body<D, R>(g, fa, my_tile(), L);
 }
 template <int D, int R>
+__global__ __launch_bounds__(256) void k_face_uct(GD g, FaceArgs fa) {
+  __shared__ FaceLDS L;
+  face_body<D, R, true>(g, fa, my_tile(), L);
+}
+template <int D, int R>
 __global__ __launch_bounds__(256) void kb_face(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                                FaceArgs fa) {
   __shared__ FaceLDS L;
@@ -1494,6 +1579,7 @@ __global__ __launch_bounds__(256) void kb_vertex(const PatchDesc* __restrict__ P
 }
 
 __global__ __launch_bounds__(256) void k_edge(GD g, EdgeArgs ea) { edge_body(g, ea, my_tile()); }
+__global__ __launch_bounds__(256) void k_edge_uct(GD g, EdgeArgs ea) { edge_body<true>(g, ea, my_tile()); }
 __global__ __launch_bounds__(256) void kb_edge(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                                EdgeArgs ea) {
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
@@ -2290,6 +2376,7 @@ int check_params(const asterx_params* p) {
   if (!(p->gamma > 1.0)) return fail(ASTERX_EARG, "params: gamma must be > 1");
   if (p->recon < 0 || p->recon > 3) return fail(ASTERX_EARG, "params: unknown reconstruction");
   if (p->riemann < 0 || p->riemann > 1) return fail(ASTERX_EARG, "params: unknown Riemann solver");
+  if (p->ct < 0 || p->ct > 1) return fail(ASTERX_EARG, "params: unknown electric-field scheme");
   if (p->gauge < 0 || p->gauge > 1) return fail(ASTERX_EARG, "params: unknown gauge");
   if (p->speeds < 0 || p->speeds > 1) return fail(ASTERX_EARG, "params: unknown speed estimate");
   if (p->c2p_method < 0 || p->c2p_method > 2) return fail(ASTERX_EARG, "params: unknown c2p method");
@@ -2436,6 +2523,29 @@ int faces_r(const GD& g, const asterx_batch* b, const FaceArgs& fa, hipStream_t 
   return RUN_PHASE(KT_FACE_Z, PH_FACE, (k_face<2, R>), (kb_face<2, R>), fa);
 }
 
+// Upwind CT (single blocks): faces over transverse indices [-3, n+1].
+template <int R>
+int faces_uct_r(const GD& g, const FaceArgs& fa, hipStream_t s) {
+  int rc;
+  auto tiles = [&](int D) {
+    int e[3] = {g.n[0] + 5, g.n[1] + 5, g.n[2] + 5};
+    e[D] = g.n[D] + 1;
+    return face_tiles(e);
+  };
+  if ((rc = timed(KT_FACE_X, s, [&] { hipLaunchKernelGGL((k_face_uct<0, R>), dim3(tiles(0)), dim3(256), 0, s, g, fa); })))
+    return rc;
+  if ((rc = timed(KT_FACE_Y, s, [&] { hipLaunchKernelGGL((k_face_uct<1, R>), dim3(tiles(1)), dim3(256), 0, s, g, fa); })))
+    return rc;
+  return timed(KT_FACE_Z, s, [&] { hipLaunchKernelGGL((k_face_uct<2, R>), dim3(tiles(2)), dim3(256), 0, s, g, fa); });
+}
+
+int faces_uct(const GD& g, const FaceArgs& fa, int recon, hipStream_t s) {
+  if (recon == ASTERX_RECON_MINMOD) return faces_uct_r<ASTERX_RECON_MINMOD>(g, fa, s);
+  if (recon == ASTERX_RECON_PPM) return faces_uct_r<ASTERX_RECON_PPM>(g, fa, s);
+  if (recon == ASTERX_RECON_MP5) return faces_uct_r<ASTERX_RECON_MP5>(g, fa, s);
+  return faces_uct_r<ASTERX_RECON_WENOZ>(g, fa, s);
+}
+
 int faces(const GD& g, const asterx_batch* b, const FaceArgs& fa, int recon, hipStream_t s) {
   if (recon == ASTERX_RECON_MINMOD) return faces_r<ASTERX_RECON_MINMOD>(g, b, fa, s);
   if (recon == ASTERX_RECON_PPM) return faces_r<ASTERX_RECON_PPM>(g, b, fa, s);
@@ -2491,17 +2601,23 @@ int do_rhs(const GD& g, const asterx_batch* b, const asterx_params* p, const dou
   double* flux = ws + 3 * g.N;
   double* ga = ws + 24 * g.N;
   double* fp = ws + 25 * g.N;
+  double* apm = ws + 28 * g.N;
+  const bool uct = p->ct == ASTERX_CT_UCT;
   if ((rc = RUN_PHASE(KT_BCENT, PH_BCENT, k_bcent, kb_bcent, A, bc))) return rc;
   FaceArgs fa{metric, prim, A, bc, flux, red, p->gamma, p->weno_eps, p->weno_q, p->gamma / (p->gamma - 1.0),
-              p->recon, p->speeds, p->riemann};
-  if ((rc = faces(g, b, fa, p->recon, s))) return rc;
+              p->recon, p->speeds, p->riemann, apm};
+  if ((rc = uct ? faces_uct(g, fa, p->recon, s) : faces(g, b, fa, p->recon, s))) return rc;
   CellArgs ca{metric, curv, prim, A, bc, flux, rhs, red, p->gamma, cmb};
   if ((rc = RUN_PHASE(KT_CELL, PH_CELL, k_cell, kb_cell, ca))) return rc;
   if (p->gauge == ASTERX_GAUGE_LORENZ) {
     VertexArgs va{metric, A, psi, ga, fp};
     if ((rc = RUN_PHASE(KT_VERTEX, PH_VERTEX, k_vertex, kb_vertex, va))) return rc;
   }
-  EdgeArgs ea{metric, psi, flux, ga, fp, rhs, p->xi / dt_max, p->gauge, cmb};
+  EdgeArgs ea{metric, psi, flux, ga, fp, rhs, p->xi / dt_max, p->gauge, cmb, A, apm};
+  if (uct)
+    return timed(KT_EDGE, s, [&] {
+      hipLaunchKernelGGL(k_edge_uct, dim3(tiles_for(PH_EDGE, g)), dim3(256), 0, s, g, ea);
+    });
   return RUN_PHASE(KT_EDGE, PH_EDGE, k_edge, kb_edge, ea);
 }
 
@@ -2615,7 +2731,7 @@ int asterx_timing_reset(void) {
 
 const char* asterx_timing_name(int32_t k) { return (k >= 0 && k < KT_N) ? kt_names[k] : ""; }
 
-int asterx_version(void) { return 4; }
+int asterx_version(void) { return 5; }
 
 const char* asterx_last_error(void) { return g_err.c_str(); }
 
@@ -2693,6 +2809,7 @@ int asterx_rhs(const asterx_grid* gr, const asterx_params* p, const double* metr
   if ((rc = check_params(p))) return rc;
   // the face kernels load a six-cell stencil (i-3..i+2) for every scheme
   if ((rc = check_grid(gr, 3))) return rc;
+  if (p->ct == ASTERX_CT_UCT && gr->ng < 4) return fail(ASTERX_EARG, "rhs: upwind CT needs ng >= 4");
   if (!metric || !curv || !prim || !A || !psi || !rhs || !workspace) return fail(ASTERX_EARG, "rhs: NULL array");
   if (ws_bytes < asterx_rhs_workspace_size(gr)) return fail(ASTERX_EARG, "rhs: workspace too small");
   if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs: dt_max must be > 0");
@@ -2715,6 +2832,7 @@ int asterx_rhs_rk(const asterx_grid* gr, const asterx_params* p, const double* m
                   const asterx_rk_out* outs, double* red, void* workspace, size_t ws_bytes, void* stream) {
   int rc;
   if ((rc = check_params(p)) || (rc = check_grid(gr, 3))) return rc;
+  if (p->ct == ASTERX_CT_UCT && gr->ng < 4) return fail(ASTERX_EARG, "rhs_rk: upwind CT needs ng >= 4");
   if (!metric || !curv || !prim || !A || !psi || !workspace) return fail(ASTERX_EARG, "rhs_rk: NULL array");
   if (ws_bytes < asterx_rhs_workspace_size(gr)) return fail(ASTERX_EARG, "rhs_rk: workspace too small");
   if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs_rk: dt_max must be > 0");
@@ -2865,6 +2983,7 @@ int asterx_batch_rhs(const asterx_batch* b, const asterx_params* p, const double
   int rc;
   if (!b) return fail(ASTERX_EARG, "batch is NULL");
   if ((rc = check_params(p))) return rc;
+  if (p->ct == ASTERX_CT_UCT) return fail(ASTERX_EARG, "batch: upwind CT is available for single blocks only");
   if (!metric || !curv || !prim || !A || !psi || !rhs || !workspace) return fail(ASTERX_EARG, "rhs: NULL array");
   if (ws_bytes < asterx_batch_workspace_size(b)) return fail(ASTERX_EARG, "rhs: workspace too small");
   if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs: dt_max must be > 0");
@@ -2878,6 +2997,7 @@ int asterx_batch_rhs_rk(const asterx_batch* b, const asterx_params* p, const dou
   int rc;
   if (!b) return fail(ASTERX_EARG, "batch is NULL");
   if ((rc = check_params(p))) return rc;
+  if (p->ct == ASTERX_CT_UCT) return fail(ASTERX_EARG, "batch: upwind CT is available for single blocks only");
   if (!metric || !curv || !prim || !A || !psi || !workspace) return fail(ASTERX_EARG, "rhs_rk: NULL array");
   if (ws_bytes < asterx_batch_workspace_size(b)) return fail(ASTERX_EARG, "rhs_rk: workspace too small");
   if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs_rk: dt_max must be > 0");
@@ -3015,6 +3135,7 @@ int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
                        double* gamma_bar, void* workspace, size_t ws_bytes, void* stream) {
   int rc;
   if ((rc = check_adjoint(gr, p, ws_bytes))) return rc;
+  if (p->ct == ASTERX_CT_UCT) return fail(ASTERX_EARG, "rhs_adjoint: upwind CT is not differentiated");
   if (!metric || !curv || !cons || !prim_guess || !A || !psi || !rhs_bar || !cons_bar || !A_bar || !psi_bar ||
       !gamma_bar || !workspace)
     return fail(ASTERX_EARG, "rhs_adjoint: NULL array");

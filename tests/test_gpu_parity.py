@@ -157,12 +157,24 @@ def _rhs_case(ax, torch, orc, w):
     return _host(out), ref, _host(red), red_ref
 
 
-@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz", "mp5", "ppm+lxf", "mp5+lxf"])
+def _scheme(w, recon):
+    """recon may carry a Riemann solver and an edge-field scheme: "ppm+lxf", "mp5+hlle+uct"."""
+    parts = recon.split("+")
+    w.params["riemann"] = parts[1] if len(parts) > 1 else "hlle"
+    w.params["ct"] = parts[2] if len(parts) > 2 else "fct"
+    return parts[0]
+
+
+def _ng(recon):
+    return 4 if recon.endswith("+uct") else 3
+
+
+@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz", "mp5", "ppm+lxf", "mp5+lxf", "ppm+hlle+uct",
+                                   "wenoz+hlle+uct", "mp5+lxf+uct", "minmod+hlle+uct"])
 @pytest.mark.parametrize("shape", [(70, 9, 7), (13, 11, 9)])
 def test_rhs_parity_curved(ax, torch_mod, orc, recon, shape):
-    rec, _, riemann = recon.partition("+")
-    w = W.curved_block(seed=15, n=shape, recon=rec)
-    w.params["riemann"] = riemann or "hlle"
+    w = W.curved_block(seed=15, n=shape, recon=recon.split("+")[0], ng=_ng(recon))
+    _scheme(w, recon)
     w.psi = w.layout.zeros(1) + 0.01 * np.random.default_rng(3).normal(size=(1,) + w.layout.shape3)
     print("case rhs", recon, shape, flush=True)
     g, c, red, red_ref = _rhs_case(ax, torch_mod, orc, w)
@@ -205,11 +217,10 @@ def test_steps_parity_riemann32(ax, torch_mod, orc):
     assert st[3] == 0 and stats[3] == 0
 
 
-@pytest.mark.parametrize("recon", ["ppm", "wenoz", "mp5", "ppm+lxf"])
+@pytest.mark.parametrize("recon", ["ppm", "wenoz", "mp5", "ppm+lxf", "ppm+hlle+uct"])
 def test_steps_parity_curved(ax, torch_mod, orc, recon):
-    rec, _, riemann = recon.partition("+")
-    w = W.curved_block(seed=18, n=(20, 13, 11), recon=rec, nsteps=2)
-    w.params["riemann"] = riemann or "hlle"
+    w = W.curved_block(seed=18, n=(20, 13, 11), recon=recon.split("+")[0], nsteps=2, ng=_ng(recon))
+    _scheme(w, recon)
     print("case steps curved", recon, flush=True)
     blk, state, prim, stats, red = _run_both(ax, torch_mod, orc, w, 2)
     assert_fields_close(_host(blk.state), state, 1e-10, w.layout.owned, STATE_NAMES)
@@ -217,12 +228,13 @@ def test_steps_parity_curved(ax, torch_mod, orc, recon):
 
 
 @pytest.mark.parametrize("recon,rk,shape", [("ppm", 4, (24, 13, 11)), ("wenoz", 4, (70, 9, 7)),
-                                             ("minmod", 2, (33, 12, 10))])
+                                             ("minmod", 2, (33, 12, 10)), ("ppm+hlle+uct", 4, (24, 13, 11))])
 def test_fused_stage_outputs_bitwise_equal_stored(ax, torch_mod, recon, rk, shape):
     """asterx_rhs_rk (the right-hand side combined into the stage outputs by the cell and edge kernels) against
     asterx_rhs + asterx_rk_stage: bitwise equal states, primitives, reductions and c2p counters after 3 steps."""
     torch = torch_mod
-    w = W.curved_block(seed=33, n=shape, recon=recon, nsteps=3, rk=rk)
+    w = W.curved_block(seed=33, n=shape, recon=recon.split("+")[0], nsteps=3, rk=rk, ng=_ng(recon))
+    _scheme(w, recon)
     print("case fused vs stored", recon, rk, shape, flush=True)
     a = ax.Block(w, fused=True)
     b = ax.Block(w, fused=False)
@@ -319,3 +331,20 @@ def test_rhs_and_step_parity_tiny_ragged(ax, torch_mod, orc, shape):
     assert_fields_close(g, c, 1e-12, w.layout.owned, STATE_NAMES)
     blk, state, prim, stats, red = _run_both(ax, torch_mod, orc, w, 1)
     assert_fields_close(_host(blk.state), state, 1e-10, w.layout.owned, STATE_NAMES)
+
+
+def test_uct_refused_where_not_supported(ax, torch_mod):
+    """Upwind CT with three ghost layers, in a batch and in the adjoint: refused with an error, nothing launched."""
+    torch = torch_mod
+    w = W.curved_block(seed=35, n=(8, 8, 8), recon="ppm", nsteps=1)
+    w.params["ct"] = "uct"
+    blk = ax.Block(w)
+    with pytest.raises(RuntimeError, match="ng >= 4"):
+        blk.step()
+    wls = W.patch_set(seed=3, npatches=2, sides=(16,), levels=1, nsteps=1, recon="ppm")
+    for x in wls:
+        x.params["ct"] = "uct"
+    bt = ax.Batch(wls)
+    with pytest.raises(RuntimeError, match="single blocks"):
+        bt.step()
+    torch.cuda.synchronize()
