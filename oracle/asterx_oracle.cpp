@@ -1023,6 +1023,57 @@ template <class T> static inline T load_metric_point(const Grid& g, const T* met
   return m[0];
 }
 
+// Covariant stress-energy tensor T_{mu nu} at vertices (Sec. 3.1: it lives at the vertices with the
+// spacetime variables, for the spacetime solver; eq. tmunu for T^{mu nu}), on every vertex of the block,
+// indices [0, n] per axis.  The vertex fluid state is the arithmetic mean of the primitives and of the
+// centre fields of the 8 cells sharing the vertex (the paper does not say how the cell data reach the
+// vertex); the metric is the vertex's own.  T_{mu nu} = g_{mu a} g_{nu b} T^{ab} with g_00 = -alpha^2 +
+// beta_k beta^k, g_0i = beta_i, g_ij = gamma_ij.  out: 10 fields T_00, T_0x, T_0y, T_0z, T_xx, T_xy,
+// T_xz, T_yy, T_yz, T_zz.
+template <class T> void tmunu_vertices(const Grid& g, const T& gam, const T* metric, const T* prim, const T* A,
+                                       T* out) {
+  size_t N = npts(g);
+  for (int k = 0; k <= g.n[2]; ++k)
+    for (int j = 0; j <= g.n[1]; ++j)
+      for (int i = 0; i <= g.n[0]; ++i) {
+        T pr[5], Bt[3];
+        for (int c = 0; c < 5; ++c) pr[c] = T(0);
+        for (int c = 0; c < 3; ++c) Bt[c] = T(0);
+        for (int dk = -1; dk <= 0; ++dk)
+          for (int dj = -1; dj <= 0; ++dj)
+            for (int di = -1; di <= 0; ++di) {
+              for (int c = 0; c < 5; ++c) pr[c] = pr[c] + prim[c * N + at(g, i + di, j + dj, k + dk)];
+              T b[3];
+              centre_B(g, A, i + di, j + dj, k + dk, b);
+              for (int c = 0; c < 3; ++c) Bt[c] = Bt[c] + b[c];
+            }
+        for (int c = 0; c < 5; ++c) pr[c] = pr[c] / T(8);
+        for (int c = 0; c < 3; ++c) Bt[c] = Bt[c] / T(8);
+        T m[10];
+        load_metric_point(g, metric, i, j, k, m);
+        Geom<T> G = make_geom(m);
+        Fluid<T> F = make_fluid(G, pr, Bt, gam);
+        T Tu[4][4];
+        stress_tensor(G, F, Tu);
+        T g4[4][4];
+        T bb = T(0);
+        for (int a = 0; a < 3; ++a) bb = bb + G.beta[a] * G.betal[a];
+        g4[0][0] = -G.alp * G.alp + bb;
+        for (int a = 0; a < 3; ++a) {
+          g4[0][a + 1] = g4[a + 1][0] = G.betal[a];
+          for (int b = 0; b < 3; ++b) g4[a + 1][b + 1] = G.g[a][b];
+        }
+        const int idx[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
+        for (int c = 0; c < 10; ++c) {
+          int mu = idx[c][0], nu = idx[c][1];
+          T s = T(0);
+          for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) s = s + g4[mu][a] * g4[nu][b] * Tu[a][b];
+          out[c * N + at(g, i, j, k)] = s;
+        }
+      }
+}
+
 // Initial prim -> cons on owned cells (Sec. 3.12: analytical expressions
 // initialise the conserved variables).
 template <class T> void prim2con_grid(const Grid& g, const Params& /*P*/, const T& gam, const T* metric, const T* A,
@@ -1488,6 +1539,11 @@ void orc_fill_ghosts(const Grid* g, double* f, int nf, const int* kinds) { fill_
 void orc_fill_ghosts_shift(const Grid* g, double* f, int nf, const double* shift) {
   const int per[3] = {BC_PERIODIC, BC_PERIODIC, BC_PERIODIC};
   fill_ghosts<double>(*g, f, nf, per, shift);
+}
+
+void orc_tmunu(const Grid* g, const Params* P, const double* metric, const double* prim, const double* A,
+               double* out) {
+  tmunu_vertices<double>(*g, P->gamma, metric, prim, A, out);
 }
 
 void orc_rhs(const Grid* g, const Params* P, const double* metric, const double* curv, const double* prim,

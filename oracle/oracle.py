@@ -140,6 +140,14 @@ def fill_ghosts(layout, f, kinds):
     lib().orc_fill_ghosts(ctypes.byref(make_grid(layout)), _p(f), ctypes.c_int(nf), karr)
 
 
+def tmunu(layout, params, metric, prim, A):
+    """T_{mu nu} at the vertices [0, n]^3 (10 fields: 00, 0x, 0y, 0z, xx, xy, xz, yy, yz, zz)."""
+    out = np.zeros((10,) + layout.shape3, dtype=np.float64)
+    lib().orc_tmunu(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), _p(metric), _p(prim),
+                    _p(A), _p(out))
+    return out
+
+
 def rhs(layout, params, metric, curv, prim, A, psi, dt_max):
     _check_ct(layout, params)
     out = np.zeros((9,) + layout.shape3, dtype=np.float64)
