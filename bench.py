@@ -129,6 +129,26 @@ def cpu_baseline(recon, riemann, ct, n_cpu):
                       "(g++ -O2 -ffp-contract=off), %.1f s" % (n_cpu, dt)}
 
 
+def time_tmunu(asterx, torch, blk, n, reps=20):
+    """T_{mu nu} at the (n+1)^3 vertices of the block's current state (asterx_tmunu), HIP events around reps
+    launches on the current stream.  Algorithmic bytes per vertex: 5 primitives, 3 potential components and 10
+    metric components read once, 10 components written (224 B)."""
+    out = torch.empty((10,) + blk.L.shape3, dtype=torch.float64, device="cuda")
+    args = (blk.L, blk.params, blk.metric, blk.prim, blk.state[5:8], out)
+    asterx.tmunu(*args)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        asterx.tmunu(*args)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nv = (n + 1) ** 3
+    gbs = 224.0 * nv / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 4), "vertices_per_s": nv / (ms * 1e-3), "algorithmic_GBs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -245,6 +265,8 @@ def main():
            "c2p_stats": [int(v) for v in blk.stats.cpu().tolist()]}
     if learned_info:
         out["learned_c2p"] = learned_info
+    if args.ct == "fct":
+        out["tmunu_vertices"] = time_tmunu(asterx, torch, blk, n)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a %d^3 sample" % args.cpu_n, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.recon, args.riemann, args.ct, args.cpu_n)

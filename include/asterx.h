@@ -174,6 +174,15 @@ int asterx_rhs_rk(const asterx_grid* g, const asterx_params* p, const double* me
                   const double* prim, const double* A, const double* psi, double dt_max, int32_t nout,
                   const asterx_rk_out* outs, double* red, void* workspace, size_t ws_bytes, void* stream);
 
+/* Covariant stress-energy tensor T_{mu nu} (eq. tmunu, lowered with the 4-metric) at the vertices
+ * [0, n]^3 of the block, where Sec. 3.1 stores it with the spacetime variables for a spacetime
+ * solver.  The vertex fluid state is the mean of the primitives (prim) and of the centre fields
+ * (from the curl of A) of the 8 cells sharing the vertex; the metric is the vertex's own (metric).
+ * Reads prim on one ghost layer and A on two.  tmunu: device, 10 vertex fields T_00, T_0x, T_0y,
+ * T_0z, T_xx, T_xy, T_xz, T_yy, T_yz, T_zz in the block's layout; other points are not written. */
+int asterx_tmunu(const asterx_grid* g, const asterx_params* p, const double* metric, const double* prim,
+                 const double* A, double* tmunu, void* stream);
+
 /* Sets red[0..1] to 0 (device double[2]); a kernel, not a memset, so that it can be
  * recorded in a captured graph. */
 int asterx_zero(double* buf, int64_t count, void* stream);

@@ -83,7 +83,7 @@ EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "
            "asterx_batch_rk_stage", "asterx_adjoint_workspace_size", "asterx_rhs_adjoint", "asterx_c2p_adjoint",
            "asterx_prim2con_adjoint", "asterx_prim2con_points", "asterx_mlp_features", "asterx_mlp_forward",
            "asterx_mlp_grad_workspace_size", "asterx_mlp_grad", "asterx_mlp_adam", "asterx_c2p_points",
-           "asterx_c2p_learned", "asterx_rhs_rk", "asterx_batch_rhs_rk"]
+           "asterx_c2p_learned", "asterx_rhs_rk", "asterx_batch_rhs_rk", "asterx_tmunu"]
 
 
 def lib():
@@ -104,6 +104,7 @@ def lib():
         L.asterx_fill_ghosts_shift.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
         L.asterx_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
         L.asterx_rk_stage.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
+        L.asterx_tmunu.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.asterx_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
                                     ctypes.c_size_t, vp]
         L.asterx_batch_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
@@ -251,6 +252,12 @@ def rk_stage(layout, a, us, b_dt, rhs_t, out, stream=None):
                                  _ptr(_f64(out)), _stream(stream)))
 
 
+def tmunu(layout, params, metric, prim, A, out, stream=None):
+    """T_{mu nu} at the vertices [0, n]^3 into out (10 fields), asterx_tmunu."""
+    _check(lib().asterx_tmunu(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                              _ptr(_f64(metric)), _ptr(_f64(prim)), _ptr(_f64(A)), _ptr(_f64(out)), _stream(stream)))
+
+
 def rhs_rk(layout, params, metric, curv, prim, A, psi, dt_max, outs, red, workspace, stream=None):
     """Right-hand side combined straight into RK stage outputs (asterx_rhs_rk); outs as make_rk_outs."""
     arr = make_rk_outs(outs)
@@ -393,8 +400,12 @@ class Block:
     alternates two stage buffers so that no output is the state being evaluated); fused=False
     stores it and combines with asterx_rk_stage.  Both give bitwise equal states."""
 
-    def __init__(self, wl, device="cuda", fused=True):
+    def __init__(self, wl, device="cuda", fused=True, metric_fn=None):
         self.fused = fused
+        # a time-dependent spacetime: metric_fn(t) -> (metric, curv) device tensors shaped like the
+        # workload's, evaluated at every stage time (RK4: t, t + dt/2, t + dt/2, t + dt; RK2: t, t + dt)
+        self.metric_fn = metric_fn
+        self.t = 0.0
         self.wl = wl
         self.L = wl.layout
         self.params = wl.params
@@ -431,6 +442,11 @@ class Block:
             fill_ghosts(self.L, U[5:8], self.wl.bc_A)
         fill_ghosts(self.L, U[8:9], self.wl.bc_cell)
 
+    def at_time(self, t):
+        """Switch to the metric of time t when the spacetime is time dependent."""
+        if self.metric_fn is not None:
+            self.metric, self.curv = self.metric_fn(t)
+
     def recover(self, U):
         """c2p on U (in place for atmosphere cells) and the primitives' ghosts."""
         c2p(self.L, self.params, self.metric, U[5:8], U[0:5], self.prim, self.flags, self.stats, mlp=self.mlp)
@@ -453,44 +469,54 @@ class Block:
             self._step_fused()
         else:
             self._step_stored()
+        self.t += self.dt
 
     def _step_fused(self):
-        dt = self.dt
+        dt, t = self.dt, self.t
         U0 = self.state
         if self.wl.rk == 2:
             U1 = self.tmp
+            self.at_time(t)
             self.stage(U0, [([1.0], [U0], dt, U1)])
             self.fill_state(U1)
+            self.at_time(t + dt)
             self.stage(U1, [([0.5, 0.5], [U0, U1], 0.5 * dt, U0)])
             self.fill_state(U0)
         else:
             Ua, Ub, acc = self.tmp, self.tmp2, self.acc
+            self.at_time(t)
             self.stage(U0, [([1.0], [U0], dt / 6.0, acc), ([1.0], [U0], 0.5 * dt, Ua)])
             self.fill_state(Ua)
+            self.at_time(t + 0.5 * dt)
             self.stage(Ua, [([1.0], [acc], dt / 3.0, acc), ([1.0], [U0], 0.5 * dt, Ub)])
             self.fill_state(Ub)
             self.stage(Ub, [([1.0], [acc], dt / 3.0, acc), ([1.0], [U0], dt, Ua)])
             self.fill_state(Ua)
+            self.at_time(t + dt)
             self.stage(Ua, [([1.0], [acc], dt / 6.0, U0)])
             self.fill_state(U0)
 
     def _step_stored(self):
-        dt = self.dt
+        dt, t = self.dt, self.t
         U0, K = self.state, self.k
         if self.wl.rk == 2:
             U1 = self.tmp
+            self.at_time(t)
             self.eval_rhs(U0, K)
             rk_stage(self.L, [1.0], [U0], dt, K, U1)
             self.fill_state(U1)
+            self.at_time(t + dt)
             self.eval_rhs(U1, K)
             rk_stage(self.L, [0.5, 0.5], [U0, U1], 0.5 * dt, K, U0)
             self.fill_state(U0)
         else:
             Ut, acc = self.tmp, self.acc
+            self.at_time(t)
             self.eval_rhs(U0, K)
             rk_stage(self.L, [1.0], [U0], 0.5 * dt, K, Ut)
             rk_stage(self.L, [1.0], [U0], dt / 6.0, K, acc)
             self.fill_state(Ut)
+            self.at_time(t + 0.5 * dt)
             self.eval_rhs(Ut, K)
             rk_stage(self.L, [1.0], [acc], dt / 3.0, K, acc)
             rk_stage(self.L, [1.0], [U0], 0.5 * dt, K, Ut)
@@ -499,6 +525,7 @@ class Block:
             rk_stage(self.L, [1.0], [acc], dt / 3.0, K, acc)
             rk_stage(self.L, [1.0], [U0], dt, K, Ut)
             self.fill_state(Ut)
+            self.at_time(t + dt)
             self.eval_rhs(Ut, K)
             rk_stage(self.L, [1.0], [acc], dt / 6.0, K, U0)
             self.fill_state(U0)

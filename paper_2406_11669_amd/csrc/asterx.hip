@@ -1085,6 +1085,26 @@ DEV void emit(const Combine& cb, double* rhs, size_t o, double v) {
     if (k < cb.nout) cb.o[k].out[o] = rk_point<2>(cb.o[k].b_dt, v, cb.o[k].u, cb.o[k].a, cb.o[k].nterms, o);
 }
 
+// T^{mu nu} = (rho h + b^2) u u + (p + b^2/2) g^{mu nu} - b b   (eq. tmunu): T^00, T^0i, T^ij (symmetric)
+DEV void tmunu_upper(const Geo& G, const State& St, double& T00, double T0[3], double Tk[6]) {
+  double ia = 1.0 / G.alp, ia2 = ia * ia;
+  double u0 = St.W * ia, u[3], b0 = St.W * St.Bv * ia, bu[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = St.W * (St.v[a] - G.beta[a] * ia);
+    bu[a] = (St.B[a] + G.alp * b0 * u[a]) / St.W;
+  }
+  double e = St.rhoh + St.bsq, pt = St.p + 0.5 * St.bsq;
+  T00 = e * u0 * u0 - pt * ia2 - b0 * b0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) T0[a] = e * u0 * u[a] + pt * G.beta[a] * ia2 - b0 * bu[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b)
+      Tk[sym(a, b)] = e * u[a] * u[b] + pt * (G.gu[sym(a, b)] - G.beta[a] * G.beta[b] * ia2) - bu[a] * bu[b];
+}
+
 struct CellArgs {
   const double* metric;
   const double* curv;
@@ -1147,24 +1167,8 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
     Bt[2] = ca.bc[2 * g.N + id];
     State St;
     state_make(G, pr, Bt, ca.gam, St);
-    // T^{mu nu} = (rho h + b^2) u u + (p + b^2/2) g^{mu nu} - b b   (eq. tmunu)
-    double ia = 1.0 / G.alp, ia2 = ia * ia;
-    double u0 = St.W * ia, u[3], b0 = St.W * St.Bv * ia, bu[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      u[a] = St.W * (St.v[a] - G.beta[a] * ia);
-      bu[a] = (St.B[a] + G.alp * b0 * u[a]) / St.W;
-    }
-    double e = St.rhoh + St.bsq, pt = St.p + 0.5 * St.bsq;
-    double T00 = e * u0 * u0 - pt * ia2 - b0 * b0;
-    double T0[3], Tk[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) T0[a] = e * u0 * u[a] + pt * G.beta[a] * ia2 - b0 * bu[a];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = a; b < 3; ++b)
-        Tk[sym(a, b)] = e * u[a] * u[b] + pt * (G.gu[sym(a, b)] - G.beta[a] * G.beta[b] * ia2) - bu[a] * bu[b];
+    double T00, T0[3], Tk[6];
+    tmunu_upper(G, St, T00, T0, Tk);
     double bl[3];
     lower(G.g, G.beta, bl);
     as = G.alp * G.sqrtg;
@@ -1253,6 +1257,80 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
   if (ca.red) {
     double wm = wave_max(divb);
     if (__lane_id() == 0) atomic_max_pos(ca.red + 1, wm);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Covariant stress-energy tensor at the vertices [0, n]^3 (Sec. 3.1: stored with the spacetime
+// variables, for a spacetime solver): the vertex fluid state is the mean of the primitives and
+// centre fields of the 8 cells sharing the vertex, the metric the vertex's own;
+// T_{mu nu} = g_{mu a} g_{nu b} T^{ab}.  Output fields 00, 0x, 0y, 0z, xx, xy, xz, yy, yz, zz.
+struct TmunuArgs {
+  const double* metric;
+  const double* prim;
+  const double* A;
+  double* out;
+  double gam;
+};
+
+DEV void tmunu_body(const GD& g, const TmunuArgs& ta, unsigned tile) {
+  int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
+  int i, j, k;
+  if (!lin_at(e, tile, threadIdx.x, i, j, k)) return;
+  double pr[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, Bt[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int dk = -1; dk <= 0; ++dk)
+#pragma unroll
+    for (int dj = -1; dj <= 0; ++dj)
+#pragma unroll
+      for (int di = -1; di <= 0; ++di) {
+        const int c = at(g, i + di, j + dj, k + dk);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) pr[q] += ta.prim[q * g.N + c];
+        double b[3];
+        centre_B(ta.A, g, c, b);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Bt[q] += b[q];
+      }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) pr[q] *= 0.125;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) Bt[q] *= 0.125;
+  const int id = at(g, i, j, k);
+  double m[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) m[q] = ta.metric[q * g.N + id];
+  Geo G;
+  geo_from(m, G);
+  State St;
+  state_make(G, pr, Bt, ta.gam, St);
+  double T00, T0[3], Tk[6];
+  tmunu_upper(G, St, T00, T0, Tk);
+  double bl[3];
+  lower(G.g, G.beta, bl);
+  double g4[4][4], Tu[4][4];
+  g4[0][0] = -G.alp * G.alp + bl[0] * G.beta[0] + bl[1] * G.beta[1] + bl[2] * G.beta[2];
+  Tu[0][0] = T00;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    g4[0][a + 1] = g4[a + 1][0] = bl[a];
+    Tu[0][a + 1] = Tu[a + 1][0] = T0[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      g4[a + 1][b + 1] = G.g[sym(a, b)];
+      Tu[a + 1][b + 1] = Tk[sym(a, b)];
+    }
+  }
+  double X[4][4];  // T^{a}_{nu}
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) X[a][n] = Tu[a][0] * g4[0][n] + Tu[a][1] * g4[1][n] + Tu[a][2] * g4[2][n] + Tu[a][3] * g4[3][n];
+  const int mu[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3}, nu[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+#pragma unroll
+  for (int c = 0; c < 10; ++c) {
+    const int a = mu[c], b = nu[c];
+    ta.out[(size_t)c * g.N + id] = g4[a][0] * X[0][b] + g4[a][1] * X[1][b] + g4[a][2] * X[2][b] + g4[a][3] * X[3][b];
   }
 }
 
@@ -1568,6 +1646,7 @@ __global__ __launch_bounds__(256) void kb_cell(const PatchDesc* __restrict__ P, 
 }
 
 __global__ __launch_bounds__(256) void k_vertex(GD g, VertexArgs va) { vertex_body(g, va, my_tile()); }
+__global__ __launch_bounds__(256) void k_tmunu(GD g, TmunuArgs ta) { tmunu_body(g, ta, my_tile()); }
 __global__ __launch_bounds__(256) void kb_vertex(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                                  VertexArgs va) {
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
@@ -2401,10 +2480,10 @@ int launched() {
 // use while a stream is being captured into a graph.
 enum {
   KT_PRIM2CON, KT_C2P, KT_FILL, KT_BCENT, KT_FACE_X, KT_FACE_Y, KT_FACE_Z, KT_CELL, KT_VERTEX, KT_EDGE, KT_RK,
-  KT_ZERO, KT_ADJ, KT_N
+  KT_ZERO, KT_ADJ, KT_TMUNU, KT_N
 };
 const char* const kt_names[KT_N] = {"prim2con", "c2p", "fill_ghosts", "centre_B", "face_x", "face_y",
-                                    "face_z", "cell", "vertex", "edge", "rk_stage", "zero", "adjoint"};
+                                    "face_z", "cell", "vertex", "edge", "rk_stage", "zero", "adjoint", "tmunu"};
 struct Pending {
   hipEvent_t a, b;
   int kind;
@@ -2731,7 +2810,7 @@ int asterx_timing_reset(void) {
 
 const char* asterx_timing_name(int32_t k) { return (k >= 0 && k < KT_N) ? kt_names[k] : ""; }
 
-int asterx_version(void) { return 5; }
+int asterx_version(void) { return 6; }
 
 const char* asterx_last_error(void) { return g_err.c_str(); }
 
@@ -2843,6 +2922,18 @@ int asterx_rhs_rk(const asterx_grid* gr, const asterx_params* p, const double* m
   if ((rc = make_combine(nout, outs, g.N, ins, nin, 6, cmb))) return rc;
   return do_rhs(g, nullptr, p, metric, curv, prim, A, psi, dt_max, nullptr, red, (double*)workspace,
                 (hipStream_t)stream, cmb);
+}
+
+int asterx_tmunu(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* prim,
+                 const double* A, double* tmunu, void* stream) {
+  int rc;
+  if ((rc = check_params(p)) || (rc = check_grid(gr, 2))) return rc;
+  if (!metric || !prim || !A || !tmunu) return fail(ASTERX_EARG, "tmunu: NULL array");
+  GD g = make_gd(gr);
+  TmunuArgs ta{metric, prim, A, tmunu, p->gamma};
+  int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
+  hipStream_t s = (hipStream_t)stream;
+  return timed(KT_TMUNU, s, [&] { hipLaunchKernelGGL(k_tmunu, dim3(lin_blocks(e)), dim3(256), 0, s, g, ta); });
 }
 
 int asterx_zero(double* buf, int64_t count, void* stream) {

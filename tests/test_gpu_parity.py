@@ -348,3 +348,79 @@ def test_uct_refused_where_not_supported(ax, torch_mod):
     with pytest.raises(RuntimeError, match="single blocks"):
         bt.step()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("shape", [(20, 13, 11), (7, 5, 3)])
+def test_tmunu_vs_oracle(ax, torch_mod, orc, shape):
+    """asterx_tmunu (T_{mu nu} at the vertices [0, n]^3 from the 8-cell vertex state) against the oracle, element by
+    element, relative to each component's scale."""
+    torch = torch_mod
+    w = W.curved_block(seed=37, n=shape, recon="ppm")
+    L = w.layout
+    print("case tmunu", shape, flush=True)
+    ref = orc.tmunu(L, w.params, w.metric, w.prim, w.A)
+    out = torch.zeros((10,) + L.shape3, dtype=torch.float64, device="cuda")
+    ax.tmunu(L, w.params, _dev(torch, w.metric), _dev(torch, w.prim), _dev(torch, w.A), out)
+    torch.cuda.synchronize()
+    got = _host(out)
+    g = L.ng
+    sl = (slice(None),) + tuple(slice(g, g + L.n[2 - a] + 1) for a in range(3))
+    for c in range(10):
+        scale = np.max(np.abs(ref[c][sl[1:]]))
+        assert np.max(np.abs(got[c][sl[1:]] - ref[c][sl[1:]])) <= 1e-12 * scale, c
+    assert np.all(got[:, :g] == 0.0)  # only the vertices [0, n]^3 are written
+
+
+def _metric_at(w, t, period):
+    """A time-dependent spacetime for the driver test: the workload's metric with the lapse scaled by
+    1 + 0.1 sin(2 pi t / period) and the shift by the opposite factor."""
+    f = 1.0 + 0.1 * np.sin(2.0 * np.pi * t / period)
+    m = w.metric.copy()
+    m[0] *= f
+    m[1:4] *= 2.0 - f
+    return m, w.curv
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_time_dependent_metric_steps_vs_oracle(ax, torch_mod, orc, fused):
+    """A metric that changes from stage to stage (Block(metric_fn=...)): two Heun steps against the same stage
+    sequence driven through the oracle's c2p, ghost fill, right-hand side and RK combine, within 1e-10."""
+    torch = torch_mod
+    w = W.curved_block(seed=36, n=(16, 12, 10), recon="ppm", nsteps=2, rk=2)
+    L, P, dt = w.layout, w.params, w.dt
+    period = 3.0 * dt
+    print("case time-dependent metric", fused, flush=True)
+    blk = ax.Block(w, fused=fused, metric_fn=lambda t: tuple(_dev(torch, x) for x in _metric_at(w, t, period)))
+    blk.run(2)
+    torch.cuda.synchronize()
+    cons = orc.prim2con(L, P, w.metric, w.A, w.prim)
+    orc.fill_ghosts(L, cons, w.bc_cell)
+    U0 = w.state(cons)
+    prim = w.prim.copy()
+
+    def fill_state(U):
+        orc.fill_ghosts(L, U[0:5], w.bc_cell)
+        if w.A_shift is not None:
+            orc.fill_ghosts_shift(L, U[5:8], w.A_shift)
+        else:
+            orc.fill_ghosts(L, U[5:8], w.bc_A)
+        orc.fill_ghosts(L, U[8:9], w.bc_cell)
+
+    def rhs_at(U, t):
+        m, K = _metric_at(w, t, period)
+        orc.c2p(L, P, m, U[5:8], U[0:5], prim)
+        orc.fill_ghosts(L, prim, w.bc_cell)
+        return orc.rhs(L, P, m, K, prim, U[5:8], U[8:9], dt)[0]
+
+    t = 0.0
+    for _ in range(2):
+        K1 = rhs_at(U0, t)
+        U1 = U0.copy()
+        orc.rk_stage(L, [1.0], [U0], dt, K1, U1)
+        fill_state(U1)
+        K2 = rhs_at(U1, t + dt)
+        orc.rk_stage(L, [0.5, 0.5], [U0, U1], 0.5 * dt, K2, U0)
+        fill_state(U0)
+        t += dt
+    assert_fields_close(_host(blk.state), U0, 1e-10, L.owned, STATE_NAMES)
+    assert_fields_close(_host(blk.prim), prim, 1e-10, L.owned, PRIM_NAMES)
