@@ -1432,6 +1432,141 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
   if (nfix_out) *nfix_out = nfix;
 }
 
+// ---------------------------------------------------------------------------
+// Inter-level operators for factor-2 mesh refinement (Sec. 3.9, the prolongation used at refinement
+// boundaries in the AMR tests of Sec. 4).  The fine grid's vertex 0 sits on coarse vertex c0 (per
+// axis), so fine spacing is half the coarse one.  Each axis of a field is cell- or vertex-centred
+// (cell fields: all cell; vertex fields: all vertex; the x-edge potential: cell in x, vertex in y, z).
+//   Prolongation, per axis: a vertex-centred direction injects where a fine vertex sits on a coarse
+//   one and takes the cubic Lagrange midpoint value (-1, 9, 9, -1)/16 in between; a cell-centred
+//   direction gives the two children of coarse cell c the conservative quadratic values
+//   u_c -+ (u_{c+1} - u_{c-1})/8 (lower child -, upper child +), whose mean is u_c.  Applied as a
+//   tensor product.  Fields centred in all three directions fall back, per coarse cell, to the
+//   minmod-limited linear children u_c + sum_a (+-1/4) minmod(u_{c+e_a} - u_c, u_c - u_{c-e_a})
+//   when any of the 8 third-order children leaves [min, max] of the 27 coarse cells around c (the
+//   shock fallback; one decision per coarse cell keeps the children's mean equal to u_c).
+//   Restriction, per axis: the mean of the two children in a cell-centred direction, injection in
+//   a vertex-centred one (tensor product).
+static inline int floordiv2(int f) { return f >= 0 ? f / 2 : -((1 - f) / 2); }
+
+// 1-D prolongation stencil of fine index f: coarse indices c[0..n-1] and weights w[0..n-1].
+static int prolong_stencil(int f, int c0, int vertex, int c[4], double w[4]) {
+  if (vertex) {
+    if (f % 2 == 0) {
+      c[0] = c0 + f / 2;
+      w[0] = 1.0;
+      return 1;
+    }
+    int b = c0 + floordiv2(f);
+    for (int q = 0; q < 4; ++q) c[q] = b - 1 + q;
+    w[0] = -1.0 / 16.0; w[1] = 9.0 / 16.0; w[2] = 9.0 / 16.0; w[3] = -1.0 / 16.0;
+    return 4;
+  }
+  int cc = c0 + floordiv2(f);
+  int child = f - 2 * floordiv2(f);  // 0 lower, 1 upper
+  c[0] = cc - 1; c[1] = cc; c[2] = cc + 1;
+  w[0] = child ? -1.0 / 8.0 : 1.0 / 8.0;
+  w[1] = 1.0;
+  w[2] = child ? 1.0 / 8.0 : -1.0 / 8.0;
+  return 3;
+}
+
+static double prolong_point(const Grid& gc, const double* cf, const int c0[3], const int stag[3], int fi, int fj,
+                            int fk) {
+  int ci[3][4], n[3];
+  double w[3][4];
+  int f[3] = {fi, fj, fk};
+  for (int a = 0; a < 3; ++a) n[a] = prolong_stencil(f[a], c0[a], stag[a], ci[a], w[a]);
+  double s = 0.0;
+  for (int r = 0; r < n[2]; ++r)
+    for (int q = 0; q < n[1]; ++q)
+      for (int p = 0; p < n[0]; ++p) s += w[0][p] * w[1][q] * w[2][r] * cf[at(gc, ci[0][p], ci[1][q], ci[2][r])];
+  return s;
+}
+
+template <class T> static T minmod_s(const T& x, const T& y) { return minmod2(x, y); }
+
+void prolong_grid(const Grid& gc, const Grid& gf, const int c0[3], const int stag[3], int nf, const double* cf,
+                  double* ff, const int lo[3], const int hi[3]) {
+  size_t Nc = npts(gc), Nf = npts(gf);
+  const bool allcell = !stag[0] && !stag[1] && !stag[2];
+  for (int q = 0; q < nf; ++q) {
+    const double* c = cf + q * Nc;
+    double* o = ff + q * Nf;
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) {
+          double v = prolong_point(gc, c, c0, stag, i, j, k);
+          if (allcell) {
+            // the coarse cell of (i, j, k) and its 8 children's third-order values
+            int cc[3] = {c0[0] + floordiv2(i), c0[1] + floordiv2(j), c0[2] + floordiv2(k)};
+            int f0[3] = {2 * floordiv2(i), 2 * floordiv2(j), 2 * floordiv2(k)};
+            double mn = c[at(gc, cc[0], cc[1], cc[2])], mx = mn;
+            for (int dk = -1; dk <= 1; ++dk)
+              for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di) {
+                  double u = c[at(gc, cc[0] + di, cc[1] + dj, cc[2] + dk)];
+                  mn = std::min(mn, u);
+                  mx = std::max(mx, u);
+                }
+            bool fall = false;
+            for (int dk = 0; dk <= 1; ++dk)
+              for (int dj = 0; dj <= 1; ++dj)
+                for (int di = 0; di <= 1; ++di) {
+                  double u = prolong_point(gc, c, c0, stag, f0[0] + di, f0[1] + dj, f0[2] + dk);
+                  if (u < mn || u > mx) fall = true;
+                }
+            if (fall) {
+              double uc = c[at(gc, cc[0], cc[1], cc[2])];
+              int fid[3] = {i, j, k};
+              v = uc;
+              for (int a = 0; a < 3; ++a) {
+                int e[3] = {0, 0, 0};
+                e[a] = 1;
+                double up = c[at(gc, cc[0] + e[0], cc[1] + e[1], cc[2] + e[2])];
+                double dn = c[at(gc, cc[0] - e[0], cc[1] - e[1], cc[2] - e[2])];
+                double sl = minmod_s(up - uc, uc - dn);
+                int child = fid[a] - 2 * floordiv2(fid[a]);
+                v += (child ? 0.25 : -0.25) * sl;
+              }
+            }
+          }
+          o[at(gf, i, j, k)] = v;
+        }
+  }
+}
+
+void restrict_grid(const Grid& gc, const Grid& gf, const int c0[3], const int stag[3], int nf, const double* ff,
+                   double* cf, const int lo[3], const int hi[3]) {
+  size_t Nc = npts(gc), Nf = npts(gf);
+  for (int q = 0; q < nf; ++q) {
+    const double* f = ff + q * Nf;
+    double* o = cf + q * Nc;
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) {
+          int c[3] = {i, j, k};
+          int n[3], fs[3][2];
+          for (int a = 0; a < 3; ++a) {
+            int base = 2 * (c[a] - c0[a]);
+            if (stag[a]) {
+              n[a] = 1;
+              fs[a][0] = base;
+            } else {
+              n[a] = 2;
+              fs[a][0] = base;
+              fs[a][1] = base + 1;
+            }
+          }
+          double s = 0.0;
+          for (int r = 0; r < n[2]; ++r)
+            for (int p2 = 0; p2 < n[1]; ++p2)
+              for (int p1 = 0; p1 < n[0]; ++p1) s += f[at(gf, fs[0][p1], fs[1][p2], fs[2][r])];
+          o[at(gc, i, j, k)] = s / double(n[0] * n[1] * n[2]);
+        }
+  }
+}
+
 // out = sum_m a_m u_m + b_dt rhs on owned points of 9 fields.
 template <class T> void rk_combine(const Grid& g, int nterms, const double* a, const T* const* u, double b_dt, const T* rhs,
                                    T* out) {
@@ -1655,6 +1790,16 @@ void orc_stage_jvp(const Grid* g, const Params* P, double dgamma, const double* 
     out[q] = r[q].v;
     dout[q] = r[q].d;
   }
+}
+
+void orc_prolong(const Grid* gc, const Grid* gf, const int* c0, const int* stag, int nf, const double* cf, double* ff,
+                 const int* lo, const int* hi) {
+  prolong_grid(*gc, *gf, c0, stag, nf, cf, ff, lo, hi);
+}
+
+void orc_restrict(const Grid* gc, const Grid* gf, const int* c0, const int* stag, int nf, const double* ff,
+                  double* cf, const int* lo, const int* hi) {
+  restrict_grid(*gc, *gf, c0, stag, nf, ff, cf, lo, hi);
 }
 
 void orc_rk_stage(const Grid* g, int nterms, const double* a, const double* const* u, double b_dt, const double* rhs,

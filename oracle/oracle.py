@@ -148,6 +148,30 @@ def tmunu(layout, params, metric, prim, A):
     return out
 
 
+STAG = {"cell": (0, 0, 0), "vertex": (1, 1, 1), "xedge": (0, 1, 1), "yedge": (1, 0, 1), "zedge": (1, 1, 0)}
+
+
+def _i3(v):
+    return (ctypes.c_int * 3)(*[int(x) for x in v])
+
+
+def prolong(coarse, fine, c0, stag, cf, ff, lo, hi):
+    """Fill fine points [lo, hi] (fine indices, inclusive) of ff (nf fields) from cf; fine vertex 0 on coarse vertex
+    c0; stag: per-axis 0 cell / 1 vertex, or a name of STAG."""
+    stag = STAG[stag] if isinstance(stag, str) else stag
+    nf = cf.shape[0]
+    lib().orc_prolong(ctypes.byref(make_grid(coarse)), ctypes.byref(make_grid(fine)), _i3(c0), _i3(stag),
+                      ctypes.c_int(nf), _p(cf), _p(ff), _i3(lo), _i3(hi))
+
+
+def restrict(coarse, fine, c0, stag, ff, cf, lo, hi):
+    """Fill coarse points [lo, hi] (coarse indices) of cf from ff."""
+    stag = STAG[stag] if isinstance(stag, str) else stag
+    nf = ff.shape[0]
+    lib().orc_restrict(ctypes.byref(make_grid(coarse)), ctypes.byref(make_grid(fine)), _i3(c0), _i3(stag),
+                       ctypes.c_int(nf), _p(ff), _p(cf), _i3(lo), _i3(hi))
+
+
 def rhs(layout, params, metric, curv, prim, A, psi, dt_max):
     _check_ct(layout, params)
     out = np.zeros((9,) + layout.shape3, dtype=np.float64)
