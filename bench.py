@@ -129,6 +129,57 @@ def cpu_baseline(recon, riemann, ct, n_cpu):
                       "(g++ -O2 -ffp-contract=off), %.1f s" % (n_cpu, dt)}
 
 
+def time_inter_level(asterx, torch, n, reps=10):
+    """Factor-2 inter-level operators on the 9 state fields (5 conserved: cell; A_x, A_y, A_z: edges; Psi: vertex):
+    prolongation of every point of an n^3 fine block with 3 ghost layers from a coarse block, then restriction of
+    the coarse cells its owned cells cover.  HIP events around reps repetitions.  Algorithmic bytes: each fine
+    point written once and each coarse value read once (prolongation); each fine value read once and each coarse
+    point written once (restriction)."""
+    from paper_2406_11669_amd.workloads import Layout
+    nc = n // 2 + 8
+    coarse, fine = Layout((nc,) * 3, 3), Layout((n,) * 3, 3)
+    c0 = (4, 4, 4)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    cf = torch.rand((9,) + coarse.shape3, generator=gen, **f64)
+    ff = torch.zeros((9,) + fine.shape3, **f64)
+    back = torch.zeros_like(cf)
+    flo, fhi = (-3, -3, -3), (n + 2,) * 3
+    clo, chi = c0, tuple(c + n // 2 - 1 for c in c0)
+    parts = [(slice(0, 5), "cell"), (slice(5, 6), "xedge"), (slice(6, 7), "yedge"), (slice(7, 8), "zedge"),
+             (slice(8, 9), "vertex")]
+
+    def prolong_all():
+        for sl, st in parts:
+            asterx.prolong(coarse, fine, c0, st, cf[sl], ff[sl], flo, fhi)
+
+    def restrict_all():
+        for sl, st in parts:
+            asterx.restrict(coarse, fine, c0, st, ff[sl], back[sl], clo, chi)
+
+    out = {}
+    for name, fn in (("prolong", prolong_all), ("restrict", restrict_all)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if name == "prolong":
+            pts = 9 * (n + 6) ** 3
+            nbytes = 8.0 * (pts + 9 * (n // 2 + 5) ** 3)
+        else:
+            pts = 9 * (n // 2) ** 3
+            nbytes = 8.0 * (pts * 8 + pts)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "points_per_s": pts / (ms * 1e-3), "algorithmic_GBs": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def time_tmunu(asterx, torch, blk, n, reps=20):
     """T_{mu nu} at the (n+1)^3 vertices of the block's current state (asterx_tmunu), HIP events around reps
     launches on the current stream.  Algorithmic bytes per vertex: 5 primitives, 3 potential components and 10
@@ -267,6 +318,7 @@ def main():
         out["learned_c2p"] = learned_info
     if args.ct == "fct":
         out["tmunu_vertices"] = time_tmunu(asterx, torch, blk, n)
+        out["inter_level_9_fields"] = time_inter_level(asterx, torch, n)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a %d^3 sample" % args.cpu_n, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.recon, args.riemann, args.ct, args.cpu_n)

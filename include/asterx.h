@@ -183,6 +183,27 @@ int asterx_rhs_rk(const asterx_grid* g, const asterx_params* p, const double* me
 int asterx_tmunu(const asterx_grid* g, const asterx_params* p, const double* metric, const double* prim,
                  const double* A, double* tmunu, void* stream);
 
+/* ---- Factor-2 mesh refinement: inter-level operators --------------------------------------
+ * For refinement boundaries (Sec. 3.9; the prolongation of the AMR tests of Sec. 4): the fine
+ * grid's vertex 0 sits on coarse vertex c0 (host int[3], coarse indices), fine spacing = coarse / 2.
+ * stag (host int[3]): per axis, 0 if the field is cell-centred along it, 1 if vertex-centred
+ * (conserved variables 0,0,0; metric and Psi 1,1,1; A_x 0,1,1; A_y 1,0,1; A_z 1,1,0).  nf fields
+ * with the grids' field strides.  Other points of the target are not written.
+ * asterx_prolong fills fine points lo..hi (host int[3], fine indices, inclusive; ghosts allowed):
+ * vertex directions inject on coincident points and take the cubic Lagrange midpoint value
+ * (-1, 9, 9, -1)/16 in between; cell directions give the two children of coarse cell c the
+ * conservative third-order values u_c -+ (u_{c+1} - u_{c-1})/8; tensor product.  Fields centred in
+ * all directions fall back, per coarse cell, to minmod-limited linear children when a third-order
+ * child would leave [min, max] of the 27 coarse cells around the parent (the shock fallback; one
+ * decision per parent keeps the children's mean equal to the parent).
+ * asterx_restrict fills coarse points lo..hi (coarse indices): the mean of the children along
+ * cell directions, injection along vertex directions; restriction undoes prolongation.
+ * ASTERX_EARG when a box or the stencil it reaches leaves the stored points of either grid. */
+int asterx_prolong(const asterx_grid* coarse, const asterx_grid* fine, const int32_t* c0, const int32_t* stag,
+                   int32_t nf, const double* cf, double* ff, const int32_t* lo, const int32_t* hi, void* stream);
+int asterx_restrict(const asterx_grid* coarse, const asterx_grid* fine, const int32_t* c0, const int32_t* stag,
+                    int32_t nf, const double* ff, double* cf, const int32_t* lo, const int32_t* hi, void* stream);
+
 /* Sets red[0..1] to 0 (device double[2]); a kernel, not a memset, so that it can be
  * recorded in a captured graph. */
 int asterx_zero(double* buf, int64_t count, void* stream);

@@ -83,7 +83,8 @@ EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "
            "asterx_batch_rk_stage", "asterx_adjoint_workspace_size", "asterx_rhs_adjoint", "asterx_c2p_adjoint",
            "asterx_prim2con_adjoint", "asterx_prim2con_points", "asterx_mlp_features", "asterx_mlp_forward",
            "asterx_mlp_grad_workspace_size", "asterx_mlp_grad", "asterx_mlp_adam", "asterx_c2p_points",
-           "asterx_c2p_learned", "asterx_rhs_rk", "asterx_batch_rhs_rk", "asterx_tmunu"]
+           "asterx_c2p_learned", "asterx_rhs_rk", "asterx_batch_rhs_rk", "asterx_tmunu", "asterx_prolong",
+           "asterx_restrict"]
 
 
 def lib():
@@ -105,6 +106,8 @@ def lib():
         L.asterx_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
         L.asterx_rk_stage.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
         L.asterx_tmunu.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.asterx_prolong.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
+        L.asterx_restrict.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.asterx_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
                                     ctypes.c_size_t, vp]
         L.asterx_batch_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
@@ -256,6 +259,27 @@ def tmunu(layout, params, metric, prim, A, out, stream=None):
     """T_{mu nu} at the vertices [0, n]^3 into out (10 fields), asterx_tmunu."""
     _check(lib().asterx_tmunu(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
                               _ptr(_f64(metric)), _ptr(_f64(prim)), _ptr(_f64(A)), _ptr(_f64(out)), _stream(stream)))
+
+
+STAG = {"cell": (0, 0, 0), "vertex": (1, 1, 1), "xedge": (0, 1, 1), "yedge": (1, 0, 1), "zedge": (1, 1, 0)}
+
+
+def _i3(v):
+    return (ctypes.c_int32 * 3)(*[int(x) for x in v])
+
+
+def prolong(coarse, fine, c0, stag, cf, ff, lo, hi, stream=None):
+    """Fine points [lo, hi] of ff (nf fields) from cf (asterx_prolong); stag a name of STAG or per-axis 0/1."""
+    stag = STAG[stag] if isinstance(stag, str) else stag
+    _check(lib().asterx_prolong(ctypes.byref(make_grid(coarse)), ctypes.byref(make_grid(fine)), _i3(c0), _i3(stag),
+                                cf.shape[0], _ptr(_f64(cf)), _ptr(_f64(ff)), _i3(lo), _i3(hi), _stream(stream)))
+
+
+def restrict(coarse, fine, c0, stag, ff, cf, lo, hi, stream=None):
+    """Coarse points [lo, hi] of cf from ff (asterx_restrict)."""
+    stag = STAG[stag] if isinstance(stag, str) else stag
+    _check(lib().asterx_restrict(ctypes.byref(make_grid(coarse)), ctypes.byref(make_grid(fine)), _i3(c0), _i3(stag),
+                                 ff.shape[0], _ptr(_f64(ff)), _ptr(_f64(cf)), _i3(lo), _i3(hi), _stream(stream)))
 
 
 def rhs_rk(layout, params, metric, curv, prim, A, psi, dt_max, outs, red, workspace, stream=None):

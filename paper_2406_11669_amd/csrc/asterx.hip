@@ -1335,6 +1335,151 @@ DEV void tmunu_body(const GD& g, const TmunuArgs& ta, unsigned tile) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Factor-2 inter-level operators (refinement boundaries, Sec. 3.9 and the AMR tests of Sec. 4).  The
+// fine grid's vertex 0 sits on coarse vertex c0; each axis of a field is cell- (stag 0) or
+// vertex-centred (stag 1).  Prolongation per axis: vertex directions inject on coincident points
+// and take (-1, 9, 9, -1)/16 at midpoints; cell directions give the children of coarse cell c the
+// conservative quadratic values u_c -+ (u_{c+1} - u_{c-1})/8; tensor product.  Cell fields fall
+// back per coarse cell to minmod-limited linear children when a third-order child leaves the
+// [min, max] of the 27 coarse cells around it.  Restriction: children's mean along cell
+// directions, injection along vertex directions.
+struct InterArgs {
+  GD gc, gf;
+  int c0[3], stag[3], lo[3], hi[3];
+  int nf;
+  const double* src;
+  double* dst;
+};
+
+DEV int fdiv2(int f) { return f >= 0 ? f / 2 : -((1 - f) / 2); }
+
+// 1-D prolongation stencil: first coarse index, count and weights
+DEV int pstencil(int f, int c0, int vertex, int& first, double w[4]) {
+  if (vertex) {
+    if ((f & 1) == 0) {
+      first = c0 + f / 2;
+      w[0] = 1.0;
+      return 1;
+    }
+    first = c0 + fdiv2(f) - 1;
+    w[0] = -1.0 / 16.0;
+    w[1] = 9.0 / 16.0;
+    w[2] = 9.0 / 16.0;
+    w[3] = -1.0 / 16.0;
+    return 4;
+  }
+  const int child = f - 2 * fdiv2(f);
+  first = c0 + fdiv2(f) - 1;
+  w[0] = child ? -1.0 / 8.0 : 1.0 / 8.0;
+  w[1] = 1.0;
+  w[2] = child ? 1.0 / 8.0 : -1.0 / 8.0;
+  return 3;
+}
+
+// Fields vertex-centred along at least one axis: one thread per fine point.
+DEV void prolong_body(const InterArgs& a, unsigned tile) {
+  const int e[3] = {a.hi[0] - a.lo[0] + 1, a.hi[1] - a.lo[1] + 1, a.hi[2] - a.lo[2] + 1};
+  int i, j, k;
+  if (!lin_at(e, tile, threadIdx.x, i, j, k)) return;
+  const int f[3] = {a.lo[0] + i, a.lo[1] + j, a.lo[2] + k};
+  int first[3], n[3];
+  double w[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) n[d] = pstencil(f[d], a.c0[d], a.stag[d], first[d], w[d]);
+  for (int q = 0; q < a.nf; ++q) {
+    const double* c = a.src + (size_t)q * a.gc.N;
+    double sum = 0.0;
+    for (int r = 0; r < n[2]; ++r)
+      for (int p2 = 0; p2 < n[1]; ++p2)
+        for (int p1 = 0; p1 < n[0]; ++p1)
+          sum += w[0][p1] * w[1][p2] * w[2][r] * c[at(a.gc, first[0] + p1, first[1] + p2, first[2] + r)];
+    a.dst[(size_t)q * a.gf.N + at(a.gf, f[0], f[1], f[2])] = sum;
+  }
+}
+
+// Cell fields: one thread per coarse parent of the fine box; the 27 parent-centred values, the fallback
+// decision and all 8 children computed once, the children inside the box stored.
+DEV void prolong_cells_body(const InterArgs& a, unsigned tile) {
+  int pl[3], e[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    pl[d] = a.c0[d] + fdiv2(a.lo[d]);
+    e[d] = a.c0[d] + fdiv2(a.hi[d]) - pl[d] + 1;
+  }
+  int i, j, k;
+  if (!lin_at(e, tile, threadIdx.x, i, j, k)) return;
+  const int cc[3] = {pl[0] + i, pl[1] + j, pl[2] + k};
+  const size_t Nc = a.gc.N, Nf = a.gf.N;
+  for (int q = 0; q < a.nf; ++q) {
+    const double* c = a.src + (size_t)q * Nc;
+    double u[27];
+#pragma unroll
+    for (int r = 0; r < 27; ++r) u[r] = c[at(a.gc, cc[0] - 1 + r % 3, cc[1] - 1 + (r / 3) % 3, cc[2] - 1 + r / 9)];
+    double mn = u[13], mx = u[13];
+#pragma unroll
+    for (int r = 0; r < 27; ++r) {
+      mn = fmin(mn, u[r]);
+      mx = fmax(mx, u[r]);
+    }
+    double ch[8];
+    bool fall = false;
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int cx = h & 1, cy = (h >> 1) & 1, cz = h >> 2;
+      const double wx[3] = {cx ? -0.125 : 0.125, 1.0, cx ? 0.125 : -0.125};
+      const double wy[3] = {cy ? -0.125 : 0.125, 1.0, cy ? 0.125 : -0.125};
+      const double wz[3] = {cz ? -0.125 : 0.125, 1.0, cz ? 0.125 : -0.125};
+      double sum = 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int p2 = 0; p2 < 3; ++p2)
+#pragma unroll
+          for (int p1 = 0; p1 < 3; ++p1) sum += wx[p1] * wy[p2] * wz[r] * u[p1 + 3 * p2 + 9 * r];
+      ch[h] = sum;
+      fall = fall || sum < mn || sum > mx;
+    }
+    if (fall) {
+      const double uc = u[13];
+      const double sx = mm(u[14] - uc, uc - u[12]), sy = mm(u[16] - uc, uc - u[10]), sz = mm(u[22] - uc, uc - u[4]);
+#pragma unroll
+      for (int h = 0; h < 8; ++h)
+        ch[h] = uc + ((h & 1) ? 0.25 : -0.25) * sx + (((h >> 1) & 1) ? 0.25 : -0.25) * sy + ((h >> 2) ? 0.25 : -0.25) * sz;
+    }
+    double* o = a.dst + (size_t)q * Nf;
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int f0 = 2 * (cc[0] - a.c0[0]) + (h & 1), f1 = 2 * (cc[1] - a.c0[1]) + ((h >> 1) & 1),
+                f2 = 2 * (cc[2] - a.c0[2]) + (h >> 2);
+      if (f0 >= a.lo[0] && f0 <= a.hi[0] && f1 >= a.lo[1] && f1 <= a.hi[1] && f2 >= a.lo[2] && f2 <= a.hi[2])
+        o[at(a.gf, f0, f1, f2)] = ch[h];
+    }
+  }
+}
+
+DEV void restrict_body(const InterArgs& a, unsigned tile) {
+  const int e[3] = {a.hi[0] - a.lo[0] + 1, a.hi[1] - a.lo[1] + 1, a.hi[2] - a.lo[2] + 1};
+  int i, j, k;
+  if (!lin_at(e, tile, threadIdx.x, i, j, k)) return;
+  const int c[3] = {a.lo[0] + i, a.lo[1] + j, a.lo[2] + k};
+  int n[3], b[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    b[d] = 2 * (c[d] - a.c0[d]);
+    n[d] = a.stag[d] ? 1 : 2;
+  }
+  const double inv = 1.0 / (double)(n[0] * n[1] * n[2]);
+  for (int q = 0; q < a.nf; ++q) {
+    const double* f = a.src + (size_t)q * a.gf.N;
+    double s = 0.0;
+    for (int r = 0; r < n[2]; ++r)
+      for (int p2 = 0; p2 < n[1]; ++p2)
+        for (int p1 = 0; p1 < n[0]; ++p1) s += f[at(a.gf, b[0] + p1, b[1] + p2, b[2] + r)];
+    a.dst[(size_t)q * a.gc.N + at(a.gc, c[0], c[1], c[2])] = s * inv;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // Vertices in [-1, n]^3: G_A = alpha Psi / sqrt(gamma) - beta^j A_j and
 // F_Psi^j = alpha sqrt(gamma) gamma^jk A_k - beta^j Psi, with A averaged to the vertex
 // along its own direction (Sec. 3.4).
@@ -1647,6 +1792,9 @@ __global__ __launch_bounds__(256) void kb_cell(const PatchDesc* __restrict__ P, 
 
 __global__ __launch_bounds__(256) void k_vertex(GD g, VertexArgs va) { vertex_body(g, va, my_tile()); }
 __global__ __launch_bounds__(256) void k_tmunu(GD g, TmunuArgs ta) { tmunu_body(g, ta, my_tile()); }
+__global__ __launch_bounds__(256) void k_prolong(InterArgs a) { prolong_body(a, my_tile()); }
+__global__ __launch_bounds__(256) void k_prolong_cells(InterArgs a) { prolong_cells_body(a, my_tile()); }
+__global__ __launch_bounds__(256) void k_restrict(InterArgs a) { restrict_body(a, my_tile()); }
 __global__ __launch_bounds__(256) void kb_vertex(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                                  VertexArgs va) {
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
@@ -2480,10 +2628,11 @@ int launched() {
 // use while a stream is being captured into a graph.
 enum {
   KT_PRIM2CON, KT_C2P, KT_FILL, KT_BCENT, KT_FACE_X, KT_FACE_Y, KT_FACE_Z, KT_CELL, KT_VERTEX, KT_EDGE, KT_RK,
-  KT_ZERO, KT_ADJ, KT_TMUNU, KT_N
+  KT_ZERO, KT_ADJ, KT_TMUNU, KT_INTER, KT_N
 };
 const char* const kt_names[KT_N] = {"prim2con", "c2p", "fill_ghosts", "centre_B", "face_x", "face_y",
-                                    "face_z", "cell", "vertex", "edge", "rk_stage", "zero", "adjoint", "tmunu"};
+                                    "face_z", "cell", "vertex", "edge", "rk_stage", "zero", "adjoint", "tmunu",
+                                    "inter_level"};
 struct Pending {
   hipEvent_t a, b;
   int kind;
@@ -2810,7 +2959,7 @@ int asterx_timing_reset(void) {
 
 const char* asterx_timing_name(int32_t k) { return (k >= 0 && k < KT_N) ? kt_names[k] : ""; }
 
-int asterx_version(void) { return 6; }
+int asterx_version(void) { return 7; }
 
 const char* asterx_last_error(void) { return g_err.c_str(); }
 
@@ -2934,6 +3083,79 @@ int asterx_tmunu(const asterx_grid* gr, const asterx_params* p, const double* me
   int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
   hipStream_t s = (hipStream_t)stream;
   return timed(KT_TMUNU, s, [&] { hipLaunchKernelGGL(k_tmunu, dim3(lin_blocks(e)), dim3(256), 0, s, g, ta); });
+}
+
+// Coarse index range reached by prolonging fine indices [lo, hi] along one axis.
+void prolong_reach(int lo, int hi, int c0, int vertex, int& cmin, int& cmax) {
+  auto fd = [](int f) { return f >= 0 ? f / 2 : -((1 - f) / 2); };
+  cmin = c0 + fd(lo) - 1;
+  cmax = c0 + fd(hi) + (vertex ? 2 : 1);
+}
+
+int check_inter(const asterx_grid* gc, const asterx_grid* gf, const int32_t* c0, const int32_t* stag, int32_t nf,
+                const void* src, const void* dst, const int32_t* lo, const int32_t* hi, bool prolong) {
+  int rc;
+  if ((rc = check_grid(gc, 2)) || (rc = check_grid(gf, 2))) return rc;
+  if (!c0 || !stag || !lo || !hi || !src || !dst || nf < 1) return fail(ASTERX_EARG, "inter-level: bad arguments");
+  for (int d = 0; d < 3; ++d) {
+    if (stag[d] != 0 && stag[d] != 1) return fail(ASTERX_EARG, "inter-level: stag must be 0 (cell) or 1 (vertex)");
+    if (lo[d] > hi[d]) return fail(ASTERX_EARG, "inter-level: empty box");
+    const asterx_grid* out = prolong ? gf : gc;
+    if (lo[d] < -out->ng || hi[d] > out->n[d] + out->ng) return fail(ASTERX_EARG, "inter-level: box outside the target grid");
+    int rmin, rmax;
+    const asterx_grid* in = prolong ? gc : gf;
+    if (prolong) {
+      prolong_reach(lo[d], hi[d], c0[d], stag[d], rmin, rmax);
+    } else {
+      rmin = 2 * (lo[d] - c0[d]);
+      rmax = 2 * (hi[d] - c0[d]) + 1;
+    }
+    if (rmin < -in->ng || rmax > in->n[d] + in->ng) return fail(ASTERX_EARG, "inter-level: stencil outside the source grid");
+  }
+  return 0;
+}
+
+int inter_launch(const asterx_grid* gc, const asterx_grid* gf, const int32_t* c0, const int32_t* stag, int32_t nf,
+                 const double* src, double* dst, const int32_t* lo, const int32_t* hi, bool prolong, void* stream) {
+  InterArgs a;
+  a.gc = make_gd(gc);
+  a.gf = make_gd(gf);
+  for (int d = 0; d < 3; ++d) {
+    a.c0[d] = c0[d];
+    a.stag[d] = stag[d];
+    a.lo[d] = lo[d];
+    a.hi[d] = hi[d];
+  }
+  a.nf = nf;
+  a.src = src;
+  a.dst = dst;
+  int e[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
+  const bool cells = !stag[0] && !stag[1] && !stag[2];
+  if (prolong && cells)
+    for (int d = 0; d < 3; ++d) {
+      auto fd = [](int f) { return f >= 0 ? f / 2 : -((1 - f) / 2); };
+      e[d] = fd(hi[d]) - fd(lo[d]) + 1;  // coarse parents of the fine box
+    }
+  hipStream_t s = (hipStream_t)stream;
+  return timed(KT_INTER, s, [&] {
+    if (prolong && cells) hipLaunchKernelGGL(k_prolong_cells, dim3(lin_blocks(e)), dim3(256), 0, s, a);
+    else if (prolong) hipLaunchKernelGGL(k_prolong, dim3(lin_blocks(e)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_restrict, dim3(lin_blocks(e)), dim3(256), 0, s, a);
+  });
+}
+
+int asterx_prolong(const asterx_grid* coarse, const asterx_grid* fine, const int32_t* c0, const int32_t* stag,
+                   int32_t nf, const double* cf, double* ff, const int32_t* lo, const int32_t* hi, void* stream) {
+  int rc;
+  if ((rc = check_inter(coarse, fine, c0, stag, nf, cf, ff, lo, hi, true))) return rc;
+  return inter_launch(coarse, fine, c0, stag, nf, cf, ff, lo, hi, true, stream);
+}
+
+int asterx_restrict(const asterx_grid* coarse, const asterx_grid* fine, const int32_t* c0, const int32_t* stag,
+                    int32_t nf, const double* ff, double* cf, const int32_t* lo, const int32_t* hi, void* stream) {
+  int rc;
+  if ((rc = check_inter(coarse, fine, c0, stag, nf, ff, cf, lo, hi, false))) return rc;
+  return inter_launch(coarse, fine, c0, stag, nf, ff, cf, lo, hi, false, stream);
 }
 
 int asterx_zero(double* buf, int64_t count, void* stream) {

@@ -133,6 +133,26 @@ def test_rk_out_layout_and_fused_stage_validation(lib, tmp_path):
                              wsb, None) == -1 and b"bad output" in lib.asterx_last_error()
 
 
+def test_inter_level_validation_on_host(lib):
+    """asterx_prolong / asterx_restrict refuse boxes whose stencils leave the stored points, before any launch."""
+    from paper_2406_11669_amd import asterx
+    from paper_2406_11669_amd.workloads import Layout
+    gc = asterx.make_grid(Layout((10, 9, 8), 3))
+    gf = asterx.make_grid(Layout((10, 8, 6), 3))
+    i3 = lambda *v: (ctypes.c_int32 * 3)(*v)
+    dummy = ctypes.c_void_p(16)
+    # fine box reaching past the coarse grid's last stored cell
+    rc = lib.asterx_prolong(ctypes.byref(gc), ctypes.byref(gf), i3(9, 3, 1), i3(0, 0, 0), 1, dummy, dummy,
+                            i3(0, 0, 0), i3(9, 7, 5), None)
+    assert rc == -1 and b"source grid" in lib.asterx_last_error()
+    rc = lib.asterx_restrict(ctypes.byref(gc), ctypes.byref(gf), i3(2, 3, 1), i3(0, 0, 0), 1, dummy, dummy,
+                             i3(0, 0, 0), i3(9, 8, 7), None)
+    assert rc == -1 and b"source grid" in lib.asterx_last_error()
+    rc = lib.asterx_prolong(ctypes.byref(gc), ctypes.byref(gf), i3(2, 3, 1), i3(2, 0, 0), 1, dummy, dummy,
+                            i3(0, 0, 0), i3(1, 1, 1), None)
+    assert rc == -1 and b"stag" in lib.asterx_last_error()
+
+
 def test_oracle_ghost_fill_matches_definitions(orc):
     import numpy as np
     from paper_2406_11669_amd.workloads import Layout
