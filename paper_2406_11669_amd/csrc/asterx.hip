@@ -690,6 +690,77 @@ DEV void fill_body(const GD& g, const FillArgs& a, unsigned tile) {
   }
 }
 
+// One-pass ghost fill when no axis extrapolates (periodic and copy kinds: every ghost point is a
+// remapped owned point): the ghost points of x (all y, z), of y (owned x, all z) and of z (owned x,
+// y) in one launch, each read from the owned point its per-axis maps reach; periodic offsets are
+// added axis by axis in x, y, z order, exactly as the three axis passes add them, so the result is
+// the same bit for bit.
+struct Fill1Args {
+  double* f;
+  int nf;
+  int kind[3];
+  double shift[3][3];  // [field][axis], fields 0..2
+};
+
+DEV long long fill1_points(const GD& g) {
+  const long long G = 2 * g.ng + 1, E1 = g.n[1] + 2 * g.ng + 1, E2 = g.n[2] + 2 * g.ng + 1;
+  return G * E1 * E2 + (long long)g.n[0] * G * E2 + (long long)g.n[0] * g.n[1] * G;
+}
+
+DEV void fill1_body(const GD& g, const Fill1Args& a, unsigned tile) {
+#pragma clang fp contract(off)
+  const int ng = g.ng, G = 2 * ng + 1;
+  const int E1 = g.n[1] + 2 * ng + 1;
+  const long long s0 = (long long)G * E1 * (g.n[2] + 2 * ng + 1), s1 = (long long)g.n[0] * G * (g.n[2] + 2 * ng + 1),
+                  s2 = (long long)g.n[0] * g.n[1] * G;
+  long long t = (long long)tile * 256 + threadIdx.x;
+  auto gh = [&](int q, int n) { return q < ng ? q - ng : n + (q - ng); };
+  int idx[3];
+  if (t < s0) {
+    idx[0] = gh((int)(t % G), g.n[0]);
+    const long long r = t / G;
+    idx[1] = (int)(r % E1) - ng;
+    idx[2] = (int)(r / E1) - ng;
+  } else if ((t -= s0) < s1) {
+    idx[0] = (int)(t % g.n[0]);
+    const long long r = t / g.n[0];
+    idx[1] = gh((int)(r % G), g.n[1]);
+    idx[2] = (int)(r / G) - ng;
+  } else if ((t -= s1) < s2) {
+    idx[0] = (int)(t % g.n[0]);
+    const long long r = t / g.n[0];
+    idx[1] = (int)(r % g.n[1]);
+    idx[2] = gh((int)(r / g.n[1]), g.n[2]);
+  } else {
+    return;
+  }
+  int src[3], wrap[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int sd = idx[d], n = g.n[d];
+    if (sd >= 0 && sd < n) {
+      src[d] = sd;
+      wrap[d] = 0;
+    } else if (a.kind[d] == ASTERX_BC_PERIODIC) {
+      src[d] = ((sd % n) + n) % n;
+      wrap[d] = (sd - src[d]) / n;
+    } else {
+      src[d] = sd < 0 ? 0 : n - 1;
+      wrap[d] = 0;
+    }
+  }
+  const int dst = at(g, idx[0], idx[1], idx[2]), so = at(g, src[0], src[1], src[2]);
+  for (int f = 0; f < a.nf; ++f) {
+    double* F = a.f + (size_t)f * g.N;
+    double val = F[so];
+    if (f < 3)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (wrap[d] != 0 && a.shift[f][d] != 0.0) val = val + (double)wrap[d] * a.shift[f][d];
+    F[dst] = val;
+  }
+}
+
 // Centre field of every cell in [-ng, n+ng-1]^3 (read by the face stencils).
 DEV void bcent_body(const GD& g, const double* __restrict__ A, double* __restrict__ bc, unsigned tile) {
   int e[3] = {g.n[0] + 2 * g.ng, g.n[1] + 2 * g.ng, g.n[2] + 2 * g.ng};
@@ -1719,6 +1790,17 @@ __global__ __launch_bounds__(256) void kb_c2p(const PatchDesc* __restrict__ P, c
 }
 
 __global__ __launch_bounds__(256) void k_fill(GD g, FillArgs a) { fill_body(g, a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_fill1(GD g, Fill1Args a) { fill1_body(g, a, blockIdx.x); }
+__global__ __launch_bounds__(256) void kb_fill1(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
+                                                Fill1Args a) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item m = it[w];
+    const PatchDesc d = P[m.patch];
+    Fill1Args b = a;
+    b.f = a.f + d.off;
+    fill1_body(d.g, b, (unsigned)m.tile);
+  }
+}
 __global__ __launch_bounds__(256) void kb_fill(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                                FillArgs a) {
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
@@ -2677,7 +2759,8 @@ int timed(int kind, hipStream_t s, F&& launch) {
 // ---------------------------------------------------------------------------------------
 // Launch targets.  A single block launches one workgroup per tile of each phase; a batch
 // of patches launches a persistent grid over that phase's (patch, tile) work list.
-enum { PH_P2C, PH_C2P, PH_FILLX, PH_FILLY, PH_FILLZ, PH_BCENT, PH_FACE, PH_CELL, PH_VERTEX, PH_EDGE, PH_RK, PH_N };
+enum { PH_P2C, PH_C2P, PH_FILLX, PH_FILLY, PH_FILLZ, PH_BCENT, PH_FACE, PH_CELL, PH_VERTEX, PH_EDGE, PH_RK, PH_FILL1,
+       PH_N };
 
 unsigned host_tile_blocks(const GD& g) {
   return (unsigned)(((g.n[0] + CTX - 1) / CTX) * ((g.n[1] + CTY - 1) / CTY) * ((g.n[2] + CTZ - 1) / CTZ));
@@ -2701,6 +2784,11 @@ unsigned tiles_for(int phase, const GD& g) {
     case PH_BCENT:
       for (int a = 0; a < 3; ++a) e[a] = g.n[a] + 2 * g.ng;
       return lin_blocks(e);
+    case PH_FILL1: {
+      const long long G = 2 * g.ng + 1, E1 = g.n[1] + 2 * g.ng + 1, E2 = g.n[2] + 2 * g.ng + 1;
+      const long long cnt = G * E1 * E2 + (long long)g.n[0] * G * E2 + (long long)g.n[0] * g.n[1] * G;
+      return (unsigned)((cnt + 255) / 256);
+    }
     case PH_FACE:
       for (int a = 0; a < 3; ++a) e[a] = g.n[a] + 1;
       return face_tiles(e);
@@ -2807,6 +2895,13 @@ int do_c2p_learned(const GD& g, const asterx_params* p, const double* metric, co
 int do_fill(const GD& g, const asterx_batch* b, double* f, int nf, const int32_t* kinds, hipStream_t s,
             const double* shift = nullptr) {
   int rc;
+  if (kinds[0] != ASTERX_BC_LINEAR && kinds[1] != ASTERX_BC_LINEAR && kinds[2] != ASTERX_BC_LINEAR) {
+    Fill1Args fa{f, nf, {kinds[0], kinds[1], kinds[2]}, {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}}};
+    if (shift)
+      for (int q = 0; q < 3 && q < nf; ++q)
+        for (int a = 0; a < 3; ++a) fa.shift[q][a] = shift[q * 3 + a];
+    return RUN_PHASE(KT_FILL, PH_FILL1, k_fill1, kb_fill1, fa);
+  }
   for (int a = 0; a < 3; ++a) {
     FillArgs fa{f, nf, a, kinds[a], {0.0, 0.0, 0.0}};
     if (shift)
