@@ -34,8 +34,9 @@ namespace {
 thread_local std::string g_err;
 
 // rhs workspace: centre field (3) + face fluxes (3 directions x 7) + G_A (1) + F_Psi (3)
-// right-hand side workspace: centre field 3, face fluxes 21, G_A 1, F_Psi 3, upwind-CT speeds 6
-constexpr int WS_FIELDS = 3 + 21 + 1 + 3 + 6;
+// right-hand side workspace: centre field 3, face fluxes 21, G_A 1, F_Psi 3, upwind-CT speeds and face
+// fields 9
+constexpr int WS_FIELDS = 3 + 21 + 1 + 3 + 9;
 
 int fail(int code, const char* msg) {
   g_err = msg;
@@ -786,7 +787,7 @@ struct FaceArgs {
   double* red;
   double gam, weno_eps, weno_q, gfac;
   int recon, speeds, riemann;
-  double* apm;  // UCT: a_+ and a_- per direction
+  double* apm;  // UCT: a_+, a_- and the normal field per direction
 };
 
 // Paired-lane variant: lanes 2f and 2f+1 of a wavefront handle the left and the right state
@@ -963,7 +964,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   // y and z faces: the direct 16-point gather (one transverse direction is x, so a
   // wavefront's loads are contiguous rows) measured faster than the staged block, except
   // for z faces under WENO-Z
-  constexpr bool METRIC_LDS = !UCT && !(D == 1 || (D == 2 && RECON != ASTERX_RECON_WENOZ));
+  constexpr bool METRIC_LDS = !(D == 1 || (D == 2 && RECON != ASTERX_RECON_WENOZ));
   if (!METRIC_LDS || rest) {
     if (valid) {
       const int s1 = st[t1], s2 = st[t2];
@@ -988,7 +989,8 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       }
     }
   } else {
-    const int X0 = D == 0 ? ax0 : ax0 - 2, Y0 = D == 1 ? by0 : by0 - 2, Z0 = D == 2 ? cz : cz - 2;
+    // the block starts one vertex below the first face's transverse position (face index - LO)
+    const int X0 = D == 0 ? ax0 : ax0 - LO - 1, Y0 = D == 1 ? by0 : by0 - LO - 1, Z0 = D == 2 ? cz : cz - LO - 1;
     int foff[FB::NR];
     double pre[FB::NR];
 #pragma unroll
@@ -1095,8 +1097,9 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       if (side == 0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) fa.flux[(size_t)(D * 7 + q) * g.N + id] = out[q];
-        fa.apm[(size_t)(D * 2) * g.N + id] = cmax;
-        fa.apm[(size_t)(D * 2 + 1) * g.N + id] = cmin;
+        fa.apm[(size_t)(D * 3) * g.N + id] = cmax;
+        fa.apm[(size_t)(D * 3 + 1) * g.N + id] = cmin;
+        fa.apm[(size_t)(D * 3 + 2) * g.N + id] = Bn;
       } else {
         fa.flux[(size_t)(D * 7 + 4) * g.N + id] = out[4];
         fa.flux[(size_t)(D * 7 + 5) * g.N + id] = vbar[0];
@@ -1601,42 +1604,32 @@ struct EdgeArgs {
   double xi;
   int gauge;
   Combine cmb;
-  const double* A;    // UCT: the face fields come from the curl of A
-  const double* apm;  // UCT: a_+ and a_- per face direction
+  const double* apm;  // UCT: a_+, a_- and the normal field per face direction (stored by the face kernel)
 };
-
-// Normal densitized field on a face of direction FD.
-template <int FD>
-DEV double face_Bn(const GD& g, const double* A, int id) {
-  const double* Ax = A;
-  const double* Ay = A + g.N;
-  const double* Az = A + 2 * g.N;
-  if constexpr (FD == 0) return faceBx(Ay, Az, id, g.sy, g.sz, g);
-  else if constexpr (FD == 1) return faceBy(Ax, Az, id, g.sy, g.sz, g);
-  else return faceBz(Ax, Ay, id, g.sy, g.sz, g);
-}
 
 // One term of the upwind edge field (Sec. 3.4, eq. eq3.20) at the edge owned by point id: the 1-D
 // Riemann problem along DIR, from the FD-faces in the row through the edge along DIR (their upwind
-// velocity component DIR and normal field, PPM-reconstructed to the edge from below (L) and above
-// (R)), with the larger speeds of the two DIR-faces meeting at the edge (offset along SDIR).
+// velocity component DIR and normal field, both stored by the UCT face kernel, PPM-reconstructed to
+// the edge from below (L) and above (R)), with the larger speeds of the two DIR-faces meeting at the
+// edge (offset along SDIR).
 template <int DIR, int FD, int SDIR>
 DEV double uct_term(const GD& g, const EdgeArgs& ea, int id) {
   const int st[3] = {1, g.sy, g.sz};
   const int sd = st[DIR];
   constexpr int slot = DIR == (FD + 1) % 3 ? 5 : 6;
   const double* vb = ea.flux + (size_t)(FD * 7 + slot) * g.N;
+  const double* bn = ea.apm + (size_t)(FD * 3 + 2) * g.N;
   double v6[6], b6[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     v6[s] = vb[id + (s - 3) * sd];
-    b6[s] = face_Bn<FD>(g, ea.A, id + (s - 3) * sd);
+    b6[s] = bn[id + (s - 3) * sd];
   }
   const double vm[5] = {v6[5], v6[4], v6[3], v6[2], v6[1]}, bm[5] = {b6[5], b6[4], b6[3], b6[2], b6[1]};
   const double vl = recon_right_face<ASTERX_RECON_PPM>(v6, 0.0, 1.0), vr = recon_right_face<ASTERX_RECON_PPM>(vm, 0.0, 1.0);
   const double bl = recon_right_face<ASTERX_RECON_PPM>(b6, 0.0, 1.0), br = recon_right_face<ASTERX_RECON_PPM>(bm, 0.0, 1.0);
-  const double* ap = ea.apm + (size_t)(DIR * 2) * g.N;
-  const double* am = ea.apm + (size_t)(DIR * 2 + 1) * g.N;
+  const double* ap = ea.apm + (size_t)(DIR * 3) * g.N;
+  const double* am = ea.apm + (size_t)(DIR * 3 + 1) * g.N;
   const int o = st[SDIR];
   const double a_p = fmax(ap[id], ap[id - o]), a_m = fmax(am[id], am[id - o]);
   const double den = a_p + a_m;
@@ -2936,7 +2929,7 @@ int do_rhs(const GD& g, const asterx_batch* b, const asterx_params* p, const dou
     VertexArgs va{metric, A, psi, ga, fp};
     if ((rc = RUN_PHASE(KT_VERTEX, PH_VERTEX, k_vertex, kb_vertex, va))) return rc;
   }
-  EdgeArgs ea{metric, psi, flux, ga, fp, rhs, p->xi / dt_max, p->gauge, cmb, A, apm};
+  EdgeArgs ea{metric, psi, flux, ga, fp, rhs, p->xi / dt_max, p->gauge, cmb, apm};
   if (uct)
     return timed(KT_EDGE, s, [&] {
       hipLaunchKernelGGL(k_edge_uct, dim3(tiles_for(PH_EDGE, g)), dim3(256), 0, s, g, ea);

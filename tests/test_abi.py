@@ -78,7 +78,7 @@ def test_host_side_argument_validation(lib):
     g.ld[1] = 10
     rc = lib.asterx_fill_ghosts(ctypes.byref(g), dummy, 1, (ctypes.c_int32 * 3)(0, 0, 0), None)
     assert rc == -1 and b"ld" in lib.asterx_last_error()
-    assert lib.asterx_rhs_workspace_size(ctypes.byref(asterx.make_grid(L))) == 34 * 8 * L.npts
+    assert lib.asterx_rhs_workspace_size(ctypes.byref(asterx.make_grid(L))) == 37 * 8 * L.npts
 
 
 def test_rk_out_layout_and_fused_stage_validation(lib, tmp_path):
