@@ -1347,10 +1347,38 @@ struct TmunuArgs {
   double gam;
 };
 
-DEV void tmunu_body(const GD& g, const TmunuArgs& ta, unsigned tile) {
-  int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
-  int i, j, k;
-  if (!lin_at(e, tile, threadIdx.x, i, j, k)) return;
+// Tiles of 16 x 4 x 4 vertices: the primitives and centre fields of the 17 x 5 x 5 cells they share are
+// staged through LDS once (the centre field from the curl of A), then each vertex averages its 8 cells.
+constexpr int TV_X = 16, TV_Y = 4, TV_Z = 4, TC_X = TV_X + 1, TC_Y = TV_Y + 1, TC_Z = TV_Z + 1;
+constexpr int TC_N = TC_X * TC_Y * TC_Z;
+struct TmunuLDS {
+  double c[8][TC_N];
+};
+
+unsigned tmunu_tiles(const GD& g) {
+  return (unsigned)(((g.n[0] + TV_X) / TV_X) * ((g.n[1] + TV_Y) / TV_Y) * ((g.n[2] + TV_Z) / TV_Z));
+}
+
+DEV void tmunu_body(const GD& g, const TmunuArgs& ta, unsigned tile, TmunuLDS& L) {
+  const int nbx = (g.n[0] + TV_X) / TV_X, nby = (g.n[1] + TV_Y) / TV_Y;
+  const int i0 = (int)(tile % nbx) * TV_X, j0 = (int)((tile / nbx) % nby) * TV_Y, k0 = (int)(tile / (nbx * nby)) * TV_Z;
+  for (int q = threadIdx.x; q < TC_N; q += 256) {
+    const int ci = i0 - 1 + q % TC_X, cj = j0 - 1 + (q / TC_X) % TC_Y, ck = k0 - 1 + q / (TC_X * TC_Y);
+    // cells -1 .. n serve the vertices 0 .. n; cells beyond are not staged (no vertex reads them)
+    if (ci <= g.n[0] && cj <= g.n[1] && ck <= g.n[2]) {
+      const int c = at(g, ci, cj, ck);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) L.c[v][q] = ta.prim[v * g.N + c];
+      double b[3];
+      centre_B(ta.A, g, c, b);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) L.c[5 + v][q] = b[v];
+    }
+  }
+  __syncthreads();
+  const int vx = threadIdx.x % TV_X, vy = (threadIdx.x / TV_X) % TV_Y, vz = threadIdx.x / (TV_X * TV_Y);
+  const int i = i0 + vx, j = j0 + vy, k = k0 + vz;
+  if (i > g.n[0] || j > g.n[1] || k > g.n[2]) return;
   double pr[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, Bt[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int dk = -1; dk <= 0; ++dk)
@@ -1358,13 +1386,11 @@ DEV void tmunu_body(const GD& g, const TmunuArgs& ta, unsigned tile) {
     for (int dj = -1; dj <= 0; ++dj)
 #pragma unroll
       for (int di = -1; di <= 0; ++di) {
-        const int c = at(g, i + di, j + dj, k + dk);
+        const int q = (vx + 1 + di) + TC_X * ((vy + 1 + dj) + TC_Y * (vz + 1 + dk));
 #pragma unroll
-        for (int q = 0; q < 5; ++q) pr[q] += ta.prim[q * g.N + c];
-        double b[3];
-        centre_B(ta.A, g, c, b);
+        for (int v = 0; v < 5; ++v) pr[v] += L.c[v][q];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) Bt[q] += b[q];
+        for (int v = 0; v < 3; ++v) Bt[v] += L.c[5 + v][q];
       }
 #pragma unroll
   for (int q = 0; q < 5; ++q) pr[q] *= 0.125;
@@ -1866,7 +1892,10 @@ __global__ __launch_bounds__(256) void kb_cell(const PatchDesc* __restrict__ P, 
 }
 
 __global__ __launch_bounds__(256) void k_vertex(GD g, VertexArgs va) { vertex_body(g, va, my_tile()); }
-__global__ __launch_bounds__(256) void k_tmunu(GD g, TmunuArgs ta) { tmunu_body(g, ta, my_tile()); }
+__global__ __launch_bounds__(256) void k_tmunu(GD g, TmunuArgs ta) {
+  __shared__ TmunuLDS L;
+  tmunu_body(g, ta, my_tile(), L);
+}
 __global__ __launch_bounds__(256) void k_prolong(InterArgs a) { prolong_body(a, my_tile()); }
 __global__ __launch_bounds__(256) void k_prolong_cells(InterArgs a) { prolong_cells_body(a, my_tile()); }
 __global__ __launch_bounds__(256) void k_restrict(InterArgs a) { restrict_body(a, my_tile()); }
@@ -3168,9 +3197,8 @@ int asterx_tmunu(const asterx_grid* gr, const asterx_params* p, const double* me
   if (!metric || !prim || !A || !tmunu) return fail(ASTERX_EARG, "tmunu: NULL array");
   GD g = make_gd(gr);
   TmunuArgs ta{metric, prim, A, tmunu, p->gamma};
-  int e[3] = {g.n[0] + 1, g.n[1] + 1, g.n[2] + 1};
   hipStream_t s = (hipStream_t)stream;
-  return timed(KT_TMUNU, s, [&] { hipLaunchKernelGGL(k_tmunu, dim3(lin_blocks(e)), dim3(256), 0, s, g, ta); });
+  return timed(KT_TMUNU, s, [&] { hipLaunchKernelGGL(k_tmunu, dim3(tmunu_tiles(g)), dim3(256), 0, s, g, ta); });
 }
 
 // Coarse index range reached by prolonging fine indices [lo, hi] along one axis.
