@@ -60,7 +60,7 @@ enum {
 
 /* Block geometry.  n: owned cells per axis (>= 1); ng: ghost layers (>= 3 for
  * asterx_rhs, whose face stencils span six cells; >= 2 elsewhere); ld: allocated extents
- * (>= n + 2 ng + 1; ld[0]*ld[1]*ld[2] below 2^31); dx: spacing. */
+ * (>= n + 2 ng + 1; ld[0]*ld[1]*ld[2] below 2^29, so that byte offsets within a field fit 32 bits); dx: spacing. */
 typedef struct {
   int32_t n[3];
   int32_t ng;

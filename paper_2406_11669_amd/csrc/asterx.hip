@@ -71,6 +71,14 @@ GD make_gd(const asterx_grid* g) {
 
 DEV int at(const GD& g, int i, int j, int k) { return ((k + g.ng) * g.ld1 + (j + g.ng)) * g.ld0 + (i + g.ng); }
 
+// Element i >= 0 of a field whose base is the same for the whole wavefront: the address is
+// formed by the load from the scalar base and a 32-bit per-lane byte offset (fields hold fewer
+// than 2^29 points, checked on the host), instead of a 64-bit vector add per access.
+template <class T>
+DEV T ldu(const T* base, int i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (unsigned)i * (unsigned)sizeof(T));
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs; remap the linear block id so that
 // each XCD walks a contiguous range of tiles (neighbouring tiles share its L2).
 DEV unsigned xcd_block(unsigned bid, unsigned nblocks) {
@@ -334,7 +342,7 @@ DEV TileIdx tile_index(const GD& g, const TileCell& t) {
 // cells outside the block, whose results are discarded.
 DEV void tile_fetch(const double* __restrict__ f, const TileIdx& x, double pre[NFETCH]) {
 #pragma unroll
-  for (int r = 0; r < NFETCH; ++r) pre[r] = f[x.fetch[r] >= 0 ? x.fetch[r] : 0];
+  for (int r = 0; r < NFETCH; ++r) pre[r] = ldu(f, x.fetch[r] >= 0 ? x.fetch[r] : 0);
 }
 
 DEV void tile_store(const TileIdx& x, const double pre[NFETCH], double* sv) {
@@ -797,7 +805,14 @@ struct FaceArgs {
 // exchanges metric halves and side results through lane shuffles and both evaluate HLLE,
 // the left lane storing components 0-3, the right lane 4-6.  Half the live state per lane
 // of a one-lane-per-face kernel, twice the lanes in flight.
-DEV double shfl1(double v) { return __shfl_xor(v, 1, 64); }
+// The swap is a DPP quad permutation (1, 0, 3, 2) of the two 32-bit halves: a VALU move, with no
+// round trip through the LDS crossbar; both lanes of a pair are always active together.
+DEV double shfl1(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0xB1, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 template <int kind, class T>
 DEV T recon_right_face(const T a[5], double eps, double q) {
@@ -863,7 +878,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   const int st[3] = {1, g.sy, g.sz};
   const int sD = st[D];
   // reconstruction of this lane's side: left lane cells i-3..i+1, right lane i+2..i-2
-  double X[7], C[7];
+  double X[7];
   auto direct_recon = [&]() {
     const int o0 = side ? 2 : -3, os = side ? -1 : 1;
     if constexpr (RECON == ASTERX_RECON_WENOZ && D == 2) {
@@ -873,7 +888,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       auto field = [&](int v) { return v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N; };
       double nx[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) nx[q] = field(0)[id + (o0 + os * q) * sD];
+      for (int q = 0; q < 5; ++q) nx[q] = ldu(field(0), id + (o0 + os * q) * sD);
 #pragma unroll 1
       for (int v = 0; v < 7; ++v) {
         double s5[5];
@@ -882,14 +897,11 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
         if (v < 6) {
           const double* f = field(v + 1);
 #pragma unroll
-          for (int q = 0; q < 5; ++q) nx[q] = f[id + (o0 + os * q) * sD];
+          for (int q = 0; q < 5; ++q) nx[q] = ldu(f, id + (o0 + os * q) * sD);
         }
         const double xv = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-          X[k] = v == k ? xv : X[k];
-          C[k] = v == k ? s5[2] : C[k];
-        }
+        for (int k = 0; k < 7; ++k) X[k] = v == k ? xv : X[k];
       }
     } else if constexpr (RECON == ASTERX_RECON_WENOZ) {
 #pragma unroll 1
@@ -897,13 +909,10 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
         const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
         double s5[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) s5[q] = f[id + (o0 + os * q) * sD];
+        for (int q = 0; q < 5; ++q) s5[q] = ldu(f, id + (o0 + os * q) * sD);
         const double xv = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-          X[k] = v == k ? xv : X[k];
-          C[k] = v == k ? s5[2] : C[k];
-        }
+        for (int k = 0; k < 7; ++k) X[k] = v == k ? xv : X[k];
       }
     } else {
       // all 35 stencil values are loaded before the first reconstruction
@@ -912,13 +921,10 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       for (int v = 0; v < 7; ++v) {
         const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) s5[v][q] = f[id + (o0 + os * q) * sD];
+        for (int q = 0; q < 5; ++q) s5[v][q] = ldu(f, id + (o0 + os * q) * sD);
       }
 #pragma unroll
-      for (int v = 0; v < 7; ++v) {
-        X[v] = recon_right_face<RECON>(s5[v], fa.weno_eps, fa.weno_q);
-        C[v] = s5[v][2];
-      }
+      for (int v = 0; v < 7; ++v) X[v] = recon_right_face<RECON>(s5[v], fa.weno_eps, fa.weno_q);
     }
   };
   if (D == 1 && RECON == ASTERX_RECON_WENOZ && !UCT && !rest) {
@@ -951,10 +957,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
         stencil(v, s5);
         const double xv = recon_right_face<RECON>(s5, fa.weno_eps, fa.weno_q);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-          X[k] = v == k ? xv : X[k];
-          C[k] = v == k ? s5[2] : C[k];
-        }
+        for (int k = 0; k < 7; ++k) X[k] = v == k ? xv : X[k];
       }
     }
   } else if (valid) {
@@ -999,7 +1002,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       const int X = X0 + q % FB::BX, Y = Y0 + (q / FB::BX) % FB::BY, Z = Z0 + q / (FB::BX * FB::BY);
       const bool in = q < FB::N && X <= g.n[0] + g.ng && Y <= g.n[1] + g.ng && Z <= g.n[2] + g.ng;
       foff[r] = in ? at(g, X, Y, Z) : -1;
-      pre[r] = in ? fa.metric[foff[r]] : 0.0;
+      pre[r] = in ? ldu(fa.metric, foff[r]) : 0.0;
     }
     const int lst[3] = {1, FB::BX, FB::BX * FB::BY};
     const int ls1 = lst[t1], ls2 = lst[t2];
@@ -1013,7 +1016,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       __syncthreads();
       if (q < 9)
 #pragma unroll
-        for (int r = 0; r < FB::NR; ++r) pre[r] = foff[r] >= 0 ? fa.metric[(size_t)(q + 1) * g.N + foff[r]] : 0.0;
+        for (int r = 0; r < FB::NR; ++r) pre[r] = foff[r] >= 0 ? ldu(fa.metric + (size_t)(q + 1) * g.N, foff[r]) : 0.0;
       double ra = 0.0, rb = 0.0;
       if (valid) {
         const double* p = buf + lbase;
@@ -1036,14 +1039,16 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
     const double* Az = fa.A + 2 * g.N;
     double Bn = D == 0 ? faceBx(Ay, Az, id, g.sy, g.sz, g)
                        : (D == 1 ? faceBy(Ax, Az, id, g.sy, g.sz, g) : faceBz(Ax, Ay, id, g.sy, g.sz, g));
-    // an unphysical reconstructed state falls back to the cell's own values
+    // an unphysical reconstructed state falls back to the values of this side's own cell (i-1 for
+    // the left lane, i for the right one), read again (rare) rather than kept in registers
     {
       double vl[3], v[3] = {X[2], X[3], X[4]};
       lower(G.g, v, vl);
       double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
       if (!(X[0] > 0.0) || !(X[1] > 0.0) || !(v2 < 1.0)) {
+        const int own = side ? id : id - sD;
 #pragma unroll
-        for (int q = 0; q < 7; ++q) X[q] = C[q];
+        for (int q = 0; q < 7; ++q) X[q] = ldu(q < 5 ? fa.prim + q * g.N : fa.bc + (q == 5 ? t1 : t2) * g.N, own);
       }
     }
     double Bt[3];
@@ -1075,7 +1080,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       w_own = w_oth = 0.5;
       w_u = side ? -hw : hw;
     } else {
-      double id_ = den > 0.0 ? 1.0 / den : 0.0;
+      double id_ = den > 0.0 ? recip(den) : 0.0;
       double cc = cmax * cmin;
       w_own = den > 0.0 ? (side ? cmin : cmax) * id_ : 0.5;
       w_oth = den > 0.0 ? (side ? cmax : cmin) * id_ : 0.5;
@@ -1314,7 +1319,7 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const double* F = ca.flux + (size_t)(d * 7 + c) * g.N;
-        sdiv += (F[id + st[d]] - F[id]) * g.idx[d];
+        sdiv += (ldu(F, id + st[d]) - ldu(F, id)) * g.idx[d];
       }
       emit(ca.cmb, ca.rhs, (size_t)c * g.N + id, as * src[c] - sdiv);
     }
@@ -1842,12 +1847,12 @@ __global__ __launch_bounds__(256) void kb_bcent(const PatchDesc* __restrict__ P,
 }
 
 template <int D, int R>
-__global__ __launch_bounds__(256) void k_face(GD g, FaceArgs fa) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_face(GD g, FaceArgs fa) {
   __shared__ FaceLDS L;
   face_body<D, R>(g, fa, my_tile(), L);
 }
 template <int D, int R>
-__global__ __launch_bounds__(256) void k_face_uct(GD g, FaceArgs fa) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_face_uct(GD g, FaceArgs fa) {
   __shared__ FaceLDS L;
   face_body<D, R, true>(g, fa, my_tile(), L);
 }
@@ -2698,7 +2703,7 @@ int check_grid(const asterx_grid* g, int min_ng) {
   }
   if (g->ng < min_ng) return fail(ASTERX_EARG, "grid: too few ghost layers for this stencil");
   double npts = (double)g->ld[0] * g->ld[1] * g->ld[2];
-  if (npts >= 2147483647.0) return fail(ASTERX_EARG, "grid: ld[0]*ld[1]*ld[2] must be below 2^31");
+  if (npts >= 536870912.0) return fail(ASTERX_EARG, "grid: ld[0]*ld[1]*ld[2] must be below 2^29");
   return 0;
 }
 
