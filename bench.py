@@ -85,7 +85,7 @@ def parse():
                     help="edge electric field: flux CT or upwind CT (4 ghost layers)")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=56, help="edge of the block the CPU oracle times")
+    ap.add_argument("--cpu-n", type=int, default=88, help="edge of the block the CPU oracle times")
     ap.add_argument("--learned-c2p", action="store_true",
                     help="seed every c2p with the learned guess (network trained first, outside the timed region)")
     ap.add_argument("--copy-calibration", action="store_true",

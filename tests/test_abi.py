@@ -78,6 +78,14 @@ def test_host_side_argument_validation(lib):
     g.ld[1] = 10
     rc = lib.asterx_fill_ghosts(ctypes.byref(g), dummy, 1, (ctypes.c_int32 * 3)(0, 0, 0), None)
     assert rc == -1 and b"ld" in lib.asterx_last_error()
+    # a field of 2^29 points or more: byte offsets within a field would not fit 32 bits
+    g3 = asterx.make_grid(Layout((8, 8, 8), 3))
+    g3.ld[0], g3.ld[1], g3.ld[2] = 1024, 1024, 512
+    rc = lib.asterx_fill_ghosts(ctypes.byref(g3), dummy, 1, (ctypes.c_int32 * 3)(0, 0, 0), None)
+    assert rc == -1 and b"2^29" in lib.asterx_last_error()
+    g3.ld[2] = 511  # passes the size check, then stops at nf = 0 before any launch
+    rc = lib.asterx_fill_ghosts(ctypes.byref(g3), dummy, 0, (ctypes.c_int32 * 3)(0, 0, 0), None)
+    assert rc == -1 and b"bad arguments" in lib.asterx_last_error()
     assert lib.asterx_rhs_workspace_size(ctypes.byref(asterx.make_grid(L))) == 37 * 8 * L.npts
 
 
