@@ -424,3 +424,36 @@ def test_time_dependent_metric_steps_vs_oracle(ax, torch_mod, orc, fused):
         t += dt
     assert_fields_close(_host(blk.state), U0, 1e-10, L.owned, STATE_NAMES)
     assert_fields_close(_host(blk.prim), prim, 1e-10, L.owned, PRIM_NAMES)
+
+
+@pytest.mark.parametrize("recon", ["ppm", "ppm+hlle+uct"])
+def test_block_graph_replays_match_eager(ax, torch_mod, recon):
+    """The benchmark's form: one fused RK4 step of a block captured in a HIP graph and replayed, with eager work
+    and synchronizations between the replays; every replay equals the eagerly stepped block bit for bit
+    (state, primitives, running reductions and c2p counters)."""
+    torch = torch_mod
+    w = W.curved_block(seed=21, n=(24, 13, 11), recon=recon.split("+")[0], nsteps=4, rk=4, ng=_ng(recon))
+    _scheme(w, recon)
+    print("case graph replays", recon, flush=True)
+    eager = ax.Block(w)
+    graphed = ax.Block(w)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        graphed.step()  # step 1, eager, on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        graphed.step()
+    eager.step()
+    torch.cuda.synchronize()
+    for rep in range(3):  # steps 2, 3 and 4
+        g.replay()
+        torch.cuda.synchronize()
+        eager.step()
+        torch.cuda.synchronize()
+        assert torch.equal(graphed.state, eager.state), rep
+        assert torch.equal(graphed.prim, eager.prim), rep
+        assert torch.equal(graphed.red, eager.red) and torch.equal(graphed.stats, eager.stats), rep
+        assert np.isfinite(eager.state.sum().item())  # eager work between replays
