@@ -846,10 +846,15 @@ struct FaceBlk {
 constexpr int FACE_LDS = 32 * 7 * 4;
 // y faces stage their reconstruction stencils instead: 7 variables x 9 rows (y) x 32 cells (x)
 constexpr int FACE_RY = 9, FACE_RX = 32, FACE_RV = FACE_RY * FACE_RX, FACE_RN = 7 * FACE_RV;
+// y and z faces of a main tile interpolate their metric in two passes: each lane the 4-point pass
+// across its x column, through a wavefront-private row of 35 columns per component and side, then the
+// 4-point pass along x from that row (a wavefront is one 32-face row of the tile).
+constexpr int FACE_GC = 35;
 struct FaceLDS {
   union {
     double m[2][FACE_LDS];
     double r[FACE_RN];
+    double g[4][5][2][FACE_GC];
   };
 };
 static_assert(FaceBlk<0>::N <= FACE_LDS && FaceBlk<1>::N <= FACE_LDS && FaceBlk<2>::N <= FACE_LDS, "face LDS");
@@ -968,7 +973,52 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   // wavefront's loads are contiguous rows) measured faster than the staged block, except
   // for z faces under WENO-Z
   constexpr bool METRIC_LDS = !(D == 1 || (D == 2 && RECON != ASTERX_RECON_WENOZ));
-  if (!METRIC_LDS || rest) {
+  // y faces (other than WENO-Z's, whose stencils occupy the LDS) and gathered z faces of main tiles:
+  // the x pass of the face metric is shared through a wavefront-private LDS row
+  // (main tiles are 32 faces wide when the face row is; narrower rows gather directly)
+  constexpr bool METRIC_ROW = !METRIC_LDS && !(D == 1 && RECON == ASTERX_RECON_WENOZ);
+  if (METRIC_ROW && !rest && e[0] >= 32) {
+    if (valid) {
+      // the other transverse direction (z for y faces, y for z faces); x is the wavefront's row
+      const int so = D == 1 ? g.sz : g.sy;
+      const int w = threadIdx.x >> 6, f = (threadIdx.x >> 1) & 31;
+      // vertex column x = i - 1 of this lane's face i; lanes f < 3 also take column i + 31
+      const int mb = id - so - 1;
+      const double* p0 = fa.metric + (size_t)(5 * side) * g.N + mb;
+      double zc[5], mine[5];
+      // all 20 column loads in one block, so they are in flight together
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const double* p = p0 + (size_t)q * g.N;
+        zc[q] = lag(p[0], p[so], p[2 * so], p[3 * so]);
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) L.g[w][q][side][f] = zc[q];
+      if (f < 3) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const double* p = p0 + (size_t)q * g.N + 32;
+          L.g[w][q][side][32 + f] = lag(p[0], p[so], p[2 * so], p[3 * so]);
+        }
+      }
+      // the row is written and read by this wavefront only (its LDS accesses execute in order): a
+      // wavefront-level barrier keeps the compiler from moving the reads above the writes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const double* row = L.g[w][q][side] + f;
+        mine[q] = lag(row[0], row[1], row[2], row[3]);
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        double other = shfl1(mine[q]);
+        m[q] = side ? other : mine[q];
+        m[5 + q] = side ? mine[q] : other;
+      }
+    }
+  } else if (!METRIC_LDS || rest) {
     if (valid) {
       const int s1 = st[t1], s2 = st[t2];
       const int mb = id - s1 - s2;
@@ -1847,7 +1897,7 @@ __global__ __launch_bounds__(256) void kb_bcent(const PatchDesc* __restrict__ P,
 }
 
 template <int D, int R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_face(GD g, FaceArgs fa) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == ASTERX_RECON_WENOZ ? 5 : 4))) void k_face(GD g, FaceArgs fa) {
   __shared__ FaceLDS L;
   face_body<D, R>(g, fa, my_tile(), L);
 }
