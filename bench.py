@@ -206,9 +206,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one block on one GPU; runs on more than one GPU are not part of this build "
-              "(the multi-GPU design is a domain decomposition with halo exchange, not implemented)",
-              file=sys.stderr)
+        print("bench.py measures one block on one GPU; a run on more than one GPU would need the domain "
+              "decomposition with halo exchange, which is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
 
