@@ -982,7 +982,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       // the other transverse direction (z for y faces, y for z faces); x is the wavefront's row
       const int so = D == 1 ? g.sz : g.sy;
       const int w = threadIdx.x >> 6, f = (threadIdx.x >> 1) & 31;
-      // vertex column x = i - 1 of this lane's face i; lanes f < 3 also take column i + 31
+      // vertex column x = i - 1 of this lane's face i
       const int mb = id - so - 1;
       const double* p0 = fa.metric + (size_t)(5 * side) * g.N + mb;
       double zc[5], mine[5];
@@ -994,12 +994,11 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       }
 #pragma unroll
       for (int q = 0; q < 5; ++q) L.g[w][q][side][f] = zc[q];
-      if (f < 3) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          const double* p = p0 + (size_t)q * g.N + 32;
-          L.g[w][q][side][32 + f] = lag(p[0], p[so], p[2 * so], p[3 * so]);
-        }
+      if (f < 15) {
+        // the 3 columns past the row's end, one (component, column) pair per lane
+        const int q = f / 3, c = f % 3;
+        const double* p = p0 + (size_t)q * g.N + (32 + c - f);
+        L.g[w][q][side][32 + c] = lag(p[0], p[so], p[2 * so], p[3 * so]);
       }
       // the row is written and read by this wavefront only (its LDS accesses execute in order): a
       // wavefront-level barrier keeps the compiler from moving the reads above the writes
