@@ -1040,6 +1040,52 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
         m[5 + q] = side ? mine[q] : other;
       }
     }
+  } else if constexpr (D == 0) {
+    // x faces of a main tile: the pass across z is shared by the tile's 4 rows (y).  Each round takes
+    // two components, q for the left lanes and q + 5 for the right ones: the workgroup forms the
+    // z-interpolated values at the tile's 32 x positions and 7 vertex rows y (2 x 7 x 32 items, the
+    // next round's loads in flight meanwhile), stores them in LDS (double-buffered, one barrier per
+    // round), and each lane takes the pass along y over its row's 4 vertex rows.
+    constexpr int NI = 2 * 7 * 32, NIR = (NI + 255) / 256;
+    const int Y0 = by0 - LO - 1, Z0 = cz - LO - 1;
+    int ioff[NIR], isel[NIR];
+#pragma unroll
+    for (int r = 0; r < NIR; ++r) {
+      const int it = threadIdx.x + 256 * r, rem = it % 224;
+      const int X = ax0 + rem % 32, Y = Y0 + rem / 32;
+      const bool in = it < NI && X <= g.n[0] + g.ng && Y <= g.n[1] + g.ng && Z0 + 3 <= g.n[2] + g.ng;
+      ioff[r] = in ? at(g, X, Y, Z0) : -1;
+      isel[r] = it / 224;
+    }
+    double pre[NIR][4];
+    auto fetch = [&](int q) {
+#pragma unroll
+      for (int r = 0; r < NIR; ++r) {
+        const double* f = fa.metric + (size_t)(q + 5 * isel[r]) * g.N;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) pre[r][kk] = ioff[r] >= 0 ? ldu(f, ioff[r] + kk * g.sz) : 0.0;
+      }
+    };
+    fetch(0);
+    const int w = threadIdx.x >> 6, f = (threadIdx.x >> 1) & 31;
+#pragma unroll 1
+    for (int q = 0; q < 5; ++q) {
+      double* buf = L.m[q & 1];
+#pragma unroll
+      for (int r = 0; r < NIR; ++r)
+        if (threadIdx.x + 256 * r < NI) buf[threadIdx.x + 256 * r] = lag(pre[r][0], pre[r][1], pre[r][2], pre[r][3]);
+      __syncthreads();
+      if (q < 4) fetch(q + 1);
+      double v = 0.0;
+      if (valid) {
+        const double* p = buf + side * 224 + w * 32 + f;
+        v = lag(p[0], p[32], p[64], p[96]);
+      }
+      const double o = shfl1(v);
+      const double v0 = side ? o : v, v1 = side ? v : o;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m[k] = k == q ? v0 : (k == q + 5 ? v1 : m[k]);
+    }
   } else {
     // the block starts one vertex below the first face's transverse position (face index - LO)
     const int X0 = D == 0 ? ax0 : ax0 - LO - 1, Y0 = D == 1 ? by0 : by0 - LO - 1, Z0 = D == 2 ? cz : cz - LO - 1;
