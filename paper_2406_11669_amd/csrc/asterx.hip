@@ -1068,6 +1068,9 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
     };
     fetch(0);
     const int w = threadIdx.x >> 6, f = (threadIdx.x >> 1) & 31;
+    // a persistent workgroup's previous item read its last round from the buffer the first round
+    // here writes (five rounds, two buffers)
+    __syncthreads();
 #pragma unroll 1
     for (int q = 0; q < 5; ++q) {
       double* buf = L.m[q & 1];
