@@ -1055,7 +1055,7 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
       const int X = ax0 + rem % 32, Y = Y0 + rem / 32;
       const bool in = it < NI && X <= g.n[0] + g.ng && Y <= g.n[1] + g.ng && Z0 + 3 <= g.n[2] + g.ng;
       ioff[r] = in ? at(g, X, Y, Z0) : -1;
-      isel[r] = it / 224;
+      isel[r] = it < NI ? it / 224 : 0;  // items past NI (no load) keep a component in range
     }
     double pre[NIR][4];
     auto fetch = [&](int q) {
