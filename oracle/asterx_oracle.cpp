@@ -627,6 +627,23 @@ template <class T> void centre_interp(const Grid& g, const T* f, int i, int j, i
   der[2] = lag_value(dzy);
 }
 
+// Value only of field f at cell centre (i,j,k): the same z, y and x passes as
+// centre_interp without the derivative lines (the recovery and prim -> cons need
+// no metric derivatives), so the value is bitwise the same.
+template <class T> T centre_value(const Grid& g, const T* f, int i, int j, int k) {
+  T vy[4];
+  for (int a = 0; a < 4; ++a) {
+    T c1[4];
+    for (int b = 0; b < 4; ++b) {
+      T col[4];
+      for (int c = 0; c < 4; ++c) col[c] = f[at(g, i - 1 + a, j - 1 + b, k - 1 + c)];
+      c1[b] = lag_value(col);
+    }
+    vy[a] = lag_value(c1);
+  }
+  return lag_value(vy);
+}
+
 // Value of field f at the face of direction d with index (i,j,k): the face
 // lies on vertex plane i (d = x) and midway in the two transverse directions.
 template <class T> T face_interp(const Grid& g, const T* f, int d, int i, int j, int k) {
@@ -673,6 +690,11 @@ template <class T> void centre_B(const Grid& g, const T* A, int i, int j, int k,
   Bt[0] = (face_B(g, A, 0, i, j, k) + face_B(g, A, 0, i + 1, j, k)) / T(2);
   Bt[1] = (face_B(g, A, 1, i, j, k) + face_B(g, A, 1, i, j + 1, k)) / T(2);
   Bt[2] = (face_B(g, A, 2, i, j, k) + face_B(g, A, 2, i, j, k + 1)) / T(2);
+}
+
+template <class T> void centre_metric_values(const Grid& g, const T* metric, int i, int j, int k, T m[10]) {
+  size_t N = npts(g);
+  for (int c = 0; c < 10; ++c) m[c] = centre_value(g, metric + c * N, i, j, k);
 }
 
 template <class T> void centre_metric(const Grid& g, const T* metric, int i, int j, int k, T m[10], T dm[3][10]) {
@@ -1082,8 +1104,8 @@ template <class T> void prim2con_grid(const Grid& g, const Params& /*P*/, const 
   for (int k = 0; k < g.n[2]; ++k)
     for (int j = 0; j < g.n[1]; ++j)
       for (int i = 0; i < g.n[0]; ++i) {
-        T m[10], dm[3][10];
-        centre_metric(g, metric, i, j, k, m, dm);
+        T m[10];
+        centre_metric_values(g, metric, i, j, k, m);
         Geom<T> G = make_geom(m);
         T Bt[3];
         centre_B(g, A, i, j, k, Bt);
@@ -1106,8 +1128,8 @@ template <class T> void c2p_grid(const Grid& g, const Params& P, const T& gam, c
   for (int k = 0; k < g.n[2]; ++k)
     for (int j = 0; j < g.n[1]; ++j)
       for (int i = 0; i < g.n[0]; ++i) {
-        T m[10], dm[3][10];
-        centre_metric(g, metric, i, j, k, m, dm);
+        T m[10];
+        centre_metric_values(g, metric, i, j, k, m);
         Geom<T> G = make_geom(m);
         T Bt[3];
         centre_B(g, A, i, j, k, Bt);
@@ -1304,10 +1326,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
         size_t nb[3] = {at(g, i + 1, j, k), at(g, i, j + 1, k), at(g, i, j, k + 1)};
         T m[10], dm[3][10], K6[CURV];
         centre_metric(g, metric, i, j, k, m, dm);
-        for (int c = 0; c < 6; ++c) {
-          T der[3];
-          centre_interp(g, curv + c * N, i, j, k, K6[c], der);
-        }
+        for (int c = 0; c < 6; ++c) K6[c] = centre_value(g, curv + c * N, i, j, k);
         Geom<T> G = make_geom(m);
         T pr[5], Bt[3];
         for (int c = 0; c < 5; ++c) pr[c] = prim[c * N + id];
@@ -1832,6 +1851,76 @@ void orc_count_ops(const Grid* g, const Params* P, const double* metric, const d
   Cnt::ops = 0;
   c2p_grid<Cnt>(*g, *P, Cnt(P->gamma), m.data(), a.data(), cons.data(), pr.data(), nullptr, nullptr);
   out[4] = Cnt::ops;
+}
+
+// Counts of the counting scalar on single building blocks, for the pins of the
+// counter itself: out[0] lag_value, [1] lag_deriv, [2] face_interp of one field,
+// [3] centre_value of one field, [4] centre_interp (value and three derivatives),
+// [5] face_B, [6] centre_B, [7] make_geom, [8] a fixed expression mixing every
+// counted operation with the uncounted ones (negation, fabs, comparisons).
+void orc_count_probe(unsigned long long* out) {
+  Grid g{};
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = 2;
+    g.ld[d] = 2 + 2 * 3 + 1;
+    g.dx[d] = 0.25;
+  }
+  g.ng = 3;
+  size_t N = npts(g);
+  std::vector<Cnt> f(3 * N);
+  for (size_t q = 0; q < 3 * N; ++q) f[q] = Cnt(1.0 + 0.001 * double(q % 97));
+  Cnt col[4] = {Cnt(1.0), Cnt(2.0), Cnt(4.0), Cnt(3.0)};
+  auto count = [](auto fn) {
+    Cnt::ops = 0;
+    fn();
+    return Cnt::ops;
+  };
+  Cnt sink(0.0);
+  out[0] = count([&] { sink = lag_value(col); });
+  out[1] = count([&] { sink = lag_deriv(col, 0.25); });
+  out[2] = count([&] { sink = face_interp(g, f.data(), 1, 0, 0, 0); });
+  out[3] = count([&] { sink = centre_value(g, f.data(), 0, 0, 0); });
+  out[4] = count([&] {
+    Cnt der[3];
+    centre_interp(g, f.data(), 0, 0, 0, sink, der);
+  });
+  out[5] = count([&] { sink = face_B(g, f.data(), 2, 0, 0, 0); });
+  out[6] = count([&] {
+    Cnt b[3];
+    centre_B(g, f.data(), 0, 0, 0, b);
+  });
+  out[7] = count([&] {
+    Cnt m[10] = {Cnt(0.9), Cnt(0.1), Cnt(0.0), Cnt(-0.1), Cnt(1.1), Cnt(0.05), Cnt(0.0), Cnt(1.0), Cnt(0.02),
+                 Cnt(0.95)};
+    Geom<Cnt> G = make_geom(m);
+    sink = G.sqrtg;
+  });
+  out[8] = count([&] {
+    Cnt a(1.5), b(-0.5), c(2.0), d(0.25), e(4.0);
+    Cnt t = -(((a + b) * c - d) / e);        // 4
+    t = fabs(t) + sqrt(e) + pow(a, 2.0);     // 2 additions, sqrt, pow: 4
+    if (t > a && !(t <= b) && t != c) sink = t;
+  });
+  (void)value_of(sink);
+}
+
+// Operations of one point recovery on the counting scalar (same inputs as
+// orc_pt_c2p); iters out.
+unsigned long long orc_count_c2p_point(const Params* P, const double* m10, const double* cons5, const double* Bt3,
+                                       const double* prev5, int* iters) {
+  Cnt m[10], cs[5], bt[3], pv[5], pr[5];
+  for (int c = 0; c < 10; ++c) m[c] = Cnt(m10[c]);
+  for (int c = 0; c < 5; ++c) {
+    cs[c] = Cnt(cons5[c]);
+    pv[c] = Cnt(prev5[c]);
+  }
+  for (int c = 0; c < 3; ++c) bt[c] = Cnt(Bt3[c]);
+  Geom<Cnt> G = make_geom(m);
+  Cnt::ops = 0;
+  int it = 0;
+  c2p_point(G, cs, bt, pv, Cnt(P->gamma), *P, pr, it);
+  if (iters) *iters = it;
+  return Cnt::ops;
 }
 
 // Face B (densitized) of direction d for every index in [-ng+?]: fills all

@@ -217,6 +217,25 @@ def count_ops(layout, params, metric, curv, prim, A, psi, dt_max):
     return dict(zip(["centre_B", "faces", "cells", "ct", "c2p"], [int(v) for v in out]))
 
 
+def count_probe():
+    """Operation counts of single building blocks on the counting scalar: dict(lag_value, lag_deriv,
+    face_interp, centre_value, centre_interp, face_B, centre_B, make_geom, mixed_expression)."""
+    out = np.zeros(9, dtype=np.uint64)
+    lib().orc_count_probe(out.ctypes.data_as(ctypes.c_void_p))
+    return dict(zip(["lag_value", "lag_deriv", "face_interp", "centre_value", "centre_interp", "face_B", "centre_B",
+                     "make_geom", "mixed_expression"], [int(v) for v in out]))
+
+
+def count_c2p_point(params, m10, cons5, Bt3, prev5):
+    """Operations of one point recovery on the counting scalar.  Returns (ops, iterations)."""
+    it = ctypes.c_int(0)
+    f = lib().orc_count_c2p_point
+    f.restype = ctypes.c_ulonglong
+    ops = f(ctypes.byref(make_params(params)), _p(_v(m10, 10)), _p(_v(cons5, 5)), _p(_v(Bt3, 3)), _p(_v(prev5, 5)),
+            ctypes.byref(it))
+    return int(ops), it.value
+
+
 def face_B(layout, A):
     out = np.zeros((3,) + layout.shape3, dtype=np.float64)
     lib().orc_face_B(ctypes.byref(make_grid(layout)), _p(A), _p(out))
