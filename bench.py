@@ -6,9 +6,11 @@ reconstruction, HLLE, quartic characteristic speeds, Noble c2p, RK4 at CFL 0.25.
 step (4 stages: c2p, primitive ghost fill, right-hand side, combine, state ghost fill), replayed from a
 captured HIP graph, with all inputs resident in HBM.
 
-Prints one JSON line: zone-updates/s per RK stage (interior cells x stages / wall time of the timed steps),
-the roofline of the dominant kernel (per-kernel HIP events recorded live on the launch stream), the
-whole-stage HBM roofline, and the serial CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: zone-updates/s per RK stage (interior cells x stages / wall time of the timed steps); the
+roofline of the dominant kernel and per-kernel figures of the face, cell and recovery kernels (per-kernel HIP
+events recorded live on the launch stream); the whole-stage HBM and FP64 rooflines; the same block with the other
+reconstruction, batched patches against a per-patch loop and the learned recovery guess against the plain one
+(comparison keys); and the CPU oracle timed on the host (serial on a bounded sample, all cores on the full block).
 """
 import argparse
 import json
@@ -24,6 +26,11 @@ METRIC = "zone-updates/s per RK stage (FP64, 128^3) and % of HBM roofline"
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 128 FLOP/clk x 2.4 GHz)
 
+# A-priori estimates of the work per unit, made before any implementation existed (and +-50%): about 1.4 kFLOP
+# per face (reconstruction, prim->cons and fluxes of both sides, quartic Newton, HLLE; the face metric is counted
+# with the metric interpolation) and about 6.4 kFLOP per zone-stage in all; 514 B per zone-stage of RK4.
+SURVEY_FLOPS_PER_FACE = 1400.0
+SURVEY_FLOPS_PER_ZONE_STAGE = 6400.0
 # Algorithmic FP64 operations per face of the face kernel (reconstruction of 7 variables on both sides,
 # 16-point face metric of 10 components, prim->cons, fluxes, quartic speeds, HLLE or LxF), counted by running
 # the plain serial implementation on an operation-counting scalar (+, -, *, /, sqrt, pow = 1 each) over the
@@ -31,19 +38,32 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 128 FLOP/clk x 
 # data dependent).
 FACE_FLOPS = {"ppm": 2603.1, "wenoz": 3955.0, "minmod": 2022.6, "mp5": 2480.3, "ppm+lxf": 2581.1,
               "ppm+hlle+uct": 2620.8}
+# The same count per owned cell of the cell kernel (centre metric values and derivatives, curvature values,
+# sources, flux divergence) and of the recovery (centre metric values, centre field, geometry, warm-started
+# Noble iteration) on that block.
+CELL_FLOPS = 4716.0
+C2P_FLOPS = 1795.0
 # Algorithmic bytes per face: read 5 primitives + 2 centre fields + 10 face-metric components + 2 potential
 # components, write 7 face fluxes (each value once, stencil reuse served on chip).
 FACE_BYTES = 8.0 * (5 + 2 + 10 + 2 + 7)
+# Per owned cell of the cell kernel: metric and curvature (16), primitives (5), centre field (3) and the 15 hydro
+# face fluxes read once; RK4 stage outputs of the 5 hydro fields averaged over the four stages (1.5 states read,
+# 1.75 written).
+CELL_BYTES_RK4 = 8.0 * (16 + 5 + 3 + 15 + 1.5 * 5 + 1.75 * 5)
+# Per owned cell of the recovery: conserved (5), potential (3), metric (10), previous primitives (5) read,
+# primitives (5) written.
+C2P_BYTES = 8.0 * (5 + 3 + 10 + 5 + 5)
 # Whole-stage algorithmic HBM bytes per zone-stage, RK4 averaged over its four stages: reads of the stage
 # state (9), metric and curvature (16), previous primitives (5), RK base state and accumulator (9 + 9 when
 # used); writes of primitives (5), next state (9) and accumulator (9 when used).
 STAGE_BYTES_RK4 = 514.0
 # Whole-stage algorithmic FP64 operations per zone-stage at 128^3 (same counting scalar, over one
 # right-hand side and one c2p of the 128^3 block of this workload; for PPM: centre field 41, faces of
-# the three directions 7994, cell sources and divergence 5598, constrained transport and gauge 139, c2p
-# 3265; the RK combine's 2 operations per field are not counted).
-STAGE_FLOPS = {"ppm": 17036.9, "wenoz": 21188.6, "minmod": 15254.4, "mp5": 16659.9, "ppm+lxf": 16969.3,
-               "ppm+hlle+uct": 19021.8}  # upwind CT: 129 x 133^2 faces per direction, edge field 1561
+# the three directions 7994, cell sources and divergence 4716, constrained transport and gauge 139, c2p
+# 1795; the RK combine's 2 operations per field are not counted).
+STAGE_FLOPS = {"ppm": 14684.9, "wenoz": 18836.6, "minmod": 12902.4, "mp5": 14307.9, "ppm+lxf": 14617.3,
+               "ppm+hlle+uct": 16669.8}  # upwind CT: 129 x 133^2 faces per direction, edge field 1561
+RIDGE = FP64_VECTOR_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS   # FLOP/B where the FP64 and HBM roofs meet
 
 
 def library_source_sha():
@@ -85,6 +105,8 @@ def parse():
                     help="edge electric field: flux CT or upwind CT (4 ghost layers)")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the comparison keys (other scheme, batched patches, learned guess, T_munu, inter-level)")
     ap.add_argument("--cpu-n", type=int, default=88, help="edge of the block the CPU oracle times")
     ap.add_argument("--learned-c2p", action="store_true",
                     help="seed every c2p with the learned guess (network trained first, outside the timed region)")
@@ -107,26 +129,62 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
-def cpu_baseline(recon, riemann, ct, n_cpu):
-    """The serial oracle, as it stands, on an n_cpu^3 block of the same workload: one RK4 step."""
+def host_cpu():
+    """CPU model, logical CPUs of the machine and CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(recon, riemann, ct, n_cpu, w_full=None):
+    """The oracle, as it stands, on the same workload recipe: the serial build on one RK4 step of an n_cpu^3 block
+    (about 10 s on one core), and the OpenMP build of the same source (k-planes over threads, bitwise the same
+    results) on one RK4 step of the full block w_full with every usable CPU (capped by OMP_NUM_THREADS)."""
     from oracle import oracle as O
     from paper_2406_11669_amd import workloads as W
     O.build(force=False)
+
+    def one_step(w, lib_=None):
+        w.params["riemann"] = riemann
+        w.params["ct"] = ct
+        L = w.layout
+        cons = O.prim2con(L, w.params, w.metric, w.A, w.prim)
+        O.fill_ghosts(L, cons, w.bc_cell)
+        state = w.state(cons)
+        prim = w.prim.copy()
+        t0 = time.perf_counter()
+        O.run(L, w.params, w.metric, w.curv, state, prim, w.dt, 1, 4, w.bc_cell, w.bc_A, lib_=lib_)
+        return time.perf_counter() - t0
+
+    host = host_cpu()
     w = W.curved_block(seed=0, n=n_cpu, recon=recon, nsteps=1, ng=4 if ct == "uct" else 3)
-    w.params["riemann"] = riemann
-    w.params["ct"] = ct
-    L = w.layout
-    cons = O.prim2con(L, w.params, w.metric, w.A, w.prim)
-    O.fill_ghosts(L, cons, w.bc_cell)
-    state = w.state(cons)
-    prim = w.prim.copy()
-    t0 = time.perf_counter()
-    O.run(L, w.params, w.metric, w.curv, state, prim, w.dt, 1, 4, w.bc_cell, w.bc_A)
-    dt = time.perf_counter() - t0
-    zs = n_cpu ** 3 * 4
-    return {"value": zs / dt, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "one RK4 step (4 stages) of the %d^3 block of the same workload recipe, serial FP64 oracle "
-                      "(g++ -O2 -ffp-contract=off), %.1f s" % (n_cpu, dt)}
+    dt = one_step(w)
+    out = {"value": n_cpu ** 3 * 4 / dt, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
+           "sample": "one RK4 step (4 stages) of the %d^3 block of the same workload recipe, serial FP64 oracle "
+                     "(g++ -O2 -ffp-contract=off), %.1f s" % (n_cpu, dt), "host": host}
+    if w_full is not None:
+        threads = host["usable_cpus"]
+        if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+            threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+        lo, used = O.lib_omp(threads)
+        n = w_full.layout.n
+        dt = one_step(w_full, lib_=lo)
+        out["all_cores"] = {"value": n[0] * n[1] * n[2] * 4 / dt, "unit": "zone-updates/s", "cores": used,
+                            "kind": "oracle",
+                            "sample": "one RK4 step of the full %dx%dx%d block, the same oracle source built with "
+                                      "-fopenmp (k-planes over %d threads), %.1f s" % (n[0], n[1], n[2], used, dt)}
+    return out
 
 
 def time_inter_level(asterx, torch, n, reps=10):
@@ -200,6 +258,183 @@ def time_tmunu(asterx, torch, blk, n, reps=20):
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def graph_steps(torch, blk, steps, warmup, graph=True):
+    """Time `steps` whole steps of blk (after `warmup`), replayed from one captured HIP graph unless graph is
+    False.  Returns ms for all steps (HIP events on the current stream, synchronized on both sides)."""
+    step = blk.step
+    if graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            blk.step()  # first step eagerly on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            blk.step()
+        step = g.replay
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1)
+
+
+def kernel_rooflines(kt, stages, n, scheme, ct):
+    """Per-kernel figures from the live HIP-event durations kt (one eager step): the face kernel (three direction
+    launches per stage, averaged), the cell kernel and the recovery, each against both roofs.  Achieved figures are
+    algorithmic work per launch (per-unit figure x units per launch) over the average launch duration."""
+    cells = n ** 3
+    faces = (n + 1) ** 3 if ct == "fct" else (n + 1) * (n + 5) ** 2
+    face_keys = ("face_x", "face_y", "face_z")
+    face_ms = sum(kt[k][0] for k in face_keys) / max(1, sum(kt[k][1] for k in face_keys))
+    rows = {
+        "face": dict(ms=face_ms, launches_per_stage=3, units="faces", units_per_launch=faces,
+                     flops={"estimate": SURVEY_FLOPS_PER_FACE, "oracle_count": FACE_FLOPS.get(scheme)},
+                     bytes=FACE_BYTES),
+        "cell": dict(ms=kt["cell"][0] / max(1, kt["cell"][1]), launches_per_stage=1, units="cells",
+                     units_per_launch=cells, flops={"oracle_count": CELL_FLOPS}, bytes=CELL_BYTES_RK4),
+        "c2p": dict(ms=kt["c2p"][0] / max(1, kt["c2p"][1]), launches_per_stage=1, units="cells",
+                    units_per_launch=cells, flops={"oracle_count": C2P_FLOPS}, bytes=C2P_BYTES),
+    }
+    out = {}
+    for name, r in rows.items():
+        sec = r["ms"] * 1e-3
+        gbs = r["bytes"] * r["units_per_launch"] / sec / 1e9
+        e = {"ms_per_launch": round(r["ms"], 4), "launches_per_stage": r["launches_per_stage"],
+             "units": r["units"], "units_per_launch": r["units_per_launch"], "bytes_per_unit": r["bytes"],
+             "algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+             "flops_per_unit": r["flops"]}
+        for src, f in r["flops"].items():
+            if f:
+                tf = f * r["units_per_launch"] / sec / 1e12
+                e["fp64_TFLOPs_" + src] = round(tf, 3)
+                e["fp64_frac_" + src] = round(tf / FP64_VECTOR_PEAK_TFLOPS, 4)
+        out[name] = e
+    return out
+
+
+def headline_roofline(kr, kt, stages, scheme, n):
+    """The roofline of the dominant kernel: the kernel function with the largest total time per stage (the face
+    kernel's three direction launches are one kernel).  Its bound follows from the arithmetic intensity of the
+    a-priori per-unit figures (FLOP/B against the ridge of the two roofs)."""
+    per_stage = {"face": kr["face"]["ms_per_launch"] * 3, "cell": kr["cell"]["ms_per_launch"],
+                 "c2p": kr["c2p"]["ms_per_launch"]}
+    for k, v in kt.items():
+        if k not in ("face_x", "face_y", "face_z", "cell", "c2p") and v[1] > 0:
+            per_stage[k] = v[0] / stages
+    dom = max(per_stage, key=per_stage.get)
+    largest_launch = max(((k, v[0] / max(1, v[1])) for k, v in kt.items() if v[1] > 0), key=lambda kv: kv[1])[0]
+    e = kr.get(dom, kr["face"])
+    if dom not in kr:
+        dom = "face"
+    est = e["flops_per_unit"].get("estimate") or e["flops_per_unit"].get("oracle_count")
+    intensity = est / e["bytes_per_unit"]
+    bound = "hbm" if intensity < RIDGE else "alu"
+    if bound == "hbm":
+        achieved, peak, unit = e["algorithmic_GBs"], HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved = est * e["units_per_launch"] / (e["ms_per_launch"] * 1e-3) / 1e12
+        peak, unit = FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+    return {"kernel": dom + (" (x, y, z launches averaged)" if dom == "face" else ""),
+            "dominant_by": "kernel time per stage (%s)" % ", ".join("%s %.3f ms" % kv for kv in sorted(
+                per_stage.items(), key=lambda kv: -kv[1])[:4]),
+            "largest_single_launch": largest_launch, "bound": bound, "achieved": round(achieved, 3), "peak": peak,
+            "unit": unit, "frac": round(achieved / peak, 4),
+            "traffic": measured_face_traffic(scheme, n) if dom == "face" else None,
+            "avg_launch_ms": e["ms_per_launch"], "units_per_launch": e["units_per_launch"],
+            "flops_per_unit": e["flops_per_unit"], "bytes_per_unit": e["bytes_per_unit"],
+            "intensity_flop_per_byte": round(intensity, 2), "ridge_flop_per_byte": round(RIDGE, 2),
+            "fp64_frac_estimate": e.get("fp64_frac_estimate"), "fp64_frac_oracle_count": e.get("fp64_frac_oracle_count")}
+
+
+def extra_scheme(torch, asterx, w, recon, steps):
+    """The same block and inputs with another reconstruction: graph-replayed RK4 steps."""
+    import copy
+    w2 = copy.copy(w)
+    w2.params = dict(w.params, recon=recon)
+    blk = asterx.Block(w2)
+    ms = graph_steps(torch, blk, steps, 1)
+    n = w.layout.n
+    del blk
+    torch.cuda.empty_cache()
+    return {"value": n[0] * n[1] * n[2] * 4 * steps / (ms * 1e-3), "unit": "zone-updates/s",
+            "ms_per_step": round(ms / steps, 4)}
+
+
+def extra_batched(torch, asterx, W, npatches=128, steps=3):
+    """A reduced set of the AMR-like patches (sides 16/24/32/48 + 3 ghosts, 3 levels, Riemann problems, MINMOD,
+    HLLE, RK2): the persistent batch (graph) against the per-patch launch loop (graph) and against one block of
+    about the same cell count with the same scheme."""
+    from paper_2406_11669_amd import autotune
+    wls = W.patch_set(seed=0, npatches=npatches)
+    cells = sum(w.layout.n[0] * w.layout.n[1] * w.layout.n[2] for w in wls)
+    bt = asterx.Batch(wls, tuning=(8, 0))
+    ms_b = autotune.time_batch(bt, steps=steps, graph=True)
+    del bt
+
+    class Loop:
+        def __init__(self):
+            self.blocks = [asterx.Block(w) for w in wls]
+
+        def step(self):
+            for b in self.blocks:
+                b.step()
+
+    loop = Loop()
+    ms_l = autotune.time_batch(loop, steps=steps, graph=True)
+    del loop
+    side = int(round(cells ** (1.0 / 3.0)))
+    one = asterx.Block(W.riemann_block(seed=0, n=side, nsteps=steps))
+    ms_1 = graph_steps(torch, one, steps, 1)
+    del one
+    torch.cuda.empty_cache()
+    zs = 2.0 * cells  # per step (time_batch returns milliseconds per step)
+    return {"npatches": npatches, "interior_cells": cells, "unit": "zone-updates/s",
+            "batched_graph": zs / (ms_b * 1e-3), "per_patch_loop_graph": zs / (ms_l * 1e-3),
+            "single_block_%d^3" % side: 2.0 * side ** 3 * steps / (ms_1 * 1e-3), "tuning": [8, 0]}
+
+
+def extra_learned(torch, asterx, blk, steps, n_points=256, n_train=10_000_000, epochs=20):
+    """The learned initial guess of the recovery: a network trained by the library's kernels (n_train states,
+    `epochs` epochs, outside the timed regions), then (a) point recoveries of an n_points^3 block of per-cell
+    states (Riemann-problem ranges, W ~ U[1, 10]) from the plain cold start and from the network, (b) the benchmark
+    block stepped with the network in every recovery against the plain warm start."""
+    from paper_2406_11669_amd import learned
+    from paper_2406_11669_amd import workloads as W
+    t0 = time.perf_counter()
+    feat, tgt = learned.training_set(n_train, seed=0)
+    stdz = learned.standardization(feat, tgt)
+    params, losses = learned.train(feat, tgt, stdz, epochs=epochs, batch=16384, seed=0)
+    del feat, tgt
+    mlp = asterx.make_mlp(params, stdz)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    d = learned.device_states(W.c2p_block_states(2, n_points))
+    res = learned.evaluate(d, mlp)
+    del d
+    torch.cuda.empty_cache()
+    pts = {m: {k: res[m][k] for k in ("cells_per_s", "iters_mean", "noble_failed_frac", "hard_fail_frac")}
+           for m in ("cold", "learned")}
+    n = blk.L.n
+    plain_ms = graph_steps(torch, blk, steps, 1)
+    blk.mlp = mlp
+    blk._mlp_params = params
+    learned_ms = graph_steps(torch, blk, steps, 1)
+    blk.mlp = None
+    zs = n[0] * n[1] * n[2] * 4 * steps
+    return {"train_states": n_train, "epochs": epochs, "final_loss": round(losses[-1], 5),
+            "setup_seconds": round(setup, 1), "points_%d^3" % n_points: pts,
+            "pipeline": {"plain_warm_start": zs / (plain_ms * 1e-3), "learned": zs / (learned_ms * 1e-3),
+                         "unit": "zone-updates/s"}}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -243,30 +478,7 @@ def main():
     print("bench: %s n=%d recon=%s, block resident (%.2f GB device memory)" % (
         w.name, n, args.recon, torch.cuda.memory_allocated() / 1e9), file=sys.stderr, flush=True)
 
-    step = blk.step
-    graph = None
-    if not args.no_graph:
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            blk.step()  # first step eagerly on the capture stream
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            blk.step()
-        step = graph.replay
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
+    ms = graph_steps(torch, blk, args.steps, args.warmup, graph=not args.no_graph)
     stages = blk.stages_per_step
     zone_stages = n ** 3 * stages * args.steps
     value = zone_stages / (ms * 1e-3)
@@ -280,47 +492,44 @@ def main():
     kt = asterx.timing_read()
     asterx.timing_enable(False)
     per_stage = {k: round(v[0] / stages, 4) for k, v in kt.items() if v[1] > 0}
-    face_ms = sum(kt[k][0] for k in ("face_x", "face_y", "face_z"))
-    face_launches = sum(kt[k][1] for k in ("face_x", "face_y", "face_z"))
-    dominant = max(((k, v[0]) for k, v in kt.items()), key=lambda kv: kv[1])[0]
-    faces_per_launch = (n + 1) ** 3 if args.ct == "fct" else (n + 1) * (n + 5) ** 2
-    avg_face_s = face_ms * 1e-3 / face_launches
-    face_flops = FACE_FLOPS.get(scheme)
-    achieved = face_flops * faces_per_launch / avg_face_s / 1e12 if face_flops else None
-    roofline = {"kernel": "face (x, y, z launches averaged)", "dominant_by_time": dominant,
-                "bound": "alu", "achieved": None if achieved is None else round(achieved, 3),
-                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": None if achieved is None else round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": measured_face_traffic(scheme, n),
-                "avg_launch_ms": round(avg_face_s * 1e3, 4),
-                "flops_per_face": face_flops, "faces_per_launch": faces_per_launch,
-                "algorithmic_GBs": round(FACE_BYTES * faces_per_launch / avg_face_s / 1e9, 1)}
+    kr = kernel_rooflines(kt, stages, n, scheme, args.ct)
+    roofline = headline_roofline(kr, kt, stages, scheme, n)
     stage_gbs = STAGE_BYTES_RK4 * value / 1e9
     hbm = {"bytes_per_zone_stage": STAGE_BYTES_RK4, "achieved": round(stage_gbs, 1), "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": round(stage_gbs / HBM_PEAK_GBS, 4)}
     stage_flops = STAGE_FLOPS.get(scheme) if n == 128 else None
-    stage_tf = stage_flops * value / 1e12 if stage_flops else None
-    fp64 = {"flops_per_zone_stage": stage_flops,
-            "achieved": None if stage_tf is None else round(stage_tf, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": None if stage_tf is None else round(stage_tf / FP64_VECTOR_PEAK_TFLOPS, 4)}
+    fp64 = {"unit": "TFLOP/s", "peak": FP64_VECTOR_PEAK_TFLOPS}
+    for src, f in (("estimate", SURVEY_FLOPS_PER_ZONE_STAGE), ("oracle_count", stage_flops)):
+        if f:
+            fp64["flops_per_zone_stage_" + src] = f
+            fp64["frac_" + src] = round(f * value / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4)
     out = {"metric": METRIC, "value": value, "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "curved%d-%s-rk4" % (n, scheme.replace("+", "-")), "n": n, "ng": w.layout.ng,
-                      "recon": args.recon, "riemann": args.riemann, "ct": args.ct, "rk": 4, "stages_per_step": stages, "cfl": 0.25, "gamma": 2.0,
-                      "speeds": "quartic", "graph": graph is not None,
-                      "c2p_guess": "learned" if args.learned_c2p else "warm"},
+                      "recon": args.recon, "riemann": args.riemann, "ct": args.ct, "rk": 4,
+                      "stages_per_step": stages, "cfl": 0.25, "gamma": 2.0, "speeds": "quartic",
+                      "graph": not args.no_graph, "c2p_guess": "learned" if args.learned_c2p else "warm"},
            "roofline": roofline, "hbm_roofline_stage": hbm, "fp64_roofline_stage": fp64,
-           "kernel_ms_per_stage": per_stage,
+           "kernels": kr, "kernel_ms_per_stage": per_stage,
            "c2p_stats": [int(v) for v in blk.stats.cpu().tolist()]}
     if learned_info:
         out["learned_c2p"] = learned_info
-    if args.ct == "fct":
+    if args.ct == "fct" and not args.no_extras:
         out["tmunu_vertices"] = time_tmunu(asterx, torch, blk, n)
         out["inter_level_9_fields"] = time_inter_level(asterx, torch, n)
+    if not args.no_extras and args.ct == "fct" and args.riemann == "hlle" and not args.learned_c2p:
+        other = "wenoz" if args.recon != "wenoz" else "ppm"
+        print("bench: %s on the same block" % other, file=sys.stderr, flush=True)
+        out["same_block_" + other] = extra_scheme(torch, asterx, w, other, args.steps)
+        print("bench: batched patches against the per-patch loop", file=sys.stderr, flush=True)
+        out["batched_vs_loop"] = extra_batched(torch, asterx, W)
+        print("bench: learned initial guess against the plain recovery", file=sys.stderr, flush=True)
+        out["learned_vs_plain"] = extra_learned(torch, asterx, blk, args.steps)
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle on a %d^3 sample" % args.cpu_n, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.recon, args.riemann, args.ct, args.cpu_n)
+        print("bench: timing the CPU oracle (serial on a %d^3 sample, all cores on the full block)" % args.cpu_n,
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.recon, args.riemann, args.ct, args.cpu_n, w_full=w)
     print(json.dumps(out), flush=True)
 
 

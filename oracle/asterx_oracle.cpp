@@ -7,7 +7,9 @@
 //
 // Everything here follows the paper (AsterX, arXiv 2406.11669) in its own order
 // and notation, written plainly: loops over every face, cell, edge and vertex,
-// no tiling, no fusion, no fast-math.  Build: g++ -O2 -ffp-contract=off.
+// no tiling, no fusion, no fast-math.  Build: g++ -O2 -ffp-contract=off.  The same
+// source built with -fopenmp spreads the k-planes of the grid loops over threads
+// (for the all-core CPU baseline); the serial build ignores those pragmas.
 // Where the paper is silent or ambiguous the reading taken is stated inline and
 // listed, with its reason, in the design notes of the repository.
 //
@@ -27,6 +29,9 @@
 #include <cstring>
 #include <cfloat>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <algorithm>
 
 namespace orc {
@@ -1125,6 +1130,9 @@ template <class T> void prim2con_grid(const Grid& g, const Params& /*P*/, const 
 template <class T> void c2p_grid(const Grid& g, const Params& P, const T& gam, const T* metric, const T* A, T* cons,
                                  T* prim, uint8_t* flags, unsigned long long* stats) {
   size_t N = npts(g);
+  unsigned long long n_noble = 0, n_fallback = 0, n_atmo = 0, n_hard = 0, n_nan = 0, it_max = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_noble, n_fallback, n_atmo, n_hard, n_nan) \
+    reduction(max : it_max)
   for (int k = 0; k < g.n[2]; ++k)
     for (int j = 0; j < g.n[1]; ++j)
       for (int i = 0; i < g.n[0]; ++i) {
@@ -1146,15 +1154,21 @@ template <class T> void c2p_grid(const Grid& g, const Params& P, const T& gam, c
           cons[c * N + id] = cs[c];
         }
         if (flags) flags[id] = fl;
-        if (stats) {
-          if (fl & FL_NOBLE_FAIL) stats[ST_NOBLE_FAIL]++;
-          if (fl & FL_FALLBACK) stats[ST_FALLBACK]++;
-          if (fl & FL_ATMO) stats[ST_ATMO]++;
-          if (fl & FL_HARD_FAIL) stats[ST_HARD_FAIL]++;
-          if (fl & FL_NAN_IN) stats[ST_NAN_IN]++;
-          if ((unsigned long long)iters > stats[ST_ITERS_MAX]) stats[ST_ITERS_MAX] = (unsigned long long)iters;
-        }
+        if (fl & FL_NOBLE_FAIL) n_noble++;
+        if (fl & FL_FALLBACK) n_fallback++;
+        if (fl & FL_ATMO) n_atmo++;
+        if (fl & FL_HARD_FAIL) n_hard++;
+        if (fl & FL_NAN_IN) n_nan++;
+        if ((unsigned long long)iters > it_max) it_max = (unsigned long long)iters;
       }
+  if (stats) {
+    stats[ST_NOBLE_FAIL] += n_noble;
+    stats[ST_FALLBACK] += n_fallback;
+    stats[ST_ATMO] += n_atmo;
+    stats[ST_HARD_FAIL] += n_hard;
+    stats[ST_NAN_IN] += n_nan;
+    if (it_max > stats[ST_ITERS_MAX]) stats[ST_ITERS_MAX] = it_max;
+  }
 }
 
 // Ghost fill of nf fields, axis by axis over the full extent of the other
@@ -1249,6 +1263,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
   phase_mark<T>(-1);
   // centre field everywhere it can be formed
   std::vector<T> Bc(3 * N, T(0));
+#pragma omp parallel for schedule(static)
   for (int k = -g.ng; k < g.n[2] + g.ng; ++k)
     for (int j = -g.ng; j < g.n[1] + g.ng; ++j)
       for (int i = -g.ng; i < g.n[0] + g.ng; ++i) {
@@ -1271,6 +1286,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
     int lo[3] = {tlo, tlo, tlo}, hi[3] = {g.n[0] + thi_ext, g.n[1] + thi_ext, g.n[2] + thi_ext};
     lo[d] = 0;
     hi[d] = g.n[d];
+#pragma omp parallel for schedule(static) reduction(+ : nfix) reduction(max : vmax)
     for (int k = lo[2]; k <= hi[2]; ++k)
       for (int j = lo[1]; j <= hi[1]; ++j)
         for (int i = lo[0]; i <= hi[0]; ++i) {
@@ -1319,6 +1335,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
   // hydro: flux divergence (eq. fluxconseqs) plus sources, owned cells
   const size_t CURV = 6;
   double divmax = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : divmax)
   for (int k = 0; k < g.n[2]; ++k)
     for (int j = 0; j < g.n[1]; ++j)
       for (int i = 0; i < g.n[0]; ++i) {
@@ -1363,6 +1380,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
   // G_A = alpha Psi / sqrt(gamma) - beta^j A_j at vertices (A averaged to the
   // vertex along its own direction), and F_Psi^j = alpha sqrt(gamma) gamma^jk A_k - beta^j Psi.
   std::vector<T> GA(N, T(0)), FP(3 * N, T(0));
+#pragma omp parallel for schedule(static)
   for (int k = -1; k <= g.n[2]; ++k)
     for (int j = -1; j <= g.n[1]; ++j)
       for (int i = -1; i <= g.n[0]; ++i) {
@@ -1410,6 +1428,7 @@ template <class T> void rhs_grid(const Grid& g, const Params& P, const T& gam, c
     return (ap * vL * bL + am * vR * bR - ap * am * (bR - bL)) / den;
   };
   double xi = P.xi / dt_max;
+#pragma omp parallel for schedule(static)
   for (int k = 0; k < g.n[2]; ++k)
     for (int j = 0; j < g.n[1]; ++j)
       for (int i = 0; i < g.n[0]; ++i) {
@@ -1630,6 +1649,7 @@ template <class T> void run_steps(const Grid& g, const Params& P, const T& gam, 
   };
   auto owned_loop = [&](auto fn) {
     for (int f = 0; f < 9; ++f)
+#pragma omp parallel for schedule(static)
       for (int k = 0; k < g.n[2]; ++k)
         for (int j = 0; j < g.n[1]; ++j)
           for (int i = 0; i < g.n[0]; ++i) fn(f * N + at(g, i, j, k));
@@ -1851,6 +1871,19 @@ void orc_count_ops(const Grid* g, const Params* P, const double* metric, const d
   Cnt::ops = 0;
   c2p_grid<Cnt>(*g, *P, Cnt(P->gamma), m.data(), a.data(), cons.data(), pr.data(), nullptr, nullptr);
   out[4] = Cnt::ops;
+}
+
+// Threads of the OpenMP build (OpenMP over k-planes of the grid loops; every cell is computed
+// as in the serial build and the reductions are integer sums and maxima, so results are bitwise
+// the same).  The serial build ignores the pragmas and reports 1.
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 // Counts of the counting scalar on single building blocks, for the pins of the

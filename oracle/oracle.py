@@ -17,6 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "asterx_oracle.cpp")
 LIB = os.path.join(HERE, "_build", "liboracle.so")
+LIB_OMP = os.path.join(HERE, "_build", "liboracle_omp.so")
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -41,19 +42,24 @@ CT = {"fct": 0, "uct": 1}
 BC = {"periodic": 0, "copy": 1, "linear": 2}
 
 
-def build(force=True):
-    """Compile the oracle with g++ (serial, FP64, no FP contraction, no fast-math)."""
-    os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp"
-    subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                           "-o", tmp, SRC])
-    os.replace(tmp, LIB)
-    return LIB
+FLAGS = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force=True, openmp=False):
+    """Compile the oracle with g++ (FP64, no FP contraction, no fast-math): serial, or with -fopenmp (the
+    all-core CPU baseline; bitwise the same results)."""
+    out = LIB_OMP if openmp else LIB
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
+        return out
+    tmp = out + ".tmp"
+    subprocess.check_call(FLAGS + (["-fopenmp"] if openmp else []) + ["-o", tmp, SRC])
+    os.replace(tmp, out)
+    return out
 
 
 _lib = None
+_lib_omp = None
 
 
 def lib():
@@ -62,6 +68,15 @@ def lib():
         build(force=False)
         _lib = ctypes.CDLL(LIB)
     return _lib
+
+
+def lib_omp(threads=None):
+    """The OpenMP build (loaded once); threads: number of OpenMP threads (default: all).  Returns (lib, threads)."""
+    global _lib_omp
+    if _lib_omp is None:
+        build(force=False, openmp=True)
+        _lib_omp = ctypes.CDLL(LIB_OMP)
+    return _lib_omp, int(_lib_omp.orc_set_threads(ctypes.c_int(int(threads or 0))))
 
 
 def _p(a):
@@ -190,9 +205,10 @@ def rk_stage(layout, a, us, b_dt, rhs_arr, out):
                        _p(rhs_arr), _p(out))
 
 
-def run(layout, params, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A, A_shift=None):
+def run(layout, params, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A, A_shift=None, lib_=None):
     """Advance state (9 fields) and prim in place by nsteps.  Returns (flags, stats, redmax).
-    A_shift (3x3, optional): periodic fill of A with A_shift[q, d] added per period along axis d."""
+    A_shift (3x3, optional): periodic fill of A with A_shift[q, d] added per period along axis d.
+    lib_: the library to run (default: the serial build; lib_omp()[0] for the OpenMP build)."""
     _check_ct(layout, params)
     flags = np.zeros(layout.shape3, dtype=np.uint8)
     stats = np.zeros(6, dtype=np.uint64)
@@ -200,10 +216,10 @@ def run(layout, params, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A
     bcc = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_cell])
     bca = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_A])
     sh = None if A_shift is None else np.ascontiguousarray(A_shift, dtype=np.float64)
-    lib().orc_run(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), _p(metric), _p(curv),
-                  _p(state), _p(prim), ctypes.c_double(dt), ctypes.c_int(nsteps), ctypes.c_int(rk), bcc, bca,
-                  flags.ctypes.data_as(ctypes.c_void_p), stats.ctypes.data_as(ctypes.c_void_p), _p(redmax),
-                  None if sh is None else _p(sh))
+    (lib_ or lib()).orc_run(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), _p(metric),
+                            _p(curv), _p(state), _p(prim), ctypes.c_double(dt), ctypes.c_int(nsteps),
+                            ctypes.c_int(rk), bcc, bca, flags.ctypes.data_as(ctypes.c_void_p),
+                            stats.ctypes.data_as(ctypes.c_void_p), _p(redmax), None if sh is None else _p(sh))
     return flags, stats, redmax
 
 

@@ -152,10 +152,18 @@ def test_adam_step_vs_reference(L):
 @pytest.fixture(scope="module")
 def trained(L):
     """A network trained briefly (2e6 states, 10 epochs) by the library's own kernels."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
     feat, tgt = L.training_set(2_000_000, seed=21)
     st = L.standardization(feat, tgt)
+    # loss of the untrained network (same seeded initial parameters) on the first batch of states
+    grad = torch.zeros(ax.MLP_NPARAMS + 1, dtype=torch.float32, device="cuda")
+    ws = torch.empty(ax.mlp_grad_workspace_size(16384) // 4 + 1, dtype=torch.float32, device="cuda")
+    mlp0 = ax.make_mlp(torch.from_numpy(L.init_params(3)).cuda(), st)
+    ax.mlp_grad(mlp0, feat[:, :16384].contiguous(), tgt[:, :16384].contiguous(), grad, ws)
+    loss0 = float(grad[ax.MLP_NPARAMS].item())
     params, losses = L.train(feat, tgt, st, epochs=10, batch=16384, seed=3)
-    return params, st, losses
+    return params, st, [loss0] + losses
 
 
 def test_trained_guess_cuts_newton_iterations(L, trained):
@@ -164,7 +172,8 @@ def test_trained_guess_cuts_newton_iterations(L, trained):
     import torch
     from paper_2406_11669_amd import asterx as ax
     params, st, losses = trained
-    assert losses[-1] < 0.75 * losses[0], losses
+    print("untrained loss %.4g, epoch losses %s" % (losses[0], ["%.4g" % x for x in losses[1:]]), flush=True)
+    assert losses[-1] < 0.5 * losses[0], losses
     mlp = ax.make_mlp(params, st)
     d = L.device_states(W.c2p_states(22, 20_000))
     res = L.evaluate(d, mlp, seed=1)
