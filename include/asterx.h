@@ -174,6 +174,21 @@ int asterx_rhs_rk(const asterx_grid* g, const asterx_params* p, const double* me
                   const double* prim, const double* A, const double* psi, double dt_max, int32_t nout,
                   const asterx_rk_out* outs, double* red, void* workspace, size_t ws_bytes, void* stream);
 
+/* asterx_rhs_rk without a caller-provided workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * workspace is a library-held device array of ASTERX_NOALLOC_WS_BYTES (64 MiB) per device,
+ * enough for blocks whose asterx_rhs_workspace_size is at most that (cubes up to 52^3 cells
+ * with 3 ghost layers; ASTERX_EARG beyond, before any launch).  The call allocates and frees nothing.
+ * The array used is the one of the device current on the calling thread, which must be the
+ * device of `stream`.  Every call on a device shares that device's array and nothing in it
+ * needs to start at zero (each call writes all it reads); calls that overlap on one device
+ * (other streams, other threads) race and must be ordered by the caller.  Other arguments,
+ * results and errors as asterx_rhs_rk. */
+#define ASTERX_NOALLOC_WS_BYTES (64ull << 20)
+int asterx_rhs_rk_noalloc(const asterx_grid* g, const asterx_params* p, const double* metric, const double* curv,
+                          const double* prim, const double* A, const double* psi, double dt_max, int32_t nout,
+                          const asterx_rk_out* outs, double* red, void* stream);
+
 /* Covariant stress-energy tensor T_{mu nu} (eq. tmunu, lowered with the 4-metric) at the vertices
  * [0, n]^3 of the block, where Sec. 3.1 stores it with the spacetime variables for a spacetime
  * solver.  The vertex fluid state is the mean of the primitives (prim) and of the centre fields

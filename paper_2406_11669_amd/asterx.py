@@ -84,7 +84,7 @@ EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "
            "asterx_prim2con_adjoint", "asterx_prim2con_points", "asterx_mlp_features", "asterx_mlp_forward",
            "asterx_mlp_grad_workspace_size", "asterx_mlp_grad", "asterx_mlp_adam", "asterx_c2p_points",
            "asterx_c2p_learned", "asterx_rhs_rk", "asterx_batch_rhs_rk", "asterx_tmunu", "asterx_prolong",
-           "asterx_restrict"]
+           "asterx_restrict", "asterx_rhs_rk_noalloc"]
 
 
 def lib():
@@ -110,6 +110,8 @@ def lib():
         L.asterx_restrict.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.asterx_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
                                     ctypes.c_size_t, vp]
+        L.asterx_rhs_rk_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp,
+                                            vp]
         L.asterx_batch_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
                                           ctypes.c_size_t, vp]
         L.asterx_zero.argtypes = [vp, ctypes.c_int64, vp]
@@ -289,6 +291,17 @@ def rhs_rk(layout, params, metric, curv, prim, A, psi, dt_max, outs, red, worksp
                                _ptr(_f64(metric)), _ptr(_f64(curv)), _ptr(_f64(prim)), _ptr(_f64(A)),
                                _ptr(_f64(psi)), float(dt_max), len(outs), arr, _ptr(red), _ptr(workspace),
                                workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+NOALLOC_WS_BYTES = 64 << 20  # ASTERX_NOALLOC_WS_BYTES
+
+
+def rhs_rk_noalloc(layout, params, metric, curv, prim, A, psi, dt_max, outs, red, stream=None):
+    """asterx_rhs_rk with the library-held workspace (asterx_rhs_rk_noalloc): no device allocation."""
+    arr = make_rk_outs(outs)
+    _check(lib().asterx_rhs_rk_noalloc(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                                       _ptr(_f64(metric)), _ptr(_f64(curv)), _ptr(_f64(prim)), _ptr(_f64(A)),
+                                       _ptr(_f64(psi)), float(dt_max), len(outs), arr, _ptr(red), _stream(stream)))
 
 
 def adjoint_workspace_size(layout):

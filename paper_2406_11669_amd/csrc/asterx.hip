@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -3143,6 +3144,39 @@ namespace axh {
 int set_error(int code, const char* msg) { return fail(code, msg); }
 }  // namespace axh
 
+// ---------------------------------------------------------------------------------------
+// Library-held right-hand side workspace of asterx_rhs_rk_noalloc, for callers that cannot
+// allocate.  Each device holds its own copy of the array until the process ends; host code
+// reaches it only through the device address hipGetSymbolAddress returns with that device
+// current (the array's name in host code is not a device address).  Every call on a device
+// shares its copy, so calls that overlap on one device race.
+static __device__ __align__(256) double scratch[ASTERX_NOALLOC_WS_BYTES / sizeof(double)];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once per device.
+int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(ASTERX_ELAUNCH, "rhs_rk_noalloc: no current device");
+  if (dev >= SCRATCH_MAX_DEVICES) return fail(ASTERX_EARG, "rhs_rk_noalloc: device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      g_err = std::string("rhs_rk_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+      return ASTERX_ELAUNCH;
+    }
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return 0;
+}
+}  // namespace
+
 extern "C" {
 
 int asterx_timing_enable(int32_t on) {
@@ -3291,6 +3325,19 @@ int asterx_rhs_rk(const asterx_grid* gr, const asterx_params* p, const double* m
   if ((rc = make_combine(nout, outs, g.N, ins, nin, 6, cmb))) return rc;
   return do_rhs(g, nullptr, p, metric, curv, prim, A, psi, dt_max, nullptr, red, (double*)workspace,
                 (hipStream_t)stream, cmb);
+}
+
+int asterx_rhs_rk_noalloc(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* curv,
+                          const double* prim, const double* A, const double* psi, double dt_max, int32_t nout,
+                          const asterx_rk_out* outs, double* red, void* stream) {
+  int rc;
+  if ((rc = check_params(p)) || (rc = check_grid(gr, 3))) return rc;
+  const size_t need = asterx_rhs_workspace_size(gr);
+  if (need > ASTERX_NOALLOC_WS_BYTES)
+    return fail(ASTERX_EARG, "rhs_rk_noalloc: the grid needs more workspace than the library holds (64 MiB)");
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return asterx_rhs_rk(gr, p, metric, curv, prim, A, psi, dt_max, nout, outs, red, ws, need, stream);
 }
 
 int asterx_tmunu(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* prim,

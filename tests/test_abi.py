@@ -226,3 +226,20 @@ def test_extension_entry_points_validate_on_host(lib):
     # batch: at least one patch, sane ghosts
     h = ctypes.c_void_p()
     assert lib.asterx_batch_create(0, None, None, ctypes.byref(h)) == -1
+
+
+def test_noalloc_refuses_grids_beyond_its_workspace_on_host(lib):
+    """asterx_rhs_rk_noalloc refuses a block whose workspace exceeds the library-held 64 MiB (53^3 cells with 3 ghost
+    layers) before touching any device (the pointers are never dereferenced)."""
+    from paper_2406_11669_amd import asterx
+    from paper_2406_11669_amd.workloads import Layout, default_params
+    p = asterx.make_params(default_params(recon="ppm"))
+    for n, fits in (((52, 52, 52), True), ((53, 53, 53), False)):
+        g = asterx.make_grid(Layout(n, 3))
+        assert (lib.asterx_rhs_workspace_size(ctypes.byref(g)) <= asterx.NOALLOC_WS_BYTES) == fits
+    g = asterx.make_grid(Layout((53, 53, 53), 3))
+    dummy = ctypes.c_void_p(1 << 40)
+    outs = (asterx.RKOut * 1)()
+    rc = lib.asterx_rhs_rk_noalloc(ctypes.byref(g), ctypes.byref(p), dummy, dummy, dummy, dummy, dummy, 0.01, 1, outs,
+                                   None, None)
+    assert rc == -1 and b"64 MiB" in lib.asterx_last_error()
