@@ -353,6 +353,30 @@ int asterx_c2p_learned(const asterx_grid* g, const asterx_params* p, const doubl
                        double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats, const asterx_mlp* mlp,
                        void* stream);
 
+/* ---- One stage with the recovery and the sources together -------------------------------
+ * The geometric sources of the right-hand side (Sec. 2.2, eq. grmhdsrc) at a cell depend only
+ * on the cell's primitives, its centre field and the centre metric with its derivatives and the
+ * extrinsic curvature.  asterx_c2p_src recovers the primitives (asterx_c2p, or asterx_c2p_learned
+ * when mlp is not NULL) and then evaluates these sources from the recovered state in the same
+ * kernel, whose centre-metric values serve both; asterx_rhs_rk_src is asterx_rhs_rk with the
+ * sources taken from there.  The pair gives bitwise the results of asterx_c2p (or
+ * asterx_c2p_learned) followed by asterx_rhs_rk.
+ * c2p_src: curv is K_ij at vertices ([6], as in asterx_rhs); src (device, ASTERX_SRC_FIELDS
+ * fields of the block's index space, out): fields 0-3 receive alpha sqrt(gamma) times the sources
+ * of S_x, S_y, S_z and tau on owned cells (that of D is 0); fields 4-13 the ten metric components
+ * at the x faces of owned cells (Sec. 3.2 interpolation, indexed like cells: the face between
+ * cells i-1 and i at cell i, i = 0..n), which the kernel's centre-derivative passes form on the
+ * way.  Other arguments as asterx_c2p.  rhs_rk_src: src as written by asterx_c2p_src for the same
+ * prim, A and metric (the x faces read their metric from it); other arguments as asterx_rhs_rk
+ * (the outputs may not overlap src either). */
+#define ASTERX_SRC_FIELDS 14
+int asterx_c2p_src(const asterx_grid* g, const asterx_params* p, const double* metric, const double* curv,
+                   const double* A, double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats,
+                   const asterx_mlp* mlp, double* src, void* stream);
+int asterx_rhs_rk_src(const asterx_grid* g, const asterx_params* p, const double* metric, const double* prim,
+                      const double* A, const double* psi, const double* src, double dt_max, int32_t nout,
+                      const asterx_rk_out* outs, double* red, void* workspace, size_t ws_bytes, void* stream);
+
 /* Per-kernel timing (diagnostics).  When enabled, every launch of the library is bracketed
  * by two HIP events on its stream; asterx_timing_read waits for the recorded events and
  * returns, for each kernel class k < n, the accumulated milliseconds ms[k] and launch count

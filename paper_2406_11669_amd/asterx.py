@@ -84,7 +84,7 @@ EXPORTS = ["asterx_version", "asterx_last_error", "asterx_rhs_workspace_size", "
            "asterx_prim2con_adjoint", "asterx_prim2con_points", "asterx_mlp_features", "asterx_mlp_forward",
            "asterx_mlp_grad_workspace_size", "asterx_mlp_grad", "asterx_mlp_adam", "asterx_c2p_points",
            "asterx_c2p_learned", "asterx_rhs_rk", "asterx_batch_rhs_rk", "asterx_tmunu", "asterx_prolong",
-           "asterx_restrict", "asterx_rhs_rk_noalloc"]
+           "asterx_restrict", "asterx_rhs_rk_noalloc", "asterx_c2p_src", "asterx_rhs_rk_src"]
 
 
 def lib():
@@ -110,6 +110,9 @@ def lib():
         L.asterx_restrict.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.asterx_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
                                     ctypes.c_size_t, vp]
+        L.asterx_c2p_src.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.asterx_rhs_rk_src.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
+                                        ctypes.c_size_t, vp]
         L.asterx_rhs_rk_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp,
                                             vp]
         L.asterx_batch_rhs_rk.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
@@ -227,6 +230,15 @@ def c2p(layout, params, metric, A, cons, prim, flags=None, stats=None, stream=No
                             _ptr(stats), _stream(stream)))
 
 
+def c2p_src(layout, params, metric, curv, A, cons, prim, src, flags=None, stats=None, stream=None, mlp=None):
+    """asterx_c2p_src: the recovery (learned guess when an asterx_mlp is given), the geometric sources of the
+    recovered state (densitized) and the x-face metric, into src (SRC_FIELDS fields)."""
+    _check(lib().asterx_c2p_src(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                                _ptr(_f64(metric)), _ptr(_f64(curv)), _ptr(_f64(A)), _ptr(_f64(cons)),
+                                _ptr(_f64(prim)), _ptr(flags), _ptr(stats),
+                                ctypes.byref(mlp) if mlp is not None else None, _ptr(_f64(src)), _stream(stream)))
+
+
 def fill_ghosts_shift(layout, f, shift, stream=None):
     """Periodic ghost fill of f (nf <= 3 fields) plus shift[q, d] per period of wrap along axis d."""
     nf = f.shape[0] if f.dim() == 4 else 1
@@ -294,6 +306,16 @@ def rhs_rk(layout, params, metric, curv, prim, A, psi, dt_max, outs, red, worksp
 
 
 NOALLOC_WS_BYTES = 64 << 20  # ASTERX_NOALLOC_WS_BYTES
+SRC_FIELDS = 14  # ASTERX_SRC_FIELDS: sources (4) and x-face metric (10) handed from asterx_c2p_src to asterx_rhs_rk_src
+
+
+def rhs_rk_src(layout, params, metric, prim, A, psi, src, dt_max, outs, red, workspace, stream=None):
+    """asterx_rhs_rk_src: asterx_rhs_rk with the sources written by asterx_c2p_src."""
+    arr = make_rk_outs(outs)
+    _check(lib().asterx_rhs_rk_src(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)),
+                                   _ptr(_f64(metric)), _ptr(_f64(prim)), _ptr(_f64(A)), _ptr(_f64(psi)),
+                                   _ptr(_f64(src)), float(dt_max), len(outs), arr, _ptr(red), _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
 def rhs_rk_noalloc(layout, params, metric, curv, prim, A, psi, dt_max, outs, red, stream=None):
@@ -435,10 +457,13 @@ class Block:
     RK2 is Heun's method, RK4 the classical scheme (accumulator form).  With fused=True (the
     default) the right-hand side goes straight into the stage outputs (asterx_rhs_rk; RK4
     alternates two stage buffers so that no output is the state being evaluated); fused=False
-    stores it and combines with asterx_rk_stage.  Both give bitwise equal states."""
+    stores it and combines with asterx_rk_stage.  In the fused form the geometric sources are
+    evaluated by the recovery kernel (asterx_c2p_src + asterx_rhs_rk_src) unless src_in_c2p is
+    False (asterx_c2p + asterx_rhs_rk).  All give bitwise equal states."""
 
-    def __init__(self, wl, device="cuda", fused=True, metric_fn=None):
+    def __init__(self, wl, device="cuda", fused=True, metric_fn=None, src_in_c2p=True):
         self.fused = fused
+        self.src_in_c2p = fused and src_in_c2p
         # a time-dependent spacetime: metric_fn(t) -> (metric, curv) device tensors shaped like the
         # workload's, evaluated at every stage time (RK4: t, t + dt/2, t + dt/2, t + dt; RK2: t, t + dt)
         self.metric_fn = metric_fn
@@ -460,6 +485,7 @@ class Block:
         self.k = torch.zeros_like(self.state)
         self.tmp2 = torch.zeros_like(self.state) if fused and wl.rk == 4 else None
         self.ws = torch.empty(workspace_size(self.L) // 8, dtype=torch.float64, device=dev)
+        self.src = torch.zeros((SRC_FIELDS,) + self.L.shape3, dtype=torch.float64, device=dev) if self.src_in_c2p else None
         self.red = torch.zeros(2, dtype=torch.float64, device=dev)
         self.stats = torch.zeros(6, dtype=torch.int64, device=dev)
         self.flags = torch.zeros(self.L.shape3, dtype=torch.uint8, device=dev)
@@ -497,6 +523,13 @@ class Block:
 
     def stage(self, U, outs):
         """c2p on U, then its right-hand side combined into outs = [(a, us, b_dt, out)]."""
+        if self.src_in_c2p:
+            c2p_src(self.L, self.params, self.metric, self.curv, U[5:8], U[0:5], self.prim, self.src, self.flags,
+                    self.stats, mlp=self.mlp)
+            fill_ghosts(self.L, self.prim, self.wl.bc_cell)
+            rhs_rk_src(self.L, self.params, self.metric, self.prim, U[5:8], U[8:9], self.src, self.dt, outs,
+                       self.red, self.ws)
+            return
         self.recover(U)
         rhs_rk(self.L, self.params, self.metric, self.curv, self.prim, U[5:8], U[8:9], self.dt, outs, self.red,
                self.ws)

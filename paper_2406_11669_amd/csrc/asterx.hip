@@ -438,7 +438,10 @@ DEV void tile_store2d(const TileIdx& x, const double pre[2][NFETCH], TileLDS2D& 
     }
 }
 
-DEV void tile_derivs2(TileLDS2D& S, const TileIdx& x, const GD& g, double d0[3], double d1[3]) {
+// xf: the two components' values after the z and y passes at the vertex x positions on both sides
+// of the thread's cell, i.e. at its lower and upper x faces (the x-face metric, interpolated across z
+// then y as the x-face kernel does).
+DEV void tile_derivs2(TileLDS2D& S, const TileIdx& x, const GD& g, double d0[3], double d1[3], double xf[2][2]) {
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < NZR; ++r)
@@ -473,6 +476,8 @@ DEV void tile_derivs2(TileLDS2D& S, const TileIdx& x, const GD& g, double d0[3],
     d[0] = dlag(p[0], p[1], p[2], p[3]) * g.idx[0];
     d[1] = lag(q[0], q[1], q[2], q[3]) * g.idx[1];
     d[2] = lag(w[0], w[1], w[2], w[3]) * g.idx[2];
+    xf[c][0] = p[1];
+    xf[c][1] = p[2];
   }
 }
 
@@ -503,6 +508,182 @@ DEV void tile_derivs(TileLDS& S, const TileIdx& x, const GD& g, double d[3]) {
   d[0] = dlag(p[0], p[1], p[2], p[3]) * g.idx[0];
   d[1] = lag(p[NYP], p[NYP + 1], p[NYP + 2], p[NYP + 3]) * g.idx[1];
   d[2] = lag(p[2 * NYP], p[2 * NYP + 1], p[2 * NYP + 2], p[2 * NYP + 3]) * g.idx[2];
+}
+
+// T^{mu nu} = (rho h + b^2) u u + (p + b^2/2) g^{mu nu} - b b   (eq. tmunu): T^00, T^0i, T^ij (symmetric)
+DEV void tmunu_upper(const Geo& G, const State& St, double& T00, double T0[3], double Tk[6]) {
+  double ia = 1.0 / G.alp, ia2 = ia * ia;
+  double u0 = St.W * ia, u[3], b0 = St.W * St.Bv * ia, bu[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = St.W * (St.v[a] - G.beta[a] * ia);
+    bu[a] = (St.B[a] + G.alp * b0 * u[a]) / St.W;
+  }
+  double e = St.rhoh + St.bsq, pt = St.p + 0.5 * St.bsq;
+  T00 = e * u0 * u0 - pt * ia2 - b0 * b0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) T0[a] = e * u0 * u[a] + pt * G.beta[a] * ia2 - b0 * bu[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b)
+      Tk[sym(a, b)] = e * u[a] * u[b] + pt * (G.gu[sym(a, b)] - G.beta[a] * G.beta[b] * ia2) - bu[a] * bu[b];
+}
+
+// Geometric sources at a cell (eq. grmhdsrc in the 3+1 form): the momentum source
+// 1/2 T^{mu nu} d_j g_{mu nu} is linear in the derivatives of the ten stored metric components,
+// sum_c w_c d_j m_c, with weights w_c built from T, beta and gamma; the energy source is
+// sum_q kc_q K_q over the six stored components of the extrinsic curvature (kc from T and beta)
+// plus wa_j d_j alpha.  as = alpha sqrt(gamma) densitizes.  The weights need the state and the
+// centre metric only, so they are formed before the curvature is interpolated.
+struct SrcW {
+  double w[10], wa[3], kc[6], as;
+};
+
+DEV void src_weights(const Geo& G, const double pr[5], const double Bt[3], double gam, SrcW& s) {
+  State St;
+  state_make(G, pr, Bt, gam, St);
+  double T00, T0[3], Tk[6];
+  tmunu_upper(G, St, T00, T0, Tk);
+  double bl[3];
+  lower(G.g, G.beta, bl);
+  s.as = G.alp * G.sqrtg;
+  // weights of d_j alpha, d_j beta^k, d_j gamma_ab in 1/2 T^{mu nu} d_j g_{mu nu}
+  s.w[0] = -T00 * G.alp;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    s.w[1 + k] = T00 * bl[k] + T0[0] * G.g[sym(0, k)] + T0[1] * G.g[sym(1, k)] + T0[2] * G.g[sym(2, k)];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      if (a == b)
+        s.w[4 + sym(a, b)] = 0.5 * T00 * G.beta[a] * G.beta[a] + T0[a] * G.beta[a] + 0.5 * Tk[sym(a, a)];
+      else
+        s.w[4 + sym(a, b)] = T00 * G.beta[a] * G.beta[b] + T0[a] * G.beta[b] + T0[b] * G.beta[a] + Tk[sym(a, b)];
+    }
+  // energy source: (T00 beta^a beta^b + 2 T^{0a} beta^b + T^{ab}) K_ab summed over a, b, the two
+  // orders of an off-diagonal pair joined; the lapse-gradient terms go with the derivatives of alpha
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      const double ab = T00 * G.beta[a] * G.beta[b] + 2.0 * T0[a] * G.beta[b] + Tk[sym(a, b)];
+      s.kc[sym(a, b)] = a == b ? ab : ab + (T00 * G.beta[b] * G.beta[a] + 2.0 * T0[b] * G.beta[a] + Tk[sym(a, b)]);
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s.wa[a] = -(T00 * G.beta[a] + T0[a]);
+}
+
+// The extrinsic-curvature part of the energy source.
+DEV double src_curv(const SrcW& s, const double K[6]) {
+  double se = 0.0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) se += s.kc[q] * K[q];
+  return se;
+}
+
+// Value rounds of the ten metric and six curvature components at the tile's centres, two
+// components per round (one set of barriers per pair), round r+1's vertex tiles fetched during
+// round r.  Returns with the first metric component's tile fetched again into pre (the first
+// derivative round's).  The rolled loop keeps the register footprint of one round, values
+// landing by select chains (no dynamically indexed register arrays).  The leading barrier keeps
+// a persistent workgroup's previous item reading the buffer the first round writes.  Every
+// thread of the block must call it.
+DEV void value_rounds16(const GD& g, const double* metric, const double* curv, const TileIdx& x, double m[10],
+                        double K[6], double pre[NFETCH], TileLDS2& S2) {
+  auto comp = [&](int r) { return r < 10 ? metric + r * g.N : (r < 16 ? curv + (r - 10) * g.N : metric); };
+  double pp[2][NFETCH];
+  tile_fetch(comp(0), x, pp[0]);
+  tile_fetch(comp(1), x, pp[1]);
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < 16; c += 2) {
+    tile_store2(x, pp, S2);
+    tile_fetch(comp(c + 2), x, pp[0]);
+    if (c < 14) tile_fetch(comp(c + 3), x, pp[1]);
+    double v0, v1;
+    tile_value2(S2, x, v0, v1);
+#pragma unroll
+    for (int q = 0; q < 10; ++q) m[q] = c == q ? v0 : (c + 1 == q ? v1 : m[q]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) K[q] = c == 10 + q ? v0 : (c + 1 == 10 + q ? v1 : K[q]);
+  }
+  // comp(16) (metric component 0, the first derivative round's) is already in pp[0]
+#pragma unroll
+  for (int r = 0; r < NFETCH; ++r) pre[r] = pp[0][r];
+}
+
+// Value rounds of the six curvature components alone (the pairs of value_rounds16, so the same
+// arithmetic), then metric component 0's vertex tile fetched into pre.  Leading barrier: the
+// block's previous LDS readers are done.  Every thread of the block must call it.
+DEV void curv_rounds(const GD& g, const double* metric, const double* curv, const TileIdx& x, double K[6],
+                     double pre[NFETCH], TileLDS2& S2) {
+  double pp[2][NFETCH];
+  tile_fetch(curv, x, pp[0]);
+  tile_fetch(curv + g.N, x, pp[1]);
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < 6; c += 2) {
+    tile_store2(x, pp, S2);
+    tile_fetch(c < 4 ? curv + (c + 2) * g.N : metric, x, pp[0]);
+    if (c < 4) tile_fetch(curv + (c + 3) * g.N, x, pp[1]);
+    double v0, v1;
+    tile_value2(S2, x, v0, v1);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) K[q] = c == q ? v0 : (c + 1 == q ? v1 : K[q]);
+  }
+#pragma unroll
+  for (int r = 0; r < NFETCH; ++r) pre[r] = pp[0][r];
+}
+
+// Derivative rounds of the ten metric components, two per round, accumulated into the sources:
+// src[1 + j] += w_c d_j m_c and, with alpha's, src[4] += wa_j d_j alpha.  pre0: metric
+// component 0's vertex tile, already fetched.  Every thread of the block must call it.
+// xfm (or NULL): the x-face metric of the tile's cells' faces is stored there, ten fields indexed like
+// the fluxes (the face between cells i-1 and i at cell i): each cell its lower face, the last cell of
+// a row also its upper one.  cell: the thread's cell (i, j, k), valid with `valid`.
+DEV void src_deriv_rounds(const GD& g, const double* metric, const TileIdx& x, bool valid, const double pre0[NFETCH],
+                          const SrcW& s, double src[5], TileLDS2D& SD, double* xfm = nullptr, int fid = 0,
+                          bool last_x = false) {
+  double pp[2][NFETCH];
+#pragma unroll
+  for (int r = 0; r < NFETCH; ++r) pp[0][r] = pre0[r];
+  tile_fetch(metric + g.N, x, pp[1]);
+#pragma unroll 1
+  for (int c = 0; c < 10; c += 2) {
+    __syncthreads();
+    tile_store2d(x, pp, SD);
+    if (c < 8) {
+      tile_fetch(metric + (c + 2) * g.N, x, pp[0]);
+      tile_fetch(metric + (c + 3) * g.N, x, pp[1]);
+    }
+    double d0[3], d1[3], xf[2][2];
+    tile_derivs2(SD, x, g, d0, d1, xf);
+    if (xfm && valid) {
+      xfm[(size_t)c * g.N + fid] = xf[0][0];
+      xfm[(size_t)(c + 1) * g.N + fid] = xf[1][0];
+      if (last_x) {
+        xfm[(size_t)c * g.N + fid + 1] = xf[0][1];
+        xfm[(size_t)(c + 1) * g.N + fid + 1] = xf[1][1];
+      }
+    }
+    if (valid) {
+      double w0 = s.w[0], w1 = s.w[1];
+#pragma unroll
+      for (int q = 2; q < 10; ++q) {
+        w0 = c == q ? s.w[q] : w0;
+        w1 = c + 1 == q ? s.w[q] : w1;
+      }
+      src[1] += w0 * d0[0];
+      src[2] += w0 * d0[1];
+      src[3] += w0 * d0[2];
+      if (c == 0) src[4] += s.wa[0] * d0[0] + s.wa[1] * d0[1] + s.wa[2] * d0[2];
+      src[1] += w1 * d1[0];
+      src[2] += w1 * d1[1];
+      src[3] += w1 * d1[2];
+    }
+  }
 }
 
 // =======================================================================================
@@ -539,11 +720,16 @@ struct C2PArgs {
   unsigned long long* stats;
   const float* mlp;  // learned guess (LEARNED instantiation only)
   mlpd::Stdz z;
+  const double* curv;  // SRC instantiation: curvature at vertices
+  double* src;         // SRC instantiation: densitized sources out, [4] (S_x, S_y, S_z, tau)
 };
 
 // LEARNED: each wavefront first evaluates the learned guess's network on its 64 cells (through
 // the tile's LDS, free once the metric passes are done) and seeds Noble's iteration with it.
-template <bool LEARNED>
+// SRC: the cell's geometric sources (eq. grmhdsrc) follow from the recovered state, with the
+// centre metric of the recovery's own value rounds (the six curvature components join them) and
+// the metric derivative rounds after it; stored densitized, alpha sqrt(gamma) S (rounded on its own).
+template <bool LEARNED, bool SRC = false>
 DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S, unsigned tile) {
   const double* __restrict__ metric = a.metric;
   const double* __restrict__ A = a.A;
@@ -554,18 +740,21 @@ DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S,
   const TileCell t = tile_cell(g, tile);
   const TileIdx x = tile_index(g, t);
   double m[10], pre[2][NFETCH];
+  double K[6], pre0[NFETCH];  // SRC only
   TileLDS2& S2 = *reinterpret_cast<TileLDS2*>(&S);
-  tile_fetch(metric, x, pre[0]);
-  tile_fetch(metric + g.N, x, pre[1]);
+  {
+    tile_fetch(metric, x, pre[0]);
+    tile_fetch(metric + g.N, x, pre[1]);
 #pragma unroll
-  for (int c = 0; c < 10; c += 2) {
-    // the previous pair's passes no longer read S2.v (three barriers ago)
-    tile_store2(x, pre, S2);
-    if (c < 8) {
-      tile_fetch(metric + (c + 2) * g.N, x, pre[0]);
-      tile_fetch(metric + (c + 3) * g.N, x, pre[1]);
+    for (int c = 0; c < 10; c += 2) {
+      // the previous pair's passes no longer read S2.v (three barriers ago)
+      tile_store2(x, pre, S2);
+      if (c < 8) {
+        tile_fetch(metric + (c + 2) * g.N, x, pre[0]);
+        tile_fetch(metric + (c + 3) * g.N, x, pre[1]);
+      }
+      tile_value2(S2, x, m[c], m[c + 1]);
     }
-    tile_value2(S2, x, m[c], m[c + 1]);
   }
   uint32_t fl = 0;
   int iters = 0;
@@ -627,6 +816,23 @@ DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S,
       for (int c = 0; c < 5; ++c) cons[c * g.N + id] = U[c];
     }
     if (flags) flags[id] = (uint8_t)fl;
+  }
+  if constexpr (SRC) {
+    SrcW sw;
+    sw.as = 0.0;
+    double src[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (t.valid) src_weights(G, out, Bt, P.gam, sw);
+    // curvature rounds after the recovery and the weights (fewer live registers); the tile's LDS
+    // offsets are formed again (from an opaque copy of the tile id, so they are not held across the
+    // recovery)
+    const TileIdx x2 = tile_index(g, tile_cell(g, (unsigned)__builtin_amdgcn_readfirstlane((int)tile)));
+    curv_rounds(g, metric, a.curv, x2, K, pre0, S2);
+    if (t.valid) src[4] = src_curv(sw, K);
+    src_deriv_rounds(g, metric, x2, t.valid, pre0, sw, src, *reinterpret_cast<TileLDS2D*>(&S), a.src + 4 * g.N, id,
+                     t.i0 + t.cx == g.n[0] - 1);
+    if (t.valid)
+#pragma unroll
+      for (int c = 1; c < 5; ++c) a.src[(c - 1) * g.N + id] = __dmul_rn(sw.as, src[c]);
   }
   if (stats) {
     wave_count(fl & 1u, stats + 0);
@@ -797,6 +1003,9 @@ struct FaceArgs {
   double gam, weno_eps, weno_q, gfac;
   int recon, speeds, riemann;
   double* apm;  // UCT: a_+, a_- and the normal field per direction
+  // x faces: the x-face metric stored by the recovery with sources over the faces with owned
+  // transverse indices (ten fields indexed like the fluxes), or NULL
+  const double* xfm;
 };
 
 // Paired-lane variant: lanes 2f and 2f+1 of a wavefront handle the left and the right state
@@ -970,6 +1179,10 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
     direct_recon();
   }
   double m[10];
+  // x faces whose transverse indices are all owned (not the y = -1 row block, not the z = -1 plane):
+  // the x-face metric stored by the recovery kernel (each lane loads five components and the pair
+  // swaps them), a workgroup-uniform choice
+  const bool xstored = D == 0 && !UCT && fa.xfm && !rest && by0 >= LO && cz >= LO;
   // y and z faces: the direct 16-point gather (one transverse direction is x, so a
   // wavefront's loads are contiguous rows) measured faster than the staged block, except
   // for z faces under WENO-Z
@@ -978,7 +1191,19 @@ DEV void face_body(const GD& g, const FaceArgs& fa, unsigned tile, FaceLDS& L) {
   // the x pass of the face metric is shared through a wavefront-private LDS row
   // (main tiles are 32 faces wide when the face row is; narrower rows gather directly)
   constexpr bool METRIC_ROW = !METRIC_LDS && !(D == 1 && RECON == ASTERX_RECON_WENOZ);
-  if (METRIC_ROW && !rest && e[0] >= 32) {
+  if (xstored) {
+    if (valid) {
+      double mine[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) mine[q] = ldu(fa.xfm + (size_t)(5 * side + q) * g.N, id);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        double other = shfl1(mine[q]);
+        m[q] = side ? other : mine[q];
+        m[5 + q] = side ? mine[q] : other;
+      }
+    }
+  } else if (METRIC_ROW && !rest && e[0] >= 32) {
     if (valid) {
       // the other transverse direction (z for y faces, y for z faces); x is the wavefront's row
       const int so = D == 1 ? g.sz : g.sy;
@@ -1263,26 +1488,6 @@ DEV void emit(const Combine& cb, double* rhs, size_t o, double v) {
     if (k < cb.nout) cb.o[k].out[o] = rk_point<2>(cb.o[k].b_dt, v, cb.o[k].u, cb.o[k].a, cb.o[k].nterms, o);
 }
 
-// T^{mu nu} = (rho h + b^2) u u + (p + b^2/2) g^{mu nu} - b b   (eq. tmunu): T^00, T^0i, T^ij (symmetric)
-DEV void tmunu_upper(const Geo& G, const State& St, double& T00, double T0[3], double Tk[6]) {
-  double ia = 1.0 / G.alp, ia2 = ia * ia;
-  double u0 = St.W * ia, u[3], b0 = St.W * St.Bv * ia, bu[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    u[a] = St.W * (St.v[a] - G.beta[a] * ia);
-    bu[a] = (St.B[a] + G.alp * b0 * u[a]) / St.W;
-  }
-  double e = St.rhoh + St.bsq, pt = St.p + 0.5 * St.bsq;
-  T00 = e * u0 * u0 - pt * ia2 - b0 * b0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) T0[a] = e * u0 * u[a] + pt * G.beta[a] * ia2 - b0 * bu[a];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = a; b < 3; ++b)
-      Tk[sym(a, b)] = e * u[a] * u[b] + pt * (G.gu[sym(a, b)] - G.beta[a] * G.beta[b] * ia2) - bu[a] * bu[b];
-}
-
 struct CellArgs {
   const double* metric;
   const double* curv;
@@ -1303,37 +1508,13 @@ struct CellArgs {
 // component's three derivatives at a time and accumulates them (few live registers).
 DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
   const TileCell t = tile_cell(g, tile);
-  // 26 rounds: values of the 10 metric and 6 curvature components, then derivatives of
-  // the 10 metric components; round r+1's vertex tile is fetched during round r
-  auto comp = [&](int r) { return r < 10 ? ca.metric + r * g.N : (r < 16 ? ca.curv + (r - 10) * g.N : ca.metric + (r - 16) * g.N); };
   const TileIdx x = tile_index(g, t);
   double m[10], K[6], pre[NFETCH];
-  // value rounds two components at a time (one set of barriers per pair); rolled loops keep
-  // the register footprint of one round, values landing by select chains (no dynamically
-  // indexed register arrays)
-  {
-    TileLDS2& S2 = *reinterpret_cast<TileLDS2*>(&S);
-    double pp[2][NFETCH];
-    tile_fetch(comp(0), x, pp[0]);
-    tile_fetch(comp(1), x, pp[1]);
-#pragma unroll 1
-    for (int c = 0; c < 16; c += 2) {
-      tile_store2(x, pp, S2);
-      tile_fetch(comp(c + 2), x, pp[0]);
-      if (c < 14) tile_fetch(comp(c + 3), x, pp[1]);
-      double v0, v1;
-      tile_value2(S2, x, v0, v1);
-#pragma unroll
-      for (int q = 0; q < 10; ++q) m[q] = c == q ? v0 : (c + 1 == q ? v1 : m[q]);
-#pragma unroll
-      for (int q = 0; q < 6; ++q) K[q] = c == 10 + q ? v0 : (c + 1 == 10 + q ? v1 : K[q]);
-    }
-    // comp(16) (the first derivative round's component) is already in pp[0]
-#pragma unroll
-    for (int r = 0; r < NFETCH; ++r) pre[r] = pp[0][r];
-  }
+  value_rounds16(g, ca.metric, ca.curv, x, m, K, pre, *reinterpret_cast<TileLDS2*>(&S));
   const int id = t.valid ? at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz) : 0;
-  double w[10], wa[3], src[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, as = 0.0;
+  SrcW sw;
+  sw.as = 0.0;
+  double src[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (t.valid) {
     Geo G;
     geo_from(m, G);
@@ -1343,72 +1524,10 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
     Bt[0] = ca.bc[id];
     Bt[1] = ca.bc[g.N + id];
     Bt[2] = ca.bc[2 * g.N + id];
-    State St;
-    state_make(G, pr, Bt, ca.gam, St);
-    double T00, T0[3], Tk[6];
-    tmunu_upper(G, St, T00, T0, Tk);
-    double bl[3];
-    lower(G.g, G.beta, bl);
-    as = G.alp * G.sqrtg;
-    // weights of d_j alpha, d_j beta^k, d_j gamma_ab in 1/2 T^{mu nu} d_j g_{mu nu}
-    w[0] = -T00 * G.alp;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      w[1 + k] = T00 * bl[k] + T0[0] * G.g[sym(0, k)] + T0[1] * G.g[sym(1, k)] + T0[2] * G.g[sym(2, k)];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = a; b < 3; ++b) {
-        if (a == b)
-          w[4 + sym(a, b)] = 0.5 * T00 * G.beta[a] * G.beta[a] + T0[a] * G.beta[a] + 0.5 * Tk[sym(a, a)];
-        else
-          w[4 + sym(a, b)] = T00 * G.beta[a] * G.beta[b] + T0[a] * G.beta[b] + T0[b] * G.beta[a] + Tk[sym(a, b)];
-      }
-    // energy source: K terms now, the lapse-gradient terms with the derivatives of alpha
-    double se = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        se += (T00 * G.beta[a] * G.beta[b] + 2.0 * T0[a] * G.beta[b] + Tk[sym(a, b)]) * K[sym(a, b)];
-    src[4] = se;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) wa[a] = -(T00 * G.beta[a] + T0[a]);
+    src_weights(G, pr, Bt, ca.gam, sw);
+    src[4] = src_curv(sw, K);
   }
-  {
-    // derivative rounds, two components at a time
-    TileLDS2D& SD = *reinterpret_cast<TileLDS2D*>(&S);
-    double pp[2][NFETCH];
-#pragma unroll
-    for (int r = 0; r < NFETCH; ++r) pp[0][r] = pre[r];
-    tile_fetch(comp(17), x, pp[1]);
-#pragma unroll 1
-    for (int c = 0; c < 10; c += 2) {
-      __syncthreads();
-      tile_store2d(x, pp, SD);
-      if (c < 8) {
-        tile_fetch(comp(18 + c), x, pp[0]);
-        tile_fetch(comp(19 + c), x, pp[1]);
-      }
-      double d0[3], d1[3];
-      tile_derivs2(SD, x, g, d0, d1);
-      if (t.valid) {
-        double w0 = w[0], w1 = w[1];
-#pragma unroll
-        for (int q = 2; q < 10; ++q) {
-          w0 = c == q ? w[q] : w0;
-          w1 = c + 1 == q ? w[q] : w1;
-        }
-        src[1] += w0 * d0[0];
-        src[2] += w0 * d0[1];
-        src[3] += w0 * d0[2];
-        if (c == 0) src[4] += wa[0] * d0[0] + wa[1] * d0[1] + wa[2] * d0[2];
-        src[1] += w1 * d1[0];
-        src[2] += w1 * d1[1];
-        src[3] += w1 * d1[2];
-      }
-    }
-  }
+  src_deriv_rounds(g, ca.metric, x, t.valid, pre, sw, src, *reinterpret_cast<TileLDS2D*>(&S));
   double divb = 0.0;
   if (t.valid) {
     const int st[3] = {1, g.sy, g.sz};
@@ -1420,7 +1539,8 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
         const double* F = ca.flux + (size_t)(d * 7 + c) * g.N;
         sdiv += (ldu(F, id + st[d]) - ldu(F, id)) * g.idx[d];
       }
-      emit(ca.cmb, ca.rhs, (size_t)c * g.N + id, as * src[c] - sdiv);
+      // the densitized source rounded on its own, as the recovery kernel with sources stores it
+      emit(ca.cmb, ca.rhs, (size_t)c * g.N + id, __dmul_rn(sw.as, src[c]) - sdiv);
     }
     if (ca.red) {
       const double* Ax = ca.A;
@@ -1435,6 +1555,54 @@ DEV void cell_body(const GD& g, const CellArgs& ca, TileLDS& S, unsigned tile) {
   if (ca.red) {
     double wm = wave_max(divb);
     if (__lane_id() == 0) atomic_max_pos(ca.red + 1, wm);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Cells with their sources given (stored by the recovery kernel with sources): flux divergence
+// (eq. fluxconseqs) plus the densitized source, div B, and the stage outputs, with the cell
+// kernel's arithmetic (bitwise the same results).  One thread per owned cell, x fastest, no LDS:
+// a streaming kernel over the fluxes, sources and stage states.
+struct DivArgs {
+  const double* src;  // [4] alpha sqrt(gamma) times the S_x, S_y, S_z, tau sources
+  const double* flux;
+  const double* A;
+  double* rhs;
+  double* red;
+  Combine cmb;
+};
+
+DEV void div_body(const GD& g, const DivArgs& da, unsigned tile) {
+  int i, j, k;
+  const bool in = box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k);
+  double divb = 0.0;
+  if (in) {
+    const int id = at(g, i, j, k);
+    const int st[3] = {1, g.sy, g.sz};
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      double sdiv = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double* F = da.flux + (size_t)(d * 7 + c) * g.N;
+        sdiv += (ldu(F, id + st[d]) - ldu(F, id)) * g.idx[d];
+      }
+      const double sc = c ? ldu(da.src + (size_t)(c - 1) * g.N, id) : 0.0;
+      emit(da.cmb, da.rhs, (size_t)c * g.N + id, sc - sdiv);
+    }
+    if (da.red) {
+      const double* Ax = da.A;
+      const double* Ay = da.A + g.N;
+      const double* Az = da.A + 2 * g.N;
+      double dB = (faceBx(Ay, Az, id + 1, g.sy, g.sz, g) - faceBx(Ay, Az, id, g.sy, g.sz, g)) * g.idx[0] +
+                  (faceBy(Ax, Az, id + g.sy, g.sy, g.sz, g) - faceBy(Ax, Az, id, g.sy, g.sz, g)) * g.idx[1] +
+                  (faceBz(Ax, Ay, id + g.sz, g.sy, g.sz, g) - faceBz(Ax, Ay, id, g.sy, g.sz, g)) * g.idx[2];
+      divb = fabs(dB);
+    }
+  }
+  if (da.red) {
+    double wm = wave_max(divb);
+    if (__lane_id() == 0) atomic_max_pos(da.red + 1, wm);
   }
 }
 
@@ -1896,6 +2064,16 @@ __global__ __launch_bounds__(256) void k_c2p_learned(GD g, C2PParams cp, C2PArgs
   __shared__ C2PLDS S;
   c2p_body<true>(g, cp, a, S.t, my_tile());
 }
+// 3 waves per SIMD: the stress tensor and the source weights after the recovery take about 160
+// registers; held at 4 waves the kernel spills across the recovery and measured slower.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_c2p_src(GD g, C2PParams cp, C2PArgs a) {
+  __shared__ CellLDS S;
+  c2p_body<false, true>(g, cp, a, S.t, my_tile());
+}
+__global__ __launch_bounds__(256) void k_c2p_learned_src(GD g, C2PParams cp, C2PArgs a) {
+  __shared__ CellLDS S;
+  c2p_body<true, true>(g, cp, a, S.t, my_tile());
+}
 __global__ __launch_bounds__(256) void kb_c2p(const PatchDesc* __restrict__ P, const Item* __restrict__ it, int nit,
                                               C2PParams cp, C2PArgs a) {
   __shared__ C2PLDS S;
@@ -1995,6 +2173,7 @@ __global__ __launch_bounds__(256) void kb_cell(const PatchDesc* __restrict__ P, 
   }
 }
 
+__global__ __launch_bounds__(256) void k_div(GD g, DivArgs da) { div_body(g, da, my_tile()); }
 __global__ __launch_bounds__(256) void k_vertex(GD g, VertexArgs va) { vertex_body(g, va, my_tile()); }
 __global__ __launch_bounds__(256) void k_tmunu(GD g, TmunuArgs ta) {
   __shared__ TmunuLDS L;
@@ -3018,6 +3197,34 @@ int do_c2p_learned(const GD& g, const asterx_params* p, const double* metric, co
   });
 }
 
+int do_c2p_src(const GD& g, const asterx_params* p, const double* metric, const double* curv, const double* A,
+               double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats, const float* mlp,
+               const mlpd::Stdz& z, double* src, hipStream_t s) {
+  C2PParams cp = make_c2p_params(p);
+  C2PArgs a{metric, A, cons, prim, flags, (unsigned long long*)stats, mlp, z, curv, src};
+  return timed(KT_C2P, s, [&] {
+    if (mlp)
+      hipLaunchKernelGGL(k_c2p_learned_src, dim3(tiles_for(PH_C2P, g)), dim3(256), 0, s, g, cp, a);
+    else
+      hipLaunchKernelGGL(k_c2p_src, dim3(tiles_for(PH_C2P, g)), dim3(256), 0, s, g, cp, a);
+  });
+}
+
+// The network's standardisation from an asterx_mlp (scales must be positive).
+int make_stdz(const asterx_mlp* mlp, mlpd::Stdz& z, const char* who) {
+  for (int k = 0; k < mlpd::NI; ++k) {
+    if (!(mlp->in_scale[k] > 0.0f)) return fail(ASTERX_EARG, (std::string(who) + ": network scales must be > 0").c_str());
+    z.is[k] = mlp->in_shift[k];
+    z.isc[k] = mlp->in_scale[k];
+  }
+  for (int k = 0; k < mlpd::NO; ++k) {
+    if (!(mlp->out_scale[k] > 0.0f)) return fail(ASTERX_EARG, (std::string(who) + ": network scales must be > 0").c_str());
+    z.os[k] = mlp->out_shift[k];
+    z.osc[k] = 1.0f / mlp->out_scale[k];
+  }
+  return 0;
+}
+
 int do_fill(const GD& g, const asterx_batch* b, double* f, int nf, const int32_t* kinds, hipStream_t s,
             const double* shift = nullptr) {
   int rc;
@@ -3042,9 +3249,11 @@ int do_bcent(const GD& g, const double* A, double* bc, hipStream_t s) {
   return RUN_PHASE(KT_BCENT, PH_BCENT, k_bcent, kb_bcent, A, bc);
 }
 
+// src (single blocks): densitized sources stored by the recovery with sources; the cell phase is
+// then the divergence kernel instead of the cell kernel.
 int do_rhs(const GD& g, const asterx_batch* b, const asterx_params* p, const double* metric, const double* curv,
            const double* prim, const double* A, const double* psi, double dt_max, double* rhs, double* red,
-           double* ws, hipStream_t s, const Combine& cmb = Combine{}) {
+           double* ws, hipStream_t s, const Combine& cmb = Combine{}, const double* src = nullptr) {
   int rc;
   double* bc = ws;
   double* flux = ws + 3 * g.N;
@@ -3054,10 +3263,18 @@ int do_rhs(const GD& g, const asterx_batch* b, const asterx_params* p, const dou
   const bool uct = p->ct == ASTERX_CT_UCT;
   if ((rc = RUN_PHASE(KT_BCENT, PH_BCENT, k_bcent, kb_bcent, A, bc))) return rc;
   FaceArgs fa{metric, prim, A, bc, flux, red, p->gamma, p->weno_eps, p->weno_q, p->gamma / (p->gamma - 1.0),
-              p->recon, p->speeds, p->riemann, apm};
+              p->recon, p->speeds, p->riemann, apm, (src && !uct) ? src + 4 * g.N : nullptr};
   if ((rc = uct ? faces_uct(g, fa, p->recon, s) : faces(g, b, fa, p->recon, s))) return rc;
-  CellArgs ca{metric, curv, prim, A, bc, flux, rhs, red, p->gamma, cmb};
-  if ((rc = RUN_PHASE(KT_CELL, PH_CELL, k_cell, kb_cell, ca))) return rc;
+  if (src) {
+    const DivArgs da{src, flux, A, rhs, red, cmb};
+    if ((rc = timed(KT_CELL, s, [&] {
+           hipLaunchKernelGGL(k_div, dim3(box_blocks<64, 4>(g.n)), dim3(256), 0, s, g, da);
+         })))
+      return rc;
+  } else {
+    CellArgs ca{metric, curv, prim, A, bc, flux, rhs, red, p->gamma, cmb};
+    if ((rc = RUN_PHASE(KT_CELL, PH_CELL, k_cell, kb_cell, ca))) return rc;
+  }
   if (p->gauge == ASTERX_GAUGE_LORENZ) {
     VertexArgs va{metric, A, psi, ga, fp};
     if ((rc = RUN_PHASE(KT_VERTEX, PH_VERTEX, k_vertex, kb_vertex, va))) return rc;
@@ -3250,18 +3467,25 @@ int asterx_c2p_learned(const asterx_grid* gr, const asterx_params* p, const doub
   if ((rc = check_grid(gr, 2)) || (rc = check_params(p))) return rc;
   if (!metric || !A || !prim || !cons || !mlp || !mlp->params) return fail(ASTERX_EARG, "c2p_learned: NULL array");
   mlpd::Stdz z;
-  for (int k = 0; k < mlpd::NI; ++k) {
-    if (!(mlp->in_scale[k] > 0.0f)) return fail(ASTERX_EARG, "c2p_learned: network scales must be > 0");
-    z.is[k] = mlp->in_shift[k];
-    z.isc[k] = mlp->in_scale[k];
-  }
-  for (int k = 0; k < mlpd::NO; ++k) {
-    if (!(mlp->out_scale[k] > 0.0f)) return fail(ASTERX_EARG, "c2p_learned: network scales must be > 0");
-    z.os[k] = mlp->out_shift[k];
-    z.osc[k] = 1.0f / mlp->out_scale[k];
-  }
+  if ((rc = make_stdz(mlp, z, "c2p_learned"))) return rc;
   GD g = make_gd(gr);
   return do_c2p_learned(g, p, metric, A, cons, prim, flags, stats, mlp->params, z, (hipStream_t)stream);
+}
+
+int asterx_c2p_src(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* curv,
+                   const double* A, double* cons, double* prim, uint8_t* flags, asterx_c2p_stats* stats,
+                   const asterx_mlp* mlp, double* src, void* stream) {
+  int rc;
+  if ((rc = check_grid(gr, 2)) || (rc = check_params(p))) return rc;
+  if (!metric || !curv || !A || !prim || !cons || !src) return fail(ASTERX_EARG, "c2p_src: NULL array");
+  mlpd::Stdz z{};
+  if (mlp) {
+    if (!mlp->params) return fail(ASTERX_EARG, "c2p_src: NULL network parameters");
+    if ((rc = make_stdz(mlp, z, "c2p_src"))) return rc;
+  }
+  GD g = make_gd(gr);
+  return do_c2p_src(g, p, metric, curv, A, cons, prim, flags, stats, mlp ? mlp->params : nullptr, z, src,
+                    (hipStream_t)stream);
 }
 
 int asterx_fill_ghosts(const asterx_grid* gr, double* f, int32_t nf, const int32_t* kinds, void* stream) {
@@ -3325,6 +3549,24 @@ int asterx_rhs_rk(const asterx_grid* gr, const asterx_params* p, const double* m
   if ((rc = make_combine(nout, outs, g.N, ins, nin, 6, cmb))) return rc;
   return do_rhs(g, nullptr, p, metric, curv, prim, A, psi, dt_max, nullptr, red, (double*)workspace,
                 (hipStream_t)stream, cmb);
+}
+
+int asterx_rhs_rk_src(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* prim,
+                      const double* A, const double* psi, const double* src, double dt_max, int32_t nout,
+                      const asterx_rk_out* outs, double* red, void* workspace, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_params(p)) || (rc = check_grid(gr, 3))) return rc;
+  if (p->ct == ASTERX_CT_UCT && gr->ng < 4) return fail(ASTERX_EARG, "rhs_rk_src: upwind CT needs ng >= 4");
+  if (!metric || !prim || !A || !psi || !src || !workspace) return fail(ASTERX_EARG, "rhs_rk_src: NULL array");
+  if (ws_bytes < asterx_rhs_workspace_size(gr)) return fail(ASTERX_EARG, "rhs_rk_src: workspace too small");
+  if (!(dt_max > 0.0)) return fail(ASTERX_EARG, "rhs_rk_src: dt_max must be > 0");
+  GD g = make_gd(gr);
+  const double* ins[6] = {metric, prim, A, psi, src, (const double*)workspace};
+  const size_t nin[6] = {10 * g.N, 5 * g.N, 3 * g.N, g.N, ASTERX_SRC_FIELDS * g.N, ws_bytes / sizeof(double)};
+  Combine cmb;
+  if ((rc = make_combine(nout, outs, g.N, ins, nin, 6, cmb))) return rc;
+  return do_rhs(g, nullptr, p, metric, nullptr, prim, A, psi, dt_max, nullptr, red, (double*)workspace,
+                (hipStream_t)stream, cmb, src);
 }
 
 int asterx_rhs_rk_noalloc(const asterx_grid* gr, const asterx_params* p, const double* metric, const double* curv,

@@ -24,7 +24,8 @@ def _patches(n=10, nsteps=2, recon="minmod"):
 
 
 def _per_patch(ax, wls, nsteps):
-    blocks = [ax.Block(w) for w in wls]
+    # the per-patch launch loop runs the batch's kernel bodies (sources in the cell kernel)
+    blocks = [ax.Block(w, src_in_c2p=False) for w in wls]
     for _ in range(nsteps):
         for b in blocks:
             b.step()

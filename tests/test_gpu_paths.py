@@ -261,7 +261,8 @@ def _batch_vs_loop_and_oracle(ax, orc, wls, nsteps, tuning, sampled):
     import torch
     bt = ax.Batch(wls, tuning=tuning)
     bt.run(nsteps)
-    blocks = [ax.Block(w) for w in wls]
+    # the per-patch launch loop runs the batch's kernel bodies (sources in the cell kernel)
+    blocks = [ax.Block(w, src_in_c2p=False) for w in wls]
     for _ in range(nsteps):
         for b in blocks:
             b.step()
