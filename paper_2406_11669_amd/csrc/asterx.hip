@@ -709,6 +709,14 @@ DEV void prim2con_body(const GD& g, double gam, const double* __restrict__ metri
   for (int c = 0; c < 5; ++c) cons[c * g.N + id] = U[c];
 }
 
+// LDS written by this wavefront and read back by it only: its accesses execute in order, and a
+// wavefront barrier keeps the compiler from moving the reads above the writes.
+DEV void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // c2p on owned cells, tiled: the ten metric components are interpolated to the centres
 // through LDS (Sec. 3.2), then each thread recovers its cell (Secs. 3.5, 3.6).
 struct C2PArgs {
@@ -724,8 +732,11 @@ struct C2PArgs {
   double* src;         // SRC instantiation: densitized sources out, [4] (S_x, S_y, S_z, tau)
 };
 
-// LEARNED: each wavefront first evaluates the learned guess's network on its 64 cells (through
-// the tile's LDS, free once the metric passes are done) and seeds Noble's iteration with it.
+// LEARNED: a wavefront with cells that have no usable warm start (previous primitives that are
+// not a physical state: the first recovery of a block, reset or prolonged cells) evaluates the
+// learned guess's network on its 64 cells (through its own part of the tile's LDS, free once the
+// metric passes are done) and seeds Noble's iteration of those cells with it; the other cells,
+// and wavefronts without such cells, start from their previous primitives as in the plain form.
 // SRC: the cell's geometric sources (eq. grmhdsrc) follow from the recovered state, with the
 // centre metric of the recovery's own value rounds (the six curvature components join them) and
 // the metric derivative rounds after it; stored densitized, alpha sqrt(gamma) S (rounded on its own).
@@ -774,8 +785,9 @@ DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S,
   bool use_guess = false;
   if constexpr (LEARNED) {
     using namespace mlpd;
-    // S.z and S.y are free: every thread has passed the barrier after the last y pass, and
-    // the barrier below orders the last x pass (reads S.y) before the outputs land there
+    // F and Y (one part per wavefront) lie in TileLDS's z and y arrays, i.e. over the value rounds'
+    // staged vertices and z-pass output, which every thread has finished reading at the barrier
+    // before the last x pass; that x pass reads the y-pass output, which lies beyond both
     float(*F)[64][NI] = reinterpret_cast<float(*)[64][NI]>(S.z);
     float(*Y)[64][NO] = reinterpret_cast<float(*)[64][NO]>(S.y);
     const int w = threadIdx.x >> 6, l = __lane_id(), lr = l & 15, lg = l >> 4;
@@ -784,21 +796,25 @@ DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S,
     C2PIn c;
     bool in = t.valid && isfinite(U[0]) && isfinite(U[1]) && isfinite(U[2]) && isfinite(U[3]) && isfinite(U[4]) &&
               U[0] >= G.sqrtg * P.rho_atm;
-    if (in) {
-      c2p_input(G, U, Bt, c);
-      features(G, c, P.gam, f, usable);
+    if (in) in = !warm_usable(G, prev, P);
+    // the network runs for whole wavefronts only (matrix instructions), and only where it is needed
+    if (__ballot(in) != 0) {
+      if (in) {
+        c2p_input(G, U, Bt, c);
+        features(G, c, P.gam, f, usable);
+      }
+#pragma unroll
+      for (int k = 0; k < NI; ++k) F[w][l][k] = usable ? (f[k] - a.z.is[k]) * a.z.isc[k] : 0.0f;
+      wave_lds_sync();
+      f4 y[4];
+      mlp_fwd<false>(a.mlp, F[w], y, nullptr);
+      if (lg == 0)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int q = 0; q < NO; ++q) Y[w][nt * 16 + lr][q] = a.z.os[q] + y[nt][q] / a.z.osc[q];
+      wave_lds_sync();
     }
-#pragma unroll
-    for (int k = 0; k < NI; ++k) F[w][l][k] = usable ? (f[k] - a.z.is[k]) * a.z.isc[k] : 0.0f;
-    __syncthreads();
-    f4 y[4];
-    mlp_fwd<false>(a.mlp, F[w], y, nullptr);
-    if (lg == 0)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-        for (int q = 0; q < NO; ++q) Y[w][nt * 16 + lr][q] = a.z.os[q] + y[nt][q] / a.z.osc[q];
-    __syncthreads();
     if (usable) {
       const double W = (double)__expf(Y[w][l][0]);
       const double wcap = 1.0 - 1.0 / (P.wmax * P.wmax);

@@ -612,6 +612,16 @@ DEV void c2p_input(const Geo& G, const double U[5], const double Bt[3], C2PIn& c
 // zw_guess (optional): an initial (z, w) tried first by Noble's Newton iteration; if it does
 // not converge, flag 32 is set and the plain warm/cold start follows.  iters: total Newton
 // iterations.
+// Whether previous primitives make a warm start for Noble's iteration: positive density,
+// non-negative pressure, a speed below the cap, all finite.
+DEV bool warm_usable(const Geo& G, const double prev[5], const C2PParams& P) {
+  double vl[3], v[3] = {prev[2], prev[3], prev[4]};
+  lower(G.g, v, vl);
+  const double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
+  const double wcap = 1.0 - 1.0 / (P.wmax * P.wmax);
+  return prev[0] > 0.0 && prev[1] >= 0.0 && v2 < wcap && isfinite(v2) && isfinite(prev[1]);
+}
+
 DEV uint32_t c2p_point(const Geo& G, double U[5], const double Bt[3], const double prev[5], const C2PParams& P,
                        double out[5], int& iters, const double* zw_guess = nullptr) {
   uint32_t fl = 0;

@@ -184,9 +184,12 @@ def test_trained_guess_cuts_newton_iterations(L, trained):
     assert learned["rho_rel_diff_vs_cold_max"] <= 1e-12 and learned["p_diff_vs_cold_max"] <= 1e-12
 
 
-def test_grid_c2p_learned_matches_plain(L, trained, orc):
-    """asterx_c2p_learned on a curved block (warm starts present, as inside a step) recovers the same primitives
-    as the oracle's c2p within 1e-12 (cancellation-aware), with the same flags apart from bit 32."""
+@pytest.mark.parametrize("cold_planes", [0, 3])
+def test_grid_c2p_learned_matches_plain(L, trained, orc, cold_planes):
+    """asterx_c2p_learned on a curved block recovers the same primitives as the oracle's c2p within 1e-12
+    (cancellation-aware), with the same flags apart from bit 32: with warm starts everywhere (as inside a step:
+    the network is not consulted), and with the previous primitives zeroed on some z planes (no warm start
+    there: the wavefronts holding those cells evaluate the network, the oracle starts cold)."""
     import torch
     from paper_2406_11669_amd import asterx as ax
     from tests.parity import assert_fields_close
@@ -196,6 +199,8 @@ def test_grid_c2p_learned_matches_plain(L, trained, orc):
     cons = orc.prim2con(Lg, w.params, w.metric, w.A, w.prim)
     rng = np.random.default_rng(4)
     guess = w.prim * (1.0 + rng.uniform(-0.02, 0.02, w.prim.shape))
+    for k in range(cold_planes):
+        guess[:, Lg.ng + 2 + 3 * k] = 0.0
     c_ref, p_ref = cons.copy(), guess.copy()
     fl_ref, _ = orc.c2p(Lg, w.params, w.metric, w.A, c_ref, p_ref)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
