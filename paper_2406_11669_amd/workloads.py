@@ -170,15 +170,17 @@ def flat_metric(layout):
 
 
 def riemann_block(seed=0, n=32, ng=NG_DEFAULT, recon="minmod", nsteps=10, rk=2, cfl=0.25, gamma=5.0 / 3.0,
-                  split=0.5, dx=None):
-    """Seeded relativistic MHD Riemann problem on [0, n dx]^3 (dx = 1/n by default), split on the vertex plane
-    x = split.
+                  split=0.5, dx=None, origin=(0.0, 0.0, 0.0)):
+    """Seeded relativistic MHD Riemann problem on origin + [0, n dx]^3 (dx = 1/n by default), split on the vertex
+    plane x = split (coordinates include the origin, so blocks of one seed at different origins and spacings
+    sample one global state and one global potential).
 
     Left/right: rho, p ~ U[0.1, 1], v = 0, B^x ~ U[-1, 1] shared, B^y, B^z ~ U[-1, 1] per side.
     The edge potential A = (0, int_0^x B^z dx', B^x y - int_0^x B^y dx') reproduces the
     piecewise-constant face field exactly under the discrete curl."""
     nn = (n, n, n) if np.isscalar(n) else tuple(n)
     L = Layout(nn, ng, dx=None if dx is None else (dx, dx, dx))
+    ox, oy, oz = (float(v) for v in origin)
     rng = np.random.default_rng(int(seed))
     rhoL, rhoR = rng.uniform(0.1, 1.0, 2)
     pL, pR = rng.uniform(0.1, 1.0, 2)
@@ -188,7 +190,7 @@ def riemann_block(seed=0, n=32, ng=NG_DEFAULT, recon="minmod", nsteps=10, rk=2, 
     curv = L.zeros(6)
     prim = L.zeros(5)
     xc, _, _ = L.coords("centre")
-    left = np.broadcast_to(xc < split, L.shape3)
+    left = np.broadcast_to(xc + ox < split, L.shape3)
     prim[0] = np.where(left, rhoL, rhoR)
     prim[1] = np.where(left, pL, pR)
 
@@ -197,9 +199,9 @@ def riemann_block(seed=0, n=32, ng=NG_DEFAULT, recon="minmod", nsteps=10, rk=2, 
 
     A = L.zeros(3)
     xy, yy, zy = L.coords("yedge")
-    A[1] = np.broadcast_to(int_B(xy, BzL, BzR) + 0.0 * yy + 0.0 * zy, L.shape3)
+    A[1] = np.broadcast_to(int_B(xy + ox, BzL, BzR) + 0.0 * yy + 0.0 * zy, L.shape3)
     xz, yz, zz = L.coords("zedge")
-    A[2] = np.broadcast_to(Bx * yz - int_B(xz, ByL, ByR) + 0.0 * zz, L.shape3)
+    A[2] = np.broadcast_to(Bx * (yz + oy) - int_B(xz + ox, ByL, ByR) + 0.0 * zz, L.shape3)
     psi = L.zeros(1)
     rho_max = max(rhoL, rhoR)
     params = default_params(gamma=gamma, rho_atm=1e-7 * rho_max, recon=recon)
@@ -395,6 +397,35 @@ def patch_set(seed=0, npatches=512, sides=(16, 24, 32, 48), levels=3, ng=NG_DEFA
         w.params["rho_atm"] = 1e-7 * rho_max  # one floor for the whole hierarchy
         w.info["level"] = int(np.log2(1.0 / (32.0 * w.layout.dx[0])) + 0.5)
     return out
+
+
+def box_in_box(seed=0, n=24, levels=3, ng=NG_DEFAULT, recon="minmod", nsteps=10, cfl=0.25, split=0.375):
+    """Nested refinement (box in box, as in the mesh-refinement test of Sec. 4): level 0 covers the unit box with
+    n^3 cells, level l > 0 a centred box of n^3 cells at half its parent's spacing (the middle n/2 parent cells
+    per axis).  One seeded Riemann problem (riemann_block) split on the vertex plane x = split, sampled by every
+    level in global coordinates; the default split lies on the finest level's lower x face, so the waves cross
+    refinement boundaries at once.  One global time step cfl * (finest spacing) (no subcycling).  Level 0 has
+    the copy / linear ghosts of riemann_block; finer levels take their ghosts from their parent.
+    Returns (workloads, parents, c0): parents[l] = l - 1 (None for level 0) and c0[l] the parent vertex index
+    of the patch's vertex 0."""
+    assert n % 4 == 0 and levels >= 1
+    wls, parents, c0 = [], [], []
+    for lev in range(levels):
+        dx = 1.0 / (n * 2 ** lev)
+        o = 0.5 - 0.5 * n * dx
+        w = riemann_block(seed=seed, n=n, ng=ng, recon=recon, nsteps=nsteps, rk=2, cfl=cfl, split=split, dx=dx,
+                          origin=(o, o, o))
+        w.info["level"] = lev
+        w.info["origin"] = o
+        wls.append(w)
+        parents.append(None if lev == 0 else lev - 1)
+        c0.append(None if lev == 0 else (n // 4,) * 3)
+    dt = cfl / (n * 2 ** (levels - 1))
+    rho_max = max(max(w.info["rhoL"], w.info["rhoR"]) for w in wls)
+    for w in wls:
+        w.dt = dt
+        w.params["rho_atm"] = 1e-7 * rho_max
+    return wls, parents, c0
 
 
 def gradient_direction(layout, seed, with_gamma=True):

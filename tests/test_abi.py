@@ -243,3 +243,27 @@ def test_noalloc_refuses_grids_beyond_its_workspace_on_host(lib):
     rc = lib.asterx_rhs_rk_noalloc(ctypes.byref(g), ctypes.byref(p), dummy, dummy, dummy, dummy, dummy, 0.01, 1, outs,
                                    None, None)
     assert rc == -1 and b"64 MiB" in lib.asterx_last_error()
+
+
+def test_ghost_boxes_partition_the_ghost_points():
+    """The six boxes of a refined patch's ghost zones cover every ghost point of each staggering exactly once and
+    no owned point: the ghost points are ng layers around the owned box [0, n - 1]^3, one more on the upper side
+    of a vertex-centred axis (its point n)."""
+    import numpy as np
+    from paper_2406_11669_amd.amr import ghost_boxes
+    from paper_2406_11669_amd.workloads import Layout
+    L = Layout((10, 7, 6), 3)
+    for stag in [(0, 0, 0), (1, 1, 1), (0, 1, 1), (1, 0, 1), (1, 1, 0)]:
+        count = np.zeros(L.shape3, dtype=int)
+        for lo, hi in ghost_boxes(L, stag):
+            count[lo[2] + L.ng:hi[2] + L.ng + 1, lo[1] + L.ng:hi[1] + L.ng + 1, lo[0] + L.ng:hi[0] + L.ng + 1] += 1
+        idx = [np.arange(L.ld[d]) - L.ng for d in range(3)]
+        own1 = [(i >= 0) & (i <= L.n[d] - 1) for d, i in enumerate(idx)]
+        # within ng layers of the owned range (vertex axes: of [0, n])
+        inr = [(i >= -L.ng) & (i <= L.n[d] - 1 + stag[d] + L.ng) for d, i in enumerate(idx)]
+        assert all(int(np.sum(o)) == L.n[d] for d, o in enumerate(own1))
+        assert all(int(np.sum(r)) == L.n[d] + 2 * L.ng + stag[d] for d, r in enumerate(inr))
+        own = [(i >= 0) & (i <= L.n[d] - 1) for d, i in enumerate(idx)]
+        inside = inr[2][:, None, None] & inr[1][None, :, None] & inr[0][None, None, :]
+        owned = own[2][:, None, None] & own[1][None, :, None] & own[0][None, None, :]
+        assert np.array_equal(count, (inside & ~owned).astype(int)), stag
