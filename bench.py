@@ -7,8 +7,8 @@ step (4 stages: c2p, primitive ghost fill, right-hand side, combine, state ghost
 captured HIP graph, with all inputs resident in HBM.
 
 Prints one JSON line: zone-updates/s per RK stage (interior cells x stages / wall time of the timed steps); the
-roofline of the dominant kernel and per-kernel figures of the face, cell and recovery kernels (per-kernel HIP
-events recorded live on the launch stream); the whole-stage HBM and FP64 rooflines; the same block with the other
+roofline of the dominant kernel and per-kernel figures of the face kernels, the recovery with sources and the
+divergence kernel (per-kernel HIP events recorded live on the launch stream); the whole-stage HBM and FP64 rooflines; the same block with the other
 reconstruction, batched patches against a per-patch loop and the learned recovery guess against the plain one
 (comparison keys); and the CPU oracle timed on the host (serial on a bounded sample, all cores on the full block).
 """
@@ -43,6 +43,14 @@ FACE_FLOPS = {"ppm": 2603.1, "wenoz": 3955.0, "minmod": 2022.6, "mp5": 2480.3, "
 # Noble iteration) on that block.
 CELL_FLOPS = 4716.0
 C2P_FLOPS = 1795.0
+# The benchmark's stage evaluates the sources in the recovery kernel (asterx_c2p_src) and leaves the flux
+# divergence, div B and the stage outputs to a streaming kernel (asterx_rhs_rk_src).  Counted per cell: the
+# divergence 5 components x (3 differences, 3 divisions by the spacing, 3 additions, 1 source addition) = 50, and
+# div B 6 face curls x 5 (the counter's face_B) + 3 differences + 3 divisions + 2 additions = 38; the recovery
+# with sources is the recovery plus the cell count without these, less the ten centre metric values the two
+# counts both contain (10 x 147, the counter's centre_value), which the fused kernel interpolates once.
+DIV_FLOPS = 50.0 + 38.0
+C2P_SRC_FLOPS = C2P_FLOPS + CELL_FLOPS - DIV_FLOPS - 10 * 147.0
 # Algorithmic bytes per face: read 5 primitives + 2 centre fields + 10 face-metric components + 2 potential
 # components, write 7 face fluxes (each value once, stencil reuse served on chip).
 FACE_BYTES = 8.0 * (5 + 2 + 10 + 2 + 7)
@@ -53,6 +61,12 @@ CELL_BYTES_RK4 = 8.0 * (16 + 5 + 3 + 15 + 1.5 * 5 + 1.75 * 5)
 # Per owned cell of the recovery: conserved (5), potential (3), metric (10), previous primitives (5) read,
 # primitives (5) written.
 C2P_BYTES = 8.0 * (5 + 3 + 10 + 5 + 5)
+# Per owned cell of the recovery with sources: the recovery's and the curvature (6) read; the primitives (5), the
+# densitized sources (4) and the metric at the cell's lower x face (10, handed to the x-face kernel) written.
+C2P_SRC_BYTES = 8.0 * (5 + 3 + 10 + 6 + 5 + 5 + 4 + 10)
+# Per owned cell of the divergence kernel: the 15 hydro face fluxes, the 4 sources and the potential (3, for
+# div B) read once; RK4 stage outputs of the 5 hydro fields as for the cell kernel.
+DIV_BYTES_RK4 = 8.0 * (15 + 4 + 3 + 1.5 * 5 + 1.75 * 5)
 # Whole-stage algorithmic HBM bytes per zone-stage, RK4 averaged over its four stages: reads of the stage
 # state (9), metric and curvature (16), previous primitives (5), RK base state and accumulator (9 + 9 when
 # used); writes of primitives (5), next state (9) and accumulator (9 when used).
@@ -288,8 +302,9 @@ def graph_steps(torch, blk, steps, warmup, graph=True):
 
 def kernel_rooflines(kt, stages, n, scheme, ct):
     """Per-kernel figures from the live HIP-event durations kt (one eager step): the face kernel (three direction
-    launches per stage, averaged), the cell kernel and the recovery, each against both roofs.  Achieved figures are
-    algorithmic work per launch (per-unit figure x units per launch) over the average launch duration."""
+    launches per stage, averaged), the recovery with sources (timed under "c2p") and the divergence kernel (timed
+    under "cell"), each against both roofs.  Achieved figures are algorithmic work per launch (per-unit figure x
+    units per launch) over the average launch duration."""
     cells = n ** 3
     faces = (n + 1) ** 3 if ct == "fct" else (n + 1) * (n + 5) ** 2
     face_keys = ("face_x", "face_y", "face_z")
@@ -298,10 +313,10 @@ def kernel_rooflines(kt, stages, n, scheme, ct):
         "face": dict(ms=face_ms, launches_per_stage=3, units="faces", units_per_launch=faces,
                      flops={"estimate": SURVEY_FLOPS_PER_FACE, "oracle_count": FACE_FLOPS.get(scheme)},
                      bytes=FACE_BYTES),
-        "cell": dict(ms=kt["cell"][0] / max(1, kt["cell"][1]), launches_per_stage=1, units="cells",
-                     units_per_launch=cells, flops={"oracle_count": CELL_FLOPS}, bytes=CELL_BYTES_RK4),
-        "c2p": dict(ms=kt["c2p"][0] / max(1, kt["c2p"][1]), launches_per_stage=1, units="cells",
-                    units_per_launch=cells, flops={"oracle_count": C2P_FLOPS}, bytes=C2P_BYTES),
+        "c2p_src": dict(ms=kt["c2p"][0] / max(1, kt["c2p"][1]), launches_per_stage=1, units="cells",
+                        units_per_launch=cells, flops={"oracle_count": C2P_SRC_FLOPS}, bytes=C2P_SRC_BYTES),
+        "divergence": dict(ms=kt["cell"][0] / max(1, kt["cell"][1]), launches_per_stage=1, units="cells",
+                           units_per_launch=cells, flops={"oracle_count": DIV_FLOPS}, bytes=DIV_BYTES_RK4),
     }
     out = {}
     for name, r in rows.items():
@@ -324,8 +339,8 @@ def headline_roofline(kr, kt, stages, scheme, n):
     """The roofline of the dominant kernel: the kernel function with the largest total time per stage (the face
     kernel's three direction launches are one kernel).  Its bound follows from the arithmetic intensity of the
     a-priori per-unit figures (FLOP/B against the ridge of the two roofs)."""
-    per_stage = {"face": kr["face"]["ms_per_launch"] * 3, "cell": kr["cell"]["ms_per_launch"],
-                 "c2p": kr["c2p"]["ms_per_launch"]}
+    per_stage = {"face": kr["face"]["ms_per_launch"] * 3, "divergence": kr["divergence"]["ms_per_launch"],
+                 "c2p_src": kr["c2p_src"]["ms_per_launch"]}
     for k, v in kt.items():
         if k not in ("face_x", "face_y", "face_z", "cell", "c2p") and v[1] > 0:
             per_stage[k] = v[0] / stages
@@ -491,7 +506,9 @@ def main():
     torch.cuda.synchronize()
     kt = asterx.timing_read()
     asterx.timing_enable(False)
-    per_stage = {k: round(v[0] / stages, 4) for k, v in kt.items() if v[1] > 0}
+    # the library times the recovery with sources as "c2p" and the divergence kernel as "cell"
+    names = {"c2p": "c2p_src", "cell": "divergence"}
+    per_stage = {names.get(k, k): round(v[0] / stages, 4) for k, v in kt.items() if v[1] > 0}
     kr = kernel_rooflines(kt, stages, n, scheme, args.ct)
     roofline = headline_roofline(kr, kt, stages, scheme, n)
     stage_gbs = STAGE_BYTES_RK4 * value / 1e9
