@@ -257,7 +257,7 @@ def test_full_size_curved128_rk4_step(ax, orc, recon):
 
 # ---- batched patches in the stated mix ----------------------------------------------------------------------
 
-def _batch_vs_loop_and_oracle(ax, orc, wls, nsteps, tuning, sampled):
+def _batch_vs_loop_and_oracle(ax, orc, wls, nsteps, tuning, sampled, lib_=None):
     import torch
     bt = ax.Batch(wls, tuning=tuning)
     bt.run(nsteps)
@@ -278,7 +278,7 @@ def _batch_vs_loop_and_oracle(ax, orc, wls, nsteps, tuning, sampled):
         orc.fill_ghosts(L, cons, w.bc_cell)
         state = w.state(cons)
         prim = w.prim.copy()
-        orc.run(L, w.params, w.metric, w.curv, state, prim, w.dt, nsteps, w.rk, w.bc_cell, w.bc_A)
+        orc.run(L, w.params, w.metric, w.curv, state, prim, w.dt, nsteps, w.rk, w.bc_cell, w.bc_A, lib_=lib_)
         e = assert_fields_close(bt.unpack(bt.state, p).cpu().numpy(), state, 1e-10, L.owned, STATE_NAMES)
         worst = max(worst, float(e.max()))
     return worst
@@ -301,6 +301,20 @@ def test_batch_stated_mix_ten_steps(ax, orc):
     print("case batch stated mix", {s: len(v) for s, v in by.items()}, flush=True)
     worst = _batch_vs_loop_and_oracle(ax, orc, wls, 10, (4, 1), sampled)
     print("  sampled patches max error %.2e" % worst, flush=True)
+
+
+def test_batch_stated_configuration_512_patches(ax, orc):
+    """The batched workload as stated: 512 patches of sides drawn from {16, 24, 32, 48} on 3 levels, MINMOD,
+    HLLE, RK2, 10 steps, autotuned schedule of the benchmark (8 workgroups per CU, order as given): the
+    persistent batch equals the per-patch launch loop bit for bit on every patch, and 32 sampled patches
+    (8 of each side) match the oracle (its OpenMP build, bitwise the serial one) within 1e-10."""
+    wls = W.patch_set(seed=0, npatches=512, sides=(16, 24, 32, 48), levels=3, nsteps=10)
+    by, sampled = _sample_by_side(wls, 8)
+    assert sorted(by) == [16, 24, 32, 48] and len(sampled) == 32
+    print("case batch stated configuration", {s: len(v) for s, v in by.items()}, flush=True)
+    lib_omp, threads = orc.lib_omp()
+    worst = _batch_vs_loop_and_oracle(ax, orc, wls, 10, (8, 0), sampled, lib_=lib_omp)
+    print("  32 sampled patches (oracle on %d threads) max error %.2e" % (threads, worst), flush=True)
 
 
 @pytest.mark.parametrize("recon", ["ppm", "wenoz"])
