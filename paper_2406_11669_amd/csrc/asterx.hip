@@ -2386,14 +2386,16 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
     const int st[3] = {1, g.sy, g.sz};
     const int sD = st[D], s1 = st[t1], s2 = st[t2];
     const int o0 = side ? 2 : -3, os = side ? -1 : 1;
-    // forward recomputation of this lane's side
-    double sten[7][5], X[7];
+    // forward recomputation of this lane's side (the stencils are loaded again for the transposed
+    // reconstruction at the end rather than held in registers through the dual passes)
+    auto field = [&](int v) { return v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N; };
+    double X[7];
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
-      const double* f = v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N;
+      double sten[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) sten[v][q] = f[id + (o0 + os * q) * sD];
-      X[v] = recon_right_face<RECON>(sten[v], fa.weno_eps, fa.weno_q);
+      for (int q = 0; q < 5; ++q) sten[q] = field(v)[id + (o0 + os * q) * sD];
+      X[v] = recon_right_face<RECON>(sten, fa.weno_eps, fa.weno_q);
     }
     double mine[5];
     const int mb = id - s1 - s2;
@@ -2429,8 +2431,9 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
       double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
       fallback = !(X[0] > 0.0) || !(X[1] > 0.0) || !(v2 < 1.0);
       if (fallback) {
+        // this side's own cell (stencil point 2)
 #pragma unroll
-        for (int q = 0; q < 7; ++q) X[q] = sten[q][2];
+        for (int q = 0; q < 7; ++q) X[q] = field(q)[id + (o0 + os * 2) * sD];
       }
     }
     double Bt[3];
@@ -2510,6 +2513,7 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
     }
     // local VJP through (X, Bn, Gamma) -> (U, F, c-, c+), one dual pass per input
     double Xb[7], Bnb = 0.0, gb = 0.0;
+#pragma unroll 1
     for (int dir = 0; dir < 9; ++dir) {
       Dual Xd[7];
 #pragma unroll
@@ -2532,10 +2536,14 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
         atomicAdd(dst + id + (o0 + os * 2) * sD, Xb[v]);
         continue;
       }
+      double sten[5];
+#pragma unroll
+      for (int r = 0; r < 5; ++r) sten[r] = field(v)[id + (o0 + os * r) * sD];
+#pragma unroll 1
       for (int q = 0; q < 5; ++q) {
         Dual sd[5];
 #pragma unroll
-        for (int r = 0; r < 5; ++r) sd[r] = Dual(sten[v][r], r == q ? 1.0 : 0.0);
+        for (int r = 0; r < 5; ++r) sd[r] = Dual(sten[r], r == q ? 1.0 : 0.0);
         Dual xr = recon_right_face<RECON>(sd, fa.weno_eps, fa.weno_q);
         if (xr.d != 0.0) atomicAdd(dst + id + (o0 + os * q) * sD, Xb[v] * xr.d);
       }
