@@ -457,6 +457,25 @@ template <class T> void riemann_flux(int kind, const T UL[7], const T FL[7], con
 // Reconstruction (Sec. 3.3).  Each routine takes the five cell values
 // a[0..4] = a_{c-2}..a_{c+2} around cell c and returns the values at its left
 // face (c-1/2) and right face (c+1/2).
+// Near ties of the discontinuous limiter decisions, PPM's monotonicity constraints (serial build only;
+// the counts do not enter any result; minmod and the MC slope are continuous across their switching
+// points, so their branches cannot change a result).  A comparison of p with q whose sides differ but
+// agree to 1e-12 of their magnitude is one that a different but equally valid rounding of p or q (fused
+// multiply-adds, another summation order) can decide the other way; exact equalities (uniform data) are
+// computed exactly by any rounding order.  The tests report the count beside the agreement of two
+// implementations.
+static unsigned long long g_tie_decisions = 0, g_tie_near = 0;
+template <class T> inline void note_tie(const T&, const T&) {}
+inline void note_tie(double p, double q) {
+#ifndef _OPENMP
+  ++g_tie_decisions;
+  if (p != q && std::fabs(p - q) <= 1e-12 * (std::fabs(p) + std::fabs(q))) ++g_tie_near;
+#else
+  (void)p;
+  (void)q;
+#endif
+}
+
 template <class T> T minmod2(const T& x, const T& y) {
   if (x * y > T(0)) return (x > T(0) ? T(1) : T(-1)) * (fabs(x) < fabs(y) ? fabs(x) : fabs(y));
   return T(0);
@@ -492,6 +511,8 @@ template <class T> void rec_ppm(const T a[5], T& aL, T& aR) {
   aL = (a[1] + a[2]) / T(2) - (d0 - dm1) / T(6);
   aR = (a[2] + a[3]) / T(2) - (dp1 - d0) / T(6);
   T ac = a[2];
+  note_tie(aR, ac);
+  note_tie(aL, ac);
   if ((aR - ac) * (ac - aL) <= T(0)) {
     aL = ac;
     aR = ac;
@@ -499,6 +520,8 @@ template <class T> void rec_ppm(const T a[5], T& aL, T& aR) {
     T dd = aR - aL;
     T a6 = dd * (ac - (aL + aR) / T(2));
     T d2 = dd * dd / T(6);
+    note_tie(a6, d2);
+    note_tie(-d2, a6);
     if (a6 > d2)
       aL = T(3) * ac - T(2) * aR;
     else if (-d2 > a6)
@@ -1695,6 +1718,13 @@ template <class T> void run_steps(const Grid& g, const Params& P, const T& gam, 
 using namespace orc;
 
 extern "C" {
+
+// Limiter decisions counted by note_tie since the last reset: out[0] all, out[1] near ties.
+void orc_tie_counts(unsigned long long* out, int reset) {
+  out[0] = g_tie_decisions;
+  out[1] = g_tie_near;
+  if (reset) g_tie_decisions = g_tie_near = 0;
+}
 
 int orc_version(void) { return 1; }
 

@@ -197,6 +197,15 @@ def rhs(layout, params, metric, curv, prim, A, psi, dt_max):
     return out, red, nfix.value
 
 
+def tie_counts(reset=True):
+    """PPM monotonicity-constraint decisions of the serial oracle since the last reset: (all, near ties: sides
+    that differ but agree to 1e-12 of their magnitude, where another valid rounding order can take the other,
+    discontinuous branch)."""
+    out = np.zeros(2, dtype=np.uint64)
+    lib().orc_tie_counts(out.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(1 if reset else 0))
+    return int(out[0]), int(out[1])
+
+
 def rk_stage(layout, a, us, b_dt, rhs_arr, out):
     n = len(a)
     arr_a = (ctypes.c_double * n)(*a)

@@ -212,3 +212,23 @@ def test_counter_grid_phases_decompose(orc):
     assert per[4] == per[6], per
     # a face interpolates 10 metric components (35 each), forms its geometry and normal field at least
     assert per[4][0] > 10 * 35 + 60 + 5
+
+
+def test_near_tie_counter_sees_constructed_ties(orc):
+    """The limiter near-tie counter: a PPM cell whose right-face value differs from the cell value only in its
+    last bits is counted as a near tie of the extremum test; uniform data (exact equalities) and well separated
+    data are not."""
+    import numpy as np
+    from paper_2406_11669_amd.workloads import default_params
+    P = default_params(recon="ppm")
+    orc.tie_counts()
+    orc.recon_1d(P, "ppm", np.ones(12))
+    dec, near = orc.tie_counts()
+    assert dec > 0 and near == 0
+    orc.recon_1d(P, "ppm", np.linspace(0.0, 1.0, 12) ** 2)
+    assert orc.tie_counts()[1] == 0
+    # a monotone ramp whose next value repeats the centre up to one ulp: the right face lands within
+    # rounding of the centre value
+    a = np.array([0.0, 0.25, 0.5, 0.75, 1.0, 1.0 + 2.0 ** -51, 1.0 + 2.0 ** -50, 1.5, 2.0, 2.5, 3.0, 3.5])
+    orc.recon_1d(P, "ppm", a)
+    assert orc.tie_counts()[1] > 0
