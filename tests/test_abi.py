@@ -267,3 +267,36 @@ def test_ghost_boxes_partition_the_ghost_points():
         inside = inr[2][:, None, None] & inr[1][None, :, None] & inr[0][None, None, :]
         owned = own[2][:, None, None] & own[1][None, :, None] & own[0][None, None, :]
         assert np.array_equal(count, (inside & ~owned).astype(int)), stag
+
+
+def test_recovery_with_sources_validation_on_host(lib):
+    """asterx_c2p_src and asterx_rhs_rk_src refuse bad arguments before any launch (the pointers are never
+    dereferenced): NULL arrays, too few ghost layers, a stage output overlapping the sources buffer."""
+    from paper_2406_11669_amd import asterx
+    from paper_2406_11669_amd.workloads import Layout, default_params
+    L = Layout((8, 8, 8), 3)
+    g = asterx.make_grid(L)
+    p = asterx.make_params(default_params(recon="ppm"))
+    base = 1 << 40
+    ptr = lambda k: ctypes.c_void_p(base + k * (1 << 32))
+    metric, curv, A, cons, prim, src, ws = (ptr(k) for k in range(1, 8))
+    rc = lib.asterx_c2p_src(ctypes.byref(g), ctypes.byref(p), metric, curv, A, cons, prim, None, None, None, None, None)
+    assert rc == -1 and b"NULL" in lib.asterx_last_error()
+    g1 = asterx.make_grid(Layout((8, 8, 8), 1))
+    rc = lib.asterx_c2p_src(ctypes.byref(g1), ctypes.byref(p), metric, curv, A, cons, prim, None, None, None, src, None)
+    assert rc == -1
+    wsb = lib.asterx_rhs_workspace_size(ctypes.byref(g))
+    U = base + 9 * (1 << 32)
+    outs = (asterx.RKOut * 1)()
+    outs[0].nterms = 1
+    outs[0].a[0] = 1.0
+    outs[0].u[0] = U
+    outs[0].b_dt = 0.1
+    outs[0].out = src.value + 8  # inside the sources buffer
+    psi = ctypes.c_void_p(U + 8 * 8 * L.npts)
+    rc = lib.asterx_rhs_rk_src(ctypes.byref(g), ctypes.byref(p), metric, prim, A, psi, src, 0.01, 1, outs, None, ws,
+                               wsb, None)
+    assert rc == -1 and b"overlaps an input" in lib.asterx_last_error()
+    rc = lib.asterx_rhs_rk_src(ctypes.byref(g), ctypes.byref(p), metric, prim, A, psi, None, 0.01, 1, outs, None, ws,
+                               wsb, None)
+    assert rc == -1 and b"NULL" in lib.asterx_last_error()

@@ -212,3 +212,33 @@ def test_grid_c2p_learned_matches_plain(L, trained, orc, cold_planes):
     fg = Lg.owned(flags.cpu().numpy()).astype(np.int32)
     assert np.array_equal(fg & ~32, Lg.owned(fl_ref).astype(np.int32))
     assert_fields_close(p_g.cpu().numpy(), p_ref, 1e-12, Lg.owned, ["rho", "p", "vx", "vy", "vz"])
+
+
+@pytest.mark.parametrize("cold_planes", [0, 2])
+def test_block_steps_with_learned_guess_vs_oracle(L, trained, orc, cold_planes):
+    """A curved block stepped with the learned guess in every stage's recovery (the recovery-with-sources kernel
+    that contains the network): two RK4 steps within 1e-10 of the oracle's steps; with the previous primitives
+    of some z planes zeroed before the first stage (no warm start there: those wavefronts evaluate the network,
+    the oracle starts cold)."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    from tests.parity import assert_fields_close
+    params, st, _ = trained
+    w = W.curved_block(seed=31, n=(24, 13, 11), recon="ppm", nsteps=2)
+    Lg = w.layout
+    blk = ax.Block(w)
+    assert blk.src_in_c2p
+    blk.mlp = ax.make_mlp(params, st)
+    prim0 = w.prim.copy()
+    for k in range(cold_planes):
+        prim0[:, Lg.ng + 3 + 4 * k] = 0.0
+        blk.prim[:, Lg.ng + 3 + 4 * k] = 0.0
+    blk.run(2)
+    torch.cuda.synchronize()
+    cons = orc.prim2con(Lg, w.params, w.metric, w.A, w.prim)
+    orc.fill_ghosts(Lg, cons, w.bc_cell)
+    state = w.state(cons)
+    orc.run(Lg, w.params, w.metric, w.curv, state, prim0, w.dt, 2, w.rk, w.bc_cell, w.bc_A)
+    names = ["D", "Sx", "Sy", "Sz", "tau", "Ax", "Ay", "Az", "Psi"]
+    e = assert_fields_close(blk.state.cpu().numpy(), state, 1e-10, Lg.owned, names)
+    print("  learned-guess steps, %d cold planes: max error %.2e" % (cold_planes, float(e.max())), flush=True)
