@@ -1057,6 +1057,50 @@ DEV T recon_right_face(const T a[5], double eps, double q) {
   return wenoz_face(a[0], a[1], a[2], a[3], a[4], eps, q);
 }
 
+// Transpose of recon_right_face on its active branch: ab[k] = xb d(face value) / d(a[k]).
+template <int kind>
+DEV void recon_right_face_vjp(const double a[5], double xb, double eps, double q, double ab[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) ab[k] = 0.0;
+  if (kind == ASTERX_RECON_MINMOD) {
+    // a2 + (a2 - a1) / 2 or a2 + (a3 - a2) / 2, whichever difference is smaller; a2 at an extremum
+    const double x = a[2] - a[1], y = a[3] - a[2], h = 0.5 * xb;
+    ab[2] = xb;
+    if (x * y > 0.0) {
+      if (fabs(x) <= fabs(y)) {
+        ab[2] += h;
+        ab[1] -= h;
+      } else {
+        ab[3] += h;
+        ab[2] -= h;
+      }
+    }
+  } else if (kind == ASTERX_RECON_PPM) {
+    ppm_right_vjp(a, xb, ab);
+  } else if (kind == ASTERX_RECON_MP5) {
+    Lin5 s[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      s[k] = Lin5(a[k]);
+      s[k].c[k] = 1.0;
+    }
+    const Lin5 r = mp5_face(s[0], s[1], s[2], s[3], s[4]);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) ab[k] = xb * r.c[k];
+  } else {
+    // WENO-Z: one dual-number pass per stencil value.  Forward mode keeps the tangent of the
+    // Z ratio tau / (beta + eps) exact where a smoothness indicator vanishes (eps ~ 1e-40); a
+    // reverse sweep would form it as a difference of two terms of order 1 / eps.
+#pragma unroll 1
+    for (int k = 0; k < 5; ++k) {
+      Dual s[5];
+#pragma unroll
+      for (int r = 0; r < 5; ++r) s[r] = Dual(a[r], r == k ? 1.0 : 0.0);
+      ab[k] = xb * recon_right_face<kind>(s, eps, q).d;
+    }
+  }
+}
+
 // The x-face metric goes through LDS: a workgroup's 32 x 4 x 1 faces need a vertex block of
 // 32 x 7 x 4 points per component (interpolation in y and z only), loaded once, coalesced
 // along x, into a double buffer (one barrier per component, the next component's loads in
@@ -2245,10 +2289,11 @@ __global__ __launch_bounds__(256) void kb_rk(const PatchDesc* __restrict__ P, co
 // =======================================================================================
 // Adjoint (vector-Jacobian products) of one right-hand side evaluation with its c2p.
 // The linear parts (flux divergence, FCT averages, gauge terms, staggered curl and averages,
-// periodic ghost fills) are transposed exactly; the pointwise nonlinear parts build local
-// Jacobians with dual numbers (forward mode) and contract them with the incoming
-// cotangents; converged iterations (quartic roots, c2p) are differentiated through the
-// implicit-function theorem.  Non-smooth points take the active branch; an exact tie of
+// periodic ghost fills) are transposed exactly; the face physics of each side runs one
+// hand-written reverse sweep (side_vjp), the other pointwise nonlinear parts (reconstruction,
+// sources) build local Jacobians with dual numbers (forward mode) and contract them with the
+// incoming cotangents; converged iterations (quartic roots, c2p) are differentiated through
+// the implicit-function theorem.  Non-smooth points take the active branch; an exact tie of
 // the two sides in the HLLE max/min splits the cotangent equally (the central derivative).
 
 // Adjoint workspace: fields of the block's index space.
@@ -2309,50 +2354,6 @@ DEV void fluxbar_body(const GD& g, const FluxBarArgs& a, unsigned tile) {
   fb[(size_t)(1 * 7 + 6) * g.N + id] = -0.25 * (rc(7, i, j, k) + rc(7, i + 1, j, k));  // Fy_Bx <- E_z
   fb[(size_t)(2 * 7 + 5) * g.N + id] = 0.25 * (rc(6, i, j, k) + rc(6, i + 1, j, k));   // Fz_Bx <- E_y
   fb[(size_t)(2 * 7 + 6) * g.N + id] = -0.25 * (rc(5, i, j, k) + rc(5, i, j + 1, k));  // Fz_By <- E_x
-}
-
-// Local physics of one face side, as a function of (X[7], Bn, Gamma), in dual numbers with
-// the quartic roots already known (their tangents by implicit differentiation).
-template <int D>
-DEV void side_dual(const Geo& G, const Dual X[7], Dual Bn, Dual gam, int kind, double xp, double xm, Dual U[7],
-                   Dual F[7], Dual& cm, Dual& cp) {
-  constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
-  Dual Bt[3];
-  Bt[D] = Bn;
-  Bt[t1] = X[5];
-  Bt[t2] = X[6];
-  StateT<Dual> S;
-  Dual gfac = gam / (gam - 1.0);
-  state_make(G, X, Bt, gam, S, gfac);
-  flux_of<D>(G, S, U, F);
-  if (kind == 1) {
-    speeds_of<D>(G, S, gam, 1, cm, cp);
-    return;
-  }
-  // dispersion-relation coefficients in dual arithmetic, as in speeds_of
-  double ia = 1.0 / G.alp, bD = G.beta[D], ia2 = ia * ia;
-  Dual uD = S.W * (S.v[D] - bD * ia), u0 = S.W * ia, b0 = S.W * S.Bv * ia;
-  Dual bDc = (S.B[D] + G.alp * b0 * uD) / S.W;
-  Dual cs2 = gam * S.p / S.rhoh;
-  double G0 = G.gu[sym(D, D)] - bD * bD * ia2, G1 = -2.0 * bD * ia2, G2 = -ia2;
-  Dual a0 = uD, a1 = -u0;
-  Dual A4 = S.rhoh * (1.0 - cs2), Bq = S.rhoh * cs2 + S.bsq, Cq = cs2;
-  Dual s0 = a0 * a0, s1 = 2.0 * a0 * a1, s2 = a1 * a1;
-  Dual q0 = bDc * bDc, q1 = -2.0 * bDc * b0, q2 = b0 * b0;
-  Dual c[5];
-  c[0] = A4 * s0 * s0;
-  c[1] = A4 * 2.0 * s0 * s1;
-  c[2] = A4 * (s1 * s1 + 2.0 * s0 * s2);
-  c[3] = A4 * 2.0 * s1 * s2;
-  c[4] = A4 * s2 * s2;
-  Dual r0 = -Bq * s0 + Cq * q0, r1 = -Bq * s1 + Cq * q1, r2 = -Bq * s2 + Cq * q2;
-  c[0] += r0 * G0;
-  c[1] += r0 * G1 + r1 * G0;
-  c[2] += r0 * G2 + r1 * G1 + r2 * G0;
-  c[3] += r1 * G2 + r2 * G1;
-  c[4] += r2 * G2;
-  cp = root_tangent(c, xp);
-  cm = root_tangent(c, xm);
 }
 
 struct FaceAdjArgs {
@@ -2511,24 +2512,12 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
         Ub[q] = 0.0;
       }
     }
-    // local VJP through (X, Bn, Gamma) -> (U, F, c-, c+), one dual pass per input
-    double Xb[7], Bnb = 0.0, gb = 0.0;
-#pragma unroll 1
-    for (int dir = 0; dir < 9; ++dir) {
-      Dual Xd[7];
-#pragma unroll
-      for (int q = 0; q < 7; ++q) Xd[q] = Dual(X[q], dir == q ? 1.0 : 0.0);
-      Dual Bnd(Bn, dir == 7 ? 1.0 : 0.0), gd(fa.gam, dir == 8 ? 1.0 : 0.0);
-      Dual Ud[7], Fd[7], cmd, cpd;
-      side_dual<D>(G, Xd, Bnd, gd, fa.speeds, cp, cm, Ud, Fd, cmd, cpd);
-      double s = cmb * cmd.d + cpb * cpd.d;
-#pragma unroll
-      for (int q = 0; q < 7; ++q) s += Ub[q] * Ud[q].d + Fb[q] * Fd[q].d;
-      if (dir < 7) Xb[dir] = s;
-      else if (dir == 7) Bnb = s;
-      else gb = s;
-    }
-    // through the reconstruction to the stencil cells
+    // local VJP through (X, Bn, Gamma) -> (U, F, c-, c+): one reverse sweep
+    double Xb[7], Bnb, gb;
+    side_vjp<D>(G, X, Bn, fa.gam, fa.speeds, cp, cm, Ub, Fb, cmb, cpb, Xb, Bnb, gb);
+    // the normal field is shared by both sides: sum the pair, one store per face.  It and the
+    // stencil loads below come before the scatter: atomics and loads share one counter, so a
+    // load issued after an atomic waits for that atomic to complete.
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
       double* dst = v < 5 ? fa.pbar + v * g.N : fa.bcbar + (v == 5 ? t1 : t2) * g.N;
@@ -2536,19 +2525,14 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
         atomicAdd(dst + id + (o0 + os * 2) * sD, Xb[v]);
         continue;
       }
-      double sten[5];
+      double sten[5], ab[5];
 #pragma unroll
       for (int r = 0; r < 5; ++r) sten[r] = field(v)[id + (o0 + os * r) * sD];
-#pragma unroll 1
-      for (int q = 0; q < 5; ++q) {
-        Dual sd[5];
+      recon_right_face_vjp<RECON>(sten, Xb[v], fa.weno_eps, fa.weno_q, ab);
 #pragma unroll
-        for (int r = 0; r < 5; ++r) sd[r] = Dual(sten[r], r == q ? 1.0 : 0.0);
-        Dual xr = recon_right_face<RECON>(sd, fa.weno_eps, fa.weno_q);
-        if (xr.d != 0.0) atomicAdd(dst + id + (o0 + os * q) * sD, Xb[v] * xr.d);
-      }
+      for (int q = 0; q < 5; ++q)
+        if (ab[q] != 0.0) atomicAdd(dst + id + (o0 + os * q) * sD, ab[q]);
     }
-    // the normal field is shared by both sides: sum the pair, one store per face
     double bn_total = Bnb + shfl1(Bnb);
     if (side == 0) fa.bfbar[(size_t)D * g.N + id] += bn_total;
     gsum = gb;
@@ -2969,8 +2953,10 @@ DEV void copy_body(const GD& g, const T* __restrict__ src, T* __restrict__ dst, 
 }
 
 __global__ __launch_bounds__(256) void k_fluxbar(GD g, FluxBarArgs a) { fluxbar_body(g, a, my_tile()); }
+// At the 2-wave floor (256 registers) the kernel spills 48-55 doubles yet hides more latency:
+// one wavefront per SIMD leaves every load and FP64 dependency chain exposed.
 template <int D, int R>
-__global__ __launch_bounds__(256) void k_face_adj(GD g, FaceAdjArgs fa) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_face_adj(GD g, FaceAdjArgs fa) {
   face_adj_body<D, R>(g, fa, my_tile());
 }
 __global__ __launch_bounds__(256) void k_cell_adj(GD g, CellAdjArgs ca) { cell_adj_body(g, ca, my_tile()); }

@@ -76,8 +76,8 @@ DEV Dual fmin(Dual a, double b) { return a.v <= b ? a : Dual(b, 0.0); }
 DEV Dual fmin(double a, Dual b) { return a <= b.v ? Dual(a, 0.0) : b; }
 DEV Dual copysign(Dual m, Dual s) { return (::signbit(m.v) != ::signbit(s.v)) ? -m : m; }
 DEV Dual pow(Dual a, double e) {
-  double p = ::pow(a.v, e);
-  return Dual{p, a.d * e * p / a.v};
+  // e a^(e-1) da, written without dividing by a (finite at a = 0 for e >= 1)
+  return Dual{::pow(a.v, e), a.d != 0.0 ? a.d * e * ::pow(a.v, e - 1.0) : 0.0};
 }
 
 // Reciprocal and inverse square root of positive, finite, normal operands from the hardware
@@ -331,6 +331,236 @@ DEV void speeds_of(const Geo& G, const StateT<T>& S, T gam, int kind, T& cm, T& 
   cm = root_tangent(c, xm);
 }
 
+// Reverse mode of one face side: (X[7] = rho, p, v^i, the two transverse densitized field
+// components; Bn, the normal one; Gamma) -> (U[7], F[7], c-, c+) of state_make, flux_of and
+// speeds_of, contracted with the cotangents (Ub, Fb, cmb, cpb) in one backward sweep.  The
+// speeds are the given outer roots xp, xm of the quartic (kind 0) or of the isotropic bound's
+// quadratic (kind 1); their cotangents reach the coefficients through the implicit function
+// theorem, d lambda = -(sum_k dc_k lambda^k) / Q'(lambda) (zero where Q' = 0).
+template <int D>
+DEV void side_vjp(const Geo& G, const double X[7], double Bn, double gam, int kind, double xp, double xm,
+                  const double Ub[7], const double Fb[7], double cmb, double cpb, double Xb[7], double& Bnb,
+                  double& gb) {
+  constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  // forward sweep: the state (state_make)
+  const double gfac = gam / (gam - 1.0);
+  const double rho = X[0], p = X[1], v[3] = {X[2], X[3], X[4]};
+  double vl[3];
+  lower(G.g, v, vl);
+  const double iW2 = 1.0 - (v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2]);
+  const double W = inv_sqrt(iW2);
+  const double is = recip(G.sqrtg), sg = G.sqrtg;
+  double B[3];
+  B[D] = Bn * is;
+  B[t1] = X[5] * is;
+  B[t2] = X[6] * is;
+  double Bl[3];
+  lower(G.g, B, Bl);
+  const double B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
+  const double Bv = B[0] * vl[0] + B[1] * vl[1] + B[2] * vl[2];
+  const double bsq = B2 * iW2 + Bv * Bv;
+  const double rhoh = rho + gfac * p;
+  // cotangents of the state's quantities
+  double rhob = 0.0, pb = 0.0, vb[3] = {0.0, 0.0, 0.0}, vlb[3] = {0.0, 0.0, 0.0}, iW2b = 0.0, Wb = 0.0;
+  double Bb[3] = {0.0, 0.0, 0.0}, Blb[3] = {0.0, 0.0, 0.0}, B2b = 0.0, Bvb = 0.0, bsqb = 0.0, rhohb = 0.0;
+  double gamb = 0.0;
+  // speeds (speeds_of): a = -lambda u^0 + u^D, bb = -lambda b^0 + b^D
+  {
+    const double alp = G.alp, ia = 1.0 / alp, ia2 = ia * ia, bD = G.beta[D];
+    const double uD = W * (v[D] - bD * ia), u0 = W * ia;
+    const double cs2 = gam * p / rhoh;
+    const double G0 = G.gu[sym(D, D)] - bD * bD * ia2, G1 = -2.0 * bD * ia2, G2 = -ia2;
+    const double a0 = uD, a1 = -u0;
+    double a0b = 0.0, a1b = 0.0, cs2b = 0.0;
+    if (kind == 1) {
+      // roots of (1 - w2) a^2 - w2 G = qa l^2 + qb l + qc
+      const double ih = 1.0 / (rhoh + bsq), cA2 = bsq * ih;
+      const double w2 = cs2 + cA2 - cs2 * cA2, om = 1.0 - w2;
+      const double qa = om * a1 * a1 - w2 * G2, qb = 2.0 * om * a0 * a1 - w2 * G1;
+      double qab = 0.0, qbb = 0.0, qcb = 0.0;
+      const double rr[2] = {xp, xm}, rb[2] = {cpb, cmb};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double dq = 2.0 * qa * rr[k] + qb;
+        const double s = dq != 0.0 ? -rb[k] / dq : 0.0;
+        qab += s * rr[k] * rr[k];
+        qbb += s * rr[k];
+        qcb += s;
+      }
+      const double omb = qab * a1 * a1 + 2.0 * qbb * a0 * a1 + qcb * a0 * a0;
+      const double w2b = -(qab * G2 + qbb * G1 + qcb * G0) - omb;
+      a1b = 2.0 * om * (qab * a1 + qbb * a0);
+      a0b = 2.0 * om * (qbb * a1 + qcb * a0);
+      cs2b = w2b * (1.0 - cA2);
+      const double cA2b = w2b * (1.0 - cs2);
+      bsqb += cA2b * rhoh * ih * ih;
+      rhohb -= cA2b * bsq * ih * ih;
+    } else {
+      // quartic rho h (1 - cs2) a^4 - (rho h cs2 + b^2) a^2 G + cs2 bb^2 G
+      const double b0 = W * Bv * ia, iW = 1.0 / W;
+      const double bDc = (B[D] + alp * b0 * uD) * iW;
+      const double A4 = rhoh * (1.0 - cs2), Bq = rhoh * cs2 + bsq, Cq = cs2;
+      const double s0 = a0 * a0, s1 = 2.0 * a0 * a1, s2 = a1 * a1;
+      const double q0 = bDc * bDc, q1 = -2.0 * bDc * b0, q2 = b0 * b0;
+      const double r0 = -Bq * s0 + Cq * q0, r1 = -Bq * s1 + Cq * q1, r2 = -Bq * s2 + Cq * q2;
+      const double c1 = A4 * 2.0 * s0 * s1 + r0 * G1 + r1 * G0;
+      const double c2 = A4 * (s1 * s1 + 2.0 * s0 * s2) + r0 * G2 + r1 * G1 + r2 * G0;
+      const double c3 = A4 * 2.0 * s1 * s2 + r1 * G2 + r2 * G1;
+      const double c4 = A4 * s2 * s2 + r2 * G2;
+      double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      const double rr[2] = {xp, xm}, rb[2] = {cpb, cmb};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double x = rr[k];
+        const double dq = ((4.0 * c4 * x + 3.0 * c3) * x + 2.0 * c2) * x + c1;
+        const double s = dq != 0.0 ? -rb[k] / dq : 0.0;
+        cb[0] += s;
+        cb[1] += s * x;
+        cb[2] += s * x * x;
+        cb[3] += s * x * x * x;
+        cb[4] += s * x * x * x * x;
+      }
+      const double r0b = cb[0] * G0 + cb[1] * G1 + cb[2] * G2;
+      const double r1b = cb[1] * G0 + cb[2] * G1 + cb[3] * G2;
+      const double r2b = cb[2] * G0 + cb[3] * G1 + cb[4] * G2;
+      const double A4b = cb[0] * s0 * s0 + 2.0 * cb[1] * s0 * s1 + cb[2] * (s1 * s1 + 2.0 * s0 * s2) +
+                         2.0 * cb[3] * s1 * s2 + cb[4] * s2 * s2;
+      const double s0b = 2.0 * A4 * (s0 * cb[0] + s1 * cb[1] + s2 * cb[2]) - Bq * r0b;
+      const double s1b = 2.0 * A4 * (s0 * cb[1] + s1 * cb[2] + s2 * cb[3]) - Bq * r1b;
+      const double s2b = 2.0 * A4 * (s0 * cb[2] + s1 * cb[3] + s2 * cb[4]) - Bq * r2b;
+      const double Bqb = -(r0b * s0 + r1b * s1 + r2b * s2);
+      const double Cqb = r0b * q0 + r1b * q1 + r2b * q2;
+      const double q0b = Cq * r0b, q1b = Cq * r1b, q2b = Cq * r2b;
+      a0b = 2.0 * (a0 * s0b + a1 * s1b);
+      a1b = 2.0 * (a0 * s1b + a1 * s2b);
+      const double bDcb = 2.0 * (bDc * q0b - b0 * q1b);
+      double b0b = 2.0 * (b0 * q2b - bDc * q1b);
+      rhohb += (1.0 - cs2) * A4b + cs2 * Bqb;
+      cs2b = rhoh * (Bqb - A4b) + Cqb;
+      bsqb += Bqb;
+      // bDc = (B^D + alpha b^0 u^D) / W
+      Bb[D] += bDcb * iW;
+      b0b += bDcb * alp * uD * iW;
+      a0b += bDcb * alp * b0 * iW;
+      Wb -= bDcb * bDc * iW;
+      // b^0 = W (B.v) / alpha
+      Wb += b0b * Bv * ia;
+      Bvb += b0b * W * ia;
+    }
+    // cs2 = Gamma p / rho h
+    gamb += cs2b * p / rhoh;
+    pb += cs2b * gam / rhoh;
+    rhohb -= cs2b * cs2 / rhoh;
+    // a0 = u^D = W (v^D - beta^D / alpha), a1 = -u^0 = -W / alpha
+    Wb += a0b * (v[D] - bD * ia) - a1b * ia;
+    vb[D] += a0b * W;
+  }
+  // conserved variables and fluxes (cons_of, flux_of)
+  {
+    const double alp = G.alp, as = alp * sg;
+    const double vt[3] = {alp * v[0] - G.beta[0], alp * v[1] - G.beta[1], alp * v[2] - G.beta[2]};
+    const double vtD = vt[D];
+    const double z = rhoh * W * W, Dn = rho * W, zb = z + B2;
+    double U[5];
+    U[0] = sg * Dn;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) U[1 + j] = sg * (zb * vl[j] - Bv * Bl[j]);
+    U[4] = sg * (zb - p - 0.5 * (B2 * iW2 + Bv * Bv) - Dn);
+    const double ptot = p + 0.5 * bsq, BD = B[D], m1 = BD * iW2, m2 = Bv * BD;
+    double Ubar[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) Ubar[q] = Ub[q];
+    double vtb[3] = {0.0, 0.0, 0.0}, ptotb = 0.0, m1b = 0.0, m2b = 0.0;
+    // F0 = U0 vt^D, F_{1+j} = U_{1+j} vt^D - as (B_j m1 + v_j m2) (+ as ptot for j = D),
+    // F4 = U4 vt^D + as (ptot v^D - m2)
+    Ubar[0] += Fb[0] * vtD;
+    vtb[D] += Fb[0] * U[0];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Ubar[1 + j] += Fb[1 + j] * vtD;
+      vtb[D] += Fb[1 + j] * U[1 + j];
+      Blb[j] -= as * m1 * Fb[1 + j];
+      m1b -= as * Bl[j] * Fb[1 + j];
+      vlb[j] -= as * m2 * Fb[1 + j];
+      m2b -= as * vl[j] * Fb[1 + j];
+    }
+    ptotb += as * Fb[1 + D];
+    Ubar[4] += Fb[4] * vtD;
+    vtb[D] += Fb[4] * U[4];
+    ptotb += as * v[D] * Fb[4];
+    vb[D] += as * ptot * Fb[4];
+    m2b -= as * Fb[4];
+    // induction: F5 = Bt1 vt^D - BtD vt^t1, F6 = Bt2 vt^D - BtD vt^t2, U5 = Bt1, U6 = Bt2
+    const double Bt1 = sg * B[t1], Bt2 = sg * B[t2], BtD = sg * BD;
+    const double Bt1b = Fb[5] * vtD + Ubar[5], Bt2b = Fb[6] * vtD + Ubar[6];
+    const double BtDb = -(Fb[5] * vt[t1] + Fb[6] * vt[t2]);
+    vtb[D] += Fb[5] * Bt1 + Fb[6] * Bt2;
+    vtb[t1] -= Fb[5] * BtD;
+    vtb[t2] -= Fb[6] * BtD;
+    Bb[t1] += sg * Bt1b;
+    Bb[t2] += sg * Bt2b;
+    Bb[D] += sg * BtDb + iW2 * m1b + Bv * m2b;
+    iW2b += BD * m1b;
+    Bvb += BD * m2b;
+    pb += ptotb;
+    bsqb += 0.5 * ptotb;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) vb[i] += alp * vtb[i];
+    // U0 = sg D, U_{1+j} = sg (zb v_j - (B.v) B_j), U4 = sg (zb - p - (B^2/W^2 + (B.v)^2) / 2 - D)
+    const double Dnb = sg * (Ubar[0] - Ubar[4]);
+    double zbb = sg * Ubar[4];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      zbb += sg * Ubar[1 + j] * vl[j];
+      vlb[j] += sg * zb * Ubar[1 + j];
+      Bvb -= sg * Ubar[1 + j] * Bl[j];
+      Blb[j] -= sg * Bv * Ubar[1 + j];
+    }
+    pb -= sg * Ubar[4];
+    B2b += zbb - 0.5 * sg * iW2 * Ubar[4];
+    iW2b -= 0.5 * sg * B2 * Ubar[4];
+    Bvb -= sg * Bv * Ubar[4];
+    // zb = rho h W^2 + B^2, D = rho W
+    rhohb += W * W * zbb;
+    Wb += 2.0 * rhoh * W * zbb + rho * Dnb;
+    rhob += W * Dnb;
+  }
+  // back through state_make
+  double gfacb = p * rhohb;
+  rhob += rhohb;
+  pb += gfac * rhohb;
+  B2b += iW2 * bsqb;
+  iW2b += B2 * bsqb;
+  Bvb += 2.0 * Bv * bsqb;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Bb[i] += vl[i] * Bvb + Bl[i] * B2b;
+    vlb[i] += B[i] * Bvb;
+    Blb[i] += B[i] * B2b;
+  }
+  double t[3];
+  lower(G.g, Blb, t);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Bb[i] += t[i];
+  iW2b -= 0.5 * W * W * W * Wb;
+  // iW2 = 1 - v.vl
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    vb[i] -= vl[i] * iW2b;
+    vlb[i] -= v[i] * iW2b;
+  }
+  lower(G.g, vlb, t);
+  Xb[0] = rhob;
+  Xb[1] = pb;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Xb[2 + i] = vb[i] + t[i];
+  Xb[5] = Bb[t1] * is;
+  Xb[6] = Bb[t2] * is;
+  Bnb = Bb[D] * is;
+  const double gm1 = gam - 1.0;
+  gb = gamb - gfacb / (gm1 * gm1);
+}
+
 // ---------------------------------------------------------------------------------------
 // Reconstruction (Sec. 3.3) at the face between cells i-1 and i from a[0..5] = a_{i-3..i+2}:
 // L = right-face value of cell i-1, R = left-face value of cell i.
@@ -352,18 +582,65 @@ DEV T mc_slope(T am, T a0, T ap) {
 
 // PPM cell parabola limited per Colella-Woodward; returns (left, right) face values of
 // the cell with neighbour face values fl (c-1/2) and fr (c+1/2).
+// The limiter's cases: local extremum (flat), or the parabola overshooting on the left or the right.
+DEV void ppm_cases(double ac, double fl, double fr, bool& flat, bool& over_l, bool& over_r) {
+  flat = (fr - ac) * (ac - fl) <= 0.0;
+  const double dd = fr - fl;
+  const double a6 = dd * (ac - 0.5 * (fl + fr));
+  const double d2 = dd * dd * (1.0 / 6.0);
+  over_l = a6 > d2;
+  over_r = !over_l && -d2 > a6;
+}
+
 template <class T>
 DEV void ppm_limit(T ac, T& fl, T& fr) {
   // branch-free form of: local extremum -> flat; else steepen the side the parabola overshoots
-  const bool flat = val(fr - ac) * val(ac - fl) <= 0.0;
-  T dd = fr - fl;
-  T a6 = dd * (ac - 0.5 * (fl + fr));
-  T d2 = dd * dd * (1.0 / 6.0);
-  const bool over_l = a6 > d2;
-  const bool over_r = !over_l && -d2 > a6;
+  bool flat, over_l, over_r;
+  ppm_cases(val(ac), val(fl), val(fr), flat, over_l, over_r);
   T nl = 3.0 * ac - 2.0 * fr, nr = 3.0 * ac - 2.0 * fl;
   fl = flat ? ac : (over_l ? nl : fl);
   fr = flat ? ac : (over_r ? nr : fr);
+}
+
+// Transposes of the reconstructions' active branches (the adjoint's reverse sweep): each adds
+// xb times the derivative of the face value with respect to each stencil value into ab.
+// MC slope: the centred difference, twice the smaller one-sided difference, or zero at an extremum.
+DEV void mc_slope_vjp(double am, double a0, double ap, double sb, double& gm, double& g0, double& gp) {
+  const double dl = a0 - am, dr = ap - a0, dc = 0.5 * (ap - am);
+  if (!(dl * dr > 0.0)) return;
+  const double adl = fabs(dl), adr = fabs(dr);
+  if (fabs(dc) <= 2.0 * fmin(adl, adr)) {
+    gp += 0.5 * sb;
+    gm -= 0.5 * sb;
+  } else if (adl <= adr) {
+    g0 += 2.0 * sb;
+    gm -= 2.0 * sb;
+  } else {
+    gp += 2.0 * sb;
+    g0 -= 2.0 * sb;
+  }
+}
+
+// PPM value at the right face of the middle cell of a[0..4].
+DEV void ppm_right_vjp(const double a[5], double xb, double ab[5]) {
+  const double sixth = 1.0 / 6.0;
+  const double s1 = mc_slope(a[0], a[1], a[2]), s2 = mc_slope(a[1], a[2], a[3]), s3 = mc_slope(a[2], a[3], a[4]);
+  const double fl = 0.5 * (a[1] + a[2]) - (s2 - s1) * sixth;
+  const double fr = 0.5 * (a[2] + a[3]) - (s3 - s2) * sixth;
+  bool flat, over_l, over_r;
+  ppm_cases(a[2], fl, fr, flat, over_l, over_r);
+  double flb = 0.0, frb = 0.0;
+  if (flat) ab[2] += xb;
+  else if (over_r) {
+    ab[2] += 3.0 * xb;
+    flb = -2.0 * xb;
+  } else frb = xb;
+  ab[1] += 0.5 * flb;
+  ab[2] += 0.5 * (flb + frb);
+  ab[3] += 0.5 * frb;
+  mc_slope_vjp(a[0], a[1], a[2], flb * sixth, ab[0], ab[1], ab[2]);
+  mc_slope_vjp(a[1], a[2], a[3], (frb - flb) * sixth, ab[1], ab[2], ab[3]);
+  mc_slope_vjp(a[2], a[3], a[4], -frb * sixth, ab[2], ab[3], ab[4]);
 }
 
 // WENO-Z (Borges et al. 2008) value at the right face of the middle cell of (m2..p2).
@@ -387,6 +664,33 @@ DEV T wenoz_face(T m2, T m1, T c0, T p1, T p2, double eps, double q) {
   T q0 = (2.0 * m2 - 7.0 * m1 + 11.0 * c0), q1 = (-m1 + 5.0 * c0 + 2.0 * p1), q2 = (2.0 * c0 + 5.0 * p1 - p2);
   return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0 * (w0 + w1 + w2));
 }
+
+// A linear form sum_q c_q a_q over a 5-point stencil, with its value: the piecewise-linear
+// reconstructions evaluated on it (selections follow the value) give their gradient exactly.
+struct Lin5 {
+  double v, c[5];
+  DEV Lin5() = default;
+  explicit DEV Lin5(double x) : v(x), c{0.0, 0.0, 0.0, 0.0, 0.0} {}
+};
+DEV double val(const Lin5& x) { return x.v; }
+DEV Lin5 operator+(Lin5 a, const Lin5& b) {
+  a.v += b.v;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) a.c[q] += b.c[q];
+  return a;
+}
+DEV Lin5 operator*(double s, Lin5 a) {
+  a.v *= s;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) a.c[q] *= s;
+  return a;
+}
+DEV Lin5 operator*(Lin5 a, double s) { return s * a; }
+DEV Lin5 operator-(const Lin5& a) { return -1.0 * a; }
+DEV Lin5 operator-(const Lin5& a, const Lin5& b) { return a + (-1.0 * b); }
+DEV Lin5 fabs(const Lin5& a) { return a.v < 0.0 ? -a : a; }
+DEV Lin5 fmin(const Lin5& a, const Lin5& b) { return a.v <= b.v ? a : b; }
+DEV Lin5 copysign(const Lin5& m, const Lin5& s) { return (::signbit(m.v) != ::signbit(s.v)) ? -m : m; }
 
 // MP5 (Suresh & Huynh 1997; cited in Sec. 3.3) value at the right face of the middle cell of
 // (m2..p2): the fifth-order interpolant, or, when it leaves the monotonicity-preserving range
