@@ -583,6 +583,25 @@ DEV double src_curv(const SrcW& s, const double K[6]) {
   return se;
 }
 
+// Value rounds of the ten metric components at the tile's centres, two per round, round r+1's
+// vertex tiles fetched during round r.  Every thread of the block must call it; the caller's
+// previous LDS readers must be done (a fresh block, or a barrier since).
+DEV void metric_values10(const GD& g, const double* metric, const TileIdx& x, double m[10], TileLDS2& S2) {
+  double pre[2][NFETCH];
+  tile_fetch(metric, x, pre[0]);
+  tile_fetch(metric + g.N, x, pre[1]);
+#pragma unroll
+  for (int c = 0; c < 10; c += 2) {
+    // the previous pair's passes no longer read S2.v (three barriers ago)
+    tile_store2(x, pre, S2);
+    if (c < 8) {
+      tile_fetch(metric + (c + 2) * g.N, x, pre[0]);
+      tile_fetch(metric + (c + 3) * g.N, x, pre[1]);
+    }
+    tile_value2(S2, x, m[c], m[c + 1]);
+  }
+}
+
 // Value rounds of the ten metric and six curvature components at the tile's centres, two
 // components per round (one set of barriers per pair), round r+1's vertex tiles fetched during
 // round r.  Returns with the first metric component's tile fetched again into pre (the first
@@ -686,6 +705,40 @@ DEV void src_deriv_rounds(const GD& g, const double* metric, const TileIdx& x, b
   }
 }
 
+// Derivative rounds of the ten metric components, two per round, contracted with a cotangent:
+// E[c] = sum_j r[j] d_j m_c at the tile's centres (derivatives scaled by 1/dx_j), dal[j] = d_j alpha,
+// and flat = every derivative is zero.  pre0: metric component 0's vertex tile, already fetched.
+// Every thread of the block must call it.
+DEV void metric_derivs_dot(const GD& g, const double* metric, const TileIdx& x, const double pre0[NFETCH],
+                           const double r[3], double E[10], double dal[3], bool& flat, TileLDS2D& SD) {
+  double pp[2][NFETCH];
+#pragma unroll
+  for (int q = 0; q < NFETCH; ++q) pp[0][q] = pre0[q];
+  tile_fetch(metric + g.N, x, pp[1]);
+  flat = true;
+#pragma unroll 1
+  for (int c = 0; c < 10; c += 2) {
+    __syncthreads();
+    tile_store2d(x, pp, SD);
+    if (c < 8) {
+      tile_fetch(metric + (c + 2) * g.N, x, pp[0]);
+      tile_fetch(metric + (c + 3) * g.N, x, pp[1]);
+    }
+    double d0[3], d1[3], xf[2][2];
+    tile_derivs2(SD, x, g, d0, d1, xf);
+    const double e0 = r[0] * d0[0] + r[1] * d0[1] + r[2] * d0[2];
+    const double e1 = r[0] * d1[0] + r[1] * d1[1] + r[2] * d1[2];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) E[q] = c == q ? e0 : (c + 1 == q ? e1 : E[q]);
+    if (c == 0) {
+      dal[0] = d0[0];
+      dal[1] = d0[1];
+      dal[2] = d0[2];
+    }
+    flat = flat && d0[0] == 0.0 && d0[1] == 0.0 && d0[2] == 0.0 && d1[0] == 0.0 && d1[1] == 0.0 && d1[2] == 0.0;
+  }
+}
+
 // =======================================================================================
 // prim -> cons on owned cells.
 DEV void prim2con_body(const GD& g, double gam, const double* __restrict__ metric, const double* __restrict__ A,
@@ -750,23 +803,10 @@ DEV void c2p_body(const GD& g, const C2PParams& P, const C2PArgs& a, TileLDS& S,
   unsigned long long* __restrict__ stats = a.stats;
   const TileCell t = tile_cell(g, tile);
   const TileIdx x = tile_index(g, t);
-  double m[10], pre[2][NFETCH];
+  double m[10];
   double K[6], pre0[NFETCH];  // SRC only
   TileLDS2& S2 = *reinterpret_cast<TileLDS2*>(&S);
-  {
-    tile_fetch(metric, x, pre[0]);
-    tile_fetch(metric + g.N, x, pre[1]);
-#pragma unroll
-    for (int c = 0; c < 10; c += 2) {
-      // the previous pair's passes no longer read S2.v (three barriers ago)
-      tile_store2(x, pre, S2);
-      if (c < 8) {
-        tile_fetch(metric + (c + 2) * g.N, x, pre[0]);
-        tile_fetch(metric + (c + 3) * g.N, x, pre[1]);
-      }
-      tile_value2(S2, x, m[c], m[c + 1]);
-    }
-  }
+  metric_values10(g, metric, x, m, S2);
   uint32_t fl = 0;
   int iters = 0;
   const int id = t.valid ? at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz) : 0;
@@ -2543,8 +2583,9 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
   if (__lane_id() == 0 && w != 0.0) atomicAdd(fa.gbar + (blockIdx.x & (GSLOTS - 1)), w);
 }
 
-// Geometric sources transposed, one owned cell per thread (direct 64-point interpolation of
-// the metric: the adjoint is not on the timed path).
+// Geometric sources transposed, one owned cell per thread, over the cell tiles of the forward
+// kernels: the metric's centre values and derivatives and the curvature come from the same
+// LDS-staged separable passes (metric_values10 / value_rounds16, metric_derivs30).
 struct CellAdjArgs {
   const double* metric;
   const double* curv;
@@ -2557,29 +2598,12 @@ struct CellAdjArgs {
   double gam;
 };
 
-DEV void centre_val_der_direct(const double* __restrict__ p, int sy, int sz, double& v, double d[3]) {
-  double vz[4], dyz[4], dxz[4];
-  for (int c = 0; c < 4; ++c) {
-    double vx[4], ddx[4];
-    for (int b = 0; b < 4; ++b) {
-      const double* r = p + b * sy + c * sz;
-      vx[b] = lag(r[0], r[1], r[2], r[3]);
-      ddx[b] = dlag(r[0], r[1], r[2], r[3]);
-    }
-    vz[c] = lag(vx[0], vx[1], vx[2], vx[3]);
-    dyz[c] = dlag(vx[0], vx[1], vx[2], vx[3]);
-    dxz[c] = lag(ddx[0], ddx[1], ddx[2], ddx[3]);
-  }
-  v = lag(vz[0], vz[1], vz[2], vz[3]);
-  d[2] = dlag(vz[0], vz[1], vz[2], vz[3]);
-  d[1] = lag(dyz[0], dyz[1], dyz[2], dyz[3]);
-  d[0] = lag(dxz[0], dxz[1], dxz[2], dxz[3]);
-}
-
-// Densitized sources alpha sqrt(gamma) (1/2 T^{mu nu} d_j g_{mu nu}, energy term) of one
-// state, in dual numbers (same formulas as the forward cell kernel).
-DEV void sources_dual(const Geo& G, const double dm[3][10], const double K[6], const Dual pr[5], const Dual Bt[3],
-                      Dual gam, Dual src[5]) {
+// sum_k rb_k src_k of the densitized sources alpha sqrt(gamma) (1/2 T^{mu nu} d_j g_{mu nu}, energy
+// term) of one state, in dual numbers (the formulas of the forward cell kernel).  The momentum source
+// along j is linear in the metric derivatives along j, so its contraction with rb_{1+j} is the
+// momentum formula evaluated once on E_c = sum_j rb_{1+j} d_j m_c; dal = d_j alpha, K the curvature.
+DEV Dual sources_dot_dual(const Geo& G, const double E[10], const double dal[3], const double K[6], double rb4,
+                          const Dual pr[5], const Dual Bt[3], Dual gam) {
   StateT<Dual> St;
   state_make(G, pr, Bt, gam, St, gam / (gam - 1.0));
   double ia = 1.0 / G.alp, ia2 = ia * ia;
@@ -2598,83 +2622,64 @@ DEV void sources_dual(const Geo& G, const double dm[3][10], const double K[6], c
   double bl[3];
   lower(G.g, G.beta, bl);
   double as = G.alp * G.sqrtg;
-  src[0] = Dual(0.0);
-  for (int jj = 0; jj < 3; ++jj) {
-    const double* dg = &dm[jj][4];
-    double dal = dm[jj][0], db[3] = {dm[jj][1], dm[jj][2], dm[jj][3]};
-    double bbdg = 0.0;
-    Dual Tdg(0.0);
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        bbdg += G.beta[a] * G.beta[b] * dg[sym(a, b)];
-        Tdg += Tk[sym(a, b)] * dg[sym(a, b)];
-      }
-    double d00 = -2.0 * G.alp * dal + bbdg + 2.0 * (bl[0] * db[0] + bl[1] * db[1] + bl[2] * db[2]);
-    Dual s0k(0.0);
-    for (int a = 0; a < 3; ++a) {
-      double d0a = 0.0;
-      for (int b = 0; b < 3; ++b) d0a += G.beta[b] * dg[sym(a, b)] + G.g[sym(a, b)] * db[b];
-      s0k += T0[a] * d0a;
+  // momentum, contracted
+  const double* dg = &E[4];
+  const double dalE = E[0], db[3] = {E[1], E[2], E[3]};
+  double bbdg = 0.0;
+  Dual Tdg(0.0);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      bbdg += G.beta[a] * G.beta[b] * dg[sym(a, b)];
+      Tdg += Tk[sym(a, b)] * dg[sym(a, b)];
     }
-    src[1 + jj] = as * (0.5 * T00 * d00 + s0k + 0.5 * Tdg);
+  double d00 = -2.0 * G.alp * dalE + bbdg + 2.0 * (bl[0] * db[0] + bl[1] * db[1] + bl[2] * db[2]);
+  Dual s0k(0.0);
+  for (int a = 0; a < 3; ++a) {
+    double d0a = 0.0;
+    for (int b = 0; b < 3; ++b) d0a += G.beta[b] * dg[sym(a, b)] + G.g[sym(a, b)] * db[b];
+    s0k += T0[a] * d0a;
   }
-  double dal[3] = {dm[0][0], dm[1][0], dm[2][0]}, bK[3];
+  Dual mom = 0.5 * T00 * d00 + s0k + 0.5 * Tdg;
+  // energy
+  double bK[3];
   for (int a = 0; a < 3; ++a) bK[a] = G.beta[0] * K[sym(a, 0)] + G.beta[1] * K[sym(a, 1)] + G.beta[2] * K[sym(a, 2)];
   Dual se = T00 * (G.beta[0] * bK[0] + G.beta[1] * bK[1] + G.beta[2] * bK[2] -
                    (G.beta[0] * dal[0] + G.beta[1] * dal[1] + G.beta[2] * dal[2]));
   for (int a = 0; a < 3; ++a) se += T0[a] * (2.0 * bK[a] - dal[a]);
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) se += Tk[sym(a, b)] * K[sym(a, b)];
-  src[4] = as * se;
+  return as * (mom + rb4 * se);
 }
 
-DEV void cell_adj_body(const GD& g, const CellAdjArgs& ca, unsigned tile) {
-  int i, j, k;
-  bool valid = box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k);
+DEV void cell_adj_body(const GD& g, const CellAdjArgs& ca, CellLDS& S, unsigned tile) {
+  const TileCell t = tile_cell(g, tile);
+  const TileIdx x = tile_index(g, t);
+  const int id = t.valid ? at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz) : 0;
+  double rb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (t.valid)
+    for (int c = 0; c < 5; ++c) rb[c] = ca.rbar[(size_t)c * g.N + id];
+  double m[10], K[6], pre[NFETCH], E[10], dal[3];
+  bool flat;
+  value_rounds16(g, ca.metric, ca.curv, x, m, K, pre, S.t2);
+  metric_derivs_dot(g, ca.metric, x, pre, rb + 1, E, dal, flat, S.t2d);
+  for (int c = 0; c < 6; ++c) flat = flat && K[c] == 0.0;
   double gsum = 0.0;
-  if (valid) {
-    const int id = at(g, i, j, k);
-    double rb[5];
-    bool any = false;
-    for (int c = 0; c < 5; ++c) {
-      rb[c] = ca.rbar[(size_t)c * g.N + id];
-      any = any || rb[c] != 0.0;
-    }
-    if (any) {
-      const int vb = id - 1 - g.sy - g.sz;
-      double m[10], dm[3][10], K[6];
-      bool flat = true;
-      for (int c = 0; c < 10; ++c) {
-        double d[3];
-        centre_val_der_direct(ca.metric + c * g.N + vb, g.sy, g.sz, m[c], d);
-        for (int a = 0; a < 3; ++a) {
-          dm[a][c] = d[a] * g.idx[a];
-          flat = flat && dm[a][c] == 0.0;
-        }
-      }
-      for (int c = 0; c < 6; ++c) {
-        K[c] = centre_val(ca.curv + c * g.N + vb, g.sy, g.sz);
-        flat = flat && K[c] == 0.0;
-      }
-      if (!flat) {  // a metric with no derivatives and no curvature has no sources
-        Geo G;
-        geo_from(m, G);
-        double pr[5], Bt[3];
-        for (int c = 0; c < 5; ++c) pr[c] = ca.prim[c * g.N + id];
-        for (int c = 0; c < 3; ++c) Bt[c] = ca.bc[c * g.N + id];
-        for (int dir = 0; dir < 9; ++dir) {
-          Dual pd[5], bd[3];
-          for (int c = 0; c < 5; ++c) pd[c] = Dual(pr[c], dir == c ? 1.0 : 0.0);
-          for (int c = 0; c < 3; ++c) bd[c] = Dual(Bt[c], dir == 5 + c ? 1.0 : 0.0);
-          Dual src[5];
-          sources_dual(G, dm, K, pd, bd, Dual(ca.gam, dir == 8 ? 1.0 : 0.0), src);
-          double s = 0.0;
-          for (int c = 0; c < 5; ++c) s += rb[c] * src[c].d;
-          if (dir < 5) ca.pbar[(size_t)dir * g.N + id] += s;
-          else if (dir < 8) ca.bcbar[(size_t)(dir - 5) * g.N + id] += s;
-          else gsum = s;
-        }
-      }
+  // a metric with no derivatives and no curvature has no sources
+  if (t.valid && !flat && (rb[1] != 0.0 || rb[2] != 0.0 || rb[3] != 0.0 || rb[4] != 0.0)) {
+    Geo G;
+    geo_from(m, G);
+    double pr[5], Bt[3];
+    for (int c = 0; c < 5; ++c) pr[c] = ca.prim[c * g.N + id];
+    for (int c = 0; c < 3; ++c) Bt[c] = ca.bc[c * g.N + id];
+#pragma unroll 1
+    for (int dir = 0; dir < 9; ++dir) {
+      Dual pd[5], bd[3];
+      for (int c = 0; c < 5; ++c) pd[c] = Dual(pr[c], dir == c ? 1.0 : 0.0);
+      for (int c = 0; c < 3; ++c) bd[c] = Dual(Bt[c], dir == 5 + c ? 1.0 : 0.0);
+      const double s = sources_dot_dual(G, E, dal, K, rb[4], pd, bd, Dual(ca.gam, dir == 8 ? 1.0 : 0.0)).d;
+      if (dir < 5) ca.pbar[(size_t)dir * g.N + id] += s;
+      else if (dir < 8) ca.bcbar[(size_t)(dir - 5) * g.N + id] += s;
+      else gsum = s;
     }
   }
   double w = gsum;
@@ -2801,12 +2806,14 @@ struct C2PAdjArgs {
   int mode;  // 0: c2p (solve with J_prim^T), 1: prim -> cons (multiply by J^T)
 };
 
-DEV void c2p_adj_body(const GD& g, const C2PAdjArgs& ca, unsigned tile) {
-  int i, j, k;
-  bool valid = box_at<64, 4>(g.n, tile, threadIdx.x, i, j, k);
+DEV void c2p_adj_body(const GD& g, const C2PAdjArgs& ca, TileLDS2& S2, unsigned tile) {
+  const TileCell t = tile_cell(g, tile);
+  const TileIdx x = tile_index(g, t);
+  double m[10];
+  metric_values10(g, ca.metric, x, m, S2);
   double gsum = 0.0;
-  if (valid) {
-    const int id = at(g, i, j, k);
+  if (t.valid) {
+    const int id = at(g, t.i0 + t.cx, t.j0 + t.cy, t.k0 + t.cz);
     double pb[5];
     bool any = false;
     for (int c = 0; c < 5; ++c) {
@@ -2815,8 +2822,6 @@ DEV void c2p_adj_body(const GD& g, const C2PAdjArgs& ca, unsigned tile) {
     }
     bool atmo = ca.mode == 0 && ca.flags && (ca.flags[id] & 4u);
     if (any && !atmo) {
-      double m[10];
-      centre_metric(ca.metric, g.N, id - 1 - g.sy - g.sz, g.sy, g.sz, m);
       Geo G;
       geo_from(m, G);
       double pr[5], Bt[3];
@@ -2842,23 +2847,32 @@ DEV void c2p_adj_body(const GD& g, const C2PAdjArgs& ca, unsigned tile) {
           for (int c = 0; c < 5; ++c) M[r][c] = J[c][r];
           M[r][5] = pb[r];
         }
+        // partial pivoting by row swaps with fixed indices (the first largest |M[r][c]|, r >= c, ends
+        // in row c), so that M stays in registers
+#pragma unroll
         for (int c = 0; c < 5; ++c) {
-          int piv = c;
-          for (int r = c + 1; r < 5; ++r)
-            if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
-          for (int q = 0; q < 6; ++q) {
-            double t = M[c][q];
-            M[c][q] = M[piv][q];
-            M[piv][q] = t;
-          }
-          double inv = 1.0 / M[c][c];
+#pragma unroll
           for (int r = c + 1; r < 5; ++r) {
-            double f = M[r][c] * inv;
+            const bool sw = fabs(M[r][c]) > fabs(M[c][c]);
+#pragma unroll
+            for (int q = c; q < 6; ++q) {
+              const double a = M[c][q], b = M[r][q];
+              M[c][q] = sw ? b : a;
+              M[r][q] = sw ? a : b;
+            }
+          }
+          const double inv = 1.0 / M[c][c];
+#pragma unroll
+          for (int r = c + 1; r < 5; ++r) {
+            const double f = M[r][c] * inv;
+#pragma unroll
             for (int q = c; q < 6; ++q) M[r][q] -= f * M[c][q];
           }
         }
+#pragma unroll
         for (int r = 4; r >= 0; --r) {
           double s = M[r][5];
+#pragma unroll
           for (int q = r + 1; q < 5; ++q) s -= M[r][q] * lam[q];
           lam[r] = s / M[r][r];
         }
@@ -2959,13 +2973,19 @@ template <int D, int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_face_adj(GD g, FaceAdjArgs fa) {
   face_adj_body<D, R>(g, fa, my_tile());
 }
-__global__ __launch_bounds__(256) void k_cell_adj(GD g, CellAdjArgs ca) { cell_adj_body(g, ca, my_tile()); }
+__global__ __launch_bounds__(256) void k_cell_adj(GD g, CellAdjArgs ca) {
+  __shared__ CellLDS S;
+  cell_adj_body(g, ca, S, my_tile());
+}
 __global__ __launch_bounds__(256) void k_vertex_adj(GD g, VertexAdjArgs va) { vertex_adj_body(g, va, my_tile()); }
 __global__ __launch_bounds__(256) void k_edge_adj(GD g, const double* avbar, double* abar) {
   edge_adj_body(g, avbar, abar, my_tile());
 }
 __global__ __launch_bounds__(256) void k_fillT(GD g, FillTArgs a) { fillT_body(g, a, blockIdx.x); }
-__global__ __launch_bounds__(256) void k_c2p_adj(GD g, C2PAdjArgs ca) { c2p_adj_body(g, ca, my_tile()); }
+__global__ __launch_bounds__(256) void k_c2p_adj(GD g, C2PAdjArgs ca) {
+  __shared__ TileLDS2 S2;
+  c2p_adj_body(g, ca, S2, my_tile());
+}
 __global__ __launch_bounds__(64) void k_gslots(const double* slots, double* gamma_bar) { gslots_body(slots, gamma_bar); }
 __global__ __launch_bounds__(256) void k_bcface_adj(GD g, const double* bcbar, double* bfbar) {
   bcface_adj_body(g, bcbar, bfbar, my_tile());
@@ -3994,8 +4014,10 @@ int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
   if (rc) return rc;
   CellAdjArgs ca{metric, curv, ws + AW_PRIM * g.N, ws + AW_BC * g.N, rhs_bar, ws + AW_PBAR * g.N,
                  ws + AW_BCBAR * g.N, slots, p->gamma};
-  nb = tiles_for(PH_RK, g);
-  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_cell_adj, dim3(nb), dim3(256), 0, s, g, ca); }))) return rc;
+  if ((rc = timed(KT_ADJ, s, [&] {
+         hipLaunchKernelGGL(k_cell_adj, dim3(tiles_for(PH_CELL, g)), dim3(256), 0, s, g, ca);
+       })))
+    return rc;
   VertexAdjArgs va{metric, rhs_bar, ws + AW_PSIBAR * g.N, ws + AW_AVBAR * g.N, p->xi / dt_max, p->gauge};
   nb = box_blocks<64, 4>(ev);
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_vertex_adj, dim3(nb), dim3(256), 0, s, g, va); }))) return rc;
@@ -4008,8 +4030,10 @@ int asterx_rhs_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
   if ((rc = adj_fillT(g, ws + AW_PBAR * g.N, 5, s))) return rc;
   C2PAdjArgs cpa{metric, ws + AW_PRIM * g.N, ws + AW_BC * g.N, flags, ws + AW_PBAR * g.N, cons_bar,
                  ws + AW_BCBAR * g.N, slots, p->gamma, 0};
-  nb = tiles_for(PH_RK, g);
-  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_c2p_adj, dim3(nb), dim3(256), 0, s, g, cpa); }))) return rc;
+  if ((rc = timed(KT_ADJ, s, [&] {
+         hipLaunchKernelGGL(k_c2p_adj, dim3(tiles_for(PH_C2P, g)), dim3(256), 0, s, g, cpa);
+       })))
+    return rc;
   if ((rc = adj_epilogue(g, ws, A_bar, psi_bar, s))) return rc;
   return gslots_finish(slots, gamma_bar, s);
 }
@@ -4033,7 +4057,10 @@ int asterx_c2p_adjoint(const asterx_grid* gr, const asterx_params* p, const doub
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_accum, dim3(no), dim3(256), 0, s, g, cp); }))) return rc;
   C2PAdjArgs cpa{metric, ws + AW_PRIM * g.N, ws + AW_BC * g.N, flags, ws + AW_PBAR * g.N, cons_bar,
                  ws + AW_BCBAR * g.N, slots, p->gamma, 0};
-  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_c2p_adj, dim3(no), dim3(256), 0, s, g, cpa); }))) return rc;
+  if ((rc = timed(KT_ADJ, s, [&] {
+         hipLaunchKernelGGL(k_c2p_adj, dim3(tiles_for(PH_C2P, g)), dim3(256), 0, s, g, cpa);
+       })))
+    return rc;
   if ((rc = adj_epilogue(g, ws, A_bar, nullptr, s))) return rc;
   return gslots_finish(slots, gamma_bar, s);
 }
@@ -4056,7 +4083,10 @@ int asterx_prim2con_adjoint(const asterx_grid* gr, const asterx_params* p, const
   if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_accum, dim3(no), dim3(256), 0, s, g, cp); }))) return rc;
   C2PAdjArgs cpa{metric, prim, ws + AW_BC * g.N, nullptr, ws + AW_PBAR * g.N, prim_bar, ws + AW_BCBAR * g.N,
                  slots, p->gamma, 1};
-  if ((rc = timed(KT_ADJ, s, [&] { hipLaunchKernelGGL(k_c2p_adj, dim3(no), dim3(256), 0, s, g, cpa); }))) return rc;
+  if ((rc = timed(KT_ADJ, s, [&] {
+         hipLaunchKernelGGL(k_c2p_adj, dim3(tiles_for(PH_C2P, g)), dim3(256), 0, s, g, cpa);
+       })))
+    return rc;
   if ((rc = adj_epilogue(g, ws, A_bar, nullptr, s))) return rc;
   return gslots_finish(slots, gamma_bar, s);
 }
