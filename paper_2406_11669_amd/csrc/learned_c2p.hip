@@ -7,8 +7,9 @@
 // solver and the atmosphere follow as usual, so the network never decides the result.
 //
 // Arithmetic of the network: weights, inputs and hidden activations are rounded to bfloat16
-// (round to nearest even) and contracted on the matrix cores with v_mfma_f32_16x16x16_bf16
-// (FP32 accumulate); biases, activations and the loss are FP32.  ReLU rather than tanh: the
+// (round to nearest even) and contracted on the matrix cores (FP32 accumulate): the forward
+// pass's 64-deep layers with v_mfma_f32_16x16x32_bf16, the 8-deep input layer and the backward
+// pass with v_mfma_f32_16x16x16_bf16; biases, activations and the loss are FP32.  ReLU rather than tanh: the
 // network runs inside the recovery, where a tanh (exponential and reciprocal, quarter-rate) per
 // hidden unit cost more than the Newton iterations the guess saves.  One wavefront evaluates 64
 // samples: every layer is computed transposed (H^T = W X^T), so that the accumulator layout

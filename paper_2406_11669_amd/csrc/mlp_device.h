@@ -32,6 +32,27 @@ DEV float act(float x) {  // ReLU: one instruction per activation, where tanh wo
 
 DEV f4 mfma(bf4 a, bf4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
 
+// Two 16-deep K tiles in one v_mfma_f32_16x16x32_bf16 (twice the K of the 16-deep instruction per
+// issue on gfx950).  Lane group g supplies K slots 8g..8g+7; taking slots 0-3 from tile (a0, b0) and
+// 4-7 from tile (a1, b1) -- the same logical k for A and B in every slot -- leaves the contraction
+// unchanged and lets a layer's 16 x 16 accumulator tiles feed the next layer as they are.
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+DEV f4 mfma32(s8 a, s8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+// A operand of mfma32: row r of W (row length ld), K tiles kt and kt + 1, this lane group's 4 + 4.
+DEV s8 ld8(const float* __restrict__ P, int o, int kt, int lg, bool on) {
+  s8 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r[i] = on ? bf16(P[o + kt * 16 + 4 * lg + i]) : (short)0;
+    r[4 + i] = on ? bf16(P[o + (kt + 1) * 16 + 4 * lg + i]) : (short)0;
+  }
+  return r;
+}
+
 DEV bf4 ld4(const float* __restrict__ P, int o, bool on) {
   bf4 r;
 #pragma unroll
@@ -93,7 +114,9 @@ DEV void mlp_fwd(const float* __restrict__ P, const float (*feat)[NI], f4 y[4], 
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) h[mt][nt] = mfma(a, x1[nt], bias);
   }
-  bf4 x2[4][4];
+  // activations in the packed operand layout of mfma32: x2[q][nt] holds K tiles 2q (slots 0-3) and
+  // 2q + 1 (slots 4-7), i.e. the accumulator tiles mt = 2q, 2q + 1 of the layer before
+  s8 x2[2][4];
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -102,7 +125,7 @@ DEV void mlp_fwd(const float* __restrict__ P, const float (*feat)[NI], f4 y[4], 
       for (int i = 0; i < 4; ++i) {
         float t = act(h[mt][nt][i]);
         if (TRAIN) A->t1[mt][nt][i] = t;
-        x2[mt][nt][i] = bf16(t);
+        x2[mt >> 1][nt][4 * (mt & 1) + i] = bf16(t);
       }
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
@@ -112,13 +135,13 @@ DEV void mlp_fwd(const float* __restrict__ P, const float (*feat)[NI], f4 y[4], 
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) h[mt][nt] = bias;
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt) {
-      bf4 a = ld4(P, OW2 + (mt * 16 + lr) * NH + kt * 16 + 4 * lg, true);
+    for (int q = 0; q < 2; ++q) {
+      s8 a = ld8(P, OW2 + (mt * 16 + lr) * NH, 2 * q, lg, true);
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) h[mt][nt] = mfma(a, x2[kt][nt], h[mt][nt]);
+      for (int nt = 0; nt < 4; ++nt) h[mt][nt] = mfma32(a, x2[q][nt], h[mt][nt]);
     }
   }
-  bf4 x3[4][4];
+  s8 x3[2][4];
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -127,7 +150,7 @@ DEV void mlp_fwd(const float* __restrict__ P, const float (*feat)[NI], f4 y[4], 
       for (int i = 0; i < 4; ++i) {
         float t = act(h[mt][nt][i]);
         if (TRAIN) A->t2[mt][nt][i] = t;
-        x3[mt][nt][i] = bf16(t);
+        x3[mt >> 1][nt][4 * (mt & 1) + i] = bf16(t);
       }
   f4 b3;
 #pragma unroll
@@ -135,10 +158,10 @@ DEV void mlp_fwd(const float* __restrict__ P, const float (*feat)[NI], f4 y[4], 
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) y[nt] = b3;
 #pragma unroll
-  for (int kt = 0; kt < 4; ++kt) {
-    bf4 a = ld4(P, OW3 + lr * NH + kt * 16 + 4 * lg, lr < NO);
+  for (int q = 0; q < 2; ++q) {
+    s8 a = ld8(P, OW3 + lr * NH, 2 * q, lg, lr < NO);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) y[nt] = mfma(a, x3[kt][nt], y[nt]);
+    for (int nt = 0; nt < 4; ++nt) y[nt] = mfma32(a, x3[q][nt], y[nt]);
   }
   if (TRAIN) {
 #pragma unroll
@@ -146,10 +169,12 @@ DEV void mlp_fwd(const float* __restrict__ P, const float (*feat)[NI], f4 y[4], 
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        A->x2[mt][nt] = x2[mt][nt];
-        A->x3[mt][nt] = x3[mt][nt];
-      }
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          A->x2[mt][nt][i] = x2[mt >> 1][nt][4 * (mt & 1) + i];
+          A->x3[mt][nt][i] = x3[mt >> 1][nt][4 * (mt & 1) + i];
+        }
   }
 }
 
