@@ -8,9 +8,10 @@ captured HIP graph, with all inputs resident in HBM.
 
 Prints one JSON line: zone-updates/s per RK stage (interior cells x stages / wall time of the timed steps); the
 roofline of the dominant kernel and per-kernel figures of the face kernels, the recovery with sources and the
-divergence kernel (per-kernel HIP events recorded live on the launch stream); the whole-stage HBM and FP64 rooflines; the same block with the other
-reconstruction, batched patches against a per-patch loop and the learned recovery guess against the plain one
-(comparison keys); and the CPU oracle timed on the host (serial on a bounded sample, all cores on the full block).
+divergence kernel (per-kernel HIP events recorded live on the launch stream); the whole-stage HBM and FP64
+rooflines; the same block with the other reconstruction, batched patches against a per-patch loop, the learned
+recovery guess against the plain one and one adjoint gradient, forward and reverse (comparison keys); and the CPU
+oracle timed on the host (serial on a bounded sample, all cores on the full block).
 """
 import argparse
 import json
@@ -450,6 +451,31 @@ def extra_learned(torch, asterx, blk, steps, n_points=256, n_train=10_000_000, e
                          "unit": "zone-updates/s"}}
 
 
+def extra_adjoint(torch, W, reps=3):
+    """One gradient of the differentiation workload (64^3 periodic Riemann box, PPM, 20 RK2 steps, loss = the L2
+    norm of the final density) with respect to the initial primitives and Gamma: the forward pass with per-stage
+    checkpoints and the reverse pass timed apart, wall clock with the device synchronized (the last of reps runs;
+    the first one also initialises)."""
+    from paper_2406_11669_amd import adjoint as adj
+    w = W.periodic_riemann_box(seed=0, n=64, nsteps=20, v_amp=0.1)
+    runner = adj.Runner(w)
+    for _ in range(reps):
+        prim = torch.from_numpy(w.prim.copy()).cuda().requires_grad_(True)
+        gam = torch.tensor(w.params["gamma"], dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = adj.density_loss_run(runner, prim, gam, 20)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    del runner
+    torch.cuda.empty_cache()
+    return {"workload": "periodic_riemann64-ppm-rk2, 20 steps", "forward_ms": round(1e3 * (t1 - t0), 2),
+            "reverse_ms": round(1e3 * (t2 - t1), 2), "reverse_over_forward": round((t2 - t1) / (t1 - t0), 2)}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -543,6 +569,8 @@ def main():
         out["batched_vs_loop"] = extra_batched(torch, asterx, W)
         print("bench: learned initial guess against the plain recovery", file=sys.stderr, flush=True)
         out["learned_vs_plain"] = extra_learned(torch, asterx, blk, args.steps)
+        print("bench: adjoint gradient (forward with checkpoints, reverse pass)", file=sys.stderr, flush=True)
+        out["adjoint_gradient"] = extra_adjoint(torch, W)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle (serial on a %d^3 sample, all cores on the full block)" % args.cpu_n,
               file=sys.stderr, flush=True)
