@@ -2585,7 +2585,7 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
 
 // Geometric sources transposed, one owned cell per thread, over the cell tiles of the forward
 // kernels: the metric's centre values and derivatives and the curvature come from the same
-// LDS-staged separable passes (metric_values10 / value_rounds16, metric_derivs30).
+// LDS-staged separable passes (metric_values10 / value_rounds16, metric_derivs_dot).
 struct CellAdjArgs {
   const double* metric;
   const double* curv;
