@@ -239,8 +239,8 @@ def test_fused_stage_outputs_bitwise_equal_stored(ax, torch_mod, recon, rk, shap
     """asterx_c2p + asterx_rhs_rk (the right-hand side combined into the stage outputs by the cell and edge kernels)
     against asterx_rhs + asterx_rk_stage: bitwise equal states, primitives, reductions and c2p counters after 3
     steps.  asterx_c2p_src + asterx_rhs_rk_src (sources evaluated by the recovery kernel, whose larger body the
-    compiler contracts into fused multiply-adds differently) against the same: equal counters, states and
-    primitives within 1e-13 of their scales."""
+    compiler contracts into fused multiply-adds differently) against the same: equal counters, states, primitives
+    and the maximum characteristic speed within 1e-13 of their scales, the maximum of |div B| at round-off on both."""
     torch = torch_mod
     w = W.curved_block(seed=33, n=shape, recon=recon.split("+")[0], nsteps=3, rk=rk, ng=_ng(recon))
     _scheme(w, recon)
@@ -258,7 +258,11 @@ def test_fused_stage_outputs_bitwise_equal_stored(ax, torch_mod, recon, rk, shap
     assert torch.equal(a.stats, b.stats)
     assert_fields_close(_host(a.state), _host(b.state), 1e-13, w.layout.owned, STATE_NAMES)
     assert_fields_close(_host(a.prim), _host(b.prim), 1e-13, w.layout.owned, PRIM_NAMES)
-    assert np.allclose(_host(a.red), _host(b.red), rtol=1e-13, atol=1e-300)
+    # red[0], the maximum characteristic speed, to the states' tolerance; red[1], the maximum of |div B|, is zero in
+    # exact arithmetic (constrained transport), so each path's value is its own round-off: both at round-off level
+    ra, rb = _host(a.red), _host(b.red)
+    assert abs(ra[0] - rb[0]) <= 1e-13 * abs(rb[0]), (ra, rb)
+    assert ra[1] <= 1e-12 and rb[1] <= 1e-12, (ra, rb)
 
 
 def test_fused_stage_rejects_aliased_outputs(ax, torch_mod):

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2406_11669_amd import workloads as W
-from tests.parity import assert_fields_close, field_errors
+from tests.parity import assert_fields_close, cell_relative_errors, field_errors
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -221,6 +221,17 @@ def test_curved32_ten_rk4_steps(ax, orc, recon):
     e = assert_fields_close(_host(blk.state), state, 1e-10, w.layout.owned, STATE_NAMES)
     assert_fields_close(_host(blk.prim), prim, 1e-10, w.layout.owned, PRIM_NAMES)
     print("  max state error %.2e" % e.max(), flush=True)
+    _check_cell_relative(_host(blk.state), state, w.layout.owned)
+
+
+def _check_cell_relative(gpu, ref, owned):
+    """Per-cell relative errors beside the normalised ones: asserted for the conserved density and energy (bounded
+    away from zero in these workloads), printed for every field."""
+    cr = cell_relative_errors(gpu, ref, owned)
+    print("  per-cell relative (max, fraction of cells below 1e-6 of the field's max): " +
+          ", ".join("%s %.1e (%.0e)" % (n, r, x) for n, (r, x) in zip(STATE_NAMES, cr)), flush=True)
+    for f in (0, 4):
+        assert cr[f][1] == 0.0 and cr[f][0] <= 1e-10, (STATE_NAMES[f], cr[f])
 
 
 @pytest.mark.parametrize("recon", ["ppm", "wenoz"])
@@ -257,6 +268,7 @@ def test_full_size_curved128_rk4_step(ax, orc, recon):
     orc.run(L, w.params, w.metric, w.curv, state, prim, w.dt, 1, w.rk, w.bc_cell, w.bc_A)
     e = assert_fields_close(_host(step.state), state, 1e-10, L.owned, STATE_NAMES)
     print("  first-stage and step errors ok; max state error %.2e" % e.max(), flush=True)
+    _check_cell_relative(_host(step.state), state, L.owned)
 
 
 # ---- batched patches in the stated mix ----------------------------------------------------------------------
