@@ -234,6 +234,26 @@ def _check_cell_relative(gpu, ref, owned):
         assert cr[f][1] == 0.0 and cr[f][0] <= 1e-10, (STATE_NAMES[f], cr[f])
 
 
+@pytest.mark.parametrize("recon", ["ppm", "mp5"])
+def test_unmagnetized_curved_rk4_steps(ax, orc, recon):
+    """B = 0 (A = 0): pure hydrodynamics in the curved metric -- the recovery without field terms, and the
+    dispersion quartic whose inner roots collapse to the double root a^2 = 0 (only the outer, fast roots are
+    sought).  Three RK4 steps of a 24 x 20 x 16 block: state and primitives within 1e-10 of the oracle; the
+    potential and Psi stay exactly zero (E = 0 and no gauge source) and so does the div B maximum."""
+    w = W.curved_block(seed=7, n=(24, 20, 16), recon=recon, nsteps=3)
+    w.A[...] = 0.0
+    print("case unmagnetized curved 3 RK4 steps", recon, flush=True)
+    blk, state, prim = _run_both(ax, orc, w, 3)
+    L = w.layout
+    g = _host(blk.state)
+    e = assert_fields_close(g, state, 1e-10, L.owned, STATE_NAMES)
+    assert_fields_close(_host(blk.prim), prim, 1e-10, L.owned, PRIM_NAMES)
+    assert np.all(L.owned(g)[5:9] == 0.0) and np.all(L.owned(state)[5:9] == 0.0)
+    assert float(_host(blk.red)[1]) == 0.0
+    print("  max state error %.2e" % e.max(), flush=True)
+    _check_cell_relative(g, state, L.owned)
+
+
 @pytest.mark.parametrize("recon", ["ppm", "wenoz"])
 def test_full_size_curved128_rk4_step(ax, orc, recon):
     """The 128^3 curved workload at full size, stepped as the benchmark steps it: c2p and the right-hand side of
