@@ -132,6 +132,35 @@ def test_mlp_gradient_vs_reference(L):
     assert torch.equal(grad, grad2)
 
 
+def test_network_exact_on_dyadic_network(L):
+    """On a network whose every rounded value is exactly representable (tests/mlp_exact.py: small dyadic weights,
+    inputs and targets, 1024 samples), the matrix-core forward and gradient equal the plain float64 network bit
+    for bit -- a pin that does not restate the kernel's rounding points.  Forward and gradient kernels both."""
+    import torch
+    from oracle import mlp_ref as M
+    from paper_2406_11669_amd import asterx as ax
+    from tests import mlp_exact as X
+    p, st, feat, off = X.network(3)
+    n = feat.shape[1]
+    pt = torch.from_numpy(p).cuda()
+    mlp = ax.make_mlp(pt, st)
+    out = torch.empty((2, n), dtype=torch.float32, device="cuda")
+    ax.mlp_forward(mlp, torch.from_numpy(feat).cuda(), out)
+    ref, _ = M.forward(p, feat, st, precise=True)
+    tgt = (ref - off).astype(np.float32)
+    grad = torch.empty(ax.MLP_NPARAMS + 1, dtype=torch.float32, device="cuda")
+    ws = torch.empty(ax.mlp_grad_workspace_size(n) // 4 + 1, dtype=torch.float32, device="cuda")
+    ax.mlp_grad(mlp, torch.from_numpy(feat).cuda(), torch.from_numpy(tgt).cuda(), grad, ws)
+    torch.cuda.synchronize()
+    loss, gref = M.loss_grad(p, feat, tgt, st, precise=True)
+    g = grad.cpu().numpy().astype(np.float64)
+    print("  forward mismatches %d of %d, gradient mismatches %d of %d, loss %.9g vs %.9g" % (
+        int(np.sum(out.cpu().numpy().astype(np.float64) != ref)), ref.size, int(np.sum(g[:-1] != gref)), gref.size,
+        g[-1], loss), flush=True)
+    assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+    assert np.array_equal(g[:-1], np.asarray(gref, np.float64)) and g[-1] == loss
+
+
 def test_adam_step_vs_reference(L):
     import torch
     from oracle import mlp_ref as M

@@ -65,3 +65,23 @@ def test_c2p_state_sampler_hits_W_and_sigma(orc):
         f = orc.pt_fluid(s["metric"][:, i], s["prim"][:, i], s["Bt"][:, i], s["gam"][i])
         assert abs(f["W"] - Wt[i]) <= 1e-12 * Wt[i]
         assert abs(f["bsq"] / s["prim"][0, i] - sig[i]) <= 1e-10 * sig[i]
+
+
+def test_rounded_network_exact_on_dyadic_network():
+    """On a network whose every rounded value is exactly representable (tests/mlp_exact.py), the bfloat16 forward
+    and gradient equal the plain float64 network's bit for bit -- a pin of the rounded mode that does not restate
+    where it rounds.  A transposed hidden matrix or dropped bias changes the result."""
+    from tests import mlp_exact as X
+    p, st, feat, off = X.network(3)
+    out_p, _ = M.forward(p, feat, st, precise=True)
+    out_b, _ = M.forward(p, feat, st)
+    assert np.array_equal(out_b.astype(np.float64), out_p)
+    tgt = (out_p - off).astype(np.float32)
+    assert np.array_equal(tgt.astype(np.float64), out_p - off)
+    lp, gp = M.loss_grad(p, feat, tgt, st, precise=True)
+    lb, gb = M.loss_grad(p, feat, tgt, st)
+    assert lb == lp and np.array_equal(np.asarray(gb, np.float64), np.asarray(gp, np.float64))
+    assert np.count_nonzero(gp) > 200
+    W1, b1, W2, b2, W3, b3 = M.unpack(p)
+    for q in (M.pack(W1, b1, W2.T.copy(), b2, W3, b3), M.pack(W1, b1, W2, 0.0 * b2 + 0.25, W3, b3)):
+        assert not np.array_equal(M.forward(q.astype(np.float32), feat, st)[0].astype(np.float64), out_p)
