@@ -2442,7 +2442,7 @@ DEV void face_adj_body(const GD& g, const FaceAdjArgs& fa, unsigned tile) {
     const int sD = st[D], s1 = st[t1], s2 = st[t2];
     const int o0 = side ? 2 : -3, os = side ? -1 : 1;
     // forward recomputation of this lane's side (the stencils are loaded again for the transposed
-    // reconstruction at the end rather than held in registers through the dual passes)
+    // reconstruction at the end rather than held in registers through the reverse sweep)
     auto field = [&](int v) { return v < 5 ? fa.prim + v * g.N : fa.bc + (v == 5 ? t1 : t2) * g.N; };
     double X[7];
 #pragma unroll
@@ -2981,8 +2981,8 @@ DEV void copy_body(const GD& g, const T* __restrict__ src, T* __restrict__ dst, 
 }
 
 __global__ __launch_bounds__(256) void k_fluxbar(GD g, FluxBarArgs a) { fluxbar_body(g, a, my_tile()); }
-// At the 2-wave floor (256 registers) the kernel spills 48-55 doubles yet hides more latency:
-// one wavefront per SIMD leaves every load and FP64 dependency chain exposed.
+// At the 2-wave floor (256 registers) the kernel spills 24-32 doubles per lane (PPM, WENO-Z, MP5)
+// yet hides more latency: one wavefront per SIMD leaves every load and FP64 dependency chain exposed.
 template <int D, int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_face_adj(GD g, FaceAdjArgs fa) {
   face_adj_body<D, R>(g, fa, my_tile());
