@@ -169,6 +169,36 @@ def _rhs_adjoint_gpu(ax, torch, w, cons, psi, ybar):
     return cb, Ab, pb, gb
 
 
+@pytest.mark.parametrize("part", ["cons", "A", "gamma"])
+def test_rhs_adjoint_speed_bound(adj, orc, part):
+    """Characteristic speeds from the isotropic bound (speeds = bound): the face adjoint's reverse sweep takes the
+    speed cotangents to the quadratic's coefficients by the implicit function theorem; <ybar, J v> (oracle dual
+    numbers, which differentiate the root formula itself) = <J^T ybar, v>."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    w = _curved("ppm")
+    w.params["speeds"] = "bound"
+    L = w.layout
+    print("case rhs_adjoint speed bound", part, flush=True)
+    cons, psi = _stage_inputs(orc, w)
+    rng = np.random.default_rng(9)
+    v = {"cons": None, "A": None}
+    dg = 1.0 if part == "gamma" else 0.0
+    if part != "gamma":
+        v[part] = _tangent(L, {"cons": 5, "A": 3}[part], rng)
+    ybar = _cot(L, 9, rng)
+    _, dL = orc.stage_jvp(L, w.params, w.metric, w.curv, cons, w.A, psi, w.prim, w.dt, dcons=v["cons"], dA=v["A"],
+                          dgamma=dg)
+    lhs, lscale = _dot(L, ybar, dL)
+    cb, Ab, _, gb = _rhs_adjoint_gpu(ax, torch, w, cons, psi, ybar)
+    if part == "gamma":
+        rhs, rscale = float(gb.item()), abs(float(gb.item()))
+    else:
+        rhs, rscale = _dot(L, (cb if part == "cons" else Ab).cpu().numpy(), v[part])
+    print("  <ybar, Jv> %.15e  <J^T ybar, v> %.15e" % (lhs, rhs), flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * max(lscale, rscale), (lhs, rhs, lscale)
+
+
 @pytest.mark.parametrize("part", ["cons", "gamma"])
 def test_rhs_adjoint_wenoz_exponent2(adj, orc, part):
     """WENO-Z with exponent q = 2.  On the smooth curved block <ybar, J v> (oracle dual numbers) = <J^T ybar, v>.
