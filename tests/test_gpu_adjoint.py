@@ -200,6 +200,39 @@ def test_rhs_adjoint_speed_bound(adj, orc, part):
 
 
 @pytest.mark.parametrize("part", ["cons", "gamma"])
+@pytest.mark.parametrize("recon", ["mp5", "wenoz"])
+def test_rhs_adjoint_face_fallback(adj, orc, recon, part):
+    """Faces whose reconstructed state is unphysical take the adjacent cell's values on that side; the face adjoint
+    sends those sides' cotangents to the cell itself.  On a block with a log-uniform pressure per cell (p <= 0
+    reconstructed at hundreds of faces): <ybar, J v> (oracle dual numbers) = <J^T ybar, v>."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    from tests.test_gpu_paths import _rough_pressure
+    w = _rough_pressure(W.curved_block(seed=5, n=(40, 10, 9), recon=recon, nsteps=1))
+    L = w.layout
+    print("case rhs_adjoint face fallback", recon, part, flush=True)
+    cons, psi = _stage_inputs(orc, w)
+    prim = w.prim.copy()
+    orc.c2p(L, w.params, w.metric, w.A, cons.copy(), prim)
+    orc.fill_ghosts(L, prim, w.bc_cell)
+    _, _, nfix = orc.rhs(L, w.params, w.metric, w.curv, prim, w.A, psi, w.dt)
+    assert nfix >= 100, nfix
+    rng = np.random.default_rng(10)
+    dcons = _tangent(L, 5, rng) if part == "cons" else None
+    dg = 1.0 if part == "gamma" else 0.0
+    ybar = _cot(L, 9, rng)
+    _, dL = orc.stage_jvp(L, w.params, w.metric, w.curv, cons, w.A, psi, w.prim, w.dt, dcons=dcons, dgamma=dg)
+    lhs, lscale = _dot(L, ybar, dL)
+    cb, _, _, gb = _rhs_adjoint_gpu(ax, torch, w, cons, psi, ybar)
+    if part == "gamma":
+        rhs, rscale = float(gb.item()), abs(float(gb.item()))
+    else:
+        rhs, rscale = _dot(L, cb.cpu().numpy(), dcons)
+    print("  fallback faces %d; <ybar, Jv> %.15e  <J^T ybar, v> %.15e" % (nfix, lhs, rhs), flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * max(lscale, rscale), (lhs, rhs, lscale)
+
+
+@pytest.mark.parametrize("part", ["cons", "gamma"])
 def test_rhs_adjoint_wenoz_exponent2(adj, orc, part):
     """WENO-Z with exponent q = 2.  On the smooth curved block <ybar, J v> (oracle dual numbers) = <J^T ybar, v>.
     On the periodic Riemann box, whose constant regions have vanishing smoothness indicators and Z ratios
