@@ -199,6 +199,29 @@ def test_rhs_adjoint_speed_bound(adj, orc, part):
     assert abs(lhs - rhs) <= 1e-10 * max(lscale, rscale), (lhs, rhs, lscale)
 
 
+@pytest.mark.parametrize("part", ["cons", "A"])
+def test_rhs_adjoint_algebraic_gauge(adj, orc, part):
+    """The algebraic gauge (dA/dt = -E, Psi not evolved): the vertex adjoint's gauge branch; <ybar, J v> (oracle
+    dual numbers) = <J^T ybar, v> for tangents in the conserved variables and in the potential."""
+    import torch
+    from paper_2406_11669_amd import asterx as ax
+    w = _curved("ppm")
+    w.params["gauge"] = "algebraic"
+    L = w.layout
+    print("case rhs_adjoint algebraic gauge", part, flush=True)
+    cons, psi = _stage_inputs(orc, w)
+    rng = np.random.default_rng(11)
+    v = {"cons": None, "A": None}
+    v[part] = _tangent(L, {"cons": 5, "A": 3}[part], rng)
+    ybar = _cot(L, 9, rng)
+    _, dL = orc.stage_jvp(L, w.params, w.metric, w.curv, cons, w.A, psi, w.prim, w.dt, dcons=v["cons"], dA=v["A"])
+    lhs, lscale = _dot(L, ybar, dL)
+    cb, Ab, _, _ = _rhs_adjoint_gpu(ax, torch, w, cons, psi, ybar)
+    rhs, rscale = _dot(L, (cb if part == "cons" else Ab).cpu().numpy(), v[part])
+    print("  <ybar, Jv> %.15e  <J^T ybar, v> %.15e" % (lhs, rhs), flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * max(lscale, rscale), (lhs, rhs, lscale)
+
+
 @pytest.mark.parametrize("part", ["cons", "gamma"])
 @pytest.mark.parametrize("recon", ["mp5", "wenoz"])
 def test_rhs_adjoint_face_fallback(adj, orc, recon, part):
