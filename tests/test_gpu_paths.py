@@ -255,9 +255,10 @@ def test_unmagnetized_curved_rk4_steps(ax, orc, recon):
 
 
 @pytest.mark.parametrize("recon", ["ppm", "wenoz"])
-def test_full_size_curved128_rk4_step(ax, orc, recon):
+def test_full_size_curved128_rk4_steps(ax, orc, recon):
     """The 128^3 curved workload at full size, stepped as the benchmark steps it: c2p and the right-hand side of
-    the first stage within 1e-12, and one whole RK4 step (four stages) within 1e-10, at every owned cell."""
+    the first stage within 1e-12, and ten whole RK4 steps within 1e-10, at every owned cell (the oracle's steps on
+    its OpenMP build, bitwise the serial one)."""
     import torch
     w = W.curved_block(seed=0, n=128, recon=recon, nsteps=1)
     L = w.layout
@@ -278,16 +279,19 @@ def test_full_size_curved128_rk4_step(ax, orc, recon):
     print("  first-stage right-hand side: max error %.2e; PPM constraint decisions %d, near ties %d" % (
         float(e1.max()), dec, near), flush=True)
     del ref, k_gpu
+    nsteps = 10
     step = ax.Block(w)
-    step.run(1)
+    step.run(nsteps)
     torch.cuda.synchronize()
     cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
     orc.fill_ghosts(L, cons, w.bc_cell)
     state = w.state(cons)
     prim = w.prim.copy()
-    orc.run(L, w.params, w.metric, w.curv, state, prim, w.dt, 1, w.rk, w.bc_cell, w.bc_A)
+    lib_omp, threads = orc.lib_omp()
+    orc.run(L, w.params, w.metric, w.curv, state, prim, w.dt, nsteps, w.rk, w.bc_cell, w.bc_A, lib_=lib_omp)
     e = assert_fields_close(_host(step.state), state, 1e-10, L.owned, STATE_NAMES)
-    print("  first-stage and step errors ok; max state error %.2e" % e.max(), flush=True)
+    assert_fields_close(_host(step.prim), prim, 1e-10, L.owned, PRIM_NAMES)
+    print("  %d RK4 steps (oracle on %d threads): max state error %.2e" % (nsteps, threads, e.max()), flush=True)
     _check_cell_relative(_host(step.state), state, L.owned)
 
 
