@@ -381,7 +381,11 @@ int asterx_rhs_rk_src(const asterx_grid* g, const asterx_params* p, const double
  * by two HIP events on its stream; asterx_timing_read waits for the recorded events and
  * returns, for each kernel class k < n, the accumulated milliseconds ms[k] and launch count
  * counts[k] (either may be NULL); it returns the number of kernel classes.
- * asterx_timing_name(k) names class k.  Do not enable while a stream is being captured. */
+ * asterx_timing_name(k) names class k.  Do not enable while a stream is being captured.  The
+ * timing state is process-global and unsynchronized: enable it only while one host thread
+ * drives the library (the other entry points keep no host state across calls, except
+ * asterx_last_error, which is per thread, and the no-allocation entry point's per-device
+ * address table, which is locked). */
 int asterx_timing_enable(int32_t on);
 int asterx_timing_read(double* ms, long long* counts, int32_t n);
 int asterx_timing_reset(void);
