@@ -148,9 +148,17 @@ def fill_ghosts_shift(layout, f, shift):
     lib().orc_fill_ghosts_shift(ctypes.byref(make_grid(layout)), _p(f), ctypes.c_int(nf), _p(sh))
 
 
-def fill_ghosts(layout, f, kinds):
+def _bc_kinds(layout, kinds):
+    """Boundary kinds as integers; linear extrapolation needs two owned points along its axis."""
     kinds = [BC[k] if isinstance(k, str) else k for k in kinds]
-    karr = (ctypes.c_int * 3)(*kinds)
+    for a in range(3):
+        if kinds[a] == BC["linear"] and layout.n[a] < 2:
+            raise ValueError("linear ghost extrapolation needs n >= 2 along axis %d" % a)
+    return (ctypes.c_int * 3)(*kinds)
+
+
+def fill_ghosts(layout, f, kinds):
+    karr = _bc_kinds(layout, kinds)
     nf = f.shape[0] if f.ndim == 4 else 1
     lib().orc_fill_ghosts(ctypes.byref(make_grid(layout)), _p(f), ctypes.c_int(nf), karr)
 
@@ -222,8 +230,8 @@ def run(layout, params, metric, curv, state, prim, dt, nsteps, rk, bc_cell, bc_A
     flags = np.zeros(layout.shape3, dtype=np.uint8)
     stats = np.zeros(6, dtype=np.uint64)
     redmax = np.zeros(2, dtype=np.float64)
-    bcc = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_cell])
-    bca = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_A])
+    bcc = _bc_kinds(layout, bc_cell)
+    bca = _bc_kinds(layout, bc_A)
     sh = None if A_shift is None else np.ascontiguousarray(A_shift, dtype=np.float64)
     (lib_ or lib()).orc_run(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), _p(metric),
                             _p(curv), _p(state), _p(prim), ctypes.c_double(dt), ctypes.c_int(nsteps),
@@ -396,8 +404,8 @@ def loss_jvp(layout, params, metric, curv, prim0, A0, psi0, dt, nsteps, rk, bc_c
     _check_ct(layout, params)
     out = np.zeros(2, dtype=np.float64)
     stats = np.zeros(6, dtype=np.uint64)
-    bcc = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_cell])
-    bca = (ctypes.c_int * 3)(*[BC[k] if isinstance(k, str) else k for k in bc_A])
+    bcc = _bc_kinds(layout, bc_cell)
+    bca = _bc_kinds(layout, bc_A)
     sh = None if A_shift is None else np.ascontiguousarray(A_shift, dtype=np.float64)
     dp = None if dprim0 is None else np.ascontiguousarray(dprim0, dtype=np.float64)
     lib().orc_loss_jvp(ctypes.byref(make_grid(layout)), ctypes.byref(make_params(params)), ctypes.c_double(dgamma),

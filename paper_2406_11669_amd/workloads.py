@@ -22,7 +22,9 @@ Workloads (one block, one GPU):
                 at x = 1/2 and at the wrap), flat, PPM, RK2, 20 steps, Gamma = 5/3;
                 the vector potential is periodic up to a constant per wrap.
   patch_set  -- 512 Riemann-problem patches of uneven sides and levels.
-Both are also available at other sizes for tests.
+  shock_tube -- an unmagnetized one-dimensional Riemann problem (tests against
+                the exact solution of relativistic hydrodynamics).
+All are also available at other sizes for tests.
 """
 from dataclasses import dataclass, field
 
@@ -265,6 +267,29 @@ def periodic_riemann_box(seed=0, n=64, ng=NG_DEFAULT, recon="ppm", nsteps=20, rk
                 v_amp=v_amp)
     return Workload("periodic_riemann%d" % nn[0], L, params, metric, curv, prim, A, psi, dt, nsteps, rk,
                     ("periodic",) * 3, ("periodic",) * 3, info, shift)
+
+
+def shock_tube(left, right, n=200, axis=0, ng=NG_DEFAULT, recon="ppm", t_end=0.35, rk=2, cfl=0.25,
+               gamma=5.0 / 3.0, split=0.5):
+    """Unmagnetized one-dimensional Riemann problem along `axis` on [0, 1] (n cells; one cell across the other
+    two axes, same spacing), flat metric, copy boundaries (the potential is zero and stays zero).  left/right = (rho, p, v) with v along `axis`;
+    the interface is the vertex plane at `split`.  dt = t_end / nsteps with nsteps the smallest count whose
+    step is at most cfl dx, so that nsteps steps end exactly at t_end."""
+    nn = [1, 1, 1]
+    nn[axis] = int(n)
+    dx = 1.0 / n
+    L = Layout(tuple(nn), ng, dx=(dx, dx, dx))
+    metric = flat_metric(L)
+    prim = L.zeros(5)
+    pos = L.coords("centre")[axis]
+    lft = np.broadcast_to(pos < split, L.shape3)
+    for c, q in ((0, 0), (1, 1), (2 + axis, 2)):
+        prim[c] = np.where(lft, float(left[q]), float(right[q]))
+    nsteps = int(np.ceil(t_end / (cfl * dx) - 1e-9))
+    params = default_params(gamma=gamma, rho_atm=1e-7 * max(left[0], right[0]), recon=recon)
+    info = dict(left=tuple(left), right=tuple(right), axis=axis, t_end=t_end, split=split)
+    return Workload("shock_tube%d" % n, L, params, metric, L.zeros(6), prim, L.zeros(3), L.zeros(1),
+                    t_end / nsteps, nsteps, rk, ("copy",) * 3, ("copy",) * 3, info)
 
 
 # ---- the curved periodic block -----------------------------------------------------------------------------

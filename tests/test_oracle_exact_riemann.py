@@ -1,0 +1,187 @@
+"""The oracle's full time step on unmagnetized shock tubes against the exact solution of the relativistic
+Riemann problem (the B = 0, flat-space special case of the system of Sec. 2.2, one dimension).
+
+The exact solver (tests/exact_riemann.py) is pinned first on its own: every shock it returns satisfies the
+three jump conditions, every rarefaction fan satisfies the self-similar conservation law, the two sides agree
+on the velocity of the contact, and a classic blast wave reproduces its published middle state.  The oracle's
+numerical solutions then converge to it in L1 at first order (the rate set by the discontinuities), and the
+middle states, away from the waves, match it closely."""
+import numpy as np
+import pytest
+
+from paper_2406_11669_amd import workloads as W
+from tests import exact_riemann as X
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+G53 = 5.0 / 3.0
+# a seeded draw of the Riemann-problem workload's states (rho, p ~ U[0.1, 1], fluid at rest), B = 0:
+# left shock, contact, right rarefaction
+MODERATE = ((0.3, 0.2, 0.0), (0.8, 0.9, 0.0))
+# the first blast wave of Marti & Mueller (J. Fluid Mech. 258, 1994): a rarefaction to the left, a thin dense
+# shell behind a shock moving right at 0.83 c
+BLAST1 = ((10.0, 40.0 / 3.0, 0.0), (1.0, 1e-6, 0.0))
+BLAST2 = ((1.0, 1000.0, 0.0), (1.0, 0.01, 0.0))
+
+
+def _cases():
+    rng = np.random.default_rng(2024)
+    out = [MODERATE, BLAST1, BLAST2, ((1.0, 1.0, 0.5), (0.125, 0.1, -0.3))]
+    for _ in range(6):
+        rho = rng.uniform(0.1, 1.0, 2)
+        p = rng.uniform(0.1, 1.0, 2)
+        v = rng.uniform(-0.5, 0.5, 2)
+        out.append(((rho[0], p[0], v[0]), (rho[1], p[1], v[1])))
+    return out
+
+
+@pytest.mark.parametrize("case", _cases())
+def test_exact_solver_jump_conditions_and_fans(case):
+    """Shocks: [F] = V [U] for (D, S, tau); fans: -xi dU/dxi + dF/dxi = 0 at interior points (central
+    differences, O(h^2)) and continuity with the states at both ends; the contact's velocity agrees from both
+    sides."""
+    left, right = case
+    S = X.Solution(left, right, G53)
+    assert S.v_mismatch <= 1e-12
+    star = {-1: (S.rhoL, S.p, S.v), +1: (S.rhoR, S.p, S.v)}
+    ahead = {-1: S.L, +1: S.R}
+    lh, lt, vc, rt, rh = S.wave_speeds()
+    assert lh <= lt < vc < rt <= rh
+    for sign in (-1, +1):
+        a = ahead[sign]
+        b = star[sign]
+        if S.p > a[1]:
+            rho_b, v_b, V = X.shock(a, S.p, G53, sign)
+            Ua, Ub = X.conserved(*a, G53), X.conserved(rho_b, S.p, v_b, G53)
+            Fa, Fb = X.flux(*a, G53), X.flux(rho_b, S.p, v_b, G53)
+            scale = np.max(np.abs(np.concatenate([Ua, Ub, Fa, Fb])))
+            assert np.max(np.abs((Fb - Fa) - V * (Ub - Ua))) <= 1e-13 * scale
+            assert abs(V) < 1.0 and (V - a[2]) * sign > 0.0  # the shock moves into the state ahead
+        else:
+            fan = -sign  # +1: left fan, -1: right fan
+            head, tail = (lh, lt) if sign < 0 else (rh, rt)
+            t = 1.0
+            ends = S.sample(np.array([S.x0 + head * t * (1 - 1e-12) + 1e-13 * sign,
+                                      S.x0 + tail * t + 1e-12 * sign]), t)
+            assert np.allclose(ends[:, 0], a, rtol=1e-8, atol=1e-10)
+            assert np.allclose(ends[:, 1], b, rtol=1e-8, atol=1e-10)
+            h = 1e-4 * abs(head - tail)
+            for f in (0.2, 0.5, 0.8):
+                xi = head + f * (tail - head)
+                U, F = [], []
+                for d in (-1, 1):
+                    rho, p, v = S._fan_state(a, xi + d * h, fan)
+                    U.append(X.conserved(rho, p, v, G53))
+                    F.append(X.flux(rho, p, v, G53))
+                dU = (U[1] - U[0]) / (2 * h)
+                dF = (F[1] - F[0]) / (2 * h)
+                assert np.max(np.abs(dF - xi * dU)) <= 1e-6 * np.max(np.abs(dF))
+
+
+def test_exact_solver_published_blast_wave():
+    """The first blast wave's middle state (Marti & Mueller 1994, Table 1: p* = 1.448, v* = 0.714,
+    rho_L* = 2.639, rho_R* = 5.071, shock speed 0.828), to the printed three decimals."""
+    S = X.Solution(*BLAST1, G53)
+    V = S.wave_speeds()[4]
+    for got, ref in ((S.p, 1.448), (S.v, 0.714), (S.rhoL, 2.639), (S.rhoR, 5.071), (V, 0.828)):
+        assert abs(got - ref) <= 6e-4 * ref, (got, ref)
+    assert not S.left_shock and S.right_shock
+
+
+def _oracle_tube(orc, w):
+    L = w.layout
+    cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+    orc.fill_ghosts(L, cons, w.bc_cell)
+    state = w.state(cons)
+    prim = w.prim.copy()
+    flags, stats, red = orc.run(L, w.params, w.metric, w.curv, state, prim, w.dt, w.nsteps, w.rk, w.bc_cell,
+                                w.bc_A)
+    return prim, stats, red
+
+
+def tube_profile(w, prim):
+    """(x, rho, p, v) along the tube's axis from a primitive array of the workload's layout."""
+    L = w.layout
+    a = w.info["axis"]
+    own = L.owned(prim)
+    idx = [0, 0, 0]
+    idx[2 - a] = slice(None)
+    line = own[(slice(None),) + tuple(idx)]
+    x = (np.arange(L.n[a]) + 0.5) * L.dx[a]
+    return x, np.stack([line[0], line[1], line[2 + a]])
+
+
+def l1_errors(w, prim):
+    S = X.Solution(w.info["left"], w.info["right"], w.params["gamma"], w.info["split"])
+    x, got = tube_profile(w, prim)
+    ex = S.sample(x, w.info["t_end"])
+    return np.mean(np.abs(got - ex), axis=1), S, x, got
+
+
+def plateau_errors(S, x, got, t):
+    """Largest relative error of (rho, p, v) at the cells closest to the middle of the two star regions."""
+    lh, lt, vc, rt, rh = S.wave_speeds()
+    worst = 0.0
+    for a, b in ((lt, vc), (vc, rt)):
+        i = int(np.argmin(np.abs(x - (S.x0 + 0.5 * t * (a + b)))))
+        ex = S.sample(x[i:i + 1], t)[:, 0]
+        worst = max(worst, float(np.max(np.abs(got[:, i] - ex) / np.abs(ex))))
+    return worst
+
+
+@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz", "mp5"])
+def test_shock_tube_converges_to_exact(orc, recon):
+    """The moderate tube to t = 0.35 at 100 and 200 cells (HLLE, RK2, CFL 0.25): the L1 errors of rho, p and v
+    at 200 cells stay below 6e-3 and fall by at least 1.7x from 100 cells (first order, as discontinuities
+    allow); the two middle states match the exact ones to 2e-3; no recovery failed."""
+    errs = {}
+    for n in (100, 200):
+        w = W.shock_tube(*MODERATE, n=n, recon=recon, t_end=0.35)
+        prim, stats, red = _oracle_tube(orc, w)
+        assert stats[0] == 0 and stats[3] == 0
+        errs[n], S, x, got = l1_errors(w, prim)
+    print(recon, "L1(100)", errs[100], "L1(200)", errs[200])
+    assert np.all(errs[200] <= 6e-3)
+    assert np.sum(errs[100]) >= 1.7 * np.sum(errs[200])
+    assert plateau_errors(S, x, got, 0.35) <= 2e-3
+
+
+def test_blast_wave_converges_to_exact(orc):
+    """The first blast wave (pressure ratio 1.3e7) with PPM to t = 0.4 at 100 and 200 cells: L1 errors fall by
+    at least 1.7x; at 200 cells the rarefied middle state is within 3e-3 and the dense shell (9 cells wide)
+    within 1.5% of the exact values."""
+    errs = {}
+    for n in (100, 200):
+        w = W.shock_tube(*BLAST1, n=n, recon="ppm", t_end=0.4)
+        prim, stats, red = _oracle_tube(orc, w)
+        assert stats[3] == 0
+        errs[n], S, x, got = l1_errors(w, prim)
+    scale = np.array([10.0, 40.0 / 3.0, 1.0])
+    print("blast L1(100)", errs[100], "L1(200)", errs[200])
+    assert np.sum(errs[100] / scale) >= 1.7 * np.sum(errs[200] / scale)
+    lh, lt, vc, rt, rh = S.wave_speeds()
+    for (a, b), tol in (((lt, vc), 3e-3), ((vc, rt), 1.5e-2)):
+        i = int(np.argmin(np.abs(x - (S.x0 + 0.2 * (a + b)))))
+        ex = S.sample(x[i:i + 1], 0.4)[:, 0]
+        assert np.max(np.abs(got[:, i] - ex) / np.abs(ex)) <= tol
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+def test_shock_tube_axis_symmetry(orc, axis):
+    """The same tube along y or z gives the x-tube's profile to round-off (the three directions' flux and
+    stencil code agree)."""
+    ref = W.shock_tube(*MODERATE, n=100, axis=0, recon="ppm", t_end=0.35)
+    w = W.shock_tube(*MODERATE, n=100, axis=axis, recon="ppm", t_end=0.35)
+    p0, _, _ = _oracle_tube(orc, ref)
+    p1, _, _ = _oracle_tube(orc, w)
+    _, a = tube_profile(ref, p0)
+    _, b = tube_profile(w, p1)
+    assert np.max(np.abs(a - b)) <= 1e-13
+
+
+def test_linear_fill_refused_on_one_cell_axis(orc):
+    """Linear ghost extrapolation needs two owned points: refused on a one-cell axis (as the HIP library
+    refuses it), so the tubes fill their zero potential by copy."""
+    L = W.Layout((4, 1, 4))
+    with pytest.raises(ValueError):
+        orc.fill_ghosts(L, L.zeros(1), ("copy", "linear", "copy"))

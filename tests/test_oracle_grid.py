@@ -257,8 +257,9 @@ def test_alfven_wave_self_convergence(orc):
 
 
 def test_riemann_block_smoke(orc):
-    """The seeded Riemann-problem block runs without c2p failures and keeps positivity (no exact solver exists
-    in this repository to compare against: parity with it is unpinned)."""
+    """The seeded magnetized Riemann-problem block runs without c2p failures and keeps positivity (no exact
+    magnetized solver exists here; the unmagnetized tubes are pinned to the exact solution in
+    test_oracle_exact_riemann.py)."""
     w = W.riemann_block(seed=7, n=12, nsteps=4)
     L = w.layout
     state = _init_state(orc, w)
