@@ -1,0 +1,82 @@
+"""The HIP path on unmagnetized shock tubes: parity with the oracle after a whole run, and convergence to the
+exact solution of the relativistic Riemann problem at resolutions the oracle would take minutes for (the
+B = 0, flat-space special case of Sec. 2.2 in one dimension; exact solver in tests/exact_riemann.py).
+
+Tolerance of the whole-run parity: 2e-9 on O(1) primitives after 280 steps through a shock, a contact and a
+rarefaction.  Limiter decisions taken within rounding of their switching point may go either way on the two
+sides, and the difference of one such decision is carried by the flow; MINMOD and MP5 stay within 1e-14,
+PPM and WENO-Z (whose flattening and smoothness weights switch on more points) within 4e-10."""
+import numpy as np
+import pytest
+
+from paper_2406_11669_amd import workloads as W
+from tests.test_oracle_exact_riemann import BLAST1, MODERATE, _oracle_tube, l1_errors, plateau_errors
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def ax():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_11669_amd import asterx
+    asterx.lib()
+    return asterx
+
+
+def _gpu_tube(ax, w):
+    import torch
+    blk = ax.Block(w)
+    blk.run(w.nsteps)
+    torch.cuda.synchronize()
+    return blk.prim.cpu().numpy(), blk.stats.cpu().numpy()
+
+
+@pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz", "mp5"])
+def test_shock_tube_matches_oracle(ax, orc, recon):
+    """The moderate tube at 200 cells to t = 0.35 (280 RK2 steps): primitives within 2e-9 of the oracle's, no
+    recovery failure on either side."""
+    w = W.shock_tube(*MODERATE, n=200, recon=recon, t_end=0.35)
+    print("case shock tube 200", recon, flush=True)
+    pg, st = _gpu_tube(ax, w)
+    pc, stc, _ = _oracle_tube(orc, w)
+    d = np.abs(w.layout.owned(pg) - w.layout.owned(pc)).reshape(5, -1).max(axis=1)
+    print("  max |gpu - oracle| per primitive:", d)
+    assert np.all(d <= 2e-9)
+    assert st[3] == 0 and stc[3] == 0
+
+
+def test_shock_tube_converges_to_exact(ax):
+    """The moderate tube with PPM at 400, 800, 1600 and 3200 cells: the summed L1 error of (rho, p, v) falls by
+    at least 1.6x per doubling (first order) and the middle states stay within 3e-4 of the exact ones."""
+    prev = None
+    for n in (400, 800, 1600, 3200):
+        w = W.shock_tube(*MODERATE, n=n, recon="ppm", t_end=0.35)
+        print("case shock tube", n, flush=True)
+        pg, st = _gpu_tube(ax, w)
+        assert st[3] == 0
+        e, S, x, got = l1_errors(w, pg)
+        pl = plateau_errors(S, x, got, 0.35)
+        print("  L1", e, "middle states", pl)
+        assert pl <= 3e-4
+        if prev is not None:
+            assert prev >= 1.6 * np.sum(e)
+        prev = np.sum(e)
+
+
+def test_blast_wave_converges_to_exact(ax):
+    """The first blast wave (pressure ratio 1.3e7) with PPM at 1600 and 3200 cells: L1 falls by at least 1.6x,
+    and at 3200 cells both middle states, the dense shell (146 cells wide) included, are within 4e-3."""
+    scale = np.array([10.0, 40.0 / 3.0, 1.0])
+    errs = []
+    for n in (1600, 3200):
+        w = W.shock_tube(*BLAST1, n=n, recon="ppm", t_end=0.4)
+        print("case blast wave", n, flush=True)
+        pg, st = _gpu_tube(ax, w)
+        assert st[3] == 0
+        e, S, x, got = l1_errors(w, pg)
+        errs.append(np.sum(e / scale))
+        print("  L1", e)
+    assert errs[0] >= 1.6 * errs[1]
+    assert plateau_errors(S, x, got, 0.4) <= 4e-3
