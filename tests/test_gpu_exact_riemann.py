@@ -80,3 +80,36 @@ def test_blast_wave_converges_to_exact(ax):
         print("  L1", e)
     assert errs[0] >= 1.6 * errs[1]
     assert plateau_errors(S, x, got, 0.4) <= 4e-3
+
+
+@pytest.mark.parametrize("recon", ["ppm", "mp5"])
+def test_normal_field_tube_matches_oracle(ax, orc, recon):
+    """The moderate tube with a uniform field Bn = 1.5 along it (Alfven speed above the sound speed) at 200
+    cells, 280 steps: primitives within 2e-9 of the oracle's."""
+    w = W.shock_tube(*MODERATE, n=200, recon=recon, t_end=0.35, Bn=1.5)
+    print("case normal-field tube 200", recon, flush=True)
+    pg, st = _gpu_tube(ax, w)
+    pc, stc, _ = _oracle_tube(orc, w)
+    d = np.abs(w.layout.owned(pg) - w.layout.owned(pc)).reshape(5, -1).max(axis=1)
+    print("  max |gpu - oracle| per primitive:", d)
+    assert np.all(d <= 2e-9)
+    assert st[3] == 0 and stc[3] == 0
+
+
+def test_normal_field_tube_converges_to_exact(ax):
+    """Bn = 1.5 along the moderate tube with PPM at 800, 1600 and 3200 cells: the field drops out of the flow,
+    so the primitives converge to the hydrodynamic exact solution, at first order, with middle states
+    within 5e-4."""
+    prev = None
+    for n in (800, 1600, 3200):
+        w = W.shock_tube(*MODERATE, n=n, recon="ppm", t_end=0.35, Bn=1.5)
+        print("case normal-field tube", n, flush=True)
+        pg, st = _gpu_tube(ax, w)
+        assert st[3] == 0
+        e, S, x, got = l1_errors(w, pg)
+        pl = plateau_errors(S, x, got, 0.35)
+        print("  L1", e, "middle states", pl)
+        assert pl <= 5e-4
+        if prev is not None:
+            assert prev >= 1.6 * np.sum(e)
+        prev = np.sum(e)

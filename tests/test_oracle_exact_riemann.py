@@ -166,6 +166,60 @@ def test_blast_wave_converges_to_exact(orc):
         assert np.max(np.abs(got[:, i] - ex) / np.abs(ex)) <= tol
 
 
+def tube_uniformity(w, prim):
+    """Largest difference of any owned primitive from the first transverse column's (a 1-D solution keeps
+    every column equal)."""
+    own = w.layout.owned(prim)
+    a = w.info["axis"]
+    ref = [slice(None)] * 4
+    for t in range(3):
+        if t != a:
+            ref[3 - t] = slice(0, 1)
+    return float(np.max(np.abs(own - own[tuple(ref)])))
+
+
+@pytest.mark.parametrize("recon,tol", [("minmod", 1e-13), ("mp5", 1e-13), ("ppm", 1e-9), ("wenoz", 1e-9)])
+def test_normal_field_tube_sub_alfvenic_equals_hydro(orc, recon, tol):
+    """A uniform field along the tube (Bn = 0.5) drops out of one-dimensional flow along it: b^2 = Bn^2 is
+    constant, the magnetic stress and energy add constants (-Bn^2/2 to the momentum flux, Bn^2/2 to tau), and
+    the magnetic momentum and energy fluxes cancel.  Where the Alfven speed stays below the sound speed the
+    HLLE speeds are the sound speeds too, so after 140 steps the primitives equal the unmagnetized tube's
+    (through the magnetized recovery, fluxes and quartic speeds): to 1e-13 under MINMOD and MP5; PPM's and
+    WENO-Z's limiter decisions taken within rounding of their switching points carry the round-off of the
+    magnetized arithmetic further (measured 9e-11 and 3e-11)."""
+    w0 = W.shock_tube(*MODERATE, n=100, recon=recon, t_end=0.35)
+    wb = W.shock_tube(*MODERATE, n=100, recon=recon, t_end=0.35, Bn=0.5)
+    p0, _, _ = _oracle_tube(orc, w0)
+    pb, stats, _ = _oracle_tube(orc, wb)
+    assert stats[3] == 0
+    assert tube_uniformity(wb, pb) <= 1e-12
+    _, a = tube_profile(w0, p0)
+    _, b = tube_profile(wb, pb)
+    assert np.max(np.abs(a - b)) <= tol
+
+
+@pytest.mark.parametrize("case", ["moderate", "blast1"])
+def test_normal_field_tube_converges_to_exact(orc, case):
+    """Bn = 1.5 along the tube, where the Alfven speed exceeds the sound speed (the fast speeds of the quartic
+    are the Alfven speeds along the field, so HLLE dissipates differently): the primitives still converge to
+    the hydrodynamic exact solution at first order, with the moderate tube's middle states within 2e-3 at
+    200 cells, and every transverse column stays equal."""
+    left, right = MODERATE if case == "moderate" else BLAST1
+    t_end = 0.35 if case == "moderate" else 0.4
+    scale = np.array([max(left[0], right[0]), max(left[1], right[1]), 1.0])
+    errs = {}
+    for n in (100, 200):
+        w = W.shock_tube(left, right, n=n, recon="ppm", t_end=t_end, Bn=1.5)
+        prim, stats, red = _oracle_tube(orc, w)
+        assert stats[3] == 0
+        assert tube_uniformity(w, prim) <= 1e-12
+        errs[n], S, x, got = l1_errors(w, prim)
+    print(case, "Bn 1.5 L1(100)", errs[100], "L1(200)", errs[200])
+    assert np.sum(errs[100] / scale) >= 1.7 * np.sum(errs[200] / scale)
+    if case == "moderate":
+        assert plateau_errors(S, x, got, t_end) <= 2e-3
+
+
 @pytest.mark.parametrize("axis", [1, 2])
 def test_shock_tube_axis_symmetry(orc, axis):
     """The same tube along y or z gives the x-tube's profile to round-off (the three directions' flux and
