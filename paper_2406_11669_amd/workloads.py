@@ -270,17 +270,20 @@ def periodic_riemann_box(seed=0, n=64, ng=NG_DEFAULT, recon="ppm", nsteps=20, rk
 
 
 def shock_tube(left, right, n=200, axis=0, ng=NG_DEFAULT, recon="ppm", t_end=0.35, rk=2, cfl=0.25,
-               gamma=5.0 / 3.0, split=0.5, Bn=0.0):
+               gamma=5.0 / 3.0, split=0.5, Bn=0.0, Bt=None):
     """One-dimensional Riemann problem along `axis` on [0, 1] (n cells, spacing 1/n on every axis), flat
     metric, copy boundaries for the cell fields.  left/right = (rho, p, v) with v along `axis`; the interface
     is the vertex plane at `split`.  dt = t_end / nsteps with nsteps the smallest count whose step is at most
     cfl dx, so that nsteps steps end exactly at t_end.
 
-    Bn = 0: no field, one cell across the other two axes, zero potential (copied into the ghosts).
-    Bn != 0: a uniform field Bn along `axis` (the potential's component along the second transverse axis is
-    Bn times the first transverse coordinate, filled linearly), two cells across the other axes."""
+    No field (Bn = 0, Bt None): one cell across the other two axes, zero potential (copied into the ghosts).
+    Bn: a uniform field along `axis`.  Bt = (left, right): a field along the first transverse axis t1 =
+    (axis + 1) % 3, piecewise constant like the fluid.  With a field, two cells across the other axes and
+    the potential's component along t2 = (axis + 2) % 3 is Bn x_t1 - int_0^x B^t1 dx (x along `axis`),
+    filled linearly."""
     t1, t2 = (axis + 1) % 3, (axis + 2) % 3
-    nn = [1, 1, 1] if Bn == 0.0 else [2, 2, 2]
+    magnetized = Bn != 0.0 or Bt is not None
+    nn = [2, 2, 2] if magnetized else [1, 1, 1]
     nn[axis] = int(n)
     dx = 1.0 / n
     L = Layout(tuple(nn), ng, dx=(dx, dx, dx))
@@ -291,13 +294,18 @@ def shock_tube(left, right, n=200, axis=0, ng=NG_DEFAULT, recon="ppm", t_end=0.3
     for c, q in ((0, 0), (1, 1), (2 + axis, 2)):
         prim[c] = np.where(lft, float(left[q]), float(right[q]))
     A = L.zeros(3)
-    if Bn != 0.0:
-        A[t2] = np.broadcast_to(Bn * L.coords(("xedge", "yedge", "zedge")[t2])[t1], L.shape3)
+    if magnetized:
+        ec = L.coords(("xedge", "yedge", "zedge")[t2])
+        a2 = Bn * ec[t1]
+        if Bt is not None:
+            x = ec[axis]
+            a2 = a2 - np.where(x < split, Bt[0] * x, Bt[0] * split + Bt[1] * (x - split))
+        A[t2] = np.broadcast_to(a2, L.shape3)
     nsteps = int(np.ceil(t_end / (cfl * dx) - 1e-9))
     params = default_params(gamma=gamma, rho_atm=1e-7 * max(left[0], right[0]), recon=recon)
-    info = dict(left=tuple(left), right=tuple(right), axis=axis, t_end=t_end, split=split, Bn=Bn)
+    info = dict(left=tuple(left), right=tuple(right), axis=axis, t_end=t_end, split=split, Bn=Bn, Bt=Bt)
     return Workload("shock_tube%d" % n, L, params, metric, L.zeros(6), prim, A, L.zeros(1), t_end / nsteps,
-                    nsteps, rk, ("copy",) * 3, ("copy",) * 3 if Bn == 0.0 else ("linear",) * 3, info)
+                    nsteps, rk, ("copy",) * 3, ("linear",) * 3 if magnetized else ("copy",) * 3, info)
 
 
 # ---- the curved periodic block -----------------------------------------------------------------------------

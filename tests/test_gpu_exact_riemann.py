@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 from paper_2406_11669_amd import workloads as W
-from tests.test_oracle_exact_riemann import BLAST1, MODERATE, _oracle_tube, l1_errors, plateau_errors
+from tests.test_oracle_exact_riemann import (BLAST1, MODERATE, _oracle_tube, _oracle_tube_state, l1_errors,
+                                             plateau_errors, transverse_errors, transverse_field)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -25,12 +26,13 @@ def ax():
     return asterx
 
 
-def _gpu_tube(ax, w):
+def _gpu_tube(ax, w, with_state=False):
     import torch
     blk = ax.Block(w)
     blk.run(w.nsteps)
     torch.cuda.synchronize()
-    return blk.prim.cpu().numpy(), blk.stats.cpu().numpy()
+    out = (blk.prim.cpu().numpy(), blk.stats.cpu().numpy())
+    return out + (blk.state.cpu().numpy(),) if with_state else out
 
 
 @pytest.mark.parametrize("recon", ["minmod", "ppm", "wenoz", "mp5"])
@@ -113,3 +115,38 @@ def test_normal_field_tube_converges_to_exact(ax):
         if prev is not None:
             assert prev >= 1.6 * np.sum(e)
         prev = np.sum(e)
+
+
+@pytest.mark.parametrize("recon", ["ppm", "mp5"])
+def test_transverse_field_tube_matches_oracle(ax, orc, recon):
+    """The moderate tube with a transverse field changing sign at the contact (1.0 | -0.3), 200 cells, 280
+    steps: primitives within 2e-9 of the oracle's, the field within 5e-9 (a difference quotient of the
+    potential over dx = 1/200, so the potential's differences count 200-fold; 1.6e-9 measured with PPM)."""
+    w = W.shock_tube(*MODERATE, n=200, recon=recon, t_end=0.35, Bt=(1.0, -0.3))
+    print("case transverse-field tube 200", recon, flush=True)
+    pg, st, sg = _gpu_tube(ax, w, with_state=True)
+    pc, sc, stc, _ = _oracle_tube_state(orc, w)
+    d = np.abs(w.layout.owned(pg) - w.layout.owned(pc)).reshape(5, -1).max(axis=1)
+    dB = np.max(np.abs(transverse_field(w, sg) - transverse_field(w, sc)))
+    print("  max |gpu - oracle| per primitive:", d, "field:", dB)
+    assert np.all(d <= 2e-9) and dB <= 5e-9
+    assert st[3] == 0 and stc[3] == 0
+
+
+@pytest.mark.parametrize("Bt", [(1.0, -0.3), (2.0, 0.1)])
+def test_transverse_field_tube_converges_to_exact(ax, Bt):
+    """Transverse-field tubes with PPM at 800, 1600 and 3200 cells: rho, p, v and B^t converge to the exact
+    solution at first order (normalized L1 falls by at least 1.6x per doubling), with middle states within
+    1e-3."""
+    prev = None
+    for n in (800, 1600, 3200):
+        w = W.shock_tube(*MODERATE, n=n, recon="ppm", t_end=0.35, Bt=Bt)
+        print("case transverse-field tube", Bt, n, flush=True)
+        pg, st, sg = _gpu_tube(ax, w, with_state=True)
+        assert st[3] == 0
+        e, mid, scale = transverse_errors(w, pg, sg)
+        print("  L1", e, "middle states", mid)
+        assert np.all(mid <= 1e-3)
+        if prev is not None:
+            assert prev >= 1.6 * np.sum(e / scale)
+        prev = np.sum(e / scale)

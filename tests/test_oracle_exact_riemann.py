@@ -220,6 +220,132 @@ def test_normal_field_tube_converges_to_exact(orc, case):
         assert plateau_errors(S, x, got, t_end) <= 2e-3
 
 
+# transverse fields (B^t left, B^t right) for the moderate tube's states: equal, changing sign at the
+# contact, strongly magnetized on the left
+TRANSVERSE = [(0.5, 0.5), (1.0, -0.3), (2.0, 0.1)]
+
+
+@pytest.mark.parametrize("case", _cases()[:4])
+def test_transverse_solver_reduces_to_closed_form(case):
+    """With no field the numerical solver (Taub adiabat and fan integrals by root finding and quadrature)
+    equals the closed-form one: middle state and wave speeds to 1e-12, a sampled profile to 1e-11 of each
+    variable's largest value (1.1e-12 measured, on the second blast wave's pressure ratio of 1e5)."""
+    left, right = case
+    S = X.Solution(left, right, G53)
+    T = X.TransverseSolution(tuple(left) + (0.0,), tuple(right) + (0.0,), G53)
+    assert abs(T.P - S.p) <= 1e-12 * S.p and abs(T.v - S.v) <= 1e-12
+    assert np.max(np.abs(np.array(T.wave_speeds()) - np.array(S.wave_speeds()))) <= 1e-12
+    x = np.linspace(0.005, 0.995, 199)
+    ref = S.sample(x, 0.3)
+    diff = np.max(np.abs(T.sample(x, 0.3)[:3] - ref), axis=1)
+    assert np.all(diff <= 1e-11 * np.max(np.abs(ref), axis=1))
+
+
+@pytest.mark.parametrize("Bt", TRANSVERSE)
+def test_transverse_solver_jump_conditions_and_fans(Bt):
+    """Transverse field: every shock satisfies the jump conditions of (D, S, tau, B^t); every fan satisfies
+    -xi dU/dxi + dF/dxi = 0 for the four of them; total pressure and velocity agree across the contact."""
+    S = X.TransverseSolution(MODERATE[0] + (Bt[0],), MODERATE[1] + (Bt[1],), G53)
+    assert S.v_mismatch <= 1e-12
+    PL = X.totals(*S.starL[:2], S.kL, G53)[0]
+    PR = X.totals(*S.starR[:2], S.kR, G53)[0]
+    assert abs(PL - S.P) <= 1e-12 * S.P and abs(PR - S.P) <= 1e-12 * S.P
+    lh, lt, vc, rt, rh = S.wave_speeds()
+    assert lh <= lt < vc < rt <= rh
+    for sign, a, k in ((-1, S.L, S.kL), (+1, S.R, S.kR)):
+        if S.P > X.totals(*a[:2], k, G53)[0]:
+            rho, p, v, V = X.shock_t(a, k, G53, S.P, sign)
+            Ua, Ub = X.conserved_t(*a, k, G53), X.conserved_t(rho, p, v, k, G53)
+            Fa, Fb = X.flux_t(*a, k, G53), X.flux_t(rho, p, v, k, G53)
+            scale = np.max(np.abs(np.concatenate([Ua, Ub, Fa, Fb])))
+            assert np.max(np.abs((Fb - Fa) - V * (Ub - Ua))) <= 1e-13 * scale
+        else:
+            fan = -sign
+            head, tail = (lh, lt) if sign < 0 else (rh, rt)
+            h = 1e-4 * abs(head - tail)
+            for f in (0.2, 0.5, 0.8):
+                xi = head + f * (tail - head)
+                U, F = [], []
+                for d in (-1, 1):
+                    rho, p, v = S._fan(a, k, xi + d * h, fan)
+                    U.append(X.conserved_t(rho, p, v, k, G53))
+                    F.append(X.flux_t(rho, p, v, k, G53))
+                dU = (U[1] - U[0]) / (2 * h)
+                dF = (F[1] - F[0]) / (2 * h)
+                assert np.max(np.abs(dF - xi * dU)) <= 1e-6 * np.max(np.abs(dF))
+
+
+def transverse_field(w, state):
+    """B^t1 along the tube at the cell centres' axis positions, from the potential: -d A_t2 / dx."""
+    L = w.layout
+    a = w.info["axis"]
+    t2 = (a + 2) % 3
+    g = L.ng
+    idx = [g, g, g]
+    idx[2 - a] = slice(g, g + L.n[a] + 1)
+    A2 = state[5 + t2][tuple(idx)]
+    return -(A2[1:] - A2[:-1]) / L.dx[a]
+
+
+def transverse_errors(w, prim, state):
+    """(L1 errors of rho, p, v, B^t; middle-state errors: rho, p, B^t relative to their largest exact values,
+    v absolute) against the exact solution."""
+    left, right, Bt = w.info["left"], w.info["right"], w.info["Bt"]
+    S = X.TransverseSolution(tuple(left) + (Bt[0],), tuple(right) + (Bt[1],), w.params["gamma"], w.info["split"])
+    x, got = tube_profile(w, prim)
+    got = np.vstack([got, transverse_field(w, state)])
+    t = w.info["t_end"]
+    ex = S.sample(x, t)
+    scale = np.max(np.abs(ex), axis=1)
+    scale[2] = 1.0
+    lh, lt, vc, rt, rh = S.wave_speeds()
+    mid = np.zeros(4)
+    for a, b in ((lt, vc), (vc, rt)):
+        i = int(np.argmin(np.abs(x - (S.x0 + 0.5 * t * (a + b)))))
+        mid = np.maximum(mid, np.abs(got[:, i] - ex[:, i]) / scale)
+    return np.mean(np.abs(got - ex), axis=1), mid, np.max(np.abs(ex), axis=1)
+
+
+def _oracle_tube_state(orc, w):
+    L = w.layout
+    cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+    orc.fill_ghosts(L, cons, w.bc_cell)
+    state = w.state(cons)
+    prim = w.prim.copy()
+    flags, stats, red = orc.run(L, w.params, w.metric, w.curv, state, prim, w.dt, w.nsteps, w.rk, w.bc_cell,
+                                w.bc_A)
+    return prim, state, stats, red
+
+
+@pytest.mark.parametrize("Bt", TRANSVERSE)
+def test_transverse_field_tube_converges_to_exact(orc, Bt):
+    """The moderate tube with a transverse field (PPM, 100 and 200 cells): the constrained-transport update of
+    the potential moves the field with the flow (E = -v x B is not zero here), and rho, p, v and B^t converge
+    to the exact solution at first order (normalized L1 falls by at least 1.6x); at 200 cells the middle
+    states are within 3e-3 (rho, p, B^t, of their largest values) and 2e-3 (v); div B stays zero and every
+    transverse column equal."""
+    errs = {}
+    for n in (100, 200):
+        w = W.shock_tube(*MODERATE, n=n, recon="ppm", t_end=0.35, Bt=Bt)
+        prim, state, stats, red = _oracle_tube_state(orc, w)
+        assert stats[3] == 0 and red[1] <= 1e-12
+        assert tube_uniformity(w, prim) <= 1e-12
+        errs[n], mid, scale = transverse_errors(w, prim, state)
+    print(Bt, "L1(100)", errs[100], "L1(200)", errs[200], "middle", mid)
+    assert np.sum(errs[100] / scale) >= 1.6 * np.sum(errs[200] / scale)
+    assert np.all(mid[[0, 1, 3]] <= 3e-3) and mid[2] <= 2e-3
+
+
+def test_transverse_field_tube_axis_symmetry(orc):
+    """The sign-changing transverse-field tube along y equals the x-tube (primitives and B^t) to 1e-12."""
+    ws = [W.shock_tube(*MODERATE, n=100, axis=a, recon="ppm", t_end=0.35, Bt=(1.0, -0.3)) for a in (0, 1)]
+    out = []
+    for w in ws:
+        prim, state, _, _ = _oracle_tube_state(orc, w)
+        out.append(np.vstack([tube_profile(w, prim)[1], transverse_field(w, state)]))
+    assert np.max(np.abs(out[0] - out[1])) <= 1e-12
+
+
 @pytest.mark.parametrize("axis", [1, 2])
 def test_shock_tube_axis_symmetry(orc, axis):
     """The same tube along y or z gives the x-tube's profile to round-off (the three directions' flux and
