@@ -270,7 +270,7 @@ def periodic_riemann_box(seed=0, n=64, ng=NG_DEFAULT, recon="ppm", nsteps=20, rk
 
 
 def shock_tube(left, right, n=200, axis=0, ng=NG_DEFAULT, recon="ppm", t_end=0.35, rk=2, cfl=0.25,
-               gamma=5.0 / 3.0, split=0.5, Bn=0.0, Bt=None):
+               gamma=5.0 / 3.0, split=0.5, Bn=0.0, Bt=None, frame=None):
     """One-dimensional Riemann problem along `axis` on [0, 1] (n cells, spacing 1/n on every axis), flat
     metric, copy boundaries for the cell fields.  left/right = (rho, p, v) with v along `axis`; the interface
     is the vertex plane at `split`.  dt = t_end / nsteps with nsteps the smallest count whose step is at most
@@ -280,7 +280,11 @@ def shock_tube(left, right, n=200, axis=0, ng=NG_DEFAULT, recon="ppm", t_end=0.3
     Bn: a uniform field along `axis`.  Bt = (left, right): a field along the first transverse axis t1 =
     (axis + 1) % 3, piecewise constant like the fluid.  With a field, two cells across the other axes and
     the potential's component along t2 = (axis + 2) % 3 is Bn x_t1 - int_0^x B^t1 dx (x along `axis`),
-    filled linearly."""
+    filled linearly.
+
+    frame = (alpha, beta, g): a constant lapse, shift component along `axis` and metric component g_aa
+    (flat spacetime in coordinates that move and stretch along the tube; the other components flat).  The
+    velocity given is then the contravariant component v^a."""
     t1, t2 = (axis + 1) % 3, (axis + 2) % 3
     magnetized = Bn != 0.0 or Bt is not None
     nn = [2, 2, 2] if magnetized else [1, 1, 1]
@@ -288,6 +292,10 @@ def shock_tube(left, right, n=200, axis=0, ng=NG_DEFAULT, recon="ppm", t_end=0.3
     dx = 1.0 / n
     L = Layout(tuple(nn), ng, dx=(dx, dx, dx))
     metric = flat_metric(L)
+    if frame is not None:
+        metric[0] = frame[0]
+        metric[1 + axis] = frame[1]
+        metric[(4, 7, 9)[axis]] = frame[2]
     prim = L.zeros(5)
     pos = L.coords("centre")[axis]
     lft = np.broadcast_to(pos < split, L.shape3)
@@ -303,7 +311,8 @@ def shock_tube(left, right, n=200, axis=0, ng=NG_DEFAULT, recon="ppm", t_end=0.3
         A[t2] = np.broadcast_to(a2, L.shape3)
     nsteps = int(np.ceil(t_end / (cfl * dx) - 1e-9))
     params = default_params(gamma=gamma, rho_atm=1e-7 * max(left[0], right[0]), recon=recon)
-    info = dict(left=tuple(left), right=tuple(right), axis=axis, t_end=t_end, split=split, Bn=Bn, Bt=Bt)
+    info = dict(left=tuple(left), right=tuple(right), axis=axis, t_end=t_end, split=split, Bn=Bn, Bt=Bt,
+                frame=frame)
     return Workload("shock_tube%d" % n, L, params, metric, L.zeros(6), prim, A, L.zeros(1), t_end / nsteps,
                     nsteps, rk, ("copy",) * 3, ("linear",) * 3 if magnetized else ("copy",) * 3, info)
 

@@ -6,6 +6,8 @@ three jump conditions, every rarefaction fan satisfies the self-similar conserva
 on the velocity of the contact, and a classic blast wave reproduces its published middle state.  The oracle's
 numerical solutions then converge to it in L1 at first order (the rate set by the discontinuities), and the
 middle states, away from the waves, match it closely."""
+import math
+
 import numpy as np
 import pytest
 
@@ -344,6 +346,50 @@ def test_transverse_field_tube_axis_symmetry(orc):
         prim, state, _, _ = _oracle_tube_state(orc, w)
         out.append(np.vstack([tube_profile(w, prim)[1], transverse_field(w, state)]))
     assert np.max(np.abs(out[0] - out[1])) <= 1e-12
+
+
+# constant (lapse, shift along the tube, g_aa): flat spacetime in coordinates that move and stretch
+FRAMES = [(0.8, 0.3, 1.44), (1.0, -0.25, 1.0), (0.6, 0.0, 0.64)]
+
+
+def frame_exact(w, x):
+    """The exact solution at the code positions x for a tube in a constant frame (alpha, beta, g = a^2):
+    T = alpha t and X = a (x + beta t) are inertial coordinates (ds^2 = -dT^2 + dX^2), whose observers at rest
+    are the Eulerian observers, so the fluid's inertial velocity V is the Valencia speed and v^x = V / a."""
+    al, be, g = w.info["frame"]
+    a = math.sqrt(g)
+    t = w.info["t_end"]
+    S = X.Solution(w.info["left"], w.info["right"], w.params["gamma"], a * w.info["split"])
+    ex = S.sample(a * (np.asarray(x) + be * t), al * t)
+    ex[2] /= a
+    return ex, S
+
+
+@pytest.mark.parametrize("frame", FRAMES)
+def test_shock_tube_in_moving_frame_converges_to_exact(orc, frame):
+    """The moderate tube in a constant lapse, shift and stretched metric along it (PPM, 100 and 200 cells):
+    the primitives converge at first order to the exact solution carried over to the code's coordinates (the
+    lapse sets the time, the shift moves the pattern, g_aa stretches it and scales v^x); at 200 cells every
+    L1 error is below 5e-3 and the middle states are within 5e-3."""
+    al, be, g = frame
+    a = math.sqrt(g)
+    errs = {}
+    for n in (100, 200):
+        w = W.shock_tube(*MODERATE, n=n, recon="ppm", t_end=0.35, frame=frame)
+        prim, stats, red = _oracle_tube(orc, w)
+        assert stats[3] == 0
+        x, got = tube_profile(w, prim)
+        ex, S = frame_exact(w, x)
+        errs[n] = np.mean(np.abs(got - ex), axis=1)
+    print(frame, "L1(100)", errs[100], "L1(200)", errs[200])
+    assert np.all(errs[200] <= 5e-3)
+    assert np.sum(errs[100]) >= 1.7 * np.sum(errs[200])
+    lh, lt, vc, rt, rh = S.wave_speeds()
+    t = 0.35
+    for p_, q_ in ((lt, vc), (vc, rt)):
+        xm = (S.x0 + 0.5 * al * t * (p_ + q_)) / a - be * t
+        i = int(np.argmin(np.abs(x - xm)))
+        assert np.max(np.abs(got[:, i] - ex[:, i]) / np.abs(ex[:, i])) <= 5e-3
 
 
 @pytest.mark.parametrize("axis", [1, 2])
