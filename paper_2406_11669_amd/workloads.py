@@ -317,6 +317,46 @@ def shock_tube(left, right, n=200, axis=0, ng=NG_DEFAULT, recon="ppm", t_end=0.3
                     nsteps, rk, ("copy",) * 3, ("linear",) * 3 if magnetized else ("copy",) * 3, info)
 
 
+def kerr_schild_block(n=32, origin=(3.0, 0.5, 0.5), extent=3.0, M=1.0, prim_fn=None, ng=NG_DEFAULT, recon="ppm",
+                      nsteps=10, rk=2, cfl=0.25, gamma=4.0 / 3.0, rho_atm=1e-10):
+    """A block of the Schwarzschild spacetime in Kerr-Schild coordinates (mass M at the origin), the cube
+    origin + [0, extent]^3 with n cells per side.  Every stored point, ghosts included, carries the analytic
+    metric: lapse 1/sqrt(1 + 2M/r), shift (2M/r) alpha^2 l^i, gamma_ij = delta_ij + (2M/r) l_i l_j (l = x/r),
+    and the extrinsic curvature of the static metric, K_ij = (2 M alpha / r^2)(delta_ij - (2 + M/r) l_i l_j).
+    prim_fn(x, y, z) -> (5, ...) primitives at the cell centres (ghosts included); no field.  Ghosts are
+    filled by linear extrapolation during a run."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    dx = extent / nn[0]
+    L = Layout(nn, ng, dx=(dx, dx, dx))
+    o = [float(v) for v in origin]
+
+    def at(where):
+        c = L.coords(where)
+        x, y, z = (np.broadcast_to(c[d] + o[d], L.shape3) for d in range(3))
+        r = np.sqrt(x * x + y * y + z * z)
+        return x, y, z, r, (x / r, y / r, z / r)
+
+    x, y, z, r, l = at("vertex")
+    H = M / r
+    alpha = 1.0 / np.sqrt(1.0 + 2.0 * H)
+    metric = L.zeros(10)
+    curv = L.zeros(6)
+    metric[0] = alpha
+    for d in range(3):
+        metric[1 + d] = 2.0 * H * alpha * alpha * l[d]
+    pairs = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    for c, (a, b) in enumerate(pairs):
+        delta = 1.0 if a == b else 0.0
+        metric[4 + c] = delta + 2.0 * H * l[a] * l[b]
+        curv[c] = 2.0 * M * alpha / (r * r) * (delta - (2.0 + H) * l[a] * l[b])
+    xc, yc, zc, _, _ = at("centre")
+    prim = np.ascontiguousarray(np.asarray(prim_fn(xc, yc, zc), dtype=np.float64).reshape((5,) + L.shape3))
+    params = default_params(gamma=gamma, rho_atm=rho_atm, recon=recon)
+    info = dict(M=M, origin=tuple(o), extent=extent)
+    return Workload("kerr_schild%d" % nn[0], L, params, metric, curv, prim, L.zeros(3), L.zeros(1), cfl * dx, nsteps,
+                    rk, ("linear",) * 3, ("linear",) * 3, info)
+
+
 # ---- the curved periodic block -----------------------------------------------------------------------------
 
 _TAGS = {name: t for t, name in enumerate(
