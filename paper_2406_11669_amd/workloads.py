@@ -318,13 +318,15 @@ def shock_tube(left, right, n=200, axis=0, ng=NG_DEFAULT, recon="ppm", t_end=0.3
 
 
 def kerr_schild_block(n=32, origin=(3.0, 0.5, 0.5), extent=3.0, M=1.0, prim_fn=None, ng=NG_DEFAULT, recon="ppm",
-                      nsteps=10, rk=2, cfl=0.25, gamma=4.0 / 3.0, rho_atm=1e-10):
+                      nsteps=10, rk=2, cfl=0.25, gamma=4.0 / 3.0, rho_atm=1e-10, monopole=0.0):
     """A block of the Schwarzschild spacetime in Kerr-Schild coordinates (mass M at the origin), the cube
     origin + [0, extent]^3 with n cells per side.  Every stored point, ghosts included, carries the analytic
     metric: lapse 1/sqrt(1 + 2M/r), shift (2M/r) alpha^2 l^i, gamma_ij = delta_ij + (2M/r) l_i l_j (l = x/r),
     and the extrinsic curvature of the static metric, K_ij = (2 M alpha / r^2)(delta_ij - (2 + M/r) l_i l_j).
-    prim_fn(x, y, z) -> (5, ...) primitives at the cell centres (ghosts included); no field.  Ghosts are
-    filled by linear extrapolation during a run."""
+    prim_fn(x, y, z) -> (5, ...) primitives at the cell centres (ghosts included).  monopole = Q: the field
+    of a magnetic monopole at the origin, densitized B = Q x / r^3, from the potential
+    A = Q (1 - z/r) (-y, x, 0) / (x^2 + y^2) sampled at the edges (its string lies on the negative z axis,
+    outside blocks with x^2 + y^2 > 0 throughout).  Ghosts are filled by linear extrapolation during a run."""
     nn = (n, n, n) if np.isscalar(n) else tuple(n)
     dx = extent / nn[0]
     L = Layout(nn, ng, dx=(dx, dx, dx))
@@ -351,9 +353,15 @@ def kerr_schild_block(n=32, origin=(3.0, 0.5, 0.5), extent=3.0, M=1.0, prim_fn=N
         curv[c] = 2.0 * M * alpha / (r * r) * (delta - (2.0 + H) * l[a] * l[b])
     xc, yc, zc, _, _ = at("centre")
     prim = np.ascontiguousarray(np.asarray(prim_fn(xc, yc, zc), dtype=np.float64).reshape((5,) + L.shape3))
+    A = L.zeros(3)
+    if monopole != 0.0:
+        for q, where in ((0, "xedge"), (1, "yedge")):
+            x, y, z, r, _ = at(where)
+            f = monopole * (1.0 - z / r) / (x * x + y * y)
+            A[q] = -f * y if q == 0 else f * x
     params = default_params(gamma=gamma, rho_atm=rho_atm, recon=recon)
-    info = dict(M=M, origin=tuple(o), extent=extent)
-    return Workload("kerr_schild%d" % nn[0], L, params, metric, curv, prim, L.zeros(3), L.zeros(1), cfl * dx, nsteps,
+    info = dict(M=M, origin=tuple(o), extent=extent, monopole=monopole)
+    return Workload("kerr_schild%d" % nn[0], L, params, metric, curv, prim, A, L.zeros(1), cfl * dx, nsteps,
                     rk, ("linear",) * 3, ("linear",) * 3, info)
 
 

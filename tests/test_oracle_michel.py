@@ -139,3 +139,78 @@ def test_michel_evolution_stays_exact_second_order(orc, flow):
         if n == 48:
             assert np.all(prev >= 3.2 * e) and np.all(e <= 4e-6)
         prev = e
+
+
+Q_STRONG = 10.0  # monopole strength: |B| about 1 on the block, magnetic pressure 5x the gas pressure
+
+
+def _all_rhs_errors(w, out, cons):
+    """L1 of the right-hand side: hydrodynamic components over their conserved scales, the potential's
+    components over max|A|, Psi unscaled."""
+    L = w.layout
+    r, c = L.owned(out), L.owned(cons)
+    sA = np.max(np.abs(L.owned(w.A)))
+    scale = [np.max(np.abs(c[q])) for q in range(5)] + [sA] * 3 + [1.0]
+    return np.array([np.mean(np.abs(r[q])) / scale[q] for q in range(9)])
+
+
+def test_magnetized_michel_rhs_truncation_second_order(orc, flow):
+    """A monopole field along the radial flow carries no current, so the Michel flow stays an exact solution
+    of the magnetized system (the field's stresses balance, v x B = 0, and the potential, azimuthal with a
+    radial shift, keeps beta.A = 0 and div A = 0).  With |B| about 1, the right-hand side at the exact data
+    falls by 3.6x or more per halving in all nine components (hydrodynamic, potential, Psi; 4.0-4.4x
+    measured), and the discrete div B of the face field vanishes to round-off."""
+    m, F = flow
+    prev = None
+    for n in (12, 24, 48):
+        w = W.kerr_schild_block(n=n, prim_fn=F, recon="ppm", monopole=Q_STRONG)
+        L = w.layout
+        out, red, nfix = orc.rhs(L, w.params, w.metric, w.curv, w.prim, w.A, w.psi, w.dt)
+        cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+        assert nfix == 0 and red[1] <= 1e-12
+        e = _all_rhs_errors(w, out, cons)
+        print(n, "L1 rhs / scale", e)
+        if prev is not None:
+            assert np.all(prev >= 3.6 * e)
+        prev = e
+
+
+def michel_interior_errors(orc, w, prim, state, margin=0.75):
+    """Interior L1 errors of the five primitives (over their scales) and of the three face-field components
+    (over max|B|) against the initial exact flow."""
+    L = w.layout
+    n = L.n[0]
+    own, ex = L.owned(prim), L.owned(w.prim)
+    xc = (np.arange(n) + 0.5) * L.dx[0]
+    inner = (xc > margin) & (xc < w.info["extent"] - margin)
+    sel = np.ix_(inner, inner, inner)
+    e = [np.mean(np.abs(own[q][sel] - ex[q][sel])) / np.max(np.abs(ex[q])) for q in range(5)]
+    B1, B0 = L.owned(orc.face_B(L, state[5:8])), L.owned(orc.face_B(L, w.A))
+    e += [np.mean(np.abs(B1[q][sel] - B0[q][sel])) / np.max(np.abs(B0)) for q in range(3)]
+    return np.array(e)
+
+
+def test_magnetized_michel_evolution_stays_exact_second_order(orc, flow):
+    """The magnetized flow (|B| about 1) evolved with RK2 to t = 0.5 M at 12, 24 and 48 cells per side: inside
+    the cube shrunk by 0.75 M per face the primitives and the face field stay at the exact flow, their L1
+    errors falling by 3.2x or more from 24 to 48 cells (4.4-7.5x measured), div B at round-off."""
+    m, F = flow
+    lib = orc.lib_omp()[0]
+    T = 0.5
+    prev = None
+    for n in (12, 24, 48):
+        w = W.kerr_schild_block(n=n, prim_fn=F, recon="ppm", rk=2, monopole=Q_STRONG)
+        L = w.layout
+        nsteps = int(math.ceil(T / w.dt - 1e-9))
+        cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+        orc.fill_ghosts(L, cons, w.bc_cell)
+        state = w.state(cons)
+        prim = w.prim.copy()
+        flags, stats, red = orc.run(L, w.params, w.metric, w.curv, state, prim, T / nsteps, nsteps, w.rk,
+                                    w.bc_cell, w.bc_A, lib_=lib)
+        assert stats[0] == 0 and stats[3] == 0 and red[1] <= 1e-12
+        e = michel_interior_errors(orc, w, prim, state)
+        print(n, "interior L1 / scale (rho, p, v, B)", e)
+        if n == 48:
+            assert np.all(prev >= 3.2 * e)
+        prev = e
