@@ -118,13 +118,14 @@ def test_normal_field_tube_converges_to_exact(ax):
         prev = np.sum(e)
 
 
-@pytest.mark.parametrize("recon", ["ppm", "mp5"])
-def test_transverse_field_tube_matches_oracle(ax, orc, recon):
+@pytest.mark.parametrize("recon,ct", [("ppm", "fct"), ("mp5", "fct"), ("ppm", "uct")])
+def test_transverse_field_tube_matches_oracle(ax, orc, recon, ct):
     """The moderate tube with a transverse field changing sign at the contact (1.0 | -0.3), 200 cells, 280
-    steps: primitives within 2e-9 of the oracle's, the field within 5e-9 (a difference quotient of the
+    steps (flux CT; upwind CT with PPM): primitives within 2e-9 of the oracle's, the field within 5e-9 (a difference quotient of the
     potential over dx = 1/200, so the potential's differences count 200-fold; 1.6e-9 measured with PPM)."""
-    w = W.shock_tube(*MODERATE, n=200, recon=recon, t_end=0.35, Bt=(1.0, -0.3))
-    print("case transverse-field tube 200", recon, flush=True)
+    w = W.shock_tube(*MODERATE, n=200, recon=recon, t_end=0.35, Bt=(1.0, -0.3), ng=4 if ct == "uct" else 3)
+    w.params["ct"] = ct
+    print("case transverse-field tube 200", recon, ct, flush=True)
     pg, st, sg = _gpu_tube(ax, w, with_state=True)
     pc, sc, stc, _ = _oracle_tube_state(orc, w)
     d = np.abs(w.layout.owned(pg) - w.layout.owned(pc)).reshape(5, -1).max(axis=1)

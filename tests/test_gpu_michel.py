@@ -10,7 +10,7 @@ import pytest
 from paper_2406_11669_amd import workloads as W
 from tests.michel import Michel, MichelField
 from tests.parity import assert_fields_close
-from tests.test_oracle_michel import Q_STRONG, _all_rhs_errors, michel_interior_errors
+from tests.test_oracle_michel import Q_STRONG, SCHEMES, _all_rhs_errors, michel_interior_errors, scheme_block
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 STATE_NAMES = ["D", "Sx", "Sy", "Sz", "tau", "Ax", "Ay", "Az", "Psi"]
@@ -142,13 +142,14 @@ def test_michel_evolution_stays_exact_second_order(ax, field):
         prev = e
 
 
-def test_magnetized_michel_rhs_matches_oracle(ax, orc, field):
-    """The monopole-field flow (|B| about 1) on 24^3: the right-hand side against the oracle's, measured
-    against the scale of the terms that cancel (max|D| / dx for the hydrodynamic components, max|A| / dx
-    for the potential and Psi): within 1e-13."""
-    w = W.kerr_schild_block(n=24, prim_fn=field, recon="ppm", monopole=Q_STRONG)
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_magnetized_michel_rhs_matches_oracle(ax, orc, field, scheme):
+    """The monopole-field flow (|B| about 1) on 24^3, every reconstruction, Riemann solver and edge-field
+    scheme: the right-hand side against the oracle's, measured against the scale of the terms that cancel
+    (max|D| / dx for the hydrodynamic components, max|A| / dx for the potential and Psi): within 1e-13."""
+    w = scheme_block(24, field, scheme, monopole=Q_STRONG)
     L = w.layout
-    print("case magnetized michel rhs 24", flush=True)
+    print("case magnetized michel rhs 24", scheme, flush=True)
     g = _gpu_rhs(ax, w)
     ref, red, _ = orc.rhs(L, w.params, w.metric, w.curv, w.prim, w.A, w.psi, w.dt)
     cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
@@ -159,13 +160,14 @@ def test_magnetized_michel_rhs_matches_oracle(ax, orc, field):
     assert np.all(d <= 1e-13)
 
 
-def test_magnetized_michel_rhs_truncation_second_order(ax, orc, field):
+@pytest.mark.parametrize("scheme", ["ppm+hlle+fct", "mp5+lxf+uct"])
+def test_magnetized_michel_rhs_truncation_second_order(ax, orc, field, scheme):
     """The monopole-field flow: the right-hand side at the exact data falls by 3.6x or more per halving in all
     nine components from 32 to 64 to 128 cells per side."""
     prev = None
     for n in (32, 64, 128):
-        w = W.kerr_schild_block(n=n, prim_fn=field, recon="ppm", monopole=Q_STRONG)
-        print("case magnetized michel rhs", n, flush=True)
+        w = scheme_block(n, field, scheme, monopole=Q_STRONG)
+        print("case magnetized michel rhs", scheme, n, flush=True)
         out = _gpu_rhs(ax, w)
         cons = orc.prim2con(w.layout, w.params, w.metric, w.A, w.prim)
         e = _all_rhs_errors(w, out, cons)

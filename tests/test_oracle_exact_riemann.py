@@ -319,16 +319,18 @@ def _oracle_tube_state(orc, w):
     return prim, state, stats, red
 
 
-@pytest.mark.parametrize("Bt", TRANSVERSE)
-def test_transverse_field_tube_converges_to_exact(orc, Bt):
-    """The moderate tube with a transverse field (PPM, 100 and 200 cells): the constrained-transport update of
-    the potential moves the field with the flow (E = -v x B is not zero here), and rho, p, v and B^t converge
+@pytest.mark.parametrize("Bt,ct", [(b, "fct") for b in TRANSVERSE] + [((1.0, -0.3), "uct")])
+def test_transverse_field_tube_converges_to_exact(orc, Bt, ct):
+    """The moderate tube with a transverse field (PPM, 100 and 200 cells; flux CT, and upwind CT for the
+    sign-changing field): the constrained-transport update of the potential moves the field with the flow
+    (E = -v x B is not zero here), and rho, p, v and B^t converge
     to the exact solution at first order (normalized L1 falls by at least 1.6x); at 200 cells the middle
     states are within 3e-3 (rho, p, B^t, of their largest values) and 2e-3 (v); div B stays zero and every
     transverse column equal."""
     errs = {}
     for n in (100, 200):
-        w = W.shock_tube(*MODERATE, n=n, recon="ppm", t_end=0.35, Bt=Bt)
+        w = W.shock_tube(*MODERATE, n=n, recon="ppm", t_end=0.35, Bt=Bt, ng=4 if ct == "uct" else 3)
+        w.params["ct"] = ct
         prim, state, stats, red = _oracle_tube_state(orc, w)
         assert stats[3] == 0 and red[1] <= 1e-12
         assert tube_uniformity(w, prim) <= 1e-12

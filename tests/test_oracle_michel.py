@@ -154,16 +154,31 @@ def _all_rhs_errors(w, out, cons):
     return np.array([np.mean(np.abs(r[q])) / scale[q] for q in range(9)])
 
 
-def test_magnetized_michel_rhs_truncation_second_order(orc, flow):
+SCHEMES = ["ppm+hlle+fct", "mp5+hlle+fct", "wenoz+hlle+fct", "ppm+lxf+fct", "ppm+hlle+uct", "mp5+lxf+uct"]
+
+
+def scheme_block(n, F, scheme, **kw):
+    """The Kerr-Schild block with reconstruction + Riemann solver + edge-field scheme ("ppm+hlle+uct"; upwind
+    CT takes four ghost layers)."""
+    recon, riemann, ct = scheme.split("+")
+    w = W.kerr_schild_block(n=n, prim_fn=F, recon=recon, ng=4 if ct == "uct" else 3, **kw)
+    w.params["riemann"] = riemann
+    w.params["ct"] = ct
+    return w
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_magnetized_michel_rhs_truncation_second_order(orc, flow, scheme):
     """A monopole field along the radial flow carries no current, so the Michel flow stays an exact solution
     of the magnetized system (the field's stresses balance, v x B = 0, and the potential, azimuthal with a
     radial shift, keeps beta.A = 0 and div A = 0).  With |B| about 1, the right-hand side at the exact data
-    falls by 3.6x or more per halving in all nine components (hydrodynamic, potential, Psi; 4.0-4.4x
-    measured), and the discrete div B of the face field vanishes to round-off."""
+    falls by 3.6x or more per halving in all nine components (hydrodynamic, potential, Psi; 4.0-4.45x
+    measured for every reconstruction, Riemann solver and edge-field scheme), and the discrete div B of the
+    face field vanishes to round-off."""
     m, F = flow
     prev = None
     for n in (12, 24, 48):
-        w = W.kerr_schild_block(n=n, prim_fn=F, recon="ppm", monopole=Q_STRONG)
+        w = scheme_block(n, F, scheme, monopole=Q_STRONG)
         L = w.layout
         out, red, nfix = orc.rhs(L, w.params, w.metric, w.curv, w.prim, w.A, w.psi, w.dt)
         cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
