@@ -365,6 +365,37 @@ def kerr_schild_block(n=32, origin=(3.0, 0.5, 0.5), extent=3.0, M=1.0, prim_fn=N
                     rk, ("linear",) * 3, ("linear",) * 3, info)
 
 
+def alfven_wave(n=32, ng=NG_DEFAULT, recon="minmod", t_end=2.0, rk=2, cfl=0.2, gamma=5.0 / 3.0, A0=1.0, vA=0.5,
+                Bx=1.0, rho=1.0, p=0.5):
+    """The circularly polarized Alfven wave of the paper's convergence test: x in [-0.5, 0.5] (n cells, two
+    across y and z, spacing 1/n), flat metric, rho = 1, p = 0.5, B = Bx (1, A0 cos kx, A0 sin kx),
+    v = -vA A0 (0, cos kx, sin kx), k = 2 pi, Gamma = 5/3, MINMOD, RK2, CFL 0.2; periodic in every
+    direction.  The potential A = (0, -A0 Bx cos(kx)/k, Bx y - A0 Bx sin(kx)/k) (x the physical coordinate)
+    is periodic up to the constant Bx L_y that A_z gains per period along y (A_shift).  dt = t_end / nsteps
+    with the step at most cfl dx."""
+    L = Layout((n, 2, 2), ng, dx=(1.0 / n,) * 3)
+    k = 2.0 * np.pi
+    xc, _, _ = L.coords("centre")
+    xc = xc - 0.5
+    prim = L.zeros(5)
+    prim[0] = rho
+    prim[1] = p
+    prim[3] = np.broadcast_to(-vA * A0 * np.cos(k * xc), L.shape3)
+    prim[4] = np.broadcast_to(-vA * A0 * np.sin(k * xc), L.shape3)
+    A = L.zeros(3)
+    xy, _, _ = L.coords("yedge")
+    A[1] = np.broadcast_to(-A0 * Bx * np.cos(k * (xy - 0.5)) / k, L.shape3)
+    xz, yz, _ = L.coords("zedge")
+    A[2] = np.broadcast_to(Bx * yz - A0 * Bx * np.sin(k * (xz - 0.5)) / k, L.shape3)
+    nsteps = int(np.ceil(t_end / (cfl / n) - 1e-9))
+    params = default_params(gamma=gamma, recon=recon)
+    info = dict(t_end=t_end, A0=A0, vA=vA, Bx=Bx, rho=rho, p=p)
+    shift = np.zeros((3, 3))
+    shift[2, 1] = Bx * L.n[1] * L.dx[1]
+    return Workload("alfven%d" % n, L, params, flat_metric(L), L.zeros(6), prim, A, L.zeros(1), t_end / nsteps,
+                    nsteps, rk, ("periodic",) * 3, ("periodic",) * 3, info, shift)
+
+
 # ---- the curved periodic block -----------------------------------------------------------------------------
 
 _TAGS = {name: t for t, name in enumerate(

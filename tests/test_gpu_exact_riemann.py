@@ -186,3 +186,43 @@ def test_moving_frame_tube_converges_to_exact(ax, frame):
             assert prev >= 1.6 * np.sum(e)
         prev = np.sum(e)
     assert np.all(e <= 1e-3)
+
+
+def _gpu_alfven(ax, w):
+    import torch
+    blk = ax.Block(w)
+    blk.run(w.nsteps)
+    torch.cuda.synchronize()
+    return blk.prim.cpu().numpy(), blk.state.cpu().numpy()
+
+
+def test_alfven_wave_matches_oracle(ax, orc):
+    """The Alfven-wave test of Sec. 4 (MINMOD, RK2, CFL 0.2) on 32 cells for one period (320 steps): state
+    and primitives within 1e-10 of the oracle's."""
+    from tests.test_oracle_grid import run_alfven
+    w = W.alfven_wave(n=32)
+    print("case alfven 32", flush=True)
+    pg, sg = _gpu_alfven(ax, w)
+    _, pc, sc = run_alfven(orc, 32)
+    L = w.layout
+    d = np.abs(L.owned(sg) - L.owned(sc)).reshape(9, -1).max(axis=1)
+    dp = np.abs(L.owned(pg) - L.owned(pc)).reshape(5, -1).max(axis=1)
+    print("  max |gpu - oracle| state", d, "primitives", dp)
+    assert np.all(d <= 1e-10) and np.all(dp <= 1e-10)
+
+
+@pytest.mark.parametrize("recon", ["minmod", "ppm"])
+def test_alfven_wave_converges_to_exact(ax, orc, recon):
+    """The Alfven wave for one period at 64, 128, 256 and 512 cells: the L2 errors of B^y and v^y against the
+    exact wave fall at second order (order >= 1.75 per doubling)."""
+    from tests.test_oracle_grid import alfven_errors
+    prev = None
+    for n in (64, 128, 256, 512):
+        w = W.alfven_wave(n=n, recon=recon)
+        print("case alfven", recon, n, flush=True)
+        pg, sg = _gpu_alfven(ax, w)
+        e = alfven_errors(orc, w, pg, sg)
+        print("  L2 (B^y, v^y)", e)
+        if prev is not None:
+            assert np.log2(prev[0] / e[0]) >= 1.75 and np.log2(prev[1] / e[1]) >= 1.75
+        prev = e
