@@ -396,6 +396,31 @@ def alfven_wave(n=32, ng=NG_DEFAULT, recon="minmod", t_end=2.0, rk=2, cfl=0.2, g
                     nsteps, rk, ("periodic",) * 3, ("periodic",) * 3, info, shift)
 
 
+def loop_advection(n=64, nz=1, ng=NG_DEFAULT, recon="minmod", t_end=1.2, rk=4, cfl=0.25, gamma=5.0 / 3.0,
+                   A_loop=1e-3, R_loop=0.3, vel=(1.0 / 12.0, 1.0 / 24.0, 1.0 / 24.0), rho=1.0, p=3.0):
+    """The magnetic loop advection test of Sec. 4: x, y in [-0.5, 0.5] (n x n cells, nz across z, spacing
+    1/n), flat metric, uniform rho = 1, p = 3 and v = (1/12, 1/24, 1/24); the loop's potential
+    A_z = max(0, A_loop (R_loop - r)), r = sqrt(x^2 + y^2), at the z edges (A_loop = 1e-3, R_loop = 0.3);
+    Gamma = 5/3, MINMOD, HLLE, RK4, CFL 0.25; periodic in every direction.  dt = t_end / nsteps with the
+    step at most cfl dx."""
+    L = Layout((n, n, nz), ng, dx=(1.0 / n,) * 3)
+    prim = L.zeros(5)
+    prim[0] = rho
+    prim[1] = p
+    for d in range(3):
+        prim[2 + d] = vel[d]
+    A = L.zeros(3)
+    xz, yz, _ = L.coords("zedge")
+    r = np.sqrt((xz - 0.5) ** 2 + (yz - 0.5) ** 2)
+    A[2] = np.broadcast_to(np.maximum(0.0, A_loop * (R_loop - r)), L.shape3)
+    L.periodic_wrap(A)
+    nsteps = int(np.ceil(t_end / (cfl / n) - 1e-9))
+    params = default_params(gamma=gamma, recon=recon)
+    info = dict(t_end=t_end, A_loop=A_loop, R_loop=R_loop, vel=tuple(vel))
+    return Workload("loop%d" % n, L, params, flat_metric(L), L.zeros(6), prim, A, L.zeros(1), t_end / nsteps,
+                    nsteps, rk, ("periodic",) * 3, ("periodic",) * 3, info)
+
+
 # ---- the curved periodic block -----------------------------------------------------------------------------
 
 _TAGS = {name: t for t, name in enumerate(

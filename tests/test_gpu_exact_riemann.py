@@ -226,3 +226,36 @@ def test_alfven_wave_converges_to_exact(ax, orc, recon):
         if prev is not None:
             assert np.log2(prev[0] / e[0]) >= 1.75 and np.log2(prev[1] / e[1]) >= 1.75
         prev = e
+
+
+@pytest.mark.parametrize("recon,ct", [("minmod", "fct"), ("ppm", "uct")])
+def test_loop_advection_matches_oracle(ax, orc, recon, ct):
+    """The loop advection test of Sec. 4 on 32 x 32 cells to t = 0.6 (77 RK4 steps): state within 1e-10 of
+    the oracle's (per field, against the field's largest value)."""
+    from tests.parity import assert_fields_close
+    from tests.test_oracle_loop import run_loop
+    w = W.loop_advection(n=32, recon=recon, ng=4 if ct == "uct" else 3, t_end=0.6)
+    w.params["ct"] = ct
+    print("case loop 32", recon, ct, flush=True)
+    pg, sg = _gpu_alfven(ax, w)
+    _, sc, pc, stc, _ = run_loop(orc, 32, recon, ct)
+    e = assert_fields_close(sg, sc, 1e-10, w.layout.owned)
+    print("  max error per field", e)
+
+
+@pytest.mark.parametrize("recon,ct", [("minmod", "fct"), ("ppm", "uct")])
+def test_loop_advection_converges_to_exact(ax, recon, ct):
+    """The loop to t = 1.2 at 64, 128, 256 and 512 cells per side: the L1 error of the face field against the
+    translated loop falls by 1.45x or more per doubling, and the magnetic energy kept rises toward 1."""
+    from tests.test_oracle_loop import loop_errors
+    prev = None
+    for n in (64, 128, 256, 512):
+        w = W.loop_advection(n=n, recon=recon, ng=4 if ct == "uct" else 3, t_end=1.2)
+        w.params["ct"] = ct
+        print("case loop", recon, ct, n, flush=True)
+        pg, sg = _gpu_alfven(ax, w)
+        e, kept = loop_errors(w, sg[5:8])
+        print("  L1 (B^x, B^y) / A_loop", e, "energy kept", kept)
+        if prev is not None:
+            assert np.all(prev[0] >= 1.45 * e) and prev[1] < kept < 1.0
+        prev = (e, kept)
