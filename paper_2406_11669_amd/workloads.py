@@ -421,6 +421,36 @@ def loop_advection(n=64, nz=1, ng=NG_DEFAULT, recon="minmod", t_end=1.2, rk=4, c
                     nsteps, rk, ("periodic",) * 3, ("periodic",) * 3, info)
 
 
+def static_star_block(n=40, origin=(0.0, 0.0, 0.0), extent=10.0, star_fn=None, ng=NG_DEFAULT, recon="ppm", nsteps=10,
+                      rk=4, cfl=0.25, gamma=2.0, rho_atm=1e-10, bc=("copy",) * 3):
+    """A block of a static, conformally flat spacetime with a fluid at rest: the cube origin + [0, extent]^3
+    with n cells per side.  star_fn(x, y, z, rho_atm) -> (alpha, psi^4, rho, p) gives the lapse and the
+    conformal factor (gamma_ij = psi^4 delta_ij, zero shift and extrinsic curvature) at every vertex and the
+    density and pressure at every cell centre, ghosts included."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    dx = extent / nn[0]
+    L = Layout(nn, ng, dx=(dx, dx, dx))
+    o = [float(v) for v in origin]
+
+    def at(where):
+        c = L.coords(where)
+        return tuple(np.broadcast_to(c[d] + o[d], L.shape3) for d in range(3))
+
+    alpha, psi4, _, _ = star_fn(*at("vertex"), rho_atm)
+    metric = L.zeros(10)
+    metric[0] = alpha
+    for c in (4, 7, 9):
+        metric[c] = psi4
+    _, _, rho, p = star_fn(*at("centre"), rho_atm)
+    prim = L.zeros(5)
+    prim[0] = rho
+    prim[1] = p
+    params = default_params(gamma=gamma, rho_atm=rho_atm, recon=recon)
+    info = dict(origin=tuple(o), extent=extent)
+    return Workload("static_star%d" % nn[0], L, params, metric, L.zeros(6), prim, L.zeros(3), L.zeros(1), cfl * dx,
+                    nsteps, rk, tuple(bc), tuple(bc), info)
+
+
 # ---- the curved periodic block -----------------------------------------------------------------------------
 
 _TAGS = {name: t for t, name in enumerate(
