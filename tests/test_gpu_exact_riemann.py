@@ -230,11 +230,11 @@ def test_alfven_wave_converges_to_exact(ax, orc, recon):
 
 @pytest.mark.parametrize("recon,ct", [("minmod", "fct"), ("ppm", "uct")])
 def test_loop_advection_matches_oracle(ax, orc, recon, ct):
-    """The loop advection test of Sec. 4 on 32 x 32 cells to t = 0.6 (77 RK4 steps): state within 1e-10 of
+    """The loop advection test of Sec. 4 on 32 x 32 cells to t = 0.3 (39 RK4 steps): state within 1e-10 of
     the oracle's (per field, against the field's largest value)."""
     from tests.parity import assert_fields_close
     from tests.test_oracle_loop import run_loop
-    w = W.loop_advection(n=32, recon=recon, ng=4 if ct == "uct" else 3, t_end=0.6)
+    w = W.loop_advection(n=32, recon=recon, ng=4 if ct == "uct" else 3, t_end=0.3)
     w.params["ct"] = ct
     print("case loop 32", recon, ct, flush=True)
     pg, sg = _gpu_alfven(ax, w)
