@@ -1,5 +1,6 @@
 """A static polytropic star (Tolman-Oppenheimer-Volkoff) in isotropic coordinates, as a fixed 3+1 metric and
-hydrostatic primitives (test helper, independent of the oracle and of the HIP path).
+hydrostatic primitives.  Initial data only: the oracle and the HIP path both receive its metric and
+primitives as inputs, and neither uses this module.
 
 Polytrope p = K rho^G with the ideal-gas energy density e = rho + p / (G - 1).  In the Schwarzschild radius
 r the structure follows dm/dr = 4 pi r^2 e, dp/dr = -(e + p)(m + 4 pi r^3 p) / (r (r - 2m)) and the lapse

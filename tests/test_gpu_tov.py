@@ -1,12 +1,12 @@
 """The HIP path on a static TOV star in its fixed isotropic metric (the Cowling set-up of the paper's TOV
-test, Sec. 4; tests/tov.py): right-hand side against the oracle and second-order truncation of the
+test, Sec. 4; paper_2406_11669_amd/tov.py): right-hand side against the oracle and second-order truncation of the
 hydrostatic balance at sizes the oracle would take long for."""
 import numpy as np
 import pytest
 
 from paper_2406_11669_amd import workloads as W
 from tests.test_oracle_tov import interior_rhs
-from tests.tov import TOV
+from paper_2406_11669_amd.tov import TOV
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 

@@ -1,5 +1,5 @@
 """The oracle against a static star: a TOV polytrope (K = 100, Gamma = 2, central density 1.28e-3; M = 1.400,
-Schwarzschild radius 9.586, isotropic radius 8.125; tests/tov.py) in its own fixed isotropic metric (the
+Schwarzschild radius 9.586, isotropic radius 8.125; paper_2406_11669_amd/tov.py) in its own fixed isotropic metric (the
 Cowling set-up of the paper's TOV test, Sec. 4), on the octant [0, 10]^3.  Hydrostatic equilibrium makes the
 right-hand side vanish, so its discrete value at the exact data is truncation error: the momentum
 components, a pressure gradient balanced by the lapse's and conformal factor's derivatives, fall at second
@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2406_11669_amd import workloads as W
-from tests.tov import TOV
+from paper_2406_11669_amd.tov import TOV
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
