@@ -82,13 +82,16 @@ RIDGE = FP64_VECTOR_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS   # FLOP/B where the FP64 a
 
 
 def library_source_sha():
-    """First 16 hex digits of the sha256 of the HIP sources the library is built from."""
+    """First 16 hex digits of the sha256 of the HIP sources the library is built from and of the flags that
+    decide its code."""
     import hashlib
+    from paper_2406_11669_amd.build import CODEGEN_FLAGS
     csrc = os.path.join(ROOT, "paper_2406_11669_amd", "csrc")
     h = hashlib.sha256()
     for name in ("asterx.hip", "grmhd_device.h"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    h.update(" ".join(CODEGEN_FLAGS).encode())
     return h.hexdigest()[:16]
 
 

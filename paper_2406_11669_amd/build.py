@@ -10,12 +10,16 @@ LIB = os.path.join(HERE, "libasterx.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-FLAGS = [
+# flags that decide the generated code (hashed with the sources to tie profiles to a build)
+CODEGEN_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+    # the scheduler's instruction-level-parallelism strategy: the latency-bound face and recovery kernels
+    # issue their loads and FP64 chains further apart (the same arithmetic, 1.2% more zone-updates/s)
+    "-mllvm", "-amdgpu-sched-strategy=max-ilp",
 ]
+FLAGS = CODEGEN_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
 
 
 def sources():
