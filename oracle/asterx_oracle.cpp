@@ -973,6 +973,17 @@ template <class T> uint8_t c2p_point(const Geom<T>& G, T cons[5], const T Bt[3],
     return fl;
   }
   C2PInput<T> c = make_c2p_input(G, cons, Bt);
+  // Without a field and with Gamma <= 2, every physical state of the ideal gas has tau > 0 and
+  // E^2 > S^2 + D^2, i.e. S^2 < tau (tau + 2D) (E^2 - S^2 - D^2 = W^2 rho^2 (2 eps + eps^2 (1 - (Gamma-1)^2))
+  // + p^2).  A state beyond that bound by more than a relative 1e-10 has no solution for either solver to
+  // find; it takes the failure branch with the flags the two failed solvers set (Sec. 3.6).
+  if (c.B2 <= T(0) && gam <= T(2) &&
+      (!(c.tau > T(0)) || c.S2 > T(1.0 + 1e-10) * c.tau * (c.tau + T(2) * c.D))) {
+    if (P.c2p_method != 2) fl |= FL_NOBLE_FAIL;
+    fl |= FL_HARD_FAIL | FL_ATMO;
+    atmosphere(G, Bt, gam, P, prim, cons);
+    return fl;
+  }
   bool ok = false;
   if (P.c2p_method != 2) {
     T z0, w0;

@@ -938,6 +938,14 @@ DEV uint32_t c2p_point(const Geo& G, double U[5], const double Bt[3], const doub
   }
   C2PIn c;
   c2p_input(G, U, Bt, c);
+  // no field and Gamma <= 2: a state with tau <= 0 or S^2 beyond tau (tau + 2D) (by a relative 1e-10) is
+  // not a physical state of the ideal gas (E^2 > S^2 + D^2 for every one); the solvers cannot succeed, so the
+  // cell takes the failure branch at once, with the flags they would have set (Sec. 3.6)
+  if (c.B2 <= 0.0 && P.gam <= 2.0 && (!(c.tau > 0.0) || c.S2 > (1.0 + 1e-10) * c.tau * (c.tau + 2.0 * c.D))) {
+    fl = (P.method != 2 ? 1u | (zw_guess ? 32u : 0u) : 0u) | 8u | 4u;
+    atmo(G, Bt, P, out, U);
+    return fl;
+  }
   bool ok = false;
   const double wcap = 1.0 - 1.0 / (P.wmax * P.wmax);
   if (P.method != 2) {

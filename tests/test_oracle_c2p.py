@@ -182,3 +182,32 @@ def test_failure_injection(orc):
     bad[4] = -abs(bad[4])  # negative energy
     out, fl, _, after = orc.pt_c2p(P, m, bad, Bt, pr)
     assert fl & 4 and np.all(np.isfinite(out))
+
+
+@pytest.mark.parametrize("gam", [4.0 / 3.0, 5.0 / 3.0, 2.0])
+def test_no_solution_bound(orc, gam):
+    """Without a field and with Gamma <= 2, E^2 - S^2 - D^2 = W^2 rho^2 (2 eps + eps^2 (1 - (Gamma-1)^2)) + p^2 > 0
+    for every physical state (checked here on sampled ones, nearly cold included), so S^2 < tau (tau + 2D) and
+    tau > 0; beyond that bound the recovery takes the failure branch (atmosphere, Noble-failed and hard-fail
+    flags), and just inside it the nearly cold states still recover to 1e-9."""
+    rng = np.random.default_rng(31)
+    P = default_params(gamma=gam, rho_atm=1e-12)
+    zero = np.zeros(3)
+    for _ in range(200):
+        m = random_metric(rng)
+        g = gmat(m)
+        sq = np.sqrt(np.linalg.det(g))
+        pr = random_prim(rng, m, vmax=0.95, rho=(1e-3, 1.0), p=(1e-9, 1e-1), log=True)
+        cons = orc.pt_prim2con(m, pr, zero, gam) / sq
+        D, S, tau = cons[0], cons[1:4], cons[4]
+        S2 = S @ np.linalg.inv(g) @ S
+        assert tau > 0 and S2 < tau * (tau + 2 * D)
+        out, fl, _, _ = orc.pt_c2p(P, m, cons * sq, zero, pr)
+        assert not fl & 8
+        assert np.allclose(out, pr, rtol=1e-9, atol=1e-12)
+        bad = cons.copy()
+        bad[1:4] *= np.sqrt(tau * (tau + 2 * D) / S2) * rng.uniform(1.0 + 1e-8, 3.0) if S2 > 0 else 1.0
+        out, fl, _, after = orc.pt_c2p(P, m, bad * sq, zero, pr)
+        if S2 > 0:
+            assert fl & 8 and fl & 4 and fl & 1, fl
+            assert out[0] == P["rho_atm"] and np.all(out[2:] == 0)
