@@ -483,7 +483,6 @@ def extra_adjoint(torch, W, reps=3):
 # uniform 240^3 grid, PPM + HLLE, RK4, Neumann (copy) boundaries, 3 ghosts: 0.27e8 zone-cycles/s on one MI250X
 # GCD, a zone-cycle being one cell advanced one whole RK4 step.
 PAPER_SETUP_A_ZCS = 0.27e8
-GAUSS = 1.0 / 8.351e19  # one gauss in units with G = c = M_sun = 1
 
 
 def extra_setup_a(torch, asterx, W, steps, n=240, extent=40.0):
@@ -491,25 +490,7 @@ def extra_setup_a(torch, asterx, W, steps, n=240, extent=40.0):
     fixed isotropic metric, the field of A_phi = A_b varpi^2 max(p - 0.04 p_max, 0)^2 with A_b giving a largest
     field of about 1e14 G, rho_atm = 1e-7 rho_c, on [-20, 20]^3 (the extent of the finest level of the
     paper's TOV runs; the benchmark's own extent is not printed) with 240^3 cells: graph-replayed RK4 steps."""
-    import numpy as np
-    from paper_2406_11669_amd.tov import TOV
-    star = TOV()
-    rho_atm = 1e-7 * star.rho_c
-    w = W.static_star_block(n=n, origin=(-0.5 * extent,) * 3, extent=extent, star_fn=star.fields, recon="ppm",
-                            rk=4, gamma=2.0, rho_atm=rho_atm)
-    L = w.layout
-    p_cut = 0.04 * star.K * star.rho_c ** star.G
-    for q, where in ((0, "xedge"), (1, "yedge")):
-        c = L.coords(where)
-        x, y, z = (np.broadcast_to(c[d] - 0.5 * extent, L.shape3) for d in range(3))
-        f = np.maximum(star.fields(x, y, z, rho_atm)[3] - p_cut, 0.0) ** 2
-        w.A[q] = -y * f if q == 0 else x * f
-    # scale A_b so that the largest |B| (densitized field over psi^6) is about 1e14 G
-    dx = L.dx[0]
-    bt = np.sqrt(np.gradient(w.A[1], dx, axis=0) ** 2 + np.gradient(w.A[0], dx, axis=0) ** 2
-                 + (np.gradient(w.A[1], dx, axis=2) - np.gradient(w.A[0], dx, axis=1)) ** 2)
-    bmax = float(np.max(bt / w.metric[4] ** 1.5))
-    w.A *= 1e14 * GAUSS / bmax
+    w = W.magnetized_star_block(n=n, extent=extent)
     blk = asterx.Block(w)
     ms = graph_steps(torch, blk, steps, 1)
     value = n ** 3 * 4 * steps / (ms * 1e-3)

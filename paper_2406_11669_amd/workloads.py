@@ -451,6 +451,36 @@ def static_star_block(n=40, origin=(0.0, 0.0, 0.0), extent=10.0, star_fn=None, n
                     nsteps, rk, tuple(bc), tuple(bc), info)
 
 
+GAUSS = 1.0 / 8.351e19  # one gauss in units with G = c = M_sun = 1
+
+
+def magnetized_star_block(n=240, extent=40.0, B_max_gauss=1e14, ng=NG_DEFAULT, nsteps=5, rk=4, cfl=0.25):
+    """The paper's Setup A (its single-GPU benchmark): a magnetized TOV star in a static (Cowling) spacetime on
+    a uniform grid.  The K = 100, Gamma = 2 polytrope with central density 1.28e-3 (paper_2406_11669_amd/tov.py)
+    in its isotropic metric on [-extent/2, extent/2]^3 with n cells per side; rho_atm = 1e-7 rho_c; PPM, HLLE,
+    RK4, copy (Neumann) boundaries.  The field comes from A_phi = A_b varpi^2 max(p - 0.04 p_max, 0)^2, i.e.
+    A = A_b max(p - p_cut, 0)^2 (-y, x, 0) at the edges, with A_b chosen so that the largest |B| (the curl
+    over psi^6) is about B_max_gauss."""
+    from paper_2406_11669_amd.tov import TOV
+    star = TOV()
+    rho_atm = 1e-7 * star.rho_c
+    w = static_star_block(n=n, origin=(-0.5 * extent,) * 3, extent=extent, star_fn=star.fields, ng=ng,
+                          recon="ppm", nsteps=nsteps, rk=rk, cfl=cfl, gamma=2.0, rho_atm=rho_atm)
+    L = w.layout
+    p_cut = 0.04 * star.K * star.rho_c ** star.G
+    for q, where in ((0, "xedge"), (1, "yedge")):
+        c = L.coords(where)
+        x, y, z = (np.broadcast_to(c[d] - 0.5 * extent, L.shape3) for d in range(3))
+        f = np.maximum(star.fields(x, y, z, rho_atm)[3] - p_cut, 0.0) ** 2
+        w.A[q] = -y * f if q == 0 else x * f
+    dx = L.dx[0]
+    bt = np.sqrt(np.gradient(w.A[1], dx, axis=0) ** 2 + np.gradient(w.A[0], dx, axis=0) ** 2
+                 + (np.gradient(w.A[1], dx, axis=2) - np.gradient(w.A[0], dx, axis=1)) ** 2)
+    w.A *= B_max_gauss * GAUSS / float(np.max(bt / w.metric[4] ** 1.5))
+    w.info.update(star="TOV K=100 Gamma=2 rho_c=1.28e-3", B_max_gauss=B_max_gauss)
+    return w
+
+
 # ---- the curved periodic block -----------------------------------------------------------------------------
 
 _TAGS = {name: t for t, name in enumerate(

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2406_11669_amd import workloads as W
+from tests.parity import assert_fields_close
 from tests.test_oracle_tov import interior_rhs
 from paper_2406_11669_amd.tov import TOV
 
@@ -102,3 +103,40 @@ def test_tov_star_stays_static_second_order(ax, star):
             assert prev >= 3.0 * drift
         prev = drift
     assert drift <= 1e-3
+
+
+def test_setup_a_matches_oracle(ax, orc):
+    """The paper's Setup A workload (magnetized TOV star, Cowling, PPM, HLLE, RK4, copy boundaries, 96%
+    atmosphere) at 40^3 for two RK4 steps against the oracle.  The atmosphere sits at the floor, so whether a
+    cell's D is below sqrt(gamma) rho_atm, or its recovered rho below rho_atm, is decided within rounding (the
+    two sides form sqrt(gamma) in different orders): a few thousand of 64000 cells take the reset on one side
+    and a solved near-floor state on the other, and their momentum (about 1e-13) differs.  So the comparison
+    is made where rho >= 1e3 rho_atm on both sides (the star and its surface): the state, rho and p within
+    1e-10 of the field scales (2.7e-11 measured); the velocities within 2e-9 (7.3e-10 measured: v = S / (rho h
+    W^2) at the lowest compared densities magnifies the state's differences there); the outcome counters
+    within 10% of each other (the atmosphere resets 4.5% apart, the failures 0.03%)."""
+    import torch
+    w = W.magnetized_star_block(n=40)
+    print("case setup A 40", flush=True)
+    blk = ax.Block(w)
+    blk.run(2)
+    torch.cuda.synchronize()
+    L = w.layout
+    cons = orc.prim2con(L, w.params, w.metric, w.A, w.prim)
+    orc.fill_ghosts(L, cons, w.bc_cell)
+    state = w.state(cons)
+    prim = w.prim.copy()
+    flags, stats, red = orc.run(L, w.params, w.metric, w.curv, state, prim, w.dt, 2, w.rk, w.bc_cell, w.bc_A)
+    sg, pg = blk.state.cpu().numpy(), blk.prim.cpu().numpy()
+    cg = blk.stats.cpu().numpy()[:5].astype(np.int64)
+    cc = np.asarray(stats[:5], dtype=np.int64)
+    print("  counters gpu", cg, "oracle", cc)
+    dense = (L.owned(pg[0]) >= 1e3 * w.params["rho_atm"]) & (L.owned(prim[0]) >= 1e3 * w.params["rho_atm"])
+    print("  cells compared", int(dense.sum()), "of", dense.size)
+    for name, g, c, tol in (("state", sg, state, [1e-10] * 9), ("prim", pg, prim, [1e-10] * 2 + [2e-9] * 3)):
+        go, co = L.owned(g), L.owned(c)
+        e = [float(np.max(np.abs(go[f][dense] - co[f][dense])) / max(np.max(np.abs(co[f])), 1e-300))
+             for f in range(g.shape[0])]
+        print("  %s max error per field over its scale" % name, np.array(e))
+        assert all(a <= b for a, b in zip(e, tol))
+    assert np.all(np.abs(cg - cc) <= 0.1 * np.maximum(cc, 1))
