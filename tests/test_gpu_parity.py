@@ -391,7 +391,7 @@ def test_tmunu_vs_oracle(ax, torch_mod, orc, shape):
 
 
 def _metric_at(w, t, period):
-    """A time-dependent spacetime for the driver test: the workload's metric with the lapse scaled by
+    """A time-dependent spacetime for the RK driver test: the workload's metric with the lapse scaled by
     1 + 0.1 sin(2 pi t / period) and the shift by the opposite factor."""
     f = 1.0 + 0.1 * np.sin(2.0 * np.pi * t / period)
     m = w.metric.copy()
