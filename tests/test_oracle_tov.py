@@ -57,3 +57,24 @@ def test_tov_rhs_truncation(orc, star):
         if prev is not None:
             assert np.all(prev[1:4] >= 3.6 * e[1:4]) and prev[0] >= 3.2 * e[0] and prev[4] >= 3.2 * e[4]
         prev = e
+
+
+def test_setup_a_star_field(orc):
+    """The Setup A workload's field: divergence-free to round-off under the discrete curl, confined to the
+    star (zero on every face outside the isotropic radius), and largest at about 1e14 G (the scaling uses
+    centred differences, the curl the staggered ones: within 20%)."""
+    w = W.magnetized_star_block(n=32)
+    L = w.layout
+    Bf = orc.face_B(L, w.A)
+    g = L.ng
+    own = Bf[:, g:g + 32, g:g + 32, g:g + 32]
+    div = (np.diff(Bf[0], axis=2)[g:g + 32, g:g + 32, g:g + 32] + np.diff(Bf[1], axis=1)[g:g + 32, g:g + 32, g:g + 32]
+           + np.diff(Bf[2], axis=0)[g:g + 32, g:g + 32, g:g + 32])
+    assert np.max(np.abs(div)) <= 1e-12 * np.max(np.abs(own))
+    x, y, z = L.coords("centre")
+    r = np.sqrt((x - 20.0) ** 2 + (y - 20.0) ** 2 + (z - 20.0) ** 2)[g:g + 32, g:g + 32, g:g + 32]
+    outside = r > 8.125 + 2.0
+    assert np.all(own[:, outside] == 0.0)
+    psi6 = L.owned(w.metric[4]) ** 1.5
+    bmax = np.max(np.sqrt(np.sum(own ** 2, axis=0)) / psi6) * 8.351e19
+    assert 0.8e14 <= bmax <= 1.2e14, bmax
