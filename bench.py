@@ -10,8 +10,9 @@ Prints one JSON line: zone-updates/s per RK stage (interior cells x stages / wal
 roofline of the dominant kernel and per-kernel figures of the face kernels, the recovery with sources and the
 divergence kernel (per-kernel HIP events recorded live on the launch stream); the whole-stage HBM and FP64
 rooflines; the same block with the other reconstruction, batched patches against a per-patch loop, the learned
-recovery guess against the plain one and one adjoint gradient, forward and reverse (comparison keys); and the CPU
-oracle timed on the host (serial on a bounded sample, all cores on the full block).
+recovery guess against the plain one, one adjoint gradient, forward and reverse, and the paper's own single-GPU
+benchmark (its Setup A, a magnetized TOV star at 240^3) in the paper's zone-cycles/s beside the paper's figure
+(comparison keys); and the CPU oracle timed on the host (serial on a bounded sample, all cores on the full block).
 """
 import argparse
 import json
